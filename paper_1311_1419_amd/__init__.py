@@ -1,0 +1,14 @@
+"""MI355X (gfx950) multiple-residual compressive-sensing video coder.
+
+The coder of Yu, Qiao, Luo and Yang (key frame + CS frames per GOP,
+closed-loop residual against the decoded key frame, random measurement,
+sparse recovery, eq. (4) reconstruction), with the encode/decode hot path in
+hand-written HIP behind a C ABI (include/csv.h).  This package only
+marshals arguments: it loads libcsv.so and fails loudly if it is missing.
+"""
+from ._native import (CSV_BF16, CSV_FP32, CSV_FLAG_ISTA, CSV_FLAG_LAMBDA_PIXEL_DOMAIN,
+                      CsvError, lib)
+from .api import Context, GopStream, Params
+
+__all__ = ["Context", "GopStream", "Params", "CsvError", "CSV_BF16", "CSV_FP32",
+           "CSV_FLAG_ISTA", "CSV_FLAG_LAMBDA_PIXEL_DOMAIN", "lib"]

@@ -1,0 +1,104 @@
+"""ctypes declarations of the C ABI in include/csv.h (argument marshalling
+only; every step of the coder runs in the HIP library)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcsv.so")
+
+CSV_OK = 0
+CSV_EINVAL = -1
+CSV_EUNSUPPORTED = -2
+CSV_ENOMEM = -3
+CSV_EAGAIN = -4
+CSV_EHIP = -5
+CSV_ENOTFOUND = -6
+CSV_ECANCELED = -7
+
+CSV_FP32 = 0
+CSV_BF16 = 1
+CSV_FLAG_ISTA = 1
+CSV_FLAG_LAMBDA_PIXEL_DOMAIN = 2
+
+
+class CsvParams(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("gop", C.c_int32),
+                ("block", C.c_int32), ("m", C.c_int32), ("rho", C.c_float),
+                ("phi_seed", C.c_uint64), ("stream_id", C.c_uint32),
+                ("key_qstep", C.c_int32), ("iters", C.c_int32),
+                ("lambda_frac", C.c_float), ("precision", C.c_int32),
+                ("flags", C.c_int32)]
+
+
+class CsvGopStream(C.Structure):
+    _fields_ = [("key_levels", C.c_void_p), ("codes", C.c_void_p),
+                ("exps", C.c_void_p), ("bits", C.c_void_p)]
+
+
+class CsvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"csv error {code}: {msg}")
+        self.code = code
+
+
+_P = C.POINTER
+_SIGS = {
+    "csv_create": (C.c_int, [_P(C.c_void_p), C.c_int, C.c_size_t]),
+    "csv_destroy": (C.c_int, [C.c_void_p]),
+    "csv_last_error": (C.c_char_p, []),
+    "csv_version": (C.c_char_p, []),
+    "csv_ctx_bytes": (C.c_int, [C.c_void_p, _P(C.c_size_t)]),
+    "csv_params_default": (C.c_int, [_P(CsvParams)]),
+    "csv_resolve": (C.c_int, [_P(CsvParams), _P(C.c_int32), _P(C.c_int32)]),
+    "csv_encoded_size": (C.c_int, [_P(CsvParams), _P(C.c_size_t), _P(C.c_size_t),
+                                   _P(C.c_size_t), _P(C.c_uint64)]),
+    "csv_compression_ratio": (C.c_int, [_P(CsvParams), C.c_uint64, C.c_uint64,
+                                        _P(C.c_double), _P(C.c_double), _P(C.c_double)]),
+    "csv_encode_gop": (C.c_int, [C.c_void_p, _P(CsvParams), C.c_void_p,
+                                 _P(CsvGopStream), C.c_void_p]),
+    "csv_decode_gop": (C.c_int, [C.c_void_p, _P(CsvParams), _P(CsvGopStream), C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csv_decode_batch": (C.c_int, [C.c_void_p, C.c_int32, _P(CsvParams), _P(CsvGopStream),
+                                   _P(C.c_void_p), _P(C.c_void_p), _P(C.c_void_p),
+                                   C.c_void_p]),
+    "csv_phi_matrix": (C.c_int, [C.c_void_p, _P(CsvParams), C.c_void_p, C.c_void_p]),
+    "csv_operator_matrix": (C.c_int, [C.c_void_p, _P(CsvParams), C.c_void_p, C.c_void_p]),
+    "csv_step_constant": (C.c_int, [C.c_void_p, _P(CsvParams), _P(C.c_double),
+                                    _P(C.c_int32)]),
+    "csv_key_encode": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csv_key_decode": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                 C.c_void_p, C.c_void_p]),
+    "csv_measure_frame": (C.c_int, [C.c_void_p, _P(CsvParams), C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csv_recover_blocks": (C.c_int, [C.c_void_p, _P(CsvParams), C.c_int32, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]),
+}
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libcsv.so; raises if the HIP library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"HIP library not built: {LIB_PATH} is missing "
+                "(run python -m paper_1311_1419_amd.build)")
+        handle = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def check(rc: int) -> None:
+    if rc != CSV_OK:
+        msg = lib().csv_last_error()
+        raise CsvError(rc, msg.decode() if msg else "")

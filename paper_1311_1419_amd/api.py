@@ -1,0 +1,270 @@
+"""Python face of the HIP coder: torch tensors for device memory and streams,
+ctypes calls into libcsv.so for every step of the coder."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field, replace
+
+import torch
+
+from . import _native as N
+
+
+@dataclass(frozen=True)
+class Params:
+    """One stream's coding parameters (mirrors csv_params)."""
+    width: int
+    height: int
+    gop: int
+    block: int = 16
+    m: int = 0
+    rho: float = 0.25
+    phi_seed: int = 0
+    stream_id: int = 0
+    key_qstep: int = 16
+    iters: int = 300
+    lambda_frac: float = 0.01
+    precision: int = N.CSV_BF16
+    flags: int = 0
+
+    def to_c(self) -> N.CsvParams:
+        return N.CsvParams(self.width, self.height, self.gop, self.block, self.m,
+                           self.rho, self.phi_seed & (2**64 - 1),
+                           self.stream_id & 0xFFFFFFFF, self.key_qstep, self.iters,
+                           self.lambda_frac, self.precision, self.flags)
+
+    @property
+    def n(self) -> int:
+        return self.block * self.block
+
+    def resolve(self) -> tuple[int, int]:
+        """(M, blocks per frame) as the library resolves them."""
+        m = C.c_int32()
+        nb = C.c_int32()
+        N.check(N.lib().csv_resolve(C.byref(self.to_c()), C.byref(m), C.byref(nb)))
+        return m.value, nb.value
+
+    @staticmethod
+    def from_spec(spec, **kw) -> "Params":
+        base = dict(width=spec.width, height=spec.height, gop=spec.gop, block=spec.block,
+                    m=spec.m, phi_seed=spec.phi_seed, stream_id=spec.stream_id,
+                    key_qstep=spec.key_qstep, iters=spec.iters,
+                    lambda_frac=spec.lambda_frac)
+        base.update(kw)
+        return Params(**base)
+
+    def with_(self, **kw) -> "Params":
+        return replace(self, **kw)
+
+
+@dataclass
+class GopStream:
+    """Encoded GOP in device memory (mirrors csv_gop_stream)."""
+    key_levels: torch.Tensor    # int16 H x W
+    codes: torch.Tensor         # int8 (G-1) x N_b x M
+    exps: torch.Tensor          # uint8 (G-1) x N_b
+    bits: torch.Tensor = field(default=None)   # int64 [key bits, CS bits]
+
+    def to_c(self) -> N.CsvGopStream:
+        return N.CsvGopStream(self.key_levels.data_ptr(),
+                              self.codes.data_ptr() if self.codes.numel() else None,
+                              self.exps.data_ptr() if self.exps.numel() else None,
+                              self.bits.data_ptr() if self.bits is not None else None)
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _require_cuda(t: torch.Tensor, dtype, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Context:
+    """A csv_ctx: per-stream operator caches and scratch on one device."""
+
+    def __init__(self, device: int = 0, mem_budget: int = 0):
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        N.check(N.lib().csv_create(C.byref(h), device, mem_budget))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            N.check(N.lib().csv_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def bytes_held(self) -> int:
+        v = C.c_size_t()
+        N.check(N.lib().csv_ctx_bytes(self._h, C.byref(v)))
+        return v.value
+
+    # ------------------------------------------------------------- sizes
+    @staticmethod
+    def encoded_size(p: Params):
+        k, c, e, b = C.c_size_t(), C.c_size_t(), C.c_size_t(), C.c_uint64()
+        N.check(N.lib().csv_encoded_size(C.byref(p.to_c()), C.byref(k), C.byref(c),
+                                         C.byref(e), C.byref(b)))
+        return k.value, c.value, e.value, b.value
+
+    @staticmethod
+    def compression_ratio(p: Params, bits_key: int, bits_cs: int):
+        t, k, c = C.c_double(), C.c_double(), C.c_double()
+        N.check(N.lib().csv_compression_ratio(C.byref(p.to_c()), bits_key, bits_cs,
+                                              C.byref(t), C.byref(k), C.byref(c)))
+        return {"total": t.value, "key": k.value, "cs": c.value}
+
+    def alloc_stream(self, p: Params) -> GopStream:
+        m, nb = p.resolve()
+        g = p.gop
+        dev = self.device
+        return GopStream(
+            torch.empty((p.height, p.width), dtype=torch.int16, device=dev),
+            torch.empty((g - 1, nb, m), dtype=torch.int8, device=dev),
+            torch.empty((g - 1, nb), dtype=torch.uint8, device=dev),
+            torch.zeros(2, dtype=torch.int64, device=dev))
+
+    # ---------------------------------------------------------- hot path
+    def encode_gop(self, frames: torch.Tensor, p: Params, out: GopStream | None = None) -> GopStream:
+        _require_cuda(frames, torch.uint8, "frames")
+        if tuple(frames.shape) != (p.gop, p.height, p.width):
+            raise ValueError("frames must be G x H x W")
+        out = out or self.alloc_stream(p)
+        N.check(N.lib().csv_encode_gop(self._h, C.byref(p.to_c()), frames.data_ptr(),
+                                       C.byref(out.to_c()), _stream(self.device)))
+        return out
+
+    def decode_gop(self, gs: GopStream, p: Params, want_float: bool = False,
+                   want_obj: bool = False):
+        m, nb = p.resolve()
+        dev = self.device
+        frames = torch.empty((p.gop, p.height, p.width), dtype=torch.uint8, device=dev)
+        fl = (torch.empty((p.gop - 1, p.height, p.width), dtype=torch.float32, device=dev)
+              if want_float else None)
+        obj = (torch.empty((p.gop - 1, nb, 2), dtype=torch.float64, device=dev)
+               if want_obj else None)
+        N.check(N.lib().csv_decode_gop(self._h, C.byref(p.to_c()), C.byref(gs.to_c()),
+                                       frames.data_ptr(), _ptr(fl), _ptr(obj),
+                                       _stream(dev)))
+        return frames, fl, obj
+
+    def decode_batch(self, items, want_float: bool = False, want_obj: bool = False):
+        """items: list of (GopStream, Params).  Returns a list of
+        (frames, cs_float or None, obj or None)."""
+        count = len(items)
+        dev = self.device
+        params = (N.CsvParams * max(count, 1))()
+        streams = (N.CsvGopStream * max(count, 1))()
+        fptr = (C.c_void_p * max(count, 1))()
+        flptr = (C.c_void_p * max(count, 1))()
+        optr = (C.c_void_p * max(count, 1))()
+        outs = []
+        for i, (gs, p) in enumerate(items):
+            m, nb = p.resolve()
+            frames = torch.empty((p.gop, p.height, p.width), dtype=torch.uint8, device=dev)
+            fl = (torch.empty((p.gop - 1, p.height, p.width), dtype=torch.float32, device=dev)
+                  if want_float else None)
+            obj = (torch.empty((p.gop - 1, nb, 2), dtype=torch.float64, device=dev)
+                   if want_obj else None)
+            params[i] = p.to_c()
+            streams[i] = gs.to_c()
+            fptr[i] = frames.data_ptr()
+            flptr[i] = _ptr(fl)
+            optr[i] = _ptr(obj)
+            outs.append((frames, fl, obj))
+        N.check(N.lib().csv_decode_batch(self._h, count, params, streams, fptr,
+                                         flptr if want_float else None,
+                                         optr if want_obj else None, _stream(dev)))
+        return outs
+
+    # ------------------------------------------------------ single steps
+    def phi_matrix(self, p: Params) -> torch.Tensor:
+        m, _ = p.resolve()
+        q = torch.empty((m, p.n), dtype=torch.int8, device=self.device)
+        N.check(N.lib().csv_phi_matrix(self._h, C.byref(p.to_c()), q.data_ptr(),
+                                       _stream(self.device)))
+        return q
+
+    def operator_matrix(self, p: Params) -> torch.Tensor:
+        m, _ = p.resolve()
+        a = torch.empty((m, p.n), dtype=torch.float64, device=self.device)
+        N.check(N.lib().csv_operator_matrix(self._h, C.byref(p.to_c()), a.data_ptr(),
+                                            _stream(self.device)))
+        return a
+
+    def step_constant(self, p: Params) -> tuple[float, int]:
+        torch.cuda.current_stream(self.device).synchronize()
+        L = C.c_double()
+        it = C.c_int32()
+        N.check(N.lib().csv_step_constant(self._h, C.byref(p.to_c()), C.byref(L), C.byref(it)))
+        return L.value, it.value
+
+    def key_encode(self, frame: torch.Tensor, qstep: int = 16):
+        _require_cuda(frame, torch.uint8, "frame")
+        h, w = frame.shape
+        lev = torch.empty((h, w), dtype=torch.int16, device=self.device)
+        bits = torch.zeros(1, dtype=torch.int64, device=self.device)
+        N.check(N.lib().csv_key_encode(self._h, w, h, qstep, frame.data_ptr(), lev.data_ptr(),
+                                       bits.data_ptr(), _stream(self.device)))
+        return lev, bits
+
+    def key_decode(self, levels: torch.Tensor, qstep: int = 16) -> torch.Tensor:
+        _require_cuda(levels, torch.int16, "levels")
+        h, w = levels.shape
+        out = torch.empty((h, w), dtype=torch.uint8, device=self.device)
+        N.check(N.lib().csv_key_decode(self._h, w, h, qstep, levels.data_ptr(), out.data_ptr(),
+                                       _stream(self.device)))
+        return out
+
+    def measure_frame(self, p: Params, frame: torch.Tensor, key_decoded: torch.Tensor):
+        _require_cuda(frame, torch.uint8, "frame")
+        _require_cuda(key_decoded, torch.uint8, "key_decoded")
+        m, nb = p.resolve()
+        y = torch.empty((nb, m), dtype=torch.int32, device=self.device)
+        codes = torch.empty((nb, m), dtype=torch.int8, device=self.device)
+        exps = torch.empty((nb,), dtype=torch.uint8, device=self.device)
+        N.check(N.lib().csv_measure_frame(self._h, C.byref(p.to_c()), frame.data_ptr(),
+                                          key_decoded.data_ptr(), y.data_ptr(), codes.data_ptr(),
+                                          exps.data_ptr(), _stream(self.device)))
+        return y, codes, exps
+
+    def recover_blocks(self, p: Params, codes: torch.Tensor, exps: torch.Tensor,
+                       want_obj: bool = False):
+        _require_cuda(codes, torch.int8, "codes")
+        _require_cuda(exps, torch.uint8, "exps")
+        m, _ = p.resolve()
+        nblk = exps.numel()
+        if codes.numel() != nblk * m:
+            raise ValueError("codes must hold n_blocks x M entries")
+        s = torch.empty((nblk, p.n), dtype=torch.float32, device=self.device)
+        lam = torch.empty((nblk,), dtype=torch.float32, device=self.device)
+        obj = torch.empty((nblk, 2), dtype=torch.float64, device=self.device) if want_obj else None
+        N.check(N.lib().csv_recover_blocks(self._h, C.byref(p.to_c()), nblk, codes.data_ptr(),
+                                           exps.data_ptr(), s.data_ptr(), lam.data_ptr(),
+                                           _ptr(obj), _stream(self.device)))
+        return s, lam, obj

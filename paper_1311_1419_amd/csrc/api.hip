@@ -1,0 +1,539 @@
+// Host side of the C ABI: validation, context and per-stream operator
+// caches, scratch management and the encode / decode orchestration.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "internal.h"
+
+namespace csv {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+template <class F>
+static int guarded(F&& f) {
+    try {
+        f();
+        return CSV_OK;
+    } catch (const Error& e) {
+        return fail(e.code, e.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(CSV_ENOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return fail(CSV_EINVAL, e.what());
+    } catch (...) {
+        return fail(CSV_EINVAL, "unknown error");
+    }
+}
+
+// ------------------------------------------------------------ parameters
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+Shape resolve(const csv_params* p) {
+    CSV_REQUIRE(p != nullptr, CSV_EINVAL, "params is NULL");
+    Shape s{};
+    CSV_REQUIRE(p->width > 0 && p->height > 0, CSV_EINVAL, "frame size must be positive");
+    CSV_REQUIRE(p->width % 8 == 0 && p->height % 8 == 0, CSV_EINVAL,
+                "frame width and height must be multiples of 8");
+    CSV_REQUIRE(p->width <= 16384 && p->height <= 16384, CSV_EINVAL, "frame too large");
+    CSV_REQUIRE(p->block == 16 || p->block == 32, CSV_EINVAL, "block must be 16 or 32");
+    CSV_REQUIRE(p->gop >= 1 && p->gop <= 1024, CSV_EINVAL, "gop must be in [1, 1024]");
+    CSV_REQUIRE(is_pow2(p->key_qstep) && p->key_qstep <= 256, CSV_EINVAL,
+                "key_qstep must be a power of two in [1, 256]");
+    CSV_REQUIRE(p->iters >= 1 && p->iters <= 100000, CSV_EINVAL, "iters must be in [1, 100000]");
+    CSV_REQUIRE(p->lambda_frac >= 0.f && std::isfinite(p->lambda_frac), CSV_EINVAL,
+                "lambda_frac must be finite and >= 0");
+    CSV_REQUIRE(p->precision == CSV_FP32 || p->precision == CSV_BF16, CSV_EINVAL,
+                "precision must be CSV_FP32 or CSV_BF16");
+    CSV_REQUIRE((p->flags & ~(CSV_FLAG_ISTA | CSV_FLAG_LAMBDA_PIXEL_DOMAIN)) == 0, CSV_EINVAL,
+                "unknown flag bits");
+    s.W = p->width;
+    s.H = p->height;
+    s.G = p->gop;
+    s.B = p->block;
+    s.n = s.B * s.B;
+    CSV_REQUIRE(s.n <= 2048, CSV_EUNSUPPORTED, "n > 2048 breaks exact FP32 measurement");
+    int M = p->m;
+    if (M == 0) {
+        CSV_REQUIRE(p->rho > 0.f && p->rho <= 1.f, CSV_EINVAL, "rho must be in (0, 1] when m == 0");
+        M = (int)std::floor((double)p->rho * s.n + 0.5);
+    }
+    CSV_REQUIRE(M >= 1 && M <= s.n, CSV_EINVAL, "m must be in [1, block*block]");
+    s.M = M;
+    s.Mp = round_up(M, 32);
+    s.nbx = ceil_div(s.W, s.B);
+    s.nby = ceil_div(s.H, s.B);
+    s.nb = s.nbx * s.nby;
+    s.qstep = p->key_qstep;
+    s.qshift = 20;
+    for (int v = p->key_qstep; v > 1; v >>= 1) ++s.qshift;
+    s.T = p->iters;
+    s.lambda_frac = p->lambda_frac;
+    s.precision = p->precision;
+    s.flags = p->flags;
+    s.seed = p->phi_seed;
+    s.sid = p->stream_id;
+    return s;
+}
+
+// ------------------------------------------------------------ allocation
+void* ctx_alloc(Ctx* c, size_t bytes) {
+    if (!bytes) return nullptr;
+    CSV_REQUIRE(c->budget == 0 || c->used + bytes <= c->budget, CSV_ENOMEM,
+                "context memory budget exceeded (" + std::to_string(c->used + bytes) + " > " +
+                    std::to_string(c->budget) + " bytes)");
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{CSV_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+    }
+    c->used += bytes;
+    return p;
+}
+
+void ctx_free(Ctx* c, void* p, size_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    c->used -= bytes;
+}
+
+void* scratch(Ctx* c, const std::string& name, size_t bytes) {
+    Scratch& s = c->scratch[name];
+    if (s.bytes >= bytes) return s.ptr;
+    if (s.ptr) {
+        CSV_HIP(hipDeviceSynchronize());   // earlier work may still read the old buffer
+        ctx_free(c, s.ptr, s.bytes);
+        s.ptr = nullptr;
+        s.bytes = 0;
+    }
+    const size_t want = ((bytes + 4095) / 4096) * 4096;
+    s.ptr = ctx_alloc(c, want);
+    s.bytes = want;
+    ++c->gen;
+    return s.ptr;
+}
+
+static void free_operator(Ctx* c, Operator* op) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(op->q);
+    c->used -= op->bytes;
+}
+
+Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
+    const auto key = std::make_tuple(s.seed, s.sid, s.n, s.M);
+    auto it = c->ops.find(key);
+    if (it != c->ops.end()) return it->second.get();
+    auto op = std::make_unique<Operator>();
+    op->B = s.B;
+    op->n = s.n;
+    op->M = s.M;
+    op->Mp = s.Mp;
+    op->seed = s.seed;
+    op->sid = s.sid;
+    op->s_phi = 1.0 / (4.0 * std::sqrt((double)s.M));
+    const size_t n = s.n, Mp = s.Mp;
+    // one allocation, carved into 256-byte aligned pieces
+    const size_t sz_q = Mp * n, sz_a64 = Mp * n * 8, sz_a32 = Mp * n * 4;
+    const size_t sz_frag = Mp * n * 2, sz_lip = 64, sz_dct = n * 4, sz_dct64 = n * 8;
+    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t total = al(sz_q) + 2 * al(sz_a64) + 2 * al(sz_a32) + 2 * al(sz_frag) +
+                         al(sz_lip) + al(sz_dct) + al(sz_dct64);
+    char* base = static_cast<char*>(ctx_alloc(c, total));
+    op->bytes = total;
+    size_t off = 0;
+    auto take = [&](size_t v) {
+        char* p = base + off;
+        off += al(v);
+        return p;
+    };
+    op->q = reinterpret_cast<int8_t*>(take(sz_q));
+    op->a64 = reinterpret_cast<double*>(take(sz_a64));
+    op->a64t = reinterpret_cast<double*>(take(sz_a64));
+    op->a32 = reinterpret_cast<float*>(take(sz_a32));
+    op->phi32 = reinterpret_cast<float*>(take(sz_a32));
+    op->frag_fwd = reinterpret_cast<uint16_t*>(take(sz_frag));
+    op->frag_adj = reinterpret_cast<uint16_t*>(take(sz_frag));
+    op->lip = reinterpret_cast<double*>(take(sz_lip));
+    op->dct = reinterpret_cast<float*>(take(sz_dct));
+    op->dct64 = reinterpret_cast<double*>(take(sz_dct64));
+    try {
+        launch_phi_q(op->q, s.M, s.Mp, s.n, s.seed, (uint64_t)s.sid, st);
+        launch_operator_setup(op.get(), st);
+        launch_bf16_frag_layout(op.get(), st);
+        double* gram = static_cast<double*>(scratch(c, "gram", (size_t)s.M * s.M * 8));
+        launch_power_iteration(op.get(), gram, st);
+    } catch (...) {
+        free_operator(c, op.get());
+        throw;
+    }
+    Operator* raw = op.get();
+    c->ops.emplace(key, std::move(op));
+    return raw;
+}
+
+// beta_k = (t_k - 1) / t_{k+1}, t_1 = 1, t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
+// (FISTA momentum, Beck and Teboulle 2009), computed in FP64 and stored as
+// FP32; all zero for the momentum-free proximal gradient.
+const float* beta_table(Ctx* c, int T, bool ista, hipStream_t st) {
+    const int key = T * 2 + (ista ? 1 : 0);
+    auto it = c->beta_tables.find(key);
+    if (it != c->beta_tables.end()) return it->second.first;
+    std::vector<float> h(T);
+    double t = 1.0;
+    for (int k = 0; k < T; ++k) {
+        const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+        h[k] = ista ? 0.f : (float)((t - 1.0) / tn);
+        t = tn;
+    }
+    float* d = static_cast<float*>(ctx_alloc(c, (size_t)T * 4));
+    CSV_HIP(hipMemcpyAsync(d, h.data(), (size_t)T * 4, hipMemcpyHostToDevice, st));
+    CSV_HIP(hipStreamSynchronize(st));
+    c->beta_tables[key] = {d, T};
+    return d;
+}
+
+// --------------------------------------------------------- recovery core
+// Recover nblk blocks of one operator from codes: y^ (dequantised), lambda,
+// FISTA (plain FP32 passes), returning coefficients in `s_out`.
+struct RecoverBufs {
+    float* y;     // nblk x Mp
+    float* lam;   // nblk
+};
+
+static void lambda_pass(Ctx* c, const Shape& s, Operator* op, const float* y, int nblk, float* lam,
+                        hipStream_t st) {
+    float* g0 = static_cast<float*>(scratch(c, "g0", (size_t)nblk * s.n * 4));
+    const float* opm = (s.flags & CSV_FLAG_LAMBDA_PIXEL_DOMAIN) ? op->phi32 : op->a32;
+    launch_gemm_nn(y, opm, g0, nblk, s.n, s.Mp, s.Mp, s.n, s.n, st);
+    launch_row_absmax(g0, nblk, s.n, s.n, s.lambda_frac, lam, st);
+}
+
+static void fista_fp32(Ctx* c, const Shape& s, Operator* op, const float* y, const float* lam,
+                       int nblk, float* S, hipStream_t st) {
+    const size_t nn = (size_t)nblk * s.n;
+    float* V = static_cast<float*>(scratch(c, "V", nn * 4));
+    float* Gd = static_cast<float*>(scratch(c, "Gd", nn * 4));
+    float* R = static_cast<float*>(scratch(c, "Rm", (size_t)nblk * s.Mp * 4));
+    const float* beta = beta_table(c, s.T, (s.flags & CSV_FLAG_ISTA) != 0, st);
+    launch_fill_f32(S, 0.f, nn, st);
+    launch_fill_f32(V, 0.f, nn, st);
+    for (int k = 0; k < s.T; ++k) {
+        // residual A v - y^ (fwd product, epilogue subtracts y^; padded rows 0)
+        launch_gemm_nt(V, op->a32, R, nblk, s.Mp, s.n, s.n, s.n, s.Mp, y, s.Mp, s.M, st);
+        // gradient A^T (A v - y^)
+        launch_gemm_nn(R, op->a32, Gd, nblk, s.n, s.Mp, s.Mp, s.n, s.n, st);
+        launch_prox(S, V, Gd, lam, op->lip, beta, k, nblk, s.n, st);
+    }
+}
+
+void recover(Ctx* c, const Shape& s, Operator* op, const int8_t* codes, const uint8_t* exps,
+             int nblk, float* S, float* lam_out, double* obj_out, hipStream_t st) {
+    if (nblk <= 0) return;
+    float* y = static_cast<float*>(scratch(c, "yhat", (size_t)nblk * s.Mp * 4));
+    float* lam = lam_out ? lam_out : static_cast<float*>(scratch(c, "lam", (size_t)nblk * 4));
+    launch_dequant(codes, exps, nblk, s.M, s.Mp, op->s_phi, y, st);
+    lambda_pass(c, s, op, y, nblk, lam, st);
+    if (s.precision == CSV_FP32) {
+        fista_fp32(c, s, op, y, lam, nblk, S, st);
+    } else {
+        throw Error{CSV_EUNSUPPORTED, "BF16 fused recovery is not available in this build"};
+    }
+    if (obj_out)
+        launch_final64(op->a64t, S, codes, exps, lam, nblk, s.M, s.Mp, s.n, op->s_phi, obj_out,
+                       st);
+}
+
+}  // namespace csv
+
+using namespace csv;
+
+struct csv_ctx {
+    Ctx impl;
+    std::mutex mu;
+};
+
+static Ctx* C(csv_ctx* c) { return &c->impl; }
+
+static void set_device(csv_ctx* ctx) { CSV_HIP(hipSetDevice(ctx->impl.device)); }
+
+extern "C" {
+
+const char* csv_last_error(void) { return g_last_error.c_str(); }
+
+const char* csv_version(void) { return "csv 0.1 gfx950"; }
+
+int csv_create(csv_ctx** out, int device, size_t mem_budget) {
+    return guarded([&] {
+        CSV_REQUIRE(out != nullptr, CSV_EINVAL, "out is NULL");
+        int count = 0;
+        CSV_HIP(hipGetDeviceCount(&count));
+        CSV_REQUIRE(device >= 0 && device < count, CSV_EINVAL, "no such device");
+        CSV_HIP(hipSetDevice(device));
+        auto* c = new csv_ctx();
+        c->impl.device = device;
+        c->impl.budget = mem_budget;
+        *out = c;
+    });
+}
+
+int csv_destroy(csv_ctx* ctx) {
+    if (!ctx) return CSV_OK;
+    return guarded([&] {
+        set_device(ctx);
+        CSV_HIP(hipDeviceSynchronize());
+        for (auto& kv : ctx->impl.ops) free_operator(&ctx->impl, kv.second.get());
+        for (auto& kv : ctx->impl.scratch) ctx_free(&ctx->impl, kv.second.ptr, kv.second.bytes);
+        for (auto& kv : ctx->impl.beta_tables) (void)hipFree(kv.second.first);
+        delete ctx;
+    });
+}
+
+int csv_ctx_bytes(const csv_ctx* ctx, size_t* bytes) {
+    if (!ctx || !bytes) return fail(CSV_EINVAL, "NULL argument");
+    *bytes = ctx->impl.used;
+    return CSV_OK;
+}
+
+int csv_params_default(csv_params* p) {
+    if (!p) return fail(CSV_EINVAL, "params is NULL");
+    std::memset(p, 0, sizeof(*p));
+    p->width = 176;
+    p->height = 144;
+    p->gop = 4;
+    p->block = 16;
+    p->m = 0;
+    p->rho = 0.25f;
+    p->key_qstep = 16;
+    p->iters = 300;
+    p->lambda_frac = 0.01f;
+    p->precision = CSV_BF16;
+    return CSV_OK;
+}
+
+int csv_resolve(const csv_params* p, int32_t* m, int32_t* blocks_per_frame) {
+    return guarded([&] {
+        const Shape s = resolve(p);
+        if (m) *m = s.M;
+        if (blocks_per_frame) *blocks_per_frame = s.nb;
+    });
+}
+
+int csv_encoded_size(const csv_params* p, size_t* key_elems, size_t* code_bytes,
+                     size_t* exp_bytes, uint64_t* bits_cs) {
+    return guarded([&] {
+        const Shape s = resolve(p);
+        if (key_elems) *key_elems = (size_t)s.W * s.H;
+        if (code_bytes) *code_bytes = (size_t)(s.G - 1) * s.nb * s.M;
+        if (exp_bytes) *exp_bytes = (size_t)(s.G - 1) * s.nb;
+        if (bits_cs) *bits_cs = (uint64_t)(s.G - 1) * s.nb * (8ull * s.M + 8ull);
+    });
+}
+
+int csv_compression_ratio(const csv_params* p, uint64_t bits_key, uint64_t bits_cs, double* total,
+                          double* key, double* cs) {
+    return guarded([&] {
+        const Shape s = resolve(p);
+        CSV_REQUIRE(bits_key + bits_cs > 0, CSV_EINVAL, "zero coded bits");
+        const double raw = 8.0 * s.W * s.H;
+        if (total) *total = s.G * raw / (double)(bits_key + bits_cs);
+        if (key) *key = bits_key ? raw / (double)bits_key : INFINITY;
+        if (cs) *cs = bits_cs ? (s.G - 1) * raw / (double)bits_cs : INFINITY;
+    });
+}
+
+int csv_encode_gop(csv_ctx* ctx, const csv_params* p, const uint8_t* frames,
+                   const csv_gop_stream* out, void* stream) {
+    return guarded([&] {
+        CSV_REQUIRE(ctx && frames && out, CSV_EINVAL, "NULL argument");
+        CSV_REQUIRE(out->key_levels, CSV_EINVAL, "out->key_levels is NULL");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        set_device(ctx);
+        const Shape s = resolve(p);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const int ncs = s.G - 1;
+        CSV_REQUIRE(ncs == 0 || (out->codes && out->exps), CSV_EINVAL, "codes/exps are NULL");
+        Ctx* c = C(ctx);
+        Operator* op = ncs ? get_operator(c, s, st) : nullptr;
+        unsigned long long* bits = reinterpret_cast<unsigned long long*>(out->bits);
+        if (bits) {
+            launch_fill_u64(bits, 0ull, 1, st);
+            launch_fill_u64(bits + 1, (unsigned long long)ncs * s.nb * (8ull * s.M + 8ull), 1, st);
+        }
+        launch_key_encode(frames, s.W, s.H, s.qshift, out->key_levels, bits, st);
+        if (!ncs) return;
+        uint8_t* keydec = static_cast<uint8_t*>(scratch(c, "keydec", (size_t)s.W * s.H));
+        launch_key_decode(out->key_levels, s.W, s.H, s.qstep, keydec, st);
+        const size_t fs = (size_t)s.W * s.H;
+        const int total = ncs * s.nb;
+        int32_t* y = static_cast<int32_t*>(scratch(c, "ymeas", (size_t)total * s.Mp * 4));
+        launch_measure(s, op->q, frames + fs, ncs, fs, keydec, y, st);
+        launch_quantise(y, s.M, s.Mp, total, out->codes, out->exps, nullptr, st);
+    });
+}
+
+static void decode_one(Ctx* c, const Shape& s, const csv_gop_stream* in, uint8_t* frames_out,
+                       float* cs_float_out, double* obj_out, hipStream_t st) {
+    CSV_REQUIRE(in && in->key_levels && frames_out, CSV_EINVAL, "NULL argument");
+    launch_key_decode(in->key_levels, s.W, s.H, s.qstep, frames_out, st);
+    const int ncs = s.G - 1;
+    if (!ncs) return;
+    CSV_REQUIRE(in->codes && in->exps, CSV_EINVAL, "codes/exps are NULL");
+    Operator* op = get_operator(c, s, st);
+    const int nblk = ncs * s.nb;
+    float* S = static_cast<float*>(scratch(c, "S", (size_t)nblk * s.n * 4));
+    recover(c, s, op, in->codes, in->exps, nblk, S, nullptr, obj_out, st);
+    const size_t fs = (size_t)s.W * s.H;
+    launch_synth(S, op->dct, frames_out, s.W, s.H, s.B, s.nbx, s.nb, ncs, frames_out + fs,
+                 cs_float_out, st);
+}
+
+int csv_decode_gop(csv_ctx* ctx, const csv_params* p, const csv_gop_stream* in,
+                   uint8_t* frames_out, float* cs_float_out, double* obj_out, void* stream) {
+    return guarded([&] {
+        CSV_REQUIRE(ctx, CSV_EINVAL, "ctx is NULL");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        set_device(ctx);
+        const Shape s = resolve(p);
+        decode_one(C(ctx), s, in, frames_out, cs_float_out, obj_out,
+                   static_cast<hipStream_t>(stream));
+    });
+}
+
+int csv_decode_batch(csv_ctx* ctx, int32_t count, const csv_params* params,
+                     const csv_gop_stream* in, uint8_t* const* frames_out,
+                     float* const* cs_float_out, double* const* obj_out, void* stream) {
+    return guarded([&] {
+        CSV_REQUIRE(ctx && params && in && frames_out, CSV_EINVAL, "NULL argument");
+        CSV_REQUIRE(count >= 0, CSV_EINVAL, "negative count");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        set_device(ctx);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        std::vector<Shape> shapes;
+        for (int i = 0; i < count; ++i) shapes.push_back(resolve(&params[i]));
+        for (int i = 1; i < count; ++i)
+            CSV_REQUIRE(shapes[i].precision == shapes[0].precision, CSV_EINVAL,
+                        "one precision per batch");
+        for (int i = 0; i < count; ++i)
+            decode_one(C(ctx), shapes[i], &in[i], frames_out[i],
+                       cs_float_out ? cs_float_out[i] : nullptr, obj_out ? obj_out[i] : nullptr,
+                       st);
+    });
+}
+
+int csv_phi_matrix(csv_ctx* ctx, const csv_params* p, int8_t* q_out, void* stream) {
+    return guarded([&] {
+        CSV_REQUIRE(ctx && q_out, CSV_EINVAL, "NULL argument");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        set_device(ctx);
+        const Shape s = resolve(p);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        Operator* op = get_operator(C(ctx), s, st);
+        CSV_HIP(hipMemcpyAsync(q_out, op->q, (size_t)s.M * s.n, hipMemcpyDeviceToDevice, st));
+    });
+}
+
+int csv_operator_matrix(csv_ctx* ctx, const csv_params* p, double* a_out, void* stream) {
+    return guarded([&] {
+        CSV_REQUIRE(ctx && a_out, CSV_EINVAL, "NULL argument");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        set_device(ctx);
+        const Shape s = resolve(p);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        Operator* op = get_operator(C(ctx), s, st);
+        CSV_HIP(hipMemcpyAsync(a_out, op->a64, (size_t)s.M * s.n * 8, hipMemcpyDeviceToDevice, st));
+    });
+}
+
+int csv_step_constant(csv_ctx* ctx, const csv_params* p, double* L_out, int32_t* iters_out) {
+    return guarded([&] {
+        CSV_REQUIRE(ctx && L_out, CSV_EINVAL, "NULL argument");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        set_device(ctx);
+        const Shape s = resolve(p);
+        Operator* op = get_operator(C(ctx), s, nullptr);
+        double h[3];
+        CSV_HIP(hipMemcpy(h, op->lip, sizeof(h), hipMemcpyDeviceToHost));
+        *L_out = h[0];
+        if (iters_out) *iters_out = (int32_t)h[2];
+    });
+}
+
+int csv_key_encode(csv_ctx* ctx, int32_t width, int32_t height, int32_t qstep,
+                   const uint8_t* frame, int16_t* levels, uint64_t* bits, void* stream) {
+    return guarded([&] {
+        CSV_REQUIRE(ctx && frame && levels, CSV_EINVAL, "NULL argument");
+        csv_params p;
+        csv_params_default(&p);
+        p.width = width;
+        p.height = height;
+        p.key_qstep = qstep;
+        p.gop = 1;
+        const Shape s = resolve(&p);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        set_device(ctx);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        unsigned long long* b = reinterpret_cast<unsigned long long*>(bits);
+        if (b) launch_fill_u64(b, 0ull, 1, st);
+        launch_key_encode(frame, s.W, s.H, s.qshift, levels, b, st);
+    });
+}
+
+int csv_key_decode(csv_ctx* ctx, int32_t width, int32_t height, int32_t qstep,
+                   const int16_t* levels, uint8_t* out, void* stream) {
+    return guarded([&] {
+        CSV_REQUIRE(ctx && levels && out, CSV_EINVAL, "NULL argument");
+        csv_params p;
+        csv_params_default(&p);
+        p.width = width;
+        p.height = height;
+        p.key_qstep = qstep;
+        p.gop = 1;
+        const Shape s = resolve(&p);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        set_device(ctx);
+        launch_key_decode(levels, s.W, s.H, s.qstep, out, static_cast<hipStream_t>(stream));
+    });
+}
+
+int csv_measure_frame(csv_ctx* ctx, const csv_params* p, const uint8_t* frame,
+                      const uint8_t* key_decoded, int32_t* y_out, int8_t* codes, uint8_t* exps,
+                      void* stream) {
+    return guarded([&] {
+        CSV_REQUIRE(ctx && frame && key_decoded && codes && exps, CSV_EINVAL, "NULL argument");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        set_device(ctx);
+        const Shape s = resolve(p);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        Ctx* c = C(ctx);
+        Operator* op = get_operator(c, s, st);
+        int32_t* y = static_cast<int32_t*>(scratch(c, "ymeas", (size_t)s.nb * s.Mp * 4));
+        launch_measure(s, op->q, frame, 1, (size_t)s.W * s.H, key_decoded, y, st);
+        launch_quantise(y, s.M, s.Mp, s.nb, codes, exps, y_out, st);
+    });
+}
+
+int csv_recover_blocks(csv_ctx* ctx, const csv_params* p, int32_t n_blocks, const int8_t* codes,
+                       const uint8_t* exps, float* s_out, float* lambda_out, double* obj_out,
+                       void* stream) {
+    return guarded([&] {
+        CSV_REQUIRE(ctx && codes && exps && s_out, CSV_EINVAL, "NULL argument");
+        CSV_REQUIRE(n_blocks >= 0, CSV_EINVAL, "negative block count");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        set_device(ctx);
+        const Shape s = resolve(p);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        Ctx* c = C(ctx);
+        Operator* op = get_operator(c, s, st);
+        recover(c, s, op, codes, exps, n_blocks, s_out, lambda_out, obj_out, st);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// Internal declarations of the HIP library behind include/csv.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "csv.h"
+
+namespace csv {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    int code;
+    std::string msg;
+};
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define CSV_HIP(expr)                                                        \
+    do {                                                                     \
+        hipError_t e_ = (expr);                                              \
+        if (e_ != hipSuccess)                                                \
+            throw ::csv::Error{CSV_EHIP, std::string(#expr) + ": " +         \
+                                             hipGetErrorString(e_)};         \
+    } while (0)
+
+#define CSV_REQUIRE(cond, code, msg)                                         \
+    do {                                                                     \
+        if (!(cond)) throw ::csv::Error{(code), (msg)};                      \
+    } while (0)
+
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+inline int round_up(int a, int b) { return ceil_div(a, b) * b; }
+
+// Resolved, validated parameter set.
+struct Shape {
+    int W, H, G, B, n, M, Mp, nbx, nby, nb;   // nb: blocks per frame
+    int qstep, qshift, T;
+    float lambda_frac;
+    int precision, flags;
+    uint64_t seed;
+    uint32_t sid;
+};
+Shape resolve(const csv_params* p);
+
+// Per-stream operator state, resident in HBM while the context lives.
+struct Operator {
+    int B = 0, n = 0, M = 0, Mp = 0;
+    uint64_t seed = 0;
+    uint32_t sid = 0;
+    double s_phi = 0;
+    int8_t* q = nullptr;          // Mp x n, rows >= M zero
+    double* a64 = nullptr;        // Mp x n, A = s_phi Q Psi
+    double* a64t = nullptr;       // n x Mp, A transposed (final FP64 check)
+    float* a32 = nullptr;         // Mp x n
+    float* phi32 = nullptr;       // Mp x n, s_phi Q
+    uint16_t* frag_fwd = nullptr; // bf16 A in forward-product fragment order
+    uint16_t* frag_adj = nullptr; // bf16 A in adjoint-product fragment order
+    double* lip = nullptr;        // device: [0] L_used, [1] Rayleigh quotient, [2] iterations
+    float* dct = nullptr;         // B x B orthonormal DCT-II, C[k][i]
+    double* dct64 = nullptr;      // same in FP64
+    size_t bytes = 0;
+};
+
+// Scratch buffers owned by a context, grown on demand.
+struct Scratch {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Ctx {
+    int device = 0;
+    size_t budget = 0;
+    size_t used = 0;
+    std::map<std::tuple<uint64_t, uint32_t, int, int>, std::unique_ptr<Operator>> ops;
+    std::map<std::string, Scratch> scratch;
+    std::map<int, std::pair<float*, int>> beta_tables;   // key: T*2 + ista
+    int gen = 0;   // bumps whenever a scratch buffer moves
+};
+
+// allocation inside the context budget
+void* ctx_alloc(Ctx* c, size_t bytes);
+void ctx_free(Ctx* c, void* p, size_t bytes);
+void* scratch(Ctx* c, const std::string& name, size_t bytes);
+Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st);
+const float* beta_table(Ctx* c, int T, bool ista, hipStream_t st);
+
+// ------------------------------------------------------------- kernels
+// encode side (k_encode.hip)
+void launch_phi_q(int8_t* q, int M, int Mp, int n, uint64_t k0, uint64_t k1, hipStream_t st);
+void launch_key_encode(const uint8_t* frame, int W, int H, int qshift, int16_t* levels,
+                       unsigned long long* bits, hipStream_t st);
+void launch_key_decode(const int16_t* levels, int W, int H, int qstep, uint8_t* out, hipStream_t st);
+void launch_measure(const Shape& s, const int8_t* q, const uint8_t* frames, int n_frames,
+                    size_t frame_stride, const uint8_t* key, int32_t* y_scratch, hipStream_t st);
+void launch_quantise(const int32_t* y, int M, int Mp, int total, int8_t* codes, uint8_t* exps,
+                     int32_t* y_out, hipStream_t st);
+void launch_fill_u64(unsigned long long* p, unsigned long long v, int count, hipStream_t st);
+
+// decode side (k_decode.hip)
+void launch_operator_setup(Operator* op, hipStream_t st);
+void launch_power_iteration(Operator* op, double* gram, hipStream_t st);
+void launch_dequant(const int8_t* codes, const uint8_t* exps, int nblk, int M, int Mp,
+                    double s_phi, float* y, hipStream_t st);
+void launch_gemm_nt(const float* X, const float* WT, float* C, int R, int N, int K,
+                    int ldx, int ldw, int ldc, const float* sub, int ldsub, int nvalid,
+                    hipStream_t st);
+void launch_gemm_nn(const float* X, const float* W, float* C, int R, int N, int K,
+                    int ldx, int ldw, int ldc, hipStream_t st);
+void launch_row_absmax(const float* X, int R, int N, int ld, float scale, float* out, hipStream_t st);
+void launch_fill_f32(float* p, float v, size_t count, hipStream_t st);
+void launch_prox(float* s, float* v, const float* g, const float* lam, const double* lip,
+                 const float* beta, int k, int R, int n, hipStream_t st);
+void launch_synth(const float* s, const float* dct, const uint8_t* key, int W, int H, int B,
+                  int nbx, int nb, int n_frames, uint8_t* out_u8, float* out_f32, hipStream_t st);
+void launch_final64(const double* a64t, const float* s, const int8_t* codes, const uint8_t* exps,
+                    const float* lam, int nblk, int M, int Mp, int n, double s_phi, double* obj,
+                    hipStream_t st);
+
+// fused BF16 recovery (k_fista_bf16.hip)
+struct FusedTile {
+    const uint16_t* frag_fwd;
+    const uint16_t* frag_adj;
+    const double* lip;
+    const float* y;      // nblk x Mp
+    const float* lam;    // nblk
+    float* s;            // nblk x n
+    int nblk;            // blocks in this tile (<= tile width)
+    int n, Mp;
+};
+void launch_bf16_frag_layout(Operator* op, hipStream_t st);
+int fused_tile_blocks(int n, int Mp);
+void launch_fista_bf16(const FusedTile* tiles_dev, int n_tiles, int n, int Mp, int T,
+                       const float* beta, int* counter, hipStream_t st);
+
+}  // namespace csv

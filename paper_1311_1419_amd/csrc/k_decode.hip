@@ -1,0 +1,510 @@
+// Decoder-side kernels: operator setup (A = Phi Psi, FP64), step constant by
+// FP64 power iteration, dequantisation, the plain FP32 recovery passes
+// (forward product with residual epilogue, adjoint product, threshold and
+// momentum pass), synthesis onto the decoded key frame and the FP64 final
+// objective.
+#include "internal.h"
+#include "mfma.h"
+
+namespace csv {
+
+// ------------------------------------------------------------ operator
+// Orthonormal DCT-II C[k][i] = a_k cos(pi (2i+1) k / (2B)) in FP64 and FP32.
+__global__ void dct_table_kernel(int B, double* __restrict__ c64, float* __restrict__ c32) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= B * B) return;
+    const int k = idx / B, i = idx % B;
+    const double a = k ? sqrt(2.0 / B) : sqrt(1.0 / B);
+    const double v = a * cos(M_PI * (2 * i + 1) * k / (2.0 * B));
+    c64[idx] = v;
+    c32[idx] = (float)v;
+}
+
+// Row m of A = Phi Psi is the orthonormal 2-D DCT of row m of Phi viewed as a
+// B x B block: A_m = C Phi_m C^T (x = Psi s  <=>  X = C^T S C).  One
+// workgroup per row, FP64 throughout; padded rows (m >= M) are zero.
+__global__ __launch_bounds__(256) void operator_kernel(const int8_t* __restrict__ q, int M, int B,
+                                                      double s_phi, const double* __restrict__ c64,
+                                                      double* __restrict__ a64,
+                                                      double* __restrict__ a64t,
+                                                      float* __restrict__ a32,
+                                                      float* __restrict__ phi32, int Mp) {
+    extern __shared__ double sh[];
+    const int n = B * B;
+    double* X = sh;          // B x B
+    double* U = sh + n;      // B x B
+    double* C = sh + 2 * n;  // B x B
+    const int m = blockIdx.x;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        X[i] = m < M ? (double)q[(size_t)m * n + i] : 0.0;
+        C[i] = c64[i];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {   // U[k][c] = sum_r C[k][r] X[r][c]
+        const int k = i / B, c = i % B;
+        double acc = 0.0;
+        for (int r = 0; r < B; ++r) acc += C[k * B + r] * X[r * B + c];
+        U[i] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {   // A[k][l] = s_phi sum_c U[k][c] C[l][c]
+        const int k = i / B, l = i % B;
+        double acc = 0.0;
+        for (int c = 0; c < B; ++c) acc += U[k * B + c] * C[l * B + c];
+        const double a = s_phi * acc;
+        a64[(size_t)m * n + i] = a;
+        a64t[(size_t)i * Mp + m] = a;
+        a32[(size_t)m * n + i] = (float)a;
+        phi32[(size_t)m * n + i] = (float)(s_phi * X[i]);
+    }
+}
+
+// Integer Gram matrix G = Q Q^T (M x M), exact in 32-bit integers
+// (|G_ij| <= 32*32*n), stored as FP64.
+__global__ __launch_bounds__(256) void gram_kernel(const int8_t* __restrict__ q, int M, int n,
+                                                  double* __restrict__ g) {
+    __shared__ int Qa[16][65];
+    __shared__ int Qb[16][65];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int i = blockIdx.y * 16 + ty, j = blockIdx.x * 16 + tx;
+    int acc = 0;
+    for (int k0 = 0; k0 < n; k0 += 64) {
+        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+            const int r = e / 64, c = e % 64;
+            const int ia = blockIdx.y * 16 + r, jb = blockIdx.x * 16 + r;
+            Qa[r][c] = ia < M ? (int)q[(size_t)ia * n + k0 + c] : 0;
+            Qb[r][c] = jb < M ? (int)q[(size_t)jb * n + k0 + c] : 0;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int c = 0; c < 64; ++c) acc += Qa[ty][c] * Qb[tx][c];
+        __syncthreads();
+    }
+    if (i < M && j < M) g[(size_t)i * M + j] = (double)acc;
+}
+
+__device__ inline double block_sum_1024(double v, double* red) {
+    // deterministic tree: wave shuffles, then the 16 wave partials in order
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    __syncthreads();
+    if (ln == 0) red[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    return t;
+}
+
+// Power iteration on G (FP64): v0 = 1/sqrt(M); w = G v; Rayleigh quotient
+// rq = v.w; stop once |rq - rq_prev| <= tol rq (from the second step), else
+// v = w / ||w||.  One workgroup of 1024 threads, thread i owns row i.
+__global__ __launch_bounds__(1024) void power_kernel(const double* __restrict__ g, int M,
+                                                    double s_phi, double tol, int max_iter,
+                                                    double* __restrict__ lip) {
+    __shared__ double v[1024];
+    __shared__ double red[16];
+    const int i = threadIdx.x;
+    if (i < M) v[i] = 1.0 / sqrt((double)M);
+    __syncthreads();
+    double rq = 0.0, rq_prev = 0.0;
+    int it = 0;
+    for (it = 1; it <= max_iter; ++it) {
+        double w = 0.0;
+        if (i < M)
+            for (int j = 0; j < M; ++j) w += g[(size_t)j * M + i] * v[j];   // G symmetric
+        rq = block_sum_1024(i < M ? v[i] * w : 0.0, red);
+        if (it > 1 && fabs(rq - rq_prev) <= tol * rq) break;
+        rq_prev = rq;
+        const double nw = sqrt(block_sum_1024(i < M ? w * w : 0.0, red));
+        if (nw == 0.0) break;
+        __syncthreads();
+        if (i < M) v[i] = w / nw;
+        __syncthreads();
+    }
+    if (i == 0) {
+        lip[0] = 1.001 * s_phi * s_phi * rq;
+        lip[1] = rq;
+        lip[2] = (double)(it > max_iter ? max_iter : it);
+    }
+}
+
+void launch_operator_setup(Operator* op, hipStream_t st) {
+    const int B = op->B, n = op->n;
+    double* c64 = op->dct64;
+    dct_table_kernel<<<dim3(ceil_div(n, 256)), dim3(256), 0, st>>>(B, c64, op->dct);
+    CSV_HIP(hipGetLastError());
+    operator_kernel<<<dim3(op->Mp), dim3(256), 3 * n * sizeof(double), st>>>(
+        op->q, op->M, B, op->s_phi, c64, op->a64, op->a64t, op->a32,
+        op->phi32, op->Mp);
+    CSV_HIP(hipGetLastError());
+}
+
+void launch_power_iteration(Operator* op, double* gram, hipStream_t st) {
+    const int M = op->M;
+    gram_kernel<<<dim3(ceil_div(M, 16), ceil_div(M, 16)), dim3(256), 0, st>>>(op->q, M, op->n,
+                                                                             gram);
+    CSV_HIP(hipGetLastError());
+    power_kernel<<<dim3(1), dim3(1024), 0, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip);
+    CSV_HIP(hipGetLastError());
+}
+
+// -------------------------------------------------------- dequantisation
+// y^[b][m] = s_phi * c * 2^e for m < M (exact in FP64, rounded once to
+// FP32); zero in the padded rows M <= m < Mp.
+__global__ void dequant_kernel(const int8_t* __restrict__ codes, const uint8_t* __restrict__ exps,
+                               int nblk, int M, int Mp, double s_phi, float* __restrict__ y) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)nblk * Mp) return;
+    const int b = (int)(idx / Mp), m = (int)(idx % Mp);
+    float v = 0.f;
+    if (m < M) v = (float)(s_phi * ldexp((double)codes[(size_t)b * M + m], (int)exps[b]));
+    y[idx] = v;
+}
+
+void launch_dequant(const int8_t* codes, const uint8_t* exps, int nblk, int M, int Mp,
+                    double s_phi, float* y, hipStream_t st) {
+    const size_t total = (size_t)nblk * Mp;
+    if (!total) return;
+    dequant_kernel<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st>>>(codes, exps, nblk,
+                                                                               M, Mp, s_phi, y);
+    CSV_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------ plain FP32 GEMMs
+// 64 x 64 output tile per workgroup, K in chunks of 16, 4 x 4 outputs per
+// thread.  Row bounds guarded (R arbitrary); N and K multiples of 16.
+constexpr int GT = 64, GK = 16;
+
+// C[r][c] = sum_k X[r][k] WT[c][k]  (- sub[r][c] when sub, for c < nvalid;
+// zero for c >= nvalid).
+__global__ __launch_bounds__(256) void gemm_nt_kernel(const float* __restrict__ X,
+                                                     const float* __restrict__ WT,
+                                                     float* __restrict__ C, int R, int N, int K,
+                                                     int ldx, int ldw, int ldc,
+                                                     const float* __restrict__ sub, int ldsub,
+                                                     int nvalid) {
+    __shared__ float As[GK][GT + 4];
+    __shared__ float Bs[GK][GT + 4];
+    const int tid = threadIdx.x;
+    const int r0 = blockIdx.y * GT, c0 = blockIdx.x * GT;
+    const int tr = (tid >> 4) * 4, tc = (tid & 15) * 4;
+    float acc[4][4] = {};
+    const int lr = tid >> 2, lk = (tid & 3) * 4;
+    for (int k0 = 0; k0 < K; k0 += GK) {
+        float4 xa = make_float4(0.f, 0.f, 0.f, 0.f), wb = xa;
+        if (r0 + lr < R) xa = *reinterpret_cast<const float4*>(X + (size_t)(r0 + lr) * ldx + k0 + lk);
+        if (c0 + lr < N) wb = *reinterpret_cast<const float4*>(WT + (size_t)(c0 + lr) * ldw + k0 + lk);
+        As[lk + 0][lr] = xa.x; As[lk + 1][lr] = xa.y; As[lk + 2][lr] = xa.z; As[lk + 3][lr] = xa.w;
+        Bs[lk + 0][lr] = wb.x; Bs[lk + 1][lr] = wb.y; Bs[lk + 2][lr] = wb.z; Bs[lk + 3][lr] = wb.w;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < GK; ++k) {
+            const float4 a = *reinterpret_cast<const float4*>(&As[k][tr]);
+            const float4 b = *reinterpret_cast<const float4*>(&Bs[k][tc]);
+            const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(av[i], bv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = r0 + tr + i;
+        if (r >= R) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = c0 + tc + j;
+            if (c >= N) continue;
+            float v = acc[i][j];
+            if (c >= nvalid) v = 0.f;
+            else if (sub) v -= sub[(size_t)r * ldsub + c];
+            C[(size_t)r * ldc + c] = v;
+        }
+    }
+}
+
+// C[r][c] = sum_k X[r][k] W[k][c].
+__global__ __launch_bounds__(256) void gemm_nn_kernel(const float* __restrict__ X,
+                                                     const float* __restrict__ W,
+                                                     float* __restrict__ C, int R, int N, int K,
+                                                     int ldx, int ldw, int ldc) {
+    __shared__ float As[GK][GT + 4];
+    __shared__ float Bs[GK][GT + 4];
+    const int tid = threadIdx.x;
+    const int r0 = blockIdx.y * GT, c0 = blockIdx.x * GT;
+    const int tr = (tid >> 4) * 4, tc = (tid & 15) * 4;
+    float acc[4][4] = {};
+    const int lr = tid >> 2, lk = (tid & 3) * 4;       // X tile: 64 rows x 16 k
+    const int wk = tid >> 4, wc = (tid & 15) * 4;      // W tile: 16 k x 64 cols
+    for (int k0 = 0; k0 < K; k0 += GK) {
+        float4 xa = make_float4(0.f, 0.f, 0.f, 0.f), wb = xa;
+        if (r0 + lr < R) xa = *reinterpret_cast<const float4*>(X + (size_t)(r0 + lr) * ldx + k0 + lk);
+        if (c0 + wc < N) wb = *reinterpret_cast<const float4*>(W + (size_t)(k0 + wk) * ldw + c0 + wc);
+        As[lk + 0][lr] = xa.x; As[lk + 1][lr] = xa.y; As[lk + 2][lr] = xa.z; As[lk + 3][lr] = xa.w;
+        *reinterpret_cast<float4*>(&Bs[wk][wc]) = wb;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < GK; ++k) {
+            const float4 a = *reinterpret_cast<const float4*>(&As[k][tr]);
+            const float4 b = *reinterpret_cast<const float4*>(&Bs[k][tc]);
+            const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(av[i], bv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = r0 + tr + i;
+        if (r >= R) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = c0 + tc + j;
+            if (c < N) C[(size_t)r * ldc + c] = acc[i][j];
+        }
+    }
+}
+
+void launch_gemm_nt(const float* X, const float* WT, float* C, int R, int N, int K, int ldx,
+                    int ldw, int ldc, const float* sub, int ldsub, int nvalid, hipStream_t st) {
+    if (R <= 0) return;
+    gemm_nt_kernel<<<dim3(ceil_div(N, GT), ceil_div(R, GT)), dim3(256), 0, st>>>(
+        X, WT, C, R, N, K, ldx, ldw, ldc, sub, ldsub, nvalid);
+    CSV_HIP(hipGetLastError());
+}
+
+void launch_gemm_nn(const float* X, const float* W, float* C, int R, int N, int K, int ldx,
+                    int ldw, int ldc, hipStream_t st) {
+    if (R <= 0) return;
+    gemm_nn_kernel<<<dim3(ceil_div(N, GT), ceil_div(R, GT)), dim3(256), 0, st>>>(X, W, C, R, N, K,
+                                                                                ldx, ldw, ldc);
+    CSV_HIP(hipGetLastError());
+}
+
+// out[r] = scale * max_c |X[r][c]|, one wave per row.
+__global__ __launch_bounds__(256) void row_absmax_kernel(const float* __restrict__ X, int R, int N,
+                                                        int ld, float scale,
+                                                        float* __restrict__ out) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6), ln = threadIdx.x & 63;
+    if (r >= R) return;
+    float mx = 0.f;
+    for (int c = ln; c < N; c += 64) mx = fmaxf(mx, fabsf(X[(size_t)r * ld + c]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    if (ln == 0) out[r] = scale * mx;
+}
+
+void launch_row_absmax(const float* X, int R, int N, int ld, float scale, float* out,
+                       hipStream_t st) {
+    if (R <= 0) return;
+    row_absmax_kernel<<<dim3(ceil_div(R, 4)), dim3(256), 0, st>>>(X, R, N, ld, scale, out);
+    CSV_HIP(hipGetLastError());
+}
+
+__global__ void fill_f32_kernel(float* __restrict__ p, float v, size_t count) {
+    const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i + 3 < count) {
+        *reinterpret_cast<float4*>(p + i) = make_float4(v, v, v, v);
+    } else {
+        for (size_t j = i; j < count; ++j) p[j] = v;
+    }
+}
+
+void launch_fill_f32(float* p, float v, size_t count, hipStream_t st) {
+    if (!count) return;
+    const size_t threads = (count + 3) / 4;
+    fill_f32_kernel<<<dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st>>>(p, v, count);
+    CSV_HIP(hipGetLastError());
+}
+
+// Threshold and momentum pass of iteration k (0-based):
+//   u = v - g / L;  s_new = soft(u, lam_b / L);  v = s_new + beta_k (s_new - s)
+// with soft(u, t) = max(u - t, 0) + min(u + t, 0) (exactly 0 for |u| <= t).
+__global__ __launch_bounds__(256) void prox_kernel(float* __restrict__ s, float* __restrict__ v,
+                                                  const float* __restrict__ g,
+                                                  const float* __restrict__ lam,
+                                                  const double* __restrict__ lip,
+                                                  const float* __restrict__ beta, int k, int R,
+                                                  int n) {
+    const size_t i4 = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i4 >= (size_t)R * n) return;   // n % 4 == 0: a float4 never straddles rows
+    const int r = (int)(i4 / n);
+    const float inv_l = (float)(1.0 / lip[0]);
+    const float tau = lam[r] * inv_l;
+    const float bk = beta[k];
+    const float4 vv = *reinterpret_cast<const float4*>(v + i4);
+    const float4 gg = *reinterpret_cast<const float4*>(g + i4);
+    const float4 ss = *reinterpret_cast<const float4*>(s + i4);
+    const float vin[4] = {vv.x, vv.y, vv.z, vv.w}, gin[4] = {gg.x, gg.y, gg.z, gg.w};
+    const float sin_[4] = {ss.x, ss.y, ss.z, ss.w};
+    float so[4], vo[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float u = fmaf(-gin[j], inv_l, vin[j]);
+        const float sn = fmaxf(u - tau, 0.f) + fminf(u + tau, 0.f);
+        so[j] = sn;
+        vo[j] = fmaf(bk, sn - sin_[j], sn);
+    }
+    *reinterpret_cast<float4*>(s + i4) = make_float4(so[0], so[1], so[2], so[3]);
+    *reinterpret_cast<float4*>(v + i4) = make_float4(vo[0], vo[1], vo[2], vo[3]);
+}
+
+void launch_prox(float* s, float* v, const float* g, const float* lam, const double* lip,
+                 const float* beta, int k, int R, int n, hipStream_t st) {
+    const size_t threads = (size_t)R * n / 4;
+    if (!threads) return;
+    prox_kernel<<<dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st>>>(s, v, g, lam, lip,
+                                                                              beta, k, R, n);
+    CSV_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------- synthesis
+// Residual block X = C^T S C (eq. (4) adds it to the decoded key frame);
+// float output = key + X, uint8 output = clip(round-half-even(key + X)).
+// One workgroup per block, one thread per pixel.
+template <int B>
+__global__ __launch_bounds__(B * B) void synth_kernel(const float* __restrict__ s,
+                                                     const float* __restrict__ dct,
+                                                     const uint8_t* __restrict__ key, int W, int H,
+                                                     int nbx, int nb, uint8_t* __restrict__ out_u8,
+                                                     float* __restrict__ out_f32) {
+    constexpr int n = B * B;
+    __shared__ float S[n];
+    __shared__ float U[n];
+    __shared__ float C[n];
+    const int gb = blockIdx.x, t = gb / nb, b = gb % nb;
+    const int tid = threadIdx.x;
+    S[tid] = s[(size_t)gb * n + tid];
+    C[tid] = dct[tid];
+    __syncthreads();
+    const int r = tid / B, c = tid % B;
+    float u = 0.f;   // U[r][l = c] = sum_k C[k][r] S[k][l]
+#pragma unroll 8
+    for (int k = 0; k < B; ++k) u = fmaf(C[k * B + r], S[k * B + c], u);
+    U[tid] = u;
+    __syncthreads();
+    float x = 0.f;   // X[r][c] = sum_l U[r][l] C[l][c]
+#pragma unroll 8
+    for (int l = 0; l < B; ++l) x = fmaf(U[r * B + l], C[l * B + c], x);
+    const int py = (b / nbx) * B + r, px = (b % nbx) * B + c;
+    if (py < H && px < W) {
+        const size_t pix = (size_t)py * W + px;
+        const float f = (float)key[pix] + x;
+        const size_t o = (size_t)t * W * H + pix;
+        if (out_f32) out_f32[o] = f;
+        out_u8[o] = (uint8_t)fminf(fmaxf(rintf(f), 0.f), 255.f);
+    }
+}
+
+void launch_synth(const float* s, const float* dct, const uint8_t* key, int W, int H, int B,
+                  int nbx, int nb, int n_frames, uint8_t* out_u8, float* out_f32, hipStream_t st) {
+    const int total = nb * n_frames;
+    if (!total) return;
+    if (B == 16)
+        synth_kernel<16><<<dim3(total), dim3(256), 0, st>>>(s, dct, key, W, H, nbx, nb, out_u8,
+                                                            out_f32);
+    else
+        synth_kernel<32><<<dim3(total), dim3(1024), 0, st>>>(s, dct, key, W, H, nbx, nb, out_u8,
+                                                             out_f32);
+    CSV_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------- FP64 final check
+// Per block: r = A s - y^ with y^ = s_phi c 2^e recomputed exactly in FP64;
+// obj = 1/2 ||r||^2 + lam ||s||_1 and ||r|| / ||y^||.  A workgroup takes 16
+// blocks (coefficients staged in LDS); lane m of a wave owns row m and reads
+// the transposed operator A^T (n x Mp) coalesced.
+constexpr int F64_BLK = 16;
+
+__global__ __launch_bounds__(256) void final64_kernel(const double* __restrict__ a64t,
+                                                     const float* __restrict__ s,
+                                                     const int8_t* __restrict__ codes,
+                                                     const uint8_t* __restrict__ exps,
+                                                     const float* __restrict__ lam, int nblk,
+                                                     int M, int Mp, int n, double s_phi,
+                                                     double* __restrict__ obj) {
+    extern __shared__ float Sx[];   // [F64_BLK][n]
+    __shared__ double red_r[4][F64_BLK], red_y[4][F64_BLK], red_l1[4][F64_BLK];
+    const int b0 = blockIdx.x * F64_BLK;
+    const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+    const int nloc = min(F64_BLK, nblk - b0);
+    for (int i = tid; i < F64_BLK * n; i += 256) {
+        const int j = i / n;
+        Sx[i] = j < nloc ? s[(size_t)(b0 + j) * n + (i - j * n)] : 0.f;
+    }
+    __syncthreads();
+    double rr[F64_BLK] = {}, yy[F64_BLK] = {}, l1[F64_BLK] = {};
+    for (int m0 = wv * 64; m0 < M; m0 += 256) {
+        const int m = m0 + ln;
+        double acc[F64_BLK] = {};
+        if (m < M) {
+            for (int k = 0; k < n; ++k) {
+                const double a = a64t[(size_t)k * Mp + m];
+#pragma unroll
+                for (int j = 0; j < F64_BLK; ++j) acc[j] = fma(a, (double)Sx[j * n + k], acc[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < F64_BLK; ++j) {
+                if (j < nloc) {
+                    const double yh = s_phi * ldexp((double)codes[(size_t)(b0 + j) * M + m],
+                                                    (int)exps[b0 + j]);
+                    const double r = acc[j] - yh;
+                    rr[j] += r * r;
+                    yy[j] += yh * yh;
+                }
+            }
+        }
+    }
+    for (int k = tid; k < n; k += 256) {
+#pragma unroll
+        for (int j = 0; j < F64_BLK; ++j) l1[j] += fabs((double)Sx[j * n + k]);
+    }
+#pragma unroll
+    for (int j = 0; j < F64_BLK; ++j) {
+        double a = rr[j], b = yy[j], c = l1[j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            a += __shfl_down(a, off);
+            b += __shfl_down(b, off);
+            c += __shfl_down(c, off);
+        }
+        if (ln == 0) {
+            red_r[wv][j] = a;
+            red_y[wv][j] = b;
+            red_l1[wv][j] = c;
+        }
+    }
+    __syncthreads();
+    if (tid < nloc) {
+        const int j = tid;
+        const double r2 = red_r[0][j] + red_r[1][j] + red_r[2][j] + red_r[3][j];
+        const double y2 = red_y[0][j] + red_y[1][j] + red_y[2][j] + red_y[3][j];
+        const double a1 = red_l1[0][j] + red_l1[1][j] + red_l1[2][j] + red_l1[3][j];
+        obj[(size_t)(b0 + j) * 2 + 0] = 0.5 * r2 + (double)lam[b0 + j] * a1;
+        obj[(size_t)(b0 + j) * 2 + 1] = y2 > 0.0 ? sqrt(r2) / sqrt(y2) : 0.0;
+    }
+}
+
+void launch_final64(const double* a64t, const float* s, const int8_t* codes, const uint8_t* exps,
+                    const float* lam, int nblk, int M, int Mp, int n, double s_phi, double* obj,
+                    hipStream_t st) {
+    if (nblk <= 0) return;
+    const size_t lds = (size_t)F64_BLK * n * sizeof(float);
+    static bool attr_set = false;
+    if (!attr_set) {
+        CSV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&final64_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    F64_BLK * 1024 * (int)sizeof(float)));
+        attr_set = true;
+    }
+    final64_kernel<<<dim3(ceil_div(nblk, F64_BLK)), dim3(256), lds, st>>>(
+        a64t, s, codes, exps, lam, nblk, M, Mp, n, s_phi, obj);
+    CSV_HIP(hipGetLastError());
+}
+
+}  // namespace csv

@@ -1,0 +1,308 @@
+// Encoder-side kernels: measurement matrix from the counter generator, key
+// frame stand-in codec, closed-loop residual measurement and quantiser.
+#include "internal.h"
+#include "mfma.h"
+
+namespace csv {
+
+// ----------------------------------------------------------------- Philox
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 64x64->128-bit products with the multipliers, the key advanced by the two
+// Weyl increments before every round after the first.
+__device__ inline void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64_t& c2, uint64_t& c3,
+                                     uint64_t k0, uint64_t k1) {
+    constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
+    constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += kW0;
+            k1 += kW1;
+        }
+        const uint64_t lo0 = kM0 * c0, hi0 = __umul64hi(kM0, c0);
+        const uint64_t lo1 = kM1 * c2, hi1 = __umul64hi(kM1, c2);
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+}
+
+// Q[i][j] = popcount(word (i*n+j) mod 4 of philox(((i*n+j)/4, n, 0, 0), key)) - 32.
+// One thread per counter (four consecutive entries of one row, n % 4 == 0).
+__global__ void phi_q_kernel(int8_t* __restrict__ q, int M, int Mp, int n, uint64_t k0,
+                             uint64_t k1) {
+    const size_t ctr = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)Mp * n / 4;
+    if (ctr >= total) return;
+    const int row = (int)(ctr * 4 / n);
+    char4 out = make_char4(0, 0, 0, 0);
+    if (row < M) {
+        uint64_t c0 = ctr, c1 = (uint64_t)n, c2 = 0, c3 = 0;
+        philox4x64_10(c0, c1, c2, c3, k0, k1);
+        out.x = (signed char)(__popcll(c0) - 32);
+        out.y = (signed char)(__popcll(c1) - 32);
+        out.z = (signed char)(__popcll(c2) - 32);
+        out.w = (signed char)(__popcll(c3) - 32);
+    }
+    reinterpret_cast<char4*>(q)[ctr] = out;
+}
+
+void launch_phi_q(int8_t* q, int M, int Mp, int n, uint64_t k0, uint64_t k1, hipStream_t st) {
+    const size_t total = (size_t)Mp * n / 4;
+    phi_q_kernel<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st>>>(q, M, Mp, n, k0, k1);
+    CSV_HIP(hipGetLastError());
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, unsigned long long v, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+void launch_fill_u64(unsigned long long* p, unsigned long long v, int count, hipStream_t st) {
+    fill_u64_kernel<<<dim3((count + 63) / 64), dim3(64), 0, st>>>(p, v, count);
+    CSV_HIP(hipGetLastError());
+}
+
+// -------------------------------------------------------- key-frame codec
+// Zigzag scan of an 8x8 block (JPEG order), as row*8 + col per scan index.
+__constant__ int kZigzag[64] = {
+    0,  1,  8,  16, 9,  2,  3,  10, 17, 24, 32, 25, 18, 11, 4,  5,
+    12, 19, 26, 33, 40, 48, 41, 34, 27, 20, 13, 6,  7,  14, 21, 28,
+    35, 42, 49, 56, 57, 50, 43, 36, 29, 22, 15, 23, 30, 37, 44, 51,
+    58, 59, 52, 45, 38, 31, 39, 46, 53, 60, 61, 54, 47, 55, 62, 63};
+
+// Integer DCT basis T[k][i] = round(1024 * a_k * cos(pi (2i+1) k / 16)); no
+// entry is near a rounding tie, so any correctly rounded cos gives it.
+__device__ inline int int_dct_entry(int k, int i) {
+    const double a = k ? sqrt(2.0 / 8.0) : sqrt(1.0 / 8.0);
+    return (int)rint(1024.0 * a * cos(M_PI * (2 * i + 1) * k / 16.0));
+}
+
+__device__ inline int ue_len(unsigned v) { return 2 * (31 - __clz(v + 1)) + 1; }
+__device__ inline int se_len(int v) { return ue_len(2u * (unsigned)abs(v) - (v > 0 ? 1u : 0u)); }
+
+// One wave per 8x8 block, four blocks per workgroup.  Lane = pixel (r, c),
+// then coefficient (k, l).  Z = T X T^T is exact in 64-bit integers; level
+// = sgn(Z) ((|Z| + 2^(s-1)) >> s) with s = 20 + log2(step).  Bits: the
+// nonzero mask in zigzag order comes from one ballot; each nonzero adds
+// ue(run) + se(level), the block adds ue(nnz).
+__global__ __launch_bounds__(256) void key_encode_kernel(const uint8_t* __restrict__ frame, int W,
+                                                        int H, int qshift,
+                                                        int16_t* __restrict__ levels,
+                                                        unsigned long long* __restrict__ bits) {
+    __shared__ int T[64];
+    __shared__ int X[4][64];
+    __shared__ int Y[4][64];
+    __shared__ int Lv[4][64];
+    const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+    if (tid < 64) T[tid] = int_dct_entry(tid >> 3, tid & 7);
+    const int bpr = W / 8, nblk = bpr * (H / 8);
+    const int blk = blockIdx.x * 4 + wv;
+    const bool live = blk < nblk;
+    const int by = live ? blk / bpr : 0, bx = live ? blk % bpr : 0;
+    const int r = ln >> 3, c = ln & 7;
+    X[wv][ln] = live ? (int)frame[(size_t)(by * 8 + r) * W + bx * 8 + c] - 128 : 0;
+    __syncthreads();
+    int y = 0;   // Y[k = r][c] = sum_i T[k][i] X[i][c]
+#pragma unroll
+    for (int i = 0; i < 8; ++i) y += T[r * 8 + i] * X[wv][i * 8 + c];
+    Y[wv][ln] = y;
+    __syncthreads();
+    long long z = 0;   // Z[k = r][l = c] = sum_j Y[k][j] T[l][j]
+#pragma unroll
+    for (int j = 0; j < 8; ++j) z += (long long)Y[wv][r * 8 + j] * T[c * 8 + j];
+    const long long az = z < 0 ? -z : z;
+    int lev = (int)((az + (1ll << (qshift - 1))) >> qshift);
+    if (z < 0) lev = -lev;
+    if (live) levels[(size_t)(by * 8 + r) * W + bx * 8 + c] = (int16_t)lev;
+    Lv[wv][ln] = lev;
+    __syncthreads();
+    const int v = Lv[wv][kZigzag[ln]];   // lane = zigzag index
+    const unsigned long long mask = __ballot(v != 0);
+    int b = 0;
+    if (v != 0) {
+        const unsigned long long below = mask & ((1ull << ln) - 1ull);
+        const int prev = below ? 63 - __clzll(below) : -1;
+        b = ue_len((unsigned)(ln - prev - 1)) + se_len(v);
+    }
+    if (ln == 0) b += ue_len((unsigned)__popcll(mask));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) b += __shfl_down(b, off);
+    if (ln == 0 && live && bits) atomicAdd(bits, (unsigned long long)b);
+}
+
+void launch_key_encode(const uint8_t* frame, int W, int H, int qshift, int16_t* levels,
+                       unsigned long long* bits, hipStream_t st) {
+    const int nblk = (W / 8) * (H / 8);
+    key_encode_kernel<<<dim3(ceil_div(nblk, 4)), dim3(256), 0, st>>>(frame, W, H, qshift, levels,
+                                                                     bits);
+    CSV_HIP(hipGetLastError());
+}
+
+// Inverse: V = T^T (step level) T in 64-bit integers, pixel =
+// clip(((V + 2^19) >> 20) + 128, 0, 255) with an arithmetic (floor) shift.
+__global__ __launch_bounds__(256) void key_decode_kernel(const int16_t* __restrict__ levels, int W,
+                                                        int H, int qstep,
+                                                        uint8_t* __restrict__ out) {
+    __shared__ int T[64];
+    __shared__ long long Cq[4][64];
+    __shared__ long long Wt[4][64];
+    const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+    if (tid < 64) T[tid] = int_dct_entry(tid >> 3, tid & 7);
+    const int bpr = W / 8, nblk = bpr * (H / 8);
+    const int blk = blockIdx.x * 4 + wv;
+    const bool live = blk < nblk;
+    const int by = live ? blk / bpr : 0, bx = live ? blk % bpr : 0;
+    const int r = ln >> 3, c = ln & 7;
+    Cq[wv][ln] = live ? (long long)levels[(size_t)(by * 8 + r) * W + bx * 8 + c] * qstep : 0;
+    __syncthreads();
+    long long w = 0;   // Wt[k = r][j = c] = sum_l Cq[k][l] T[l][j]
+#pragma unroll
+    for (int l = 0; l < 8; ++l) w += Cq[wv][r * 8 + l] * T[l * 8 + c];
+    Wt[wv][ln] = w;
+    __syncthreads();
+    long long v = 0;   // V[i = r][j = c] = sum_k T[k][i] Wt[k][j]
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v += (long long)T[k * 8 + r] * Wt[wv][k * 8 + c];
+    long long p = ((v + (1ll << 19)) >> 20) + 128;
+    p = p < 0 ? 0 : (p > 255 ? 255 : p);
+    if (live) out[(size_t)(by * 8 + r) * W + bx * 8 + c] = (uint8_t)p;
+}
+
+void launch_key_decode(const int16_t* levels, int W, int H, int qstep, uint8_t* out,
+                       hipStream_t st) {
+    const int nblk = (W / 8) * (H / 8);
+    key_decode_kernel<<<dim3(ceil_div(nblk, 4)), dim3(256), 0, st>>>(levels, W, H, qstep, out);
+    CSV_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ measurement
+// y~ = Q r for a tile of 32 blocks: the residual (frame - decoded key,
+// zero-padded outside the frame) is staged in LDS as bf16, Q streams from
+// global memory as int8 and is widened to bf16; both are exact (|r| <= 255,
+// |Q| <= 32), and so is the FP32 accumulation (every partial sum < 2^24 for
+// n <= 2048).  Each wave computes 32-row M tiles with 32x32x16 MFMA.
+template <int B>
+__global__ __launch_bounds__(256) void measure_kernel(const int8_t* __restrict__ q, int Mp,
+                                                     const uint8_t* __restrict__ frames,
+                                                     int n_frames, size_t frame_stride,
+                                                     const uint8_t* __restrict__ key, int W, int H,
+                                                     int nbx, int nb, int32_t* __restrict__ y) {
+    constexpr int n = B * B;
+    constexpr int LD = n + 8;   // bf16 row stride (16-byte pad against bank conflicts)
+    extern __shared__ uint16_t res[];   // [32][LD]
+    const int tid = threadIdx.x;
+    const int total = n_frames * nb;
+    const int gb0 = blockIdx.x * 32;
+    // stage residuals: groups of 4 pixels along a block row
+    for (int e = tid; e < 32 * n / 4; e += 256) {
+        const int j = e / (n / 4);
+        const int rem = e - j * (n / 4);
+        const int r = rem / (B / 4), c4 = (rem - r * (B / 4)) * 4;
+        const int gb = gb0 + j;
+        uint16_t v[4] = {0, 0, 0, 0};
+        if (gb < total) {
+            const int t = gb / nb, b = gb - t * nb;
+            const int py = (b / nbx) * B + r, px = (b % nbx) * B + c4;
+            if (py < H && px < W) {   // W % 8 == 0: a 4-pixel group is all in or all out
+                const uchar4 f = *reinterpret_cast<const uchar4*>(frames + t * frame_stride + (size_t)py * W + px);
+                const uchar4 k = *reinterpret_cast<const uchar4*>(key + (size_t)py * W + px);
+                v[0] = int_to_bf16_exact((int)f.x - (int)k.x);
+                v[1] = int_to_bf16_exact((int)f.y - (int)k.y);
+                v[2] = int_to_bf16_exact((int)f.z - (int)k.z);
+                v[3] = int_to_bf16_exact((int)f.w - (int)k.w);
+            }
+        }
+        uint16_t* dst = res + j * LD + r * B + c4;
+        dst[0] = v[0];
+        dst[1] = v[1];
+        dst[2] = v[2];
+        dst[3] = v[3];
+    }
+    __syncthreads();
+    const int wv = tid >> 6, ln = tid & 63, col = ln & 31, half = ln >> 5;
+    for (int mt = wv; mt < Mp / 32; mt += 4) {
+        floatx16 acc = {};
+        const int8_t* qrow = q + (size_t)(mt * 32 + col) * n + 8 * half;
+        const uint16_t* rrow = res + col * LD + 8 * half;
+#pragma unroll 4
+        for (int s = 0; s < n / 16; ++s) {
+            const uint2 qq = *reinterpret_cast<const uint2*>(qrow + 16 * s);
+            const bf16x8 a = int8x8_to_bf16x8(qq);
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(rrow + 16 * s);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+        const int gb = gb0 + col;
+        if (gb < total) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int m = mt * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+                y[(size_t)gb * Mp + m] = (int32_t)acc[r];
+            }
+        }
+    }
+}
+
+// Block-floating-point 8-bit quantiser, one wave per block: m = max|y~|,
+// e = min{e >= 0 : (m + h(e)) >> e <= 127} with h(0) = 0, h(e) = 2^(e-1);
+// code = sgn(y~) ((|y~| + h(e)) >> e).
+__global__ __launch_bounds__(256) void quantise_kernel(const int32_t* __restrict__ y, int M, int Mp,
+                                                      int total, int8_t* __restrict__ codes,
+                                                      uint8_t* __restrict__ exps,
+                                                      int32_t* __restrict__ y_out) {
+    const int gb = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int ln = threadIdx.x & 63;
+    if (gb >= total) return;   // whole wave leaves together
+    const int32_t* row = y + (size_t)gb * Mp;
+    int mx = 0;
+    for (int m = ln; m < M; m += 64) mx = max(mx, abs(row[m]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off));
+    int e = 0;
+    while (((mx + (e ? (1 << (e - 1)) : 0)) >> e) > 127) ++e;
+    const int h = e ? (1 << (e - 1)) : 0;
+    for (int m = ln; m < M; m += 64) {
+        const int v = row[m];
+        const int a = (abs(v) + h) >> e;
+        codes[(size_t)gb * M + m] = (int8_t)(v < 0 ? -a : a);
+        if (y_out) y_out[(size_t)gb * M + m] = v;
+    }
+    if (ln == 0) exps[gb] = (uint8_t)e;
+}
+
+void launch_measure(const Shape& s, const int8_t* q, const uint8_t* frames, int n_frames,
+                    size_t frame_stride, const uint8_t* key, int32_t* y_scratch, hipStream_t st) {
+    // y_scratch: (n_frames * nb) x Mp int32
+    const int total = n_frames * s.nb;
+    if (total == 0) return;
+    const dim3 grid(ceil_div(total, 32));
+    static bool attr_set = false;
+    if (!attr_set) {
+        CSV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&measure_kernel<32>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    32 * (1024 + 8) * (int)sizeof(uint16_t)));
+        attr_set = true;
+    }
+    if (s.B == 16) {
+        const size_t lds = 32 * (256 + 8) * sizeof(uint16_t);
+        measure_kernel<16><<<grid, dim3(256), lds, st>>>(q, s.Mp, frames, n_frames, frame_stride,
+                                                         key, s.W, s.H, s.nbx, s.nb, y_scratch);
+    } else {
+        const size_t lds = 32 * (1024 + 8) * sizeof(uint16_t);
+        measure_kernel<32><<<grid, dim3(256), lds, st>>>(q, s.Mp, frames, n_frames, frame_stride,
+                                                         key, s.W, s.H, s.nbx, s.nb, y_scratch);
+    }
+    CSV_HIP(hipGetLastError());
+}
+
+void launch_quantise(const int32_t* y, int M, int Mp, int total, int8_t* codes, uint8_t* exps,
+                     int32_t* y_out, hipStream_t st) {
+    if (total == 0) return;
+    quantise_kernel<<<dim3(ceil_div(total, 4)), dim3(256), 0, st>>>(y, M, Mp, total, codes, exps,
+                                                                    y_out);
+    CSV_HIP(hipGetLastError());
+}
+
+}  // namespace csv

@@ -1,0 +1,148 @@
+"""Decoder parity of the plain FP32 path against the FP64 oracle.
+
+Tolerances (FP32 arithmetic, 200-300 FISTA iterations): recovered float
+frames within 0.05 grey levels, per-frame PSNR within 0.01 dB, uint8 frames
+differing by at most one level (a rounding tie can fall either way), lambda
+and the FP64 objective within 1e-5 relative, the relative residual within
+2e-5 absolute.  The step constant is an FP64
+power iteration on both sides: 1e-9 relative."""
+import numpy as np
+import pytest
+
+import synthvid as sv
+from oracle import codec, cs, philox
+from tests.gpu_util import announce, ctx, dev, host, psnr  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_params(spec, **kw):
+    import paper_1311_1419_amd as P
+    return P.Params.from_spec(spec, precision=P.CSV_FP32, **kw)
+
+
+@pytest.mark.parametrize("m,b", [(64, 16), (13, 16), (128, 16), (256, 32), (410, 32), (1024, 32)])
+def test_step_constant_and_operator(ctx, m, b):
+    import paper_1311_1419_amd as P
+    announce(f"operator/L m={m} B={b}")
+    p = P.Params(width=64, height=64, gop=2, block=b, m=m, phi_seed=77 + m, stream_id=b)
+    L, it = ctx.step_constant(p)
+    q = philox.measurement_matrix_q(m, b * b, 77 + m, b)
+    s_phi = philox.phi_scale(m)
+    L_ref, _, it_ref = cs.lipschitz(q, s_phi)
+    assert L == pytest.approx(L_ref, rel=1e-9)
+    a = host(ctx.operator_matrix(p))
+    assert np.max(np.abs(a - cs.operator(q, s_phi, b))) < 1e-12
+
+
+def _decode_compare(ctx, spec, flags=0, **okw):
+    frames = spec.video()
+    p = _gpu_params(spec, flags=flags)
+    op = codec.Params.from_spec(spec, **okw)
+    ref_stream = codec.encode_gop(frames, op)
+    ref = codec.decode_gop(ref_stream, op)
+    gs = ctx.encode_gop(dev(frames), p)
+    out, fl, obj = ctx.decode_gop(gs, p, want_float=True, want_obj=True)
+    out, fl, obj = host(out), host(fl), host(obj)
+    assert np.array_equal(out[0], ref.frames[0])
+    for t in range(1, spec.gop):
+        err = np.max(np.abs(fl[t - 1].astype(np.float64) - ref.cs_float[t - 1]))
+        assert err <= 0.05, f"frame {t}: max abs {err}"
+        assert np.max(np.abs(out[t].astype(int) - ref.frames[t].astype(int))) <= 1
+        assert abs(psnr(frames[t], out[t]) - psnr(frames[t], ref.frames[t])) <= 0.01
+    rel = np.abs(obj[..., 0] - ref.objective) / np.maximum(ref.objective, 1e-300)
+    assert np.max(rel) <= 1e-5
+    # ||A s - y|| / ||y|| is a few percent: FP32 error in s shows up as an
+    # absolute error of the order 1e-5 (in units of ||y||)
+    assert np.max(np.abs(obj[..., 1] - ref.rel_residual)) <= 2e-5
+    return out, ref
+
+
+@pytest.mark.parametrize("spec", [sv.qcif_tiny(), sv.cif_sweep(4, 0.1, iters=300),
+                                  sv.cif_sweep(4, 0.5, iters=300),
+                                  sv.qcif_tiny().with_(block=32, m=256, gop=3)],
+                         ids=["qcif-tiny", "cif-m26", "cif-m128", "qcif-b32-padded"])
+def test_decode_fp32_matches_oracle(ctx, spec):
+    announce(f"decode fp32 {spec.width}x{spec.height} G={spec.gop} B={spec.block} M={spec.m}")
+    _decode_compare(ctx, spec)
+
+
+def test_decode_fp32_ista_and_pixel_lambda(ctx):
+    import paper_1311_1419_amd as P
+    announce("decode fp32 ISTA + pixel-domain lambda")
+    spec = sv.qcif_tiny().with_(gop=2, iters=60)
+    _decode_compare(ctx, spec, flags=P.CSV_FLAG_ISTA | P.CSV_FLAG_LAMBDA_PIXEL_DOMAIN,
+                    solver="ista", pixel_domain_lambda=True)
+
+
+def test_lambda_and_coefficients(ctx):
+    announce("recover_blocks fp32 lambda/coefficients")
+    spec = sv.qcif_tiny()
+    frames = spec.video()
+    op = codec.Params.from_spec(spec)
+    st = codec.encode_gop(frames, op)
+    p = _gpu_params(spec)
+    codes = st.codes.reshape(-1, spec.m)
+    exps = st.exps.reshape(-1)
+    s, lam, obj = ctx.recover_blocks(p, dev(codes), dev(exps), want_obj=True)
+    s, lam = host(s), host(lam)
+    q = philox.measurement_matrix_q(spec.m, spec.n, spec.phi_seed, spec.stream_id)
+    s_phi = philox.phi_scale(spec.m)
+    a = cs.operator(q, s_phi, spec.block)
+    y = cs.dequantise(codes.T, exps, s_phi)
+    lam_ref = cs.lambdas(a, y)
+    assert np.allclose(lam, lam_ref, rtol=1e-5, atol=1e-6)
+    L, _, _ = cs.lipschitz(q, s_phi)
+    s_ref = cs.fista(a, y, lam_ref, L, spec.iters).T
+    scale = np.maximum(np.abs(s_ref).max(axis=1, keepdims=True), 1.0)
+    assert np.max(np.abs(s - s_ref) / scale) < 1e-3
+
+
+def test_zero_residual_and_key_only(ctx):
+    announce("static video (zero residual) and key-only GOP")
+    spec = sv.qcif_tiny()
+    frames = spec.video(1)
+    static = np.repeat(frames, 4, axis=0)
+    p = _gpu_params(spec)
+    gs = ctx.encode_gop(dev(static), p)
+    out, fl, obj = ctx.decode_gop(gs, p, want_float=True, want_obj=True)
+    out = host(out)
+    key = out[0]
+    # residual F_t - F^_key is the key coding error: not zero, but identical for every CS frame
+    assert np.array_equal(host(gs.codes)[0], host(gs.codes)[1])
+    assert np.array_equal(out[1], out[2]) and np.array_equal(out[2], out[3])
+    # a frame equal to the decoded key has an all-zero residual -> codes 0, s = 0
+    z = np.stack([frames[0], key, key])
+    p3 = _gpu_params(spec.with_(gop=3))
+    gs3 = ctx.encode_gop(dev(z), p3)
+    assert not host(gs3.codes).any() and not host(gs3.exps).any()
+    out3, fl3, obj3 = ctx.decode_gop(gs3, p3, want_float=True, want_obj=True)
+    assert np.array_equal(host(out3)[1], key) and np.all(host(fl3)[0] == key)
+    assert np.all(host(obj3) == 0)
+    p1 = _gpu_params(spec.with_(gop=1))
+    gs1 = ctx.encode_gop(dev(frames), p1)
+    out1, _, _ = ctx.decode_gop(gs1, p1)
+    assert np.array_equal(host(out1)[0], key)
+
+
+def test_decode_deterministic(ctx):
+    announce("decode fp32 determinism")
+    spec = sv.cif_sweep(4, 0.2, iters=100)
+    p = _gpu_params(spec)
+    gs = ctx.encode_gop(dev(spec.video()), p)
+    a = host(ctx.decode_gop(gs, p, want_float=True)[1])
+    b = host(ctx.decode_gop(gs, p, want_float=True)[1])
+    assert np.array_equal(a, b)
+
+
+def test_bad_params_rejected(ctx):
+    import paper_1311_1419_amd as P
+    announce("bad params")
+    spec = sv.qcif_tiny()
+    frames = dev(spec.video())
+    for bad in (dict(block=8), dict(m=257), dict(iters=0), dict(key_qstep=12)):
+        with pytest.raises(P.CsvError):
+            ctx.encode_gop(frames, _gpu_params(spec).with_(**bad))
+    for bad in (dict(gop=0), dict(width=170), dict(m=0, rho=0.0), dict(lambda_frac=-1.0)):
+        with pytest.raises(P.CsvError):
+            _gpu_params(spec).with_(**bad).resolve()
