@@ -202,6 +202,16 @@ int csv_recover_blocks(csv_ctx* ctx, const csv_params* p, int32_t n_blocks,
                        const int8_t* codes, const uint8_t* exps, float* s_out,
                        float* lambda_out, double* obj_out, void* stream);
 
+/* ------------------------------------------------------- measurement */
+/* Event timing of named kernel ranges on the stream they run on ("fista_bf16",
+ * "fista_fp32", "prepare", "synth", "final64", "key_decode").  While enabled,
+ * every such range records a pair of HIP events.  csv_profile_query waits
+ * for the recorded events and returns the summed milliseconds and the number
+ * of ranges for `name` since the last reset. */
+int csv_profile_enable(csv_ctx* ctx, int on);
+int csv_profile_query(csv_ctx* ctx, const char* name, double* total_ms, int64_t* launches);
+int csv_profile_reset(csv_ctx* ctx);
+
 #ifdef __cplusplus
 }
 #endif

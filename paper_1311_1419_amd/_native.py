@@ -76,6 +76,9 @@ _SIGS = {
     "csv_recover_blocks": (C.c_int, [C.c_void_p, _P(CsvParams), C.c_int32, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p]),
+    "csv_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "csv_profile_query": (C.c_int, [C.c_void_p, C.c_char_p, _P(C.c_double), _P(C.c_int64)]),
+    "csv_profile_reset": (C.c_int, [C.c_void_p]),
 }
 
 _lib = None

@@ -202,6 +202,20 @@ class Context:
                                          optr if want_obj else None, _stream(dev)))
         return outs
 
+    # ---------------------------------------------------------- profiling
+    def profile(self, on: bool = True) -> None:
+        N.check(N.lib().csv_profile_enable(self._h, 1 if on else 0))
+
+    def profile_reset(self) -> None:
+        N.check(N.lib().csv_profile_reset(self._h))
+
+    def profile_query(self, name: str) -> tuple[float, int]:
+        """(total milliseconds, number of ranges) of a named kernel range."""
+        ms = C.c_double()
+        cnt = C.c_int64()
+        N.check(N.lib().csv_profile_query(self._h, name.encode(), C.byref(ms), C.byref(cnt)))
+        return ms.value, cnt.value
+
     # ------------------------------------------------------ single steps
     def phi_matrix(self, p: Params) -> torch.Tensor:
         m, _ = p.resolve()

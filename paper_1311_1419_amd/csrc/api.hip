@@ -201,13 +201,6 @@ const float* beta_table(Ctx* c, int T, bool ista, hipStream_t st) {
 }
 
 // --------------------------------------------------------- recovery core
-// Recover nblk blocks of one operator from codes: y^ (dequantised), lambda,
-// FISTA (plain FP32 passes), returning coefficients in `s_out`.
-struct RecoverBufs {
-    float* y;     // nblk x Mp
-    float* lam;   // nblk
-};
-
 static void lambda_pass(Ctx* c, const Shape& s, Operator* op, const float* y, int nblk, float* lam,
                         hipStream_t st) {
     float* g0 = static_cast<float*>(scratch(c, "g0", (size_t)nblk * s.n * 4));
@@ -226,7 +219,7 @@ static void fista_fp32(Ctx* c, const Shape& s, Operator* op, const float* y, con
     launch_fill_f32(S, 0.f, nn, st);
     launch_fill_f32(V, 0.f, nn, st);
     for (int k = 0; k < s.T; ++k) {
-        // residual A v - y^ (fwd product, epilogue subtracts y^; padded rows 0)
+        // residual A v - y^ (forward product, epilogue subtracts y^; padded rows 0)
         launch_gemm_nt(V, op->a32, R, nblk, s.Mp, s.n, s.n, s.n, s.Mp, y, s.Mp, s.M, st);
         // gradient A^T (A v - y^)
         launch_gemm_nn(R, op->a32, Gd, nblk, s.n, s.Mp, s.Mp, s.n, s.n, st);
@@ -234,21 +227,145 @@ static void fista_fp32(Ctx* c, const Shape& s, Operator* op, const float* y, con
     }
 }
 
+// One recovery job of the fused path: nblk blocks of one operator.
+struct FusedJob {
+    const Shape* s;
+    Operator* op;
+    const float* y;
+    const float* lam;
+    float* S;
+    int nblk;
+};
+
+// Split every job into tiles of 32*CT blocks, group the tiles by (n, Mp)
+// class and give each class one persistent launch.  The tile list of a
+// class is cut into eight contiguous runs, one per XCD queue (workgroup
+// b is dispatched to XCD b % 8), so tiles of one operator stay on few L2s;
+// idle workgroups steal from the other queues.
+static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st) {
+    std::map<std::pair<int, int>, std::vector<FusedTile>> classes;
+    for (const FusedJob& j : jobs) {
+        const Shape& s = *j.s;
+        CSV_REQUIRE(fused_class_supported(s.n, s.Mp), CSV_EUNSUPPORTED,
+                    "fused BF16 recovery has no kernel for n=" + std::to_string(s.n) +
+                        ", M padded to " + std::to_string(s.Mp));
+        const int nt = fused_tile_blocks(s.n, s.Mp);
+        const float* beta = beta_table(c, s.T, (s.flags & CSV_FLAG_ISTA) != 0, st);
+        for (int b0 = 0; b0 < j.nblk; b0 += nt) {
+            FusedTile t{};
+            t.frag_fwd = j.op->frag_fwd;
+            t.frag_adj = j.op->frag_adj;
+            t.lip = j.op->lip;
+            t.y = j.y + (size_t)b0 * s.Mp;
+            t.lam = j.lam + b0;
+            t.s = j.S + (size_t)b0 * s.n;
+            t.beta = beta;
+            t.nblk = std::min(nt, j.nblk - b0);
+            t.T = s.T;
+            t.n = s.n;
+            t.Mp = s.Mp;
+            classes[{s.n, s.Mp}].push_back(t);
+        }
+    }
+    if (classes.empty()) return;
+    // host staging: [tiles][qoff 9 + queue + counters 8] per class, one upload
+    size_t tiles_bytes = 0, idx_ints = 0;
+    for (auto& kv : classes) {
+        tiles_bytes += kv.second.size() * sizeof(FusedTile);
+        idx_ints += 9 + kv.second.size() + 8;
+    }
+    const size_t bytes = tiles_bytes + idx_ints * sizeof(int) + 64;
+    if (c->stage_bytes < bytes) {
+        if (c->stage_host) {
+            CSV_HIP(hipEventSynchronize(c->stage_done));
+            CSV_HIP(hipHostFree(c->stage_host));
+        }
+        c->stage_host = nullptr;
+        c->stage_bytes = 0;
+        CSV_HIP(hipHostMalloc(&c->stage_host, bytes * 2, hipHostMallocDefault));
+        c->stage_bytes = bytes * 2;
+    } else if (c->stage_host) {
+        CSV_HIP(hipEventSynchronize(c->stage_done));   // previous upload has left the buffer
+    }
+    if (!c->stage_done) CSV_HIP(hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming));
+    char* host = static_cast<char*>(c->stage_host);
+    char* dev = static_cast<char*>(scratch(c, "tiles", bytes));
+    struct Launch {
+        int n, Mp, grid;
+        size_t tiles_off, qoff_off, queue_off, ctr_off;
+    };
+    std::vector<Launch> launches;
+    size_t off_t = 0, off_i = tiles_bytes;
+    for (auto& kv : classes) {
+        const auto& v = kv.second;
+        const int count = (int)v.size();
+        Launch L{kv.first.first, kv.first.second, std::min(count, 256), off_t, 0, 0, 0};
+        std::memcpy(host + off_t, v.data(), v.size() * sizeof(FusedTile));
+        off_t += v.size() * sizeof(FusedTile);
+        int* qoff = reinterpret_cast<int*>(host + off_i);
+        L.qoff_off = off_i;
+        for (int x = 0; x <= 8; ++x) qoff[x] = (int)((long long)count * x / 8);
+        off_i += 9 * sizeof(int);
+        int* queue = reinterpret_cast<int*>(host + off_i);
+        L.queue_off = off_i;
+        for (int i = 0; i < count; ++i) queue[i] = i;
+        off_i += count * sizeof(int);
+        int* ctr = reinterpret_cast<int*>(host + off_i);
+        L.ctr_off = off_i;
+        for (int x = 0; x < 8; ++x) ctr[x] = 0;
+        off_i += 8 * sizeof(int);
+        launches.push_back(L);
+    }
+    CSV_HIP(hipMemcpyAsync(dev, host, off_i, hipMemcpyHostToDevice, st));
+    CSV_HIP(hipEventRecord(c->stage_done, st));
+    for (const Launch& L : launches) {
+        ProfScope ps(c, "fista_bf16", st);
+        launch_fista_bf16_class(L.n, L.Mp, reinterpret_cast<const FusedTile*>(dev + L.tiles_off),
+                                reinterpret_cast<const int*>(dev + L.qoff_off),
+                                reinterpret_cast<const int*>(dev + L.queue_off),
+                                reinterpret_cast<int*>(dev + L.ctr_off), L.grid, st);
+    }
+}
+
+// Dequantise and compute lambda for nblk blocks of one operator; returns y^.
+static const float* prepare(Ctx* c, const Shape& s, Operator* op, const int8_t* codes,
+                            const uint8_t* exps, int nblk, float* lam, const std::string& tag,
+                            hipStream_t st) {
+    float* y = static_cast<float*>(scratch(c, "yhat" + tag, (size_t)nblk * s.Mp * 4));
+    launch_dequant(codes, exps, nblk, s.M, s.Mp, op->s_phi, y, st);
+    lambda_pass(c, s, op, y, nblk, lam, st);
+    return y;
+}
+
 void recover(Ctx* c, const Shape& s, Operator* op, const int8_t* codes, const uint8_t* exps,
              int nblk, float* S, float* lam_out, double* obj_out, hipStream_t st) {
     if (nblk <= 0) return;
-    float* y = static_cast<float*>(scratch(c, "yhat", (size_t)nblk * s.Mp * 4));
     float* lam = lam_out ? lam_out : static_cast<float*>(scratch(c, "lam", (size_t)nblk * 4));
-    launch_dequant(codes, exps, nblk, s.M, s.Mp, op->s_phi, y, st);
-    lambda_pass(c, s, op, y, nblk, lam, st);
+    const float* y = prepare(c, s, op, codes, exps, nblk, lam, "", st);
     if (s.precision == CSV_FP32) {
+        ProfScope ps(c, "fista_fp32", st);
         fista_fp32(c, s, op, y, lam, nblk, S, st);
     } else {
-        throw Error{CSV_EUNSUPPORTED, "BF16 fused recovery is not available in this build"};
+        fista_bf16(c, {FusedJob{&s, op, y, lam, S, nblk}}, st);
     }
-    if (obj_out)
+    if (obj_out) {
+        ProfScope ps(c, "final64", st);
         launch_final64(op->a64t, S, codes, exps, lam, nblk, s.M, s.Mp, s.n, op->s_phi, obj_out,
                        st);
+    }
+}
+
+// Event-timed ranges of named kernels on the stream they are launched on.
+ProfScope::ProfScope(Ctx* c, const char* name, hipStream_t st) : c_(c), name_(name), st_(st) {
+    if (!c_->profiling) return;
+    CSV_HIP(hipEventCreate(&a_));
+    CSV_HIP(hipEventCreate(&b_));
+    CSV_HIP(hipEventRecord(a_, st_));
+}
+
+ProfScope::~ProfScope() {
+    if (!c_->profiling || !a_) return;
+    if (hipEventRecord(b_, st_) == hipSuccess) c_->prof_pending[name_].push_back({a_, b_});
 }
 
 }  // namespace csv
@@ -292,6 +409,13 @@ int csv_destroy(csv_ctx* ctx) {
         for (auto& kv : ctx->impl.ops) free_operator(&ctx->impl, kv.second.get());
         for (auto& kv : ctx->impl.scratch) ctx_free(&ctx->impl, kv.second.ptr, kv.second.bytes);
         for (auto& kv : ctx->impl.beta_tables) (void)hipFree(kv.second.first);
+        if (ctx->impl.stage_host) (void)hipHostFree(ctx->impl.stage_host);
+        if (ctx->impl.stage_done) (void)hipEventDestroy(ctx->impl.stage_done);
+        for (auto& kv : ctx->impl.prof_pending)
+            for (auto& ev : kv.second) {
+                (void)hipEventDestroy(ev.first);
+                (void)hipEventDestroy(ev.second);
+            }
         delete ctx;
     });
 }
@@ -379,31 +503,84 @@ int csv_encode_gop(csv_ctx* ctx, const csv_params* p, const uint8_t* frames,
     });
 }
 
-static void decode_one(Ctx* c, const Shape& s, const csv_gop_stream* in, uint8_t* frames_out,
-                       float* cs_float_out, double* obj_out, hipStream_t st) {
-    CSV_REQUIRE(in && in->key_levels && frames_out, CSV_EINVAL, "NULL argument");
-    launch_key_decode(in->key_levels, s.W, s.H, s.qstep, frames_out, st);
-    const int ncs = s.G - 1;
-    if (!ncs) return;
-    CSV_REQUIRE(in->codes && in->exps, CSV_EINVAL, "codes/exps are NULL");
-    Operator* op = get_operator(c, s, st);
-    const int nblk = ncs * s.nb;
-    float* S = static_cast<float*>(scratch(c, "S", (size_t)nblk * s.n * 4));
-    recover(c, s, op, in->codes, in->exps, nblk, S, nullptr, obj_out, st);
-    const size_t fs = (size_t)s.W * s.H;
-    launch_synth(S, op->dct, frames_out, s.W, s.H, s.B, s.nbx, s.nb, ncs, frames_out + fs,
-                 cs_float_out, st);
+// Decode `count` GOPs.  Key frames first (Section 3.2: CS frames are decoded
+// only after the key frame), then one recovery pass over every CS block of
+// every GOP, then synthesis onto each decoded key frame (eq. (4)).
+static void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* in,
+                        uint8_t* const* frames_out, float* const* cs_float_out,
+                        double* const* obj_out, hipStream_t st) {
+    struct Item {
+        Operator* op;
+        int nblk;
+        float* S;
+        float* lam;
+        const float* y;
+    };
+    std::vector<Item> items(count);
+    for (int i = 0; i < count; ++i) {
+        const Shape& s = shapes[i];
+        CSV_REQUIRE(in[i].key_levels && frames_out[i], CSV_EINVAL, "NULL key_levels or frames_out");
+        CSV_REQUIRE(s.G == 1 || (in[i].codes && in[i].exps), CSV_EINVAL, "codes/exps are NULL");
+        items[i].op = s.G > 1 ? get_operator(c, s, st) : nullptr;
+        items[i].nblk = (s.G - 1) * s.nb;
+    }
+    // scratch is sized before any launch that reads it
+    for (int i = 0; i < count; ++i) {
+        const Shape& s = shapes[i];
+        if (!items[i].nblk) continue;
+        const std::string tag = "#" + std::to_string(i);
+        items[i].S = static_cast<float*>(scratch(c, "S" + tag, (size_t)items[i].nblk * s.n * 4));
+        items[i].lam = static_cast<float*>(scratch(c, "lam" + tag, (size_t)items[i].nblk * 4));
+        scratch(c, "yhat" + tag, (size_t)items[i].nblk * s.Mp * 4);
+    }
+    for (int i = 0; i < count; ++i) {
+        const Shape& s = shapes[i];
+        ProfScope ps(c, "key_decode", st);
+        launch_key_decode(in[i].key_levels, s.W, s.H, s.qstep, frames_out[i], st);
+    }
+    std::vector<FusedJob> jobs;
+    for (int i = 0; i < count; ++i) {
+        const Shape& s = shapes[i];
+        Item& it = items[i];
+        if (!it.nblk) continue;
+        {
+            ProfScope ps(c, "prepare", st);
+            it.y = prepare(c, s, it.op, in[i].codes, in[i].exps, it.nblk, it.lam,
+                           "#" + std::to_string(i), st);
+        }
+        if (s.precision == CSV_FP32) {
+            ProfScope ps(c, "fista_fp32", st);
+            fista_fp32(c, s, it.op, it.y, it.lam, it.nblk, it.S, st);
+        } else {
+            jobs.push_back(FusedJob{&shapes[i], it.op, it.y, it.lam, it.S, it.nblk});
+        }
+    }
+    if (!jobs.empty()) fista_bf16(c, jobs, st);
+    for (int i = 0; i < count; ++i) {
+        const Shape& s = shapes[i];
+        const Item& it = items[i];
+        if (!it.nblk) continue;
+        if (obj_out && obj_out[i]) {
+            ProfScope ps(c, "final64", st);
+            launch_final64(it.op->a64t, it.S, in[i].codes, in[i].exps, it.lam, it.nblk, s.M, s.Mp,
+                           s.n, it.op->s_phi, obj_out[i], st);
+        }
+        ProfScope ps(c, "synth", st);
+        const size_t fs = (size_t)s.W * s.H;
+        launch_synth(it.S, it.op->dct, frames_out[i], s.W, s.H, s.B, s.nbx, s.nb, s.G - 1,
+                     frames_out[i] + fs, cs_float_out ? cs_float_out[i] : nullptr, st);
+    }
 }
 
 int csv_decode_gop(csv_ctx* ctx, const csv_params* p, const csv_gop_stream* in,
                    uint8_t* frames_out, float* cs_float_out, double* obj_out, void* stream) {
     return guarded([&] {
-        CSV_REQUIRE(ctx, CSV_EINVAL, "ctx is NULL");
+        CSV_REQUIRE(ctx && in && frames_out, CSV_EINVAL, "NULL argument");
         std::lock_guard<std::mutex> lk(ctx->mu);
         set_device(ctx);
         const Shape s = resolve(p);
-        decode_one(C(ctx), s, in, frames_out, cs_float_out, obj_out,
-                   static_cast<hipStream_t>(stream));
+        decode_gops(C(ctx), 1, &s, in, &frames_out, &cs_float_out, &obj_out,
+                    static_cast<hipStream_t>(stream));
     });
 }
 
@@ -411,20 +588,66 @@ int csv_decode_batch(csv_ctx* ctx, int32_t count, const csv_params* params,
                      const csv_gop_stream* in, uint8_t* const* frames_out,
                      float* const* cs_float_out, double* const* obj_out, void* stream) {
     return guarded([&] {
-        CSV_REQUIRE(ctx && params && in && frames_out, CSV_EINVAL, "NULL argument");
         CSV_REQUIRE(count >= 0, CSV_EINVAL, "negative count");
+        if (count == 0) return;
+        CSV_REQUIRE(ctx && params && in && frames_out, CSV_EINVAL, "NULL argument");
         std::lock_guard<std::mutex> lk(ctx->mu);
         set_device(ctx);
-        hipStream_t st = static_cast<hipStream_t>(stream);
         std::vector<Shape> shapes;
         for (int i = 0; i < count; ++i) shapes.push_back(resolve(&params[i]));
         for (int i = 1; i < count; ++i)
             CSV_REQUIRE(shapes[i].precision == shapes[0].precision, CSV_EINVAL,
                         "one precision per batch");
-        for (int i = 0; i < count; ++i)
-            decode_one(C(ctx), shapes[i], &in[i], frames_out[i],
-                       cs_float_out ? cs_float_out[i] : nullptr, obj_out ? obj_out[i] : nullptr,
-                       st);
+        decode_gops(C(ctx), count, shapes.data(), in, frames_out, cs_float_out, obj_out,
+                    static_cast<hipStream_t>(stream));
+    });
+}
+
+int csv_profile_enable(csv_ctx* ctx, int on) {
+    return guarded([&] {
+        CSV_REQUIRE(ctx, CSV_EINVAL, "ctx is NULL");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->impl.profiling = on != 0;
+    });
+}
+
+int csv_profile_query(csv_ctx* ctx, const char* name, double* total_ms, int64_t* launches) {
+    return guarded([&] {
+        CSV_REQUIRE(ctx && name && total_ms && launches, CSV_EINVAL, "NULL argument");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        Ctx* c = C(ctx);
+        for (auto& kv : c->prof_pending) {
+            auto& tot = c->prof_total[kv.first];
+            for (auto& ev : kv.second) {
+                CSV_HIP(hipEventSynchronize(ev.second));
+                float ms = 0.f;
+                CSV_HIP(hipEventElapsedTime(&ms, ev.first, ev.second));
+                tot.first += ms;
+                tot.second += 1;
+                (void)hipEventDestroy(ev.first);
+                (void)hipEventDestroy(ev.second);
+            }
+            kv.second.clear();
+        }
+        auto it = c->prof_total.find(name);
+        *total_ms = it == c->prof_total.end() ? 0.0 : it->second.first;
+        *launches = it == c->prof_total.end() ? 0 : it->second.second;
+    });
+}
+
+int csv_profile_reset(csv_ctx* ctx) {
+    return guarded([&] {
+        CSV_REQUIRE(ctx, CSV_EINVAL, "ctx is NULL");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        Ctx* c = C(ctx);
+        for (auto& kv : c->prof_pending)
+            for (auto& ev : kv.second) {
+                (void)hipEventSynchronize(ev.second);
+                (void)hipEventDestroy(ev.first);
+                (void)hipEventDestroy(ev.second);
+            }
+        c->prof_pending.clear();
+        c->prof_total.clear();
     });
 }
 

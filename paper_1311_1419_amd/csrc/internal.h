@@ -78,10 +78,31 @@ struct Ctx {
     int device = 0;
     size_t budget = 0;
     size_t used = 0;
+    void* stage_host = nullptr;      // pinned staging for tile descriptors
+    size_t stage_bytes = 0;
+    hipEvent_t stage_done = nullptr;
+    bool profiling = false;
+    std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
+    std::map<std::string, std::pair<double, long long>> prof_total;
     std::map<std::tuple<uint64_t, uint32_t, int, int>, std::unique_ptr<Operator>> ops;
     std::map<std::string, Scratch> scratch;
     std::map<int, std::pair<float*, int>> beta_tables;   // key: T*2 + ista
     int gen = 0;   // bumps whenever a scratch buffer moves
+};
+
+// Records a pair of events around a named kernel range when profiling is on.
+class ProfScope {
+  public:
+    ProfScope(Ctx* c, const char* name, hipStream_t st);
+    ~ProfScope();
+    ProfScope(const ProfScope&) = delete;
+    ProfScope& operator=(const ProfScope&) = delete;
+
+  private:
+    Ctx* c_;
+    const char* name_;
+    hipStream_t st_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
 };
 
 // allocation inside the context budget
@@ -131,12 +152,17 @@ struct FusedTile {
     const float* y;      // nblk x Mp
     const float* lam;    // nblk
     float* s;            // nblk x n
+    const float* beta;   // T momentum factors
     int nblk;            // blocks in this tile (<= tile width)
+    int T;
     int n, Mp;
 };
 void launch_bf16_frag_layout(Operator* op, hipStream_t st);
 int fused_tile_blocks(int n, int Mp);
-void launch_fista_bf16(const FusedTile* tiles_dev, int n_tiles, int n, int Mp, int T,
-                       const float* beta, int* counter, hipStream_t st);
+bool fused_class_supported(int n, int Mp);
+// one persistent launch over the tiles of one (n, Mp) class; qoff[0..8]
+// delimit eight per-XCD queues of tile indices, counters[8] start at zero
+void launch_fista_bf16_class(int n, int Mp, const FusedTile* tiles, const int* qoff,
+                             const int* queue, int* counters, int grid, hipStream_t st);
 
 }  // namespace csv

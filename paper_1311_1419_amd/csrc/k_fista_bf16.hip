@@ -1,22 +1,317 @@
-// Fused BF16 recovery kernel (placeholder until the fused path lands).
+// Fused BF16 recovery: all T FISTA iterations of a tile of 32*CT blocks run
+// inside one workgroup, iterates on chip, both products on MFMA.
+//
+// Problem per block (eq. (1) read as a LASSO in the 2-D DCT basis):
+//   min_s 1/2 ||A s - y||^2 + lam ||s||_1,   A = Phi Psi (M x n)
+// FISTA with constant step 1/L (Beck and Teboulle 2009):
+//   u = v - A^T (A v - y) / L;  s_k = soft(u, lam / L);
+//   v = s_k + beta_k (s_k - s_{k-1}).
+//
+// Layout.  A workgroup is four waves; wave w owns coefficient rows
+// [w n/4, (w+1) n/4) of every block of the tile and keeps s_{k-1} and v in
+// FP32 registers, in the 32x32 MFMA accumulator layout (lane l, register r:
+// row 8(r/4) + 4(l/32) + r%4 of a 32-row group, column l%32).  Per
+// iteration:
+//   forward  P = A V  (M x 32CT, K = n): output tiles split over the waves by
+//            M rows; V comes from LDS as bf16 B fragments; A streams from
+//            global memory (L2) as bf16 A fragments;  R = P - y  (FP32,
+//            y held in registers) is written back to LDS as bf16;
+//   adjoint  G = A^T R  (n x 32CT, K = M): each wave computes its own rows,
+//            R from LDS, A^T streamed as bf16 fragments; the threshold and
+//            momentum update runs on the accumulators in registers and the
+//            new V is written to LDS as bf16.
+// A 32-row accumulator tile feeds the next product's K dimension without a
+// shuffle: in K step s of a 32x32x16 MFMA, lane half h, element e carries
+// row kappa_s(h, e) = 16 s + 8 (e / 4) + 4 h + e % 4 of the group, which is
+// register 8 s + e of the accumulator.  The operator fragments are stored
+// with that same K order, so the products are exact permutations of the
+// plain sums.
 #include "internal.h"
 #include "mfma.h"
 
 namespace csv {
 
+constexpr int kWaves = 4;
+
+// K index inside a 32-group carried by (K step s, lane half h, element e).
+__host__ __device__ inline int kappa(int s, int h, int e) {
+    return 16 * s + 8 * (e / 4) + 4 * h + (e % 4);
+}
+
+// frag_fwd[mt][ks][lane][e] = A[mt*32 + lane%32][32*(ks/2) + kappa(ks%2, lane/32, e)]
+// frag_adj[nt][ks][lane][e] = A[32*(ks/2) + kappa(ks%2, lane/32, e)][nt*32 + lane%32]
+__global__ void frag_layout_kernel(const float* __restrict__ a32, int n, int Mp,
+                                   uint16_t* __restrict__ fwd, uint16_t* __restrict__ adj) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)Mp * n;
+    if (idx >= total) return;
+    const int e = (int)(idx & 7), lane = (int)((idx >> 3) & 63);
+    const size_t frag = idx >> 9;
+    const int h = lane >> 5, i = lane & 31;
+    {   // forward: fragments ordered [mt][ks], ks over n/16
+        const int ks = (int)(frag % (n / 16)), mt = (int)(frag / (n / 16));
+        const int row = mt * 32 + i, col = 32 * (ks / 2) + kappa(ks % 2, h, e);
+        fwd[idx] = f32_to_bf16_rne(a32[(size_t)row * n + col]);
+    }
+    {   // adjoint: fragments ordered [nt][ks], ks over Mp/16
+        const int ks = (int)(frag % (Mp / 16)), nt = (int)(frag / (Mp / 16));
+        const int row = 32 * (ks / 2) + kappa(ks % 2, h, e), col = nt * 32 + i;
+        adj[idx] = f32_to_bf16_rne(a32[(size_t)row * n + col]);
+    }
+}
+
 void launch_bf16_frag_layout(Operator* op, hipStream_t st) {
-    (void)op;
-    (void)st;
+    const size_t total = (size_t)op->Mp * op->n;
+    frag_layout_kernel<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st>>>(
+        op->a32, op->n, op->Mp, op->frag_fwd, op->frag_adj);
+    CSV_HIP(hipGetLastError());
 }
 
-int fused_tile_blocks(int n, int Mp) {
-    (void)n;
-    (void)Mp;
-    return 0;
+// Column tiles (of 32 blocks) per workgroup for a class (n, Mp).
+static int class_ct(int n, int Mp) {
+    if (n == 1024) return 1;
+    return Mp <= 64 ? 4 : 2;
 }
 
-void launch_fista_bf16(const FusedTile*, int, int, int, int, const float*, int*, hipStream_t) {
-    throw Error{CSV_EUNSUPPORTED, "BF16 fused recovery is not available in this build"};
+int fused_tile_blocks(int n, int Mp) { return 32 * class_ct(n, Mp); }
+
+__device__ inline u16x8 pack_bf16(const floatx16& a, int s) {
+    u16x8 o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) o[e] = __builtin_bit_cast(uint16_t, (__bf16)a[8 * s + e]);
+    return o;
+}
+
+__device__ inline int next_tile(const int* __restrict__ qoff, const int* __restrict__ queue,
+                                int* __restrict__ counters) {
+    const int x0 = blockIdx.x & 7;
+    for (int d = 0; d < 8; ++d) {
+        const int x = (x0 + d) & 7;
+        const int len = qoff[x + 1] - qoff[x];
+        if (len <= 0) continue;
+        const int i = atomicAdd(&counters[x], 1);
+        if (i < len) return queue[qoff[x] + i];
+    }
+    return -1;
+}
+
+// Forward product for the NF output tiles (mt_i, fct) of one wave,
+// mt_i = (w + 4 i) / CT, then R = P - y written to LDS as bf16.  y comes from
+// registers (yv) when YREG, else from global memory.
+template <int N, int MP, int CT, int NF, bool YREG>
+__device__ inline void forward_tiles(const u16x8* __restrict__ ffwd, const u16x8* Vb, u16x8* Rb,
+                                     const floatx16* yv, const float* __restrict__ yg, int nblk,
+                                     int w, int ln, int fct) {
+    constexpr int KSF = N / 16;
+    floatx16 acc[NF];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) acc[i] = floatx16{};
+#pragma unroll 4
+    for (int ks = 0; ks < KSF; ++ks) {
+        const bf16x8 b = __builtin_bit_cast(bf16x8, Vb[(ks * CT + fct) * 64 + ln]);
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const int mt = (w + kWaves * i) / CT;
+            const bf16x8 a = __builtin_bit_cast(bf16x8, ffwd[((size_t)mt * KSF + ks) * 64 + ln]);
+            acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[i], 0, 0, 0);
+        }
+    }
+    const int h = ln >> 5, col = ln & 31, b = fct * 32 + col;
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+        const int mt = (w + kWaves * i) / CT;
+        floatx16 rr = acc[i];
+        if constexpr (YREG) {
+            rr -= yv[i];
+        } else if (b < nblk) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 y4 = *reinterpret_cast<const float4*>(
+                    yg + (size_t)b * MP + mt * 32 + 8 * q + 4 * h);
+                rr[4 * q] -= y4.x;
+                rr[4 * q + 1] -= y4.y;
+                rr[4 * q + 2] -= y4.z;
+                rr[4 * q + 3] -= y4.w;
+            }
+        }
+        Rb[((2 * mt) * CT + fct) * 64 + ln] = pack_bf16(rr, 0);
+        Rb[((2 * mt + 1) * CT + fct) * 64 + ln] = pack_bf16(rr, 1);
+    }
+}
+
+template <int N, int MP, int CT>
+__global__ __launch_bounds__(256, 1) void fista_bf16_kernel(const FusedTile* __restrict__ tiles,
+                                                           const int* __restrict__ qoff,
+                                                           const int* __restrict__ queue,
+                                                           int* __restrict__ counters) {
+    constexpr int RT = N / 32 / kWaves;          // 32-row groups of n owned per wave
+    constexpr int TT = (MP / 32) * CT;           // forward output tiles
+    constexpr int FT = (TT + kWaves - 1) / kWaves;
+    constexpr int KSF = N / 16, KSA = MP / 16;   // K steps of forward / adjoint
+    constexpr bool YREG = FT <= 2;               // keep y in registers
+    static_assert(RT >= 1 && (CT == 1 || CT == 2 || CT == 4), "unsupported class");
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    u16x8* Vb = reinterpret_cast<u16x8*>(lds);                            // [KSF][CT][64]
+    u16x8* Rb = reinterpret_cast<u16x8*>(lds + (size_t)KSF * CT * 1024);  // [KSA][CT][64]
+    __shared__ int s_tile;
+
+    const int tid = threadIdx.x, w = tid >> 6, ln = tid & 63, h = ln >> 5, col = ln & 31;
+    const int fct = w % CT;   // column tile of this wave's forward tiles (CT divides 4)
+    const int nft = (TT - w + kWaves - 1) / kWaves;   // forward tiles of this wave: FT or FT-1
+
+    for (;;) {
+        if (tid == 0) s_tile = next_tile(qoff, queue, counters);
+        __syncthreads();
+        const int t_id = s_tile;
+        __syncthreads();
+        if (t_id < 0) break;
+        const FusedTile tl = tiles[t_id];
+        const u16x8* __restrict__ ffwd = reinterpret_cast<const u16x8*>(tl.frag_fwd);
+        const u16x8* __restrict__ fadj = reinterpret_cast<const u16x8*>(tl.frag_adj);
+        const float inv_l = (float)(1.0 / tl.lip[0]);
+        const int T = tl.T;
+        const float* __restrict__ beta = tl.beta;
+
+        float tau[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            const int b = ct * 32 + col;
+            tau[ct] = b < tl.nblk ? tl.lam[b] * inv_l : 0.f;
+        }
+        floatx16 yv[YREG ? FT : 1];
+        if constexpr (YREG) {
+#pragma unroll
+            for (int i = 0; i < FT; ++i) {
+                const int t = w + kWaves * i;
+                const int mt = t / CT;
+                const int b = fct * 32 + col;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int m = mt * 32 + 8 * (r / 4) + 4 * h + (r % 4);
+                    yv[i][r] = (t < TT && b < tl.nblk) ? tl.y[(size_t)b * MP + m] : 0.f;
+                }
+            }
+        }
+        floatx16 sp[RT][CT], vv[RT][CT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                sp[rt][ct] = floatx16{};
+                vv[rt][ct] = floatx16{};
+                const int g = w * RT + rt;
+                const u16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+                Vb[((2 * g) * CT + ct) * 64 + ln] = z;
+                Vb[((2 * g + 1) * CT + ct) * 64 + ln] = z;
+            }
+        __syncthreads();
+
+        for (int k = 0; k < T; ++k) {
+            // ---- forward: P = A V, R = P - y  (nft tiles for this wave)
+            if (nft == FT) {
+                forward_tiles<N, MP, CT, FT, YREG>(ffwd, Vb, Rb, yv, tl.y, tl.nblk, w, ln, fct);
+            } else if constexpr (FT > 1) {
+                if (nft == FT - 1)
+                    forward_tiles<N, MP, CT, (FT > 1 ? FT - 1 : 1), YREG>(ffwd, Vb, Rb, yv, tl.y,
+                                                                         tl.nblk, w, ln, fct);
+            }
+            __syncthreads();
+            // ---- adjoint: G = A^T R, then threshold + momentum on registers
+            const float bk = beta[k];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                const int g = w * RT + rt;
+                floatx16 ga[CT];
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) ga[ct] = floatx16{};
+#pragma unroll 2
+                for (int ks = 0; ks < KSA; ++ks) {
+                    const bf16x8 a =
+                        __builtin_bit_cast(bf16x8, fadj[((size_t)g * KSA + ks) * 64 + ln]);
+#pragma unroll
+                    for (int ct = 0; ct < CT; ++ct) {
+                        const bf16x8 b = __builtin_bit_cast(bf16x8, Rb[(ks * CT + ct) * 64 + ln]);
+                        ga[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, ga[ct], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) {
+                    const float tc = tau[ct];
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const float u = fmaf(-ga[ct][r], inv_l, vv[rt][ct][r]);
+                        const float sn = u - __builtin_amdgcn_fmed3f(u, -tc, tc);
+                        vv[rt][ct][r] = fmaf(bk, sn - sp[rt][ct][r], sn);
+                        sp[rt][ct][r] = sn;
+                    }
+                    Vb[((2 * g) * CT + ct) * 64 + ln] = pack_bf16(vv[rt][ct], 0);
+                    Vb[((2 * g + 1) * CT + ct) * 64 + ln] = pack_bf16(vv[rt][ct], 1);
+                }
+            }
+            __syncthreads();
+        }
+        // ---- write s_T
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const int b = ct * 32 + col;
+                if (b < tl.nblk) {
+                    float* dst = tl.s + (size_t)b * N + (w * RT + rt) * 32 + 4 * h;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const floatx16& a = sp[rt][ct];
+                        *reinterpret_cast<float4*>(dst + 8 * q) =
+                            make_float4(a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]);
+                    }
+                }
+            }
+    }
+}
+
+template <int N, int MP, int CT>
+static void launch_class(const FusedTile* tiles, const int* qoff, const int* queue, int* counters,
+                         int grid, hipStream_t st) {
+    const size_t lds = (size_t)(N / 16) * CT * 1024 + (size_t)(MP / 16) * CT * 1024;
+    static bool attr_set = false;
+    if (!attr_set) {
+        CSV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&fista_bf16_kernel<N, MP, CT>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = true;
+    }
+    fista_bf16_kernel<N, MP, CT><<<dim3(grid), dim3(256), lds, st>>>(tiles, qoff, queue,
+                                                                     counters);
+    CSV_HIP(hipGetLastError());
+}
+
+void launch_fista_bf16_class(int n, int Mp, const FusedTile* tiles, const int* qoff,
+                             const int* queue, int* counters, int grid, hipStream_t st) {
+#define CSV_CLASS(NN, MM)                                                                   \
+    if (n == NN && Mp == MM) {                                                              \
+        launch_class<NN, MM, (NN == 1024 ? 1 : (MM <= 64 ? 4 : 2))>(tiles, qoff, queue,     \
+                                                                   counters, grid, st);     \
+        return;                                                                             \
+    }
+    CSV_CLASS(256, 32)
+    CSV_CLASS(256, 64)
+    CSV_CLASS(256, 96)
+    CSV_CLASS(256, 128)
+    CSV_CLASS(1024, 64)
+    CSV_CLASS(1024, 128)
+    CSV_CLASS(1024, 224)
+    CSV_CLASS(1024, 256)
+    CSV_CLASS(1024, 416)
+#undef CSV_CLASS
+    throw Error{CSV_EUNSUPPORTED, "fused BF16 recovery has no kernel for n=" + std::to_string(n) +
+                                      ", padded M=" + std::to_string(Mp)};
+}
+
+bool fused_class_supported(int n, int Mp) {
+    static const int classes[][2] = {{256, 32},  {256, 64},   {256, 96},   {256, 128}, {1024, 64},
+                                     {1024, 128}, {1024, 224}, {1024, 256}, {1024, 416}};
+    for (const auto& c : classes)
+        if (c[0] == n && c[1] == Mp) return true;
+    return false;
 }
 
 }  // namespace csv

@@ -1,0 +1,126 @@
+"""Parity of the fused BF16 recovery (BF16 MFMA products, FP32 accumulation
+and iterates) against the FP64 oracle.
+
+Tolerances: per CS frame PSNR within 0.1 dB of the oracle's; recovered float
+frames within 4 grey levels; FP64 objective within 1e-2 relative.  BF16 keeps
+8 significant bits in the operator and in the two product operands, and the
+objective at the recovered point is 1-2 orders of magnitude more sensitive
+than the pixels.  Batched decoding must reproduce each GOP decoded alone bit
+for bit (the tile shape of a block does not depend on the batch)."""
+import numpy as np
+import pytest
+
+import synthvid as sv
+from oracle import codec, cs, philox
+from tests.gpu_util import announce, ctx, dev, host, psnr  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+PSNR_TOL = 0.1
+MAXABS_TOL = 4.0
+
+
+def _bf16(spec, **kw):
+    import paper_1311_1419_amd as P
+    return P.Params.from_spec(spec, precision=P.CSV_BF16, **kw)
+
+
+CASES = [
+    (sv.qcif_tiny(), "qcif-b16-m64"),
+    (sv.cif_sweep(4, 0.1), "cif-b16-m26"),
+    (sv.cif_sweep(4, 0.3), "cif-b16-m77"),
+    (sv.cif_sweep(4, 0.5), "cif-b16-m128"),
+    (sv.vga_precision(0.1, gop=3), "vga-b32-m102"),
+    (sv.vga_precision(0.25, gop=3), "vga-b32-m256"),
+    (sv.qcif_tiny().with_(block=32, m=205, gop=3, iters=300), "qcif-b32-m205-padded"),
+    (sv.qcif_tiny().with_(block=32, m=410, gop=2, iters=300), "qcif-b32-m410-padded"),
+    (sv.qcif_tiny().with_(block=32, m=51, gop=3, iters=300), "qcif-b32-m51-padded"),
+]
+
+
+@pytest.mark.parametrize("spec", [c[0] for c in CASES], ids=[c[1] for c in CASES])
+def test_decode_bf16_matches_oracle(ctx, spec):
+    announce(f"decode bf16 {spec.width}x{spec.height} G={spec.gop} B={spec.block} M={spec.m}")
+    frames = spec.video()
+    op = codec.Params.from_spec(spec)
+    ref = codec.decode_gop(codec.encode_gop(frames, op), op)
+    p = _bf16(spec)
+    gs = ctx.encode_gop(dev(frames), p)
+    out, fl, obj = ctx.decode_gop(gs, p, want_float=True, want_obj=True)
+    out, fl, obj = host(out), host(fl), host(obj)
+    assert np.array_equal(out[0], ref.frames[0])
+    for t in range(1, spec.gop):
+        err = np.max(np.abs(fl[t - 1].astype(np.float64) - ref.cs_float[t - 1]))
+        assert err <= MAXABS_TOL, f"frame {t}: max abs {err}"
+        dp = abs(psnr(frames[t], out[t]) - psnr(frames[t], ref.frames[t]))
+        assert dp <= PSNR_TOL, f"frame {t}: PSNR differs by {dp}"
+    rel = np.abs(obj[..., 0] - ref.objective) / np.maximum(ref.objective, 1e-300)
+    assert np.max(rel) <= 1e-2
+
+
+def test_bf16_batch_equals_alone(ctx):
+    """Each GOP decoded inside a mixed batch (several streams, sizes, M,
+    block sizes and tile classes) equals the GOP decoded alone."""
+    announce("bf16 batch vs alone")
+    specs = [sv.qcif_tiny(), sv.cif_sweep(4, 0.1, stream=1), sv.vga_precision(0.25, gop=2, stream=2),
+             sv.qcif_tiny().with_(block=32, m=102, stream_id=9, phi_seed=99),
+             sv.cif_sweep(4, 0.1, stream=3)]
+    items = []
+    for spec in specs:
+        p = _bf16(spec)
+        items.append((ctx.encode_gop(dev(spec.video()), p), p))
+    alone = [tuple(host(x) for x in ctx.decode_gop(gs, p, want_float=True)[:2]) for gs, p in items]
+    mixed = ctx.decode_batch(items, want_float=True)
+    for (fa, fla), (fm, flm, _) in zip(alone, mixed):
+        assert np.array_equal(fa, host(fm))
+        assert np.array_equal(fla, host(flm))
+
+
+def test_bf16_deterministic_and_zero_residual(ctx):
+    announce("bf16 determinism + zero residual")
+    spec = sv.cif_sweep(4, 0.25)
+    p = _bf16(spec)
+    gs = ctx.encode_gop(dev(spec.video()), p)
+    a = host(ctx.decode_gop(gs, p, want_float=True)[1])
+    b = host(ctx.decode_gop(gs, p, want_float=True)[1])
+    assert np.array_equal(a, b)
+    frames = spec.video(1)
+    key = host(ctx.key_decode(ctx.key_encode(dev(frames[0]))[0]))
+    z = np.stack([frames[0], key, key, key])
+    gz = ctx.encode_gop(dev(z), p)
+    out, fl, obj = ctx.decode_gop(gz, p, want_float=True, want_obj=True)
+    assert np.all(host(fl) == key[None].astype(np.float32))
+    assert np.all(host(obj) == 0)
+
+
+def test_bf16_full_size_sampled_blocks(ctx):
+    """640x480, GOP 16, B=32, M=256 (4500 blocks, the benchmark's shape):
+    the oracle recovers a sample of blocks one by one, including the last
+    (ragged) tile, and the GPU's pixels for those blocks must agree."""
+    announce("bf16 full-size vga g16 m256 sampled")
+    spec = sv.vga_precision(0.25)
+    frames = spec.video()
+    p = _bf16(spec)
+    gs = ctx.encode_gop(dev(frames), p)
+    out, fl, _ = ctx.decode_gop(gs, p, want_float=True)
+    fl = host(fl)
+    key = host(out)[0].astype(np.float64)
+    codes, exps = host(gs.codes), host(gs.exps)
+    q = philox.measurement_matrix_q(spec.m, spec.n, spec.phi_seed, spec.stream_id)
+    s_phi = philox.phi_scale(spec.m)
+    a = cs.operator(q, s_phi, spec.block)
+    L, _, _ = cs.lipschitz(q, s_phi)
+    nb = codes.shape[1]
+    rng = np.random.default_rng(0)
+    picks = [(t, int(b)) for t in (0, 7, 14) for b in rng.choice(nb, 5, replace=False)]
+    picks += [(14, nb - 1), (14, nb - 2)]
+    nbx = spec.width // spec.block
+    for t, b in picks:
+        y = cs.dequantise(codes[t, b][:, None], exps[t, b:b + 1], s_phi)
+        lam = cs.lambdas(a, y)
+        s_hat = cs.fista(a, y, lam, L, spec.iters)
+        x = cs.synthesise(s_hat, spec.block)[:, 0].reshape(spec.block, spec.block)
+        by, bx = divmod(b, nbx)
+        sl = (slice(by * 32, by * 32 + 32), slice(bx * 32, bx * 32 + 32))
+        ref = key[sl] + x
+        assert np.max(np.abs(fl[t][sl] - ref)) <= MAXABS_TOL, (t, b)
