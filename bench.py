@@ -1,0 +1,193 @@
+"""Benchmark: recovered Mpixel/s of the CS video decoder on one MI355X.
+
+Workload (one step): 16 synthetic 640x480 surveillance cameras, one GOP of
+16 frames each (1 key + 15 CS frames), 32x32 blocks (n = 1024), M/n = 0.25
+(M = 256), 300 FISTA iterations.  A step encodes the 16 GOPs (key-frame
+codec, closed-loop residual, measurement, quantiser) and decodes them as one
+batch (key frames, dequantisation, lambda, one fused recovery launch,
+synthesis, FP64 final objective).  Frames are resident in HBM before the
+timed region; per-stream measurement operators are built in the warm-up.
+
+Prints one JSON line.  `value` is the fused BF16 path; the plain FP32 path
+runs the same workload beside it for the BF16-vs-FP32 comparison and the
+PSNR loss.  The roofline object covers the fused recovery kernel, timed
+with HIP events on its own stream inside the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "recovered Mpixel/s at M/n=0.25, BF16-MFMA vs FP32, ≤0.1dB PSNR loss; p99 ms"
+PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
+WORKLOAD = "vga640x480-g16-b32-m256-t300-x16streams"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--streams", type=int, default=16)
+    ap.add_argument("--fp32-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--cpu-blocks", type=int, default=300,
+                    help="blocks the oracle recovers for the CPU baseline")
+    return ap.parse_args()
+
+
+def make_streams(n_streams):
+    import synthvid as sv
+    return [sv.vga_precision(0.25, stream=s) for s in range(n_streams)]
+
+
+def psnr(ref, test):
+    d = ref.astype(np.float64) - test.astype(np.float64)
+    mse = float(np.mean(d * d))
+    return 99.99 if mse == 0 else 10.0 * np.log10(255.0 ** 2 / mse)
+
+
+def run_path(ctx, P, torch, specs, frames_dev, precision, steps, warmup):
+    params = [P.Params.from_spec(s, precision=precision) for s in specs]
+    streams = [ctx.alloc_stream(p) for p in params]
+
+    def step():
+        for f, p, gs in zip(frames_dev, params, streams):
+            ctx.encode_gop(f, p, out=gs)
+        return ctx.decode_batch(list(zip(streams, params)), want_obj=True)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile_reset()
+    ctx.profile(True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = None
+    for a, b in evs:
+        a.record()
+        outs = step()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.profile(False)
+    per_step = [a.elapsed_time(b) for a, b in evs]
+    return wall, per_step, outs, streams
+
+
+def cpu_baseline(spec, gs_host, n_blocks):
+    """Oracle recovery of the first n_blocks CS blocks of one GOP (host)."""
+    from oracle import cs, philox
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    codes, exps = gs_host
+    codes = codes.reshape(-1, spec.m)[:n_blocks]
+    exps = exps.reshape(-1)[:n_blocks]
+    t0 = time.perf_counter()
+    q = philox.measurement_matrix_q(spec.m, spec.n, spec.phi_seed, spec.stream_id)
+    s_phi = philox.phi_scale(spec.m)
+    a = cs.operator(q, s_phi, spec.block)
+    L, _, _ = cs.lipschitz(q, s_phi)
+    y = cs.dequantise(codes.T, exps, s_phi)
+    lam = cs.lambdas(a, y)
+    s = cs.fista(a, y, lam, L, spec.iters)
+    cs.synthesise(s, spec.block)
+    dt = time.perf_counter() - t0
+    px = n_blocks * spec.n
+    return {"value": px / dt / 1e6, "unit": "Mpixel/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"FP64 oracle recovery (operator, step constant, lambda, {spec.iters} FISTA "
+                      f"iterations, synthesis) of {n_blocks} blocks of 32x32 at M=256 from one "
+                      f"640x480 GOP; {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path shards by stream/GOP with no exchange step, see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1311_1419_amd as P
+
+    specs = make_streams(args.streams)
+    videos = [s.video() for s in specs]
+    frames_dev = [torch.from_numpy(v).cuda() for v in videos]
+    px_per_step = sum((s.gop - 1) * s.height * s.width for s in specs)
+    blocks = sum((s.gop - 1) * ((s.height + 31) // 32) * ((s.width + 31) // 32) for s in specs)
+    flops_launch = sum((s.gop - 1) * ((s.height + 31) // 32) * ((s.width + 31) // 32)
+                       * 4.0 * s.m * s.n * s.iters for s in specs)
+
+    with P.Context(0) as ctx:
+        wall, per_step, outs, streams = run_path(ctx, P, torch, specs, frames_dev, P.CSV_BF16,
+                                                 args.steps, args.warmup)
+        k_ms, k_n = ctx.profile_query("fista_bf16")
+        torch.cuda.synchronize()
+        bf16_frames = [o[0].cpu().numpy() for o in outs]
+        codes_host = (streams[0].codes.cpu().numpy(), streams[0].exps.cpu().numpy())
+        fp32 = None
+        if not args.no_fp32:
+            w32, ps32, outs32, _ = run_path(ctx, P, torch, specs, frames_dev, P.CSV_FP32,
+                                            args.fp32_steps, 1)
+            f32_frames = [o[0].cpu().numpy() for o in outs32]
+            fp32 = {"value": px_per_step * args.fp32_steps / w32 / 1e6,
+                    "ms_per_step": 1e3 * w32 / args.fp32_steps}
+            loss = []
+            for v, fb, ff in zip(videos, bf16_frames, f32_frames):
+                for t in range(1, v.shape[0]):
+                    loss.append(psnr(v[t], ff[t]) - psnr(v[t], fb[t]))
+            fp32["psnr_loss_db_mean"] = float(np.mean(loss))
+            fp32["psnr_loss_db_max"] = float(np.max(loss))
+        mean_psnr = float(np.mean([psnr(v[t], fb[t]) for v, fb in zip(videos, bf16_frames)
+                                   for t in range(1, v.shape[0])]))
+
+    value = px_per_step * args.steps / wall / 1e6
+    avg_k_s = (k_ms / max(k_n, 1)) / 1e3
+    achieved = flops_launch / avg_k_s / 1e12 if k_n else None
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 4),
+        "p50_ms": round(float(np.percentile(per_step, 50)), 4),
+        "p99_ms": round(float(np.percentile(per_step, 99)), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "frame": "640x480", "gop": 16, "block": 32, "m": 256,
+                   "iters": 300, "streams_per_step": args.streams,
+                   "recovered_px_per_step": px_per_step, "blocks_per_step": blocks},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2) if achieved else None,
+                     "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_BF16_TFLOPS, 4) if achieved else None,
+                     "traffic": None, "kernel": "fista_bf16_kernel<1024,256,1>",
+                     "kernel_ms": round(1e3 * avg_k_s, 4), "flops_per_launch": flops_launch},
+        "fp32_path": fp32,
+        "mean_psnr_db_bf16": round(mean_psnr, 3),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(specs[0], codes_host, args.cpu_blocks)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

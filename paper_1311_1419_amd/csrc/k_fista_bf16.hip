@@ -7,8 +7,8 @@
 //   u = v - A^T (A v - y) / L;  s_k = soft(u, lam / L);
 //   v = s_k + beta_k (s_k - s_{k-1}).
 //
-// Layout.  A workgroup is four waves; wave w owns coefficient rows
-// [w n/4, (w+1) n/4) of every block of the tile and keeps s_{k-1} and v in
+// Layout.  A workgroup is eight waves (two per SIMD); wave w owns
+// coefficient rows [w n/8, (w+1) n/8) of every block of the tile and keeps s_{k-1} and v in
 // FP32 registers, in the 32x32 MFMA accumulator layout (lane l, register r:
 // row 8(r/4) + 4(l/32) + r%4 of a 32-row group, column l%32).  Per
 // iteration:
@@ -31,7 +31,7 @@
 
 namespace csv {
 
-constexpr int kWaves = 4;
+constexpr int kWaves = 8;
 
 // K index inside a 32-group carried by (K step s, lane half h, element e).
 __host__ __device__ inline int kappa(int s, int h, int e) {
@@ -95,69 +95,106 @@ __device__ inline int next_tile(const int* __restrict__ qoff, const int* __restr
     return -1;
 }
 
-// Forward product for the NF output tiles (mt_i, fct) of one wave,
-// mt_i = (w + 4 i) / CT, then R = P - y written to LDS as bf16.  y comes from
-// registers (yv) when YREG, else from global memory.
-template <int N, int MP, int CT, int NF, bool YREG>
-__device__ inline void forward_tiles(const u16x8* __restrict__ ffwd, const u16x8* Vb, u16x8* Rb,
-                                     const floatx16* yv, const float* __restrict__ yg, int nblk,
-                                     int w, int ln, int fct) {
-    constexpr int KSF = N / 16;
-    floatx16 acc[NF];
+// Ring depths (K steps of operator fragments in flight per wave).
+constexpr int kPF = 4;   // forward
+constexpr int kPA = 2;   // adjoint
+
+// Forward product for this wave's NF output tiles (mt_i, fct), mt_i =
+// (w + W i) / CT.  af holds the first kPF K steps on entry.  Returns the
+// accumulators; loads the first kPA adjoint steps into aa before the
+// forward accumulators are consumed.
+template <int N, int MP, int CT, int NF, int GR>
+__device__ inline void forward_tiles(u16x8 (&af)[kPF][NF], u16x8 (&aa)[kPA][GR],
+                                     floatx16 (&acc)[NF], const u16x8* __restrict__ ffwd,
+                                     const u16x8* __restrict__ fadj, const u16x8* Vb, int w,
+                                     int ln, int fct, int rt0) {
+    constexpr int KSF = N / 16, KSA = MP / 16;
 #pragma unroll
     for (int i = 0; i < NF; ++i) acc[i] = floatx16{};
-#pragma unroll 4
-    for (int ks = 0; ks < KSF; ++ks) {
-        const bf16x8 b = __builtin_bit_cast(bf16x8, Vb[(ks * CT + fct) * 64 + ln]);
+#pragma unroll 1
+    for (int ks0 = 0; ks0 < KSF; ks0 += kPF) {
+#pragma unroll
+        for (int j = 0; j < kPF; ++j) {
+            const int ks = ks0 + j;
+            const bf16x8 b = __builtin_bit_cast(bf16x8, Vb[(ks * CT + fct) * 64 + ln]);
+#pragma unroll
+            for (int i = 0; i < NF; ++i) {
+                acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[j][i]),
+                                                                 b, acc[i], 0, 0, 0);
+                if (ks + kPF < KSF) {
+                    const int mt = (w + kWaves * i) / CT;
+                    af[j][i] = ffwd[((size_t)mt * KSF + ks + kPF) * 64 + ln];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < kPA; ++p)
+#pragma unroll
+        for (int r = 0; r < GR; ++r)   // GR = distinct operator rows of the first group
+            aa[p][r] = fadj[((size_t)(rt0 + r / CT) * KSA + p) * 64 + ln];
+}
+
+template <int N, int MP, int CT, int NF>
+__device__ inline void load_fwd_head(u16x8 (&af)[kPF][NF], const u16x8* __restrict__ ffwd, int w,
+                                     int ln) {
+    constexpr int KSF = N / 16;
+#pragma unroll
+    for (int p = 0; p < kPF; ++p)
 #pragma unroll
         for (int i = 0; i < NF; ++i) {
             const int mt = (w + kWaves * i) / CT;
-            const bf16x8 a = __builtin_bit_cast(bf16x8, ffwd[((size_t)mt * KSF + ks) * 64 + ln]);
-            acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[i], 0, 0, 0);
+            af[p][i] = ffwd[((size_t)mt * KSF + p) * 64 + ln];
+        }
+}
+
+// R = P - y for one forward tile, written to LDS as bf16 (y from registers
+// or from global memory).
+template <int MP, int CT, bool YREG>
+__device__ inline void store_residual(const floatx16& acc, const floatx16& yv,
+                                      const float* __restrict__ yg, int nblk, int mt, int fct,
+                                      int ln, u16x8* Rb) {
+    const int h = ln >> 5, b = fct * 32 + (ln & 31);
+    floatx16 rr = acc;
+    if constexpr (YREG) {
+        rr -= yv;
+    } else if (b < nblk) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 y4 =
+                *reinterpret_cast<const float4*>(yg + (size_t)b * MP + mt * 32 + 8 * q + 4 * h);
+            rr[4 * q] -= y4.x;
+            rr[4 * q + 1] -= y4.y;
+            rr[4 * q + 2] -= y4.z;
+            rr[4 * q + 3] -= y4.w;
         }
     }
-    const int h = ln >> 5, col = ln & 31, b = fct * 32 + col;
-#pragma unroll
-    for (int i = 0; i < NF; ++i) {
-        const int mt = (w + kWaves * i) / CT;
-        floatx16 rr = acc[i];
-        if constexpr (YREG) {
-            rr -= yv[i];
-        } else if (b < nblk) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float4 y4 = *reinterpret_cast<const float4*>(
-                    yg + (size_t)b * MP + mt * 32 + 8 * q + 4 * h);
-                rr[4 * q] -= y4.x;
-                rr[4 * q + 1] -= y4.y;
-                rr[4 * q + 2] -= y4.z;
-                rr[4 * q + 3] -= y4.w;
-            }
-        }
-        Rb[((2 * mt) * CT + fct) * 64 + ln] = pack_bf16(rr, 0);
-        Rb[((2 * mt + 1) * CT + fct) * 64 + ln] = pack_bf16(rr, 1);
-    }
+    Rb[((2 * mt) * CT + fct) * 64 + ln] = pack_bf16(rr, 0);
+    Rb[((2 * mt + 1) * CT + fct) * 64 + ln] = pack_bf16(rr, 1);
 }
 
 template <int N, int MP, int CT>
-__global__ __launch_bounds__(256, 1) void fista_bf16_kernel(const FusedTile* __restrict__ tiles,
-                                                           const int* __restrict__ qoff,
-                                                           const int* __restrict__ queue,
-                                                           int* __restrict__ counters) {
-    constexpr int RT = N / 32 / kWaves;          // 32-row groups of n owned per wave
+__global__ __launch_bounds__(64 * kWaves, 1) void fista_bf16_kernel(
+    const FusedTile* __restrict__ tiles, const int* __restrict__ qoff,
+    const int* __restrict__ queue, int* __restrict__ counters) {
+    constexpr int W = kWaves;
+    constexpr int RT = N / 32 / W;               // 32-row groups of n owned per wave
+    constexpr int NG = RT * CT / 2;              // adjoint groups of two accumulator tiles
+    constexpr int AR = CT == 1 ? 2 : 1;          // distinct operator rows per group
     constexpr int TT = (MP / 32) * CT;           // forward output tiles
-    constexpr int FT = (TT + kWaves - 1) / kWaves;
+    constexpr int FT = (TT + W - 1) / W;         // forward tiles per wave (max)
     constexpr int KSF = N / 16, KSA = MP / 16;   // K steps of forward / adjoint
-    constexpr bool YREG = FT <= 2;               // keep y in registers
-    static_assert(RT >= 1 && (CT == 1 || CT == 2 || CT == 4), "unsupported class");
+    constexpr bool YREG = false;                 // y read from L2 in the epilogue (registers are the limit)
+    static_assert(RT * CT >= 2 && (RT * CT) % 2 == 0 && W % CT == 0, "unsupported class");
+    static_assert(KSF % kPF == 0 && KSA % kPA == 0, "ring depth must divide the K steps");
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     u16x8* Vb = reinterpret_cast<u16x8*>(lds);                            // [KSF][CT][64]
     u16x8* Rb = reinterpret_cast<u16x8*>(lds + (size_t)KSF * CT * 1024);  // [KSA][CT][64]
     __shared__ int s_tile;
 
     const int tid = threadIdx.x, w = tid >> 6, ln = tid & 63, h = ln >> 5, col = ln & 31;
-    const int fct = w % CT;   // column tile of this wave's forward tiles (CT divides 4)
-    const int nft = (TT - w + kWaves - 1) / kWaves;   // forward tiles of this wave: FT or FT-1
+    const int fct = w % CT;                      // column tile of this wave's forward tiles
+    const int nft = (TT - w + W - 1) / W;        // forward tiles of this wave: FT, FT-1 or 0
 
     for (;;) {
         if (tid == 0) s_tile = next_tile(qoff, queue, counters);
@@ -182,7 +219,7 @@ __global__ __launch_bounds__(256, 1) void fista_bf16_kernel(const FusedTile* __r
         if constexpr (YREG) {
 #pragma unroll
             for (int i = 0; i < FT; ++i) {
-                const int t = w + kWaves * i;
+                const int t = w + W * i;
                 const int mt = t / CT;
                 const int b = fct * 32 + col;
 #pragma unroll
@@ -204,48 +241,95 @@ __global__ __launch_bounds__(256, 1) void fista_bf16_kernel(const FusedTile* __r
                 Vb[((2 * g) * CT + ct) * 64 + ln] = z;
                 Vb[((2 * g + 1) * CT + ct) * 64 + ln] = z;
             }
+        u16x8 af[kPF][FT];
+        u16x8 aa[kPA][AR];
+        if (nft == FT) load_fwd_head<N, MP, CT, FT>(af, ffwd, w, ln);
         __syncthreads();
 
         for (int k = 0; k < T; ++k) {
             // ---- forward: P = A V, R = P - y  (nft tiles for this wave)
             if (nft == FT) {
-                forward_tiles<N, MP, CT, FT, YREG>(ffwd, Vb, Rb, yv, tl.y, tl.nblk, w, ln, fct);
-            } else if constexpr (FT > 1) {
-                if (nft == FT - 1)
-                    forward_tiles<N, MP, CT, (FT > 1 ? FT - 1 : 1), YREG>(ffwd, Vb, Rb, yv, tl.y,
-                                                                         tl.nblk, w, ln, fct);
-            }
-            __syncthreads();
-            // ---- adjoint: G = A^T R, then threshold + momentum on registers
-            const float bk = beta[k];
+                floatx16 acc[FT];
+                forward_tiles<N, MP, CT, FT, AR>(af, aa, acc, ffwd, fadj, Vb, w, ln, fct, w * RT);
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-                const int g = w * RT + rt;
-                floatx16 ga[CT];
+                for (int i = 0; i < FT; ++i)
+                    store_residual<MP, CT, YREG>(acc[i], yv[YREG ? i : 0], tl.y, tl.nblk,
+                                                 (w + W * i) / CT, fct, ln, Rb);
+            } else {
+                bool done = false;
+                if constexpr (FT > 1) {
+                    if (nft == FT - 1) {
+                        u16x8 af2[kPF][FT - 1];
+                        floatx16 acc[FT - 1];
+                        load_fwd_head<N, MP, CT, FT - 1>(af2, ffwd, w, ln);
+                        forward_tiles<N, MP, CT, FT - 1, AR>(af2, aa, acc, ffwd, fadj, Vb, w, ln,
+                                                             fct, w * RT);
 #pragma unroll
-                for (int ct = 0; ct < CT; ++ct) ga[ct] = floatx16{};
-#pragma unroll 2
-                for (int ks = 0; ks < KSA; ++ks) {
-                    const bf16x8 a =
-                        __builtin_bit_cast(bf16x8, fadj[((size_t)g * KSA + ks) * 64 + ln]);
-#pragma unroll
-                    for (int ct = 0; ct < CT; ++ct) {
-                        const bf16x8 b = __builtin_bit_cast(bf16x8, Rb[(ks * CT + ct) * 64 + ln]);
-                        ga[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, ga[ct], 0, 0, 0);
+                        for (int i = 0; i < FT - 1; ++i)
+                            store_residual<MP, CT, YREG>(acc[i], yv[YREG ? i : 0], tl.y, tl.nblk,
+                                                         (w + W * i) / CT, fct, ln, Rb);
+                        done = true;
                     }
                 }
+                if (!done) {
 #pragma unroll
-                for (int ct = 0; ct < CT; ++ct) {
+                    for (int p = 0; p < kPA; ++p)
+#pragma unroll
+                        for (int r = 0; r < AR; ++r)
+                            aa[p][r] = fadj[((size_t)(w * RT + r / CT) * KSA + p) * 64 + ln];
+                }
+            }
+            __syncthreads();
+            // ---- adjoint G = A^T R over the wave's RT x CT accumulator tiles,
+            //      two at a time (items u = 2g, 2g+1 of the row-major (rt, ct)
+            //      list); threshold and momentum on the accumulators; new V
+            //      to LDS
+            const float bk = beta[k];
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                        const int rt0 = (2 * g) / CT, ct0 = (2 * g) % CT;
+                const int rt1 = (2 * g + 1) / CT, ct1 = (2 * g + 1) % CT;
+                floatx16 ga[2] = {floatx16{}, floatx16{}};
+#pragma unroll 1
+                for (int ks0 = 0; ks0 < KSA; ks0 += kPA) {
+#pragma unroll
+                    for (int j = 0; j < kPA; ++j) {
+                        const int ks = ks0 + j;
+                        const bf16x8 b0 = __builtin_bit_cast(bf16x8, Rb[(ks * CT + ct0) * 64 + ln]);
+                        const bf16x8 b1 =
+                            ct1 == ct0 ? b0
+                                       : __builtin_bit_cast(bf16x8, Rb[(ks * CT + ct1) * 64 + ln]);
+                        const bf16x8 a0 = __builtin_bit_cast(bf16x8, aa[j][0]);
+                        const bf16x8 a1 = AR == 2 ? __builtin_bit_cast(bf16x8, aa[j][AR - 1]) : a0;
+                        ga[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, ga[0], 0, 0, 0);
+                        ga[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, ga[1], 0, 0, 0);
+                        // fragments kPA steps ahead: this group, else the next group
+                        const bool same = ks + kPA < KSA;
+                        const int nks = same ? ks + kPA : ks + kPA - KSA;
+                        const int ng = same ? g : g + 1;
+                        if (ng < NG) {
+#pragma unroll
+                            for (int r = 0; r < AR; ++r)
+                                aa[j][r] =
+                                    fadj[((size_t)(w * RT + (2 * ng + r) / CT) * KSA + nks) * 64 + ln];
+                        }
+                    }
+                }
+                if (g == NG - 1 && nft == FT) load_fwd_head<N, MP, CT, FT>(af, ffwd, w, ln);
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int rt = e ? rt1 : rt0, ct = e ? ct1 : ct0;
+                    const int gg = w * RT + rt;
                     const float tc = tau[ct];
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
-                        const float u = fmaf(-ga[ct][r], inv_l, vv[rt][ct][r]);
+                        const float u = fmaf(-ga[e][r], inv_l, vv[rt][ct][r]);
                         const float sn = u - __builtin_amdgcn_fmed3f(u, -tc, tc);
                         vv[rt][ct][r] = fmaf(bk, sn - sp[rt][ct][r], sn);
                         sp[rt][ct][r] = sn;
                     }
-                    Vb[((2 * g) * CT + ct) * 64 + ln] = pack_bf16(vv[rt][ct], 0);
-                    Vb[((2 * g + 1) * CT + ct) * 64 + ln] = pack_bf16(vv[rt][ct], 1);
+                    Vb[((2 * gg) * CT + ct) * 64 + ln] = pack_bf16(vv[rt][ct], 0);
+                    Vb[((2 * gg + 1) * CT + ct) * 64 + ln] = pack_bf16(vv[rt][ct], 1);
                 }
             }
             __syncthreads();
@@ -279,8 +363,8 @@ static void launch_class(const FusedTile* tiles, const int* qoff, const int* que
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set = true;
     }
-    fista_bf16_kernel<N, MP, CT><<<dim3(grid), dim3(256), lds, st>>>(tiles, qoff, queue,
-                                                                     counters);
+    fista_bf16_kernel<N, MP, CT><<<dim3(grid), dim3(64 * kWaves), lds, st>>>(tiles, qoff, queue,
+                                                                             counters);
     CSV_HIP(hipGetLastError());
 }
 
