@@ -416,11 +416,16 @@ void launch_synth(const float* s, const float* dct, const uint8_t* key, int W, i
 
 // ------------------------------------------------------- FP64 final check
 // Per block: r = A s - y^ with y^ = s_phi c 2^e recomputed exactly in FP64;
-// obj = 1/2 ||r||^2 + lam ||s||_1 and ||r|| / ||y^||.  A workgroup takes 16
-// blocks (coefficients staged in LDS); lane m of a wave owns row m and reads
-// the transposed operator A^T (n x Mp) coalesced.
-constexpr int F64_BLK = 16;
+// obj = 1/2 ||r||^2 + lam ||s||_1 and ||r|| / ||y^||.  The product A s runs
+// on FP64 MFMA (16x16x4): a workgroup owns 16 blocks (one MFMA column tile)
+// and all padded rows; wave w takes row tiles w, w+4, ...  Coefficients are
+// staged in LDS as FP64 in K chunks of 64; A comes from the transposed copy
+// A^T (n x Mp), read four 128-byte rows per fragment.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+constexpr int F64_BLK = 16, F64_KC = 32;
 
+// RTW: row tiles (of 16) per wave, ceil(Mp / 64).
+template <int RTW>
 __global__ __launch_bounds__(256) void final64_kernel(const double* __restrict__ a64t,
                                                      const float* __restrict__ s,
                                                      const int8_t* __restrict__ codes,
@@ -428,65 +433,88 @@ __global__ __launch_bounds__(256) void final64_kernel(const double* __restrict__
                                                      const float* __restrict__ lam, int nblk,
                                                      int M, int Mp, int n, double s_phi,
                                                      double* __restrict__ obj) {
-    extern __shared__ float Sx[];   // [F64_BLK][n]
-    __shared__ double red_r[4][F64_BLK], red_y[4][F64_BLK], red_l1[4][F64_BLK];
+    __shared__ double Sd[F64_KC][F64_BLK];
+    __shared__ double red[3][4][F64_BLK];
     const int b0 = blockIdx.x * F64_BLK;
     const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
-    const int nloc = min(F64_BLK, nblk - b0);
-    for (int i = tid; i < F64_BLK * n; i += 256) {
-        const int j = i / n;
-        Sx[i] = j < nloc ? s[(size_t)(b0 + j) * n + (i - j * n)] : 0.f;
-    }
-    __syncthreads();
-    double rr[F64_BLK] = {}, yy[F64_BLK] = {}, l1[F64_BLK] = {};
-    for (int m0 = wv * 64; m0 < M; m0 += 256) {
-        const int m = m0 + ln;
-        double acc[F64_BLK] = {};
-        if (m < M) {
-            for (int k = 0; k < n; ++k) {
-                const double a = a64t[(size_t)k * Mp + m];
+    const int j = ln & 15, kq = ln >> 4;   // MFMA column (block) and K quarter
+    const int nrt = Mp / 16;
+    doublex4 acc[RTW];
 #pragma unroll
-                for (int j = 0; j < F64_BLK; ++j) acc[j] = fma(a, (double)Sx[j * n + k], acc[j]);
+    for (int i = 0; i < RTW; ++i) acc[i] = doublex4{0.0, 0.0, 0.0, 0.0};
+    double l1 = 0.0;   // sum |s| over the staged entries of this thread
+    const int sb = tid >> 4, sk = (tid & 15) * 2;   // staging: block sb, k sk, sk+1
+    for (int k0 = 0; k0 < n; k0 += F64_KC) {
+        // issue every operator load of the chunk first (latency overlap)
+        double av[F64_KC / 4][RTW];
+#pragma unroll
+        for (int kk = 0; kk < F64_KC / 4; ++kk) {
+            const size_t krow = (size_t)(k0 + 4 * kk + kq) * Mp;
+#pragma unroll
+            for (int i = 0; i < RTW; ++i) {
+                const int rt = wv + 4 * i;
+                av[kk][i] = rt < nrt ? a64t[krow + rt * 16 + j] : 0.0;
             }
+        }
+        float2 v = make_float2(0.f, 0.f);
+        if (b0 + sb < nblk) v = *reinterpret_cast<const float2*>(s + (size_t)(b0 + sb) * n + k0 + sk);
+        __syncthreads();
+        Sd[sk + 0][sb] = v.x;
+        Sd[sk + 1][sb] = v.y;
+        l1 += fabs((double)v.x) + fabs((double)v.y);
+        __syncthreads();
 #pragma unroll
-            for (int j = 0; j < F64_BLK; ++j) {
-                if (j < nloc) {
-                    const double yh = s_phi * ldexp((double)codes[(size_t)(b0 + j) * M + m],
-                                                    (int)exps[b0 + j]);
-                    const double r = acc[j] - yh;
-                    rr[j] += r * r;
-                    yy[j] += yh * yh;
+        for (int kk = 0; kk < F64_KC / 4; ++kk) {
+            const double bv = Sd[4 * kk + kq][j];
+#pragma unroll
+            for (int i = 0; i < RTW; ++i)
+                acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk][i], bv, acc[i], 0, 0, 0);
+        }
+    }
+    // D layout (FP64 16x16x4): lane j + 16 q, register r holds row q + 4 r, column j
+    double rr = 0.0, yy = 0.0;
+    const int b = b0 + j;
+    if (b < nblk) {
+        const int e = exps[b];
+#pragma unroll
+        for (int i = 0; i < RTW; ++i) {
+            const int rt = wv + 4 * i;
+            if (rt < nrt) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = rt * 16 + kq + 4 * r;
+                    if (m < M) {
+                        const double yh = s_phi * ldexp((double)codes[(size_t)b * M + m], e);
+                        const double d = acc[i][r] - yh;
+                        rr += d * d;
+                        yy += yh * yh;
+                    }
                 }
             }
         }
     }
-    for (int k = tid; k < n; k += 256) {
+    // lanes j, j+16, j+32, j+48 share column j
+    rr += __shfl_xor(rr, 16);
+    rr += __shfl_xor(rr, 32);
+    yy += __shfl_xor(yy, 16);
+    yy += __shfl_xor(yy, 32);
+    // staging threads 16 sb .. 16 sb + 15 summed |s| of block sb
+    double l1w = l1;
 #pragma unroll
-        for (int j = 0; j < F64_BLK; ++j) l1[j] += fabs((double)Sx[j * n + k]);
-    }
-#pragma unroll
-    for (int j = 0; j < F64_BLK; ++j) {
-        double a = rr[j], b = yy[j], c = l1[j];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            a += __shfl_down(a, off);
-            b += __shfl_down(b, off);
-            c += __shfl_down(c, off);
-        }
-        if (ln == 0) {
-            red_r[wv][j] = a;
-            red_y[wv][j] = b;
-            red_l1[wv][j] = c;
-        }
-    }
+    for (int off = 8; off > 0; off >>= 1) l1w += __shfl_xor(l1w, off);
     __syncthreads();
-    if (tid < nloc) {
-        const int j = tid;
-        const double r2 = red_r[0][j] + red_r[1][j] + red_r[2][j] + red_r[3][j];
-        const double y2 = red_y[0][j] + red_y[1][j] + red_y[2][j] + red_y[3][j];
-        const double a1 = red_l1[0][j] + red_l1[1][j] + red_l1[2][j] + red_l1[3][j];
-        obj[(size_t)(b0 + j) * 2 + 0] = 0.5 * r2 + (double)lam[b0 + j] * a1;
-        obj[(size_t)(b0 + j) * 2 + 1] = y2 > 0.0 ? sqrt(r2) / sqrt(y2) : 0.0;
+    if (ln < 16) {
+        red[0][wv][ln] = rr;
+        red[1][wv][ln] = yy;
+    }
+    if ((tid & 15) == 0) red[2][0][sb] = l1w;   // 16 blocks, one writer each
+    __syncthreads();
+    if (tid < F64_BLK && b0 + tid < nblk) {
+        const int bb = b0 + tid;
+        const double r2 = red[0][0][tid] + red[0][1][tid] + red[0][2][tid] + red[0][3][tid];
+        const double y2 = red[1][0][tid] + red[1][1][tid] + red[1][2][tid] + red[1][3][tid];
+        obj[(size_t)bb * 2 + 0] = 0.5 * r2 + (double)lam[bb] * red[2][0][tid];
+        obj[(size_t)bb * 2 + 1] = y2 > 0.0 ? sqrt(r2) / sqrt(y2) : 0.0;
     }
 }
 
@@ -494,16 +522,19 @@ void launch_final64(const double* a64t, const float* s, const int8_t* codes, con
                     const float* lam, int nblk, int M, int Mp, int n, double s_phi, double* obj,
                     hipStream_t st) {
     if (nblk <= 0) return;
-    const size_t lds = (size_t)F64_BLK * n * sizeof(float);
-    static bool attr_set = false;
-    if (!attr_set) {
-        CSV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&final64_kernel),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    F64_BLK * 1024 * (int)sizeof(float)));
-        attr_set = true;
+    const int rtw = ceil_div(Mp, 64);
+    CSV_REQUIRE(rtw <= 7 && n % F64_KC == 0, CSV_EUNSUPPORTED,
+                "final FP64 check: padded M above 448 or n not a multiple of 32");
+    const dim3 grid(ceil_div(nblk, F64_BLK)), block(256);
+    switch (rtw) {
+#define CSV_F64(R)                                                                      \
+    case R:                                                                             \
+        final64_kernel<R><<<grid, block, 0, st>>>(a64t, s, codes, exps, lam, nblk, M, Mp, n, \
+                                                   s_phi, obj);                          \
+        break;
+        CSV_F64(1) CSV_F64(2) CSV_F64(3) CSV_F64(4) CSV_F64(5) CSV_F64(6) CSV_F64(7)
+#undef CSV_F64
     }
-    final64_kernel<<<dim3(ceil_div(nblk, F64_BLK)), dim3(256), lds, st>>>(
-        a64t, s, codes, exps, lam, nblk, M, Mp, n, s_phi, obj);
     CSV_HIP(hipGetLastError());
 }
 

@@ -83,11 +83,15 @@ __device__ inline int int_dct_entry(int k, int i) {
 __device__ inline int ue_len(unsigned v) { return 2 * (31 - __clz(v + 1)) + 1; }
 __device__ inline int se_len(int v) { return ue_len(2u * (unsigned)abs(v) - (v > 0 ? 1u : 0u)); }
 
-// One wave per 8x8 block, four blocks per workgroup.  Lane = pixel (r, c),
-// then coefficient (k, l).  Z = T X T^T is exact in 64-bit integers; level
-// = sgn(Z) ((|Z| + 2^(s-1)) >> s) with s = 20 + log2(step).  Bits: the
-// nonzero mask in zigzag order comes from one ballot; each nonzero adds
-// ue(run) + se(level), the block adds ue(nnz).
+// One wave per 8x8 block, four waves per workgroup, each wave looping over
+// kKeyBlocksPerWave blocks.  Lane = pixel (r, c), then coefficient (k, l).
+// Z = T X T^T is exact in 64-bit integers; level = sgn(Z) ((|Z| + 2^(s-1))
+// >> s) with s = 20 + log2(step).  Bits: the nonzero mask in zigzag order
+// comes from one ballot; each nonzero adds ue(run) + se(level), the block
+// adds ue(nnz).  The workgroup sums its bits in LDS and adds them to the
+// frame total with one atomic.
+constexpr int kKeyBlocksPerWave = 4;
+
 __global__ __launch_bounds__(256) void key_encode_kernel(const uint8_t* __restrict__ frame, int W,
                                                         int H, int qshift,
                                                         int16_t* __restrict__ levels,
@@ -96,48 +100,57 @@ __global__ __launch_bounds__(256) void key_encode_kernel(const uint8_t* __restri
     __shared__ int X[4][64];
     __shared__ int Y[4][64];
     __shared__ int Lv[4][64];
+    __shared__ int wbits[4];
     const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
     if (tid < 64) T[tid] = int_dct_entry(tid >> 3, tid & 7);
     const int bpr = W / 8, nblk = bpr * (H / 8);
-    const int blk = blockIdx.x * 4 + wv;
-    const bool live = blk < nblk;
-    const int by = live ? blk / bpr : 0, bx = live ? blk % bpr : 0;
     const int r = ln >> 3, c = ln & 7;
-    X[wv][ln] = live ? (int)frame[(size_t)(by * 8 + r) * W + bx * 8 + c] - 128 : 0;
-    __syncthreads();
-    int y = 0;   // Y[k = r][c] = sum_i T[k][i] X[i][c]
+    int acc_bits = 0;
+    for (int it = 0; it < kKeyBlocksPerWave; ++it) {
+        const int blk = (blockIdx.x * kKeyBlocksPerWave + it) * 4 + wv;
+        const bool live = blk < nblk;
+        const int by = live ? blk / bpr : 0, bx = live ? blk % bpr : 0;
+        __syncthreads();   // previous round's LDS reads are done
+        X[wv][ln] = live ? (int)frame[(size_t)(by * 8 + r) * W + bx * 8 + c] - 128 : 0;
+        __syncthreads();
+        int y = 0;   // Y[k = r][c] = sum_i T[k][i] X[i][c]
 #pragma unroll
-    for (int i = 0; i < 8; ++i) y += T[r * 8 + i] * X[wv][i * 8 + c];
-    Y[wv][ln] = y;
-    __syncthreads();
-    long long z = 0;   // Z[k = r][l = c] = sum_j Y[k][j] T[l][j]
+        for (int i = 0; i < 8; ++i) y += T[r * 8 + i] * X[wv][i * 8 + c];
+        Y[wv][ln] = y;
+        __syncthreads();
+        long long z = 0;   // Z[k = r][l = c] = sum_j Y[k][j] T[l][j]
 #pragma unroll
-    for (int j = 0; j < 8; ++j) z += (long long)Y[wv][r * 8 + j] * T[c * 8 + j];
-    const long long az = z < 0 ? -z : z;
-    int lev = (int)((az + (1ll << (qshift - 1))) >> qshift);
-    if (z < 0) lev = -lev;
-    if (live) levels[(size_t)(by * 8 + r) * W + bx * 8 + c] = (int16_t)lev;
-    Lv[wv][ln] = lev;
-    __syncthreads();
-    const int v = Lv[wv][kZigzag[ln]];   // lane = zigzag index
-    const unsigned long long mask = __ballot(v != 0);
-    int b = 0;
-    if (v != 0) {
-        const unsigned long long below = mask & ((1ull << ln) - 1ull);
-        const int prev = below ? 63 - __clzll(below) : -1;
-        b = ue_len((unsigned)(ln - prev - 1)) + se_len(v);
+        for (int j = 0; j < 8; ++j) z += (long long)Y[wv][r * 8 + j] * T[c * 8 + j];
+        const long long az = z < 0 ? -z : z;
+        int lev = (int)((az + (1ll << (qshift - 1))) >> qshift);
+        if (z < 0) lev = -lev;
+        if (live) levels[(size_t)(by * 8 + r) * W + bx * 8 + c] = (int16_t)lev;
+        Lv[wv][ln] = lev;
+        __syncthreads();
+        const int v = Lv[wv][kZigzag[ln]];   // lane = zigzag index
+        const unsigned long long mask = __ballot(v != 0);
+        int b = 0;
+        if (v != 0) {
+            const unsigned long long below = mask & ((1ull << ln) - 1ull);
+            const int prev = below ? 63 - __clzll(below) : -1;
+            b = ue_len((unsigned)(ln - prev - 1)) + se_len(v);
+        }
+        if (ln == 0) b += ue_len((unsigned)__popcll(mask));
+        if (live) acc_bits += b;
     }
-    if (ln == 0) b += ue_len((unsigned)__popcll(mask));
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) b += __shfl_down(b, off);
-    if (ln == 0 && live && bits) atomicAdd(bits, (unsigned long long)b);
+    for (int off = 32; off > 0; off >>= 1) acc_bits += __shfl_down(acc_bits, off);
+    if (ln == 0) wbits[wv] = acc_bits;
+    __syncthreads();
+    if (tid == 0 && bits)
+        atomicAdd(bits, (unsigned long long)(wbits[0] + wbits[1] + wbits[2] + wbits[3]));
 }
 
 void launch_key_encode(const uint8_t* frame, int W, int H, int qshift, int16_t* levels,
                        unsigned long long* bits, hipStream_t st) {
     const int nblk = (W / 8) * (H / 8);
-    key_encode_kernel<<<dim3(ceil_div(nblk, 4)), dim3(256), 0, st>>>(frame, W, H, qshift, levels,
-                                                                     bits);
+    key_encode_kernel<<<dim3(ceil_div(nblk, 4 * kKeyBlocksPerWave)), dim3(256), 0, st>>>(
+        frame, W, H, qshift, levels, bits);
     CSV_HIP(hipGetLastError());
 }
 
