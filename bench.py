@@ -40,8 +40,10 @@ def parse():
     ap.add_argument("--fp32-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--cpu-blocks", type=int, default=300,
+    ap.add_argument("--cpu-blocks", type=int, default=3000,
                     help="blocks the oracle recovers for the CPU baseline")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this size (counter calibration)")
     return ap.parse_args()
 
 
@@ -124,6 +126,12 @@ def main():
     import torch
     import paper_1311_1419_amd as P
 
+    if args.copy_mib:
+        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     specs = make_streams(args.streams)
     videos = [s.video() for s in specs]
     frames_dev = [torch.from_numpy(v).cuda() for v in videos]

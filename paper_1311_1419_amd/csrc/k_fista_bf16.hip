@@ -31,7 +31,16 @@
 
 namespace csv {
 
-constexpr int kWaves = 8;
+
+// Pointers into global memory.  Tile descriptors are read from memory, so
+// without the address space the compiler emits flat loads, which count on
+// the LDS counter too and force a full wait before every LDS read.
+typedef __attribute__((address_space(1))) const u16x8 gu16x8;
+typedef __attribute__((address_space(1))) const float gfloat;
+template <class T>
+__device__ inline T* as_global(const void* p) {
+    return (T*)(p);
+}
 
 // K index inside a 32-group carried by (K step s, lane half h, element e).
 __host__ __device__ inline int kappa(int s, int h, int e) {
@@ -67,6 +76,12 @@ void launch_bf16_frag_layout(Operator* op, hipStream_t st) {
     CSV_HIP(hipGetLastError());
 }
 
+#ifndef CSV_PF1024
+#define CSV_PF1024 4
+#define CSV_PA1024 2
+#define CSV_SPL1024 2
+#endif
+
 // Column tiles (of 32 blocks) per workgroup for a class (n, Mp).
 static int class_ct(int n, int Mp) {
     if (n == 1024) return 1;
@@ -95,24 +110,19 @@ __device__ inline int next_tile(const int* __restrict__ qoff, const int* __restr
     return -1;
 }
 
-// Ring depths (K steps of operator fragments in flight per wave).
-constexpr int kPF = 4;   // forward
-constexpr int kPA = 2;   // adjoint
 
 // Forward product for this wave's NF output tiles (mt_i, fct), mt_i =
-// (w + W i) / CT.  af holds the first kPF K steps on entry.  Returns the
-// accumulators; loads the first kPA adjoint steps into aa before the
-// forward accumulators are consumed.
-template <int N, int MP, int CT, int NF, int GR>
-__device__ inline void forward_tiles(u16x8 (&af)[kPF][NF], u16x8 (&aa)[kPA][GR],
-                                     floatx16 (&acc)[NF], const u16x8* __restrict__ ffwd,
-                                     const u16x8* __restrict__ fadj, const u16x8* Vb, int w,
-                                     int ln, int fct, int rt0) {
+// (w + W i) / CT.  af holds the first kPF K steps on entry.  Loads the first
+// kPA adjoint steps (rows rt0 + r / CT) into aa before returning.
+template <int N, int MP, int CT, int NF, int AR, int W, int kPF, int kPA>
+__device__ inline void forward_tiles(u16x8 (&af)[kPF][NF], u16x8 (&aa)[kPA][AR],
+                                     floatx16 (&acc)[NF], const gu16x8* ffwd, const gu16x8* fadj,
+                                     const u16x8* Vb, int w, int ln, int fct, int rt0) {
     constexpr int KSF = N / 16, KSA = MP / 16;
 #pragma unroll
     for (int i = 0; i < NF; ++i) acc[i] = floatx16{};
 #pragma unroll 1
-    for (int ks0 = 0; ks0 < KSF; ks0 += kPF) {
+    for (int ks0 = 0; ks0 < KSF - kPF; ks0 += kPF) {
 #pragma unroll
         for (int j = 0; j < kPF; ++j) {
             const int ks = ks0 + j;
@@ -121,29 +131,35 @@ __device__ inline void forward_tiles(u16x8 (&af)[kPF][NF], u16x8 (&aa)[kPA][GR],
             for (int i = 0; i < NF; ++i) {
                 acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[j][i]),
                                                                  b, acc[i], 0, 0, 0);
-                if (ks + kPF < KSF) {
-                    const int mt = (w + kWaves * i) / CT;
-                    af[j][i] = ffwd[((size_t)mt * KSF + ks + kPF) * 64 + ln];
-                }
+                const int mt = (w + W * i) / CT;
+                af[j][i] = ffwd[((size_t)mt * KSF + ks + kPF) * 64 + ln];
             }
         }
     }
 #pragma unroll
-    for (int p = 0; p < kPA; ++p)
+    for (int j = 0; j < kPF; ++j) {   // last kPF steps: no further forward loads
+        const int ks = KSF - kPF + j;
+        const bf16x8 b = __builtin_bit_cast(bf16x8, Vb[(ks * CT + fct) * 64 + ln]);
 #pragma unroll
-        for (int r = 0; r < GR; ++r)   // GR = distinct operator rows of the first group
-            aa[p][r] = fadj[((size_t)(rt0 + r / CT) * KSA + p) * 64 + ln];
+        for (int i = 0; i < NF; ++i)
+            acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[j][i]), b,
+                                                             acc[i], 0, 0, 0);
+        if (j < kPA) {
+#pragma unroll
+            for (int r = 0; r < AR; ++r)
+                aa[j][r] = fadj[((size_t)(rt0 + r / CT) * KSA + j) * 64 + ln];
+        }
+    }
 }
 
-template <int N, int MP, int CT, int NF>
-__device__ inline void load_fwd_head(u16x8 (&af)[kPF][NF], const u16x8* __restrict__ ffwd, int w,
-                                     int ln) {
+template <int N, int MP, int CT, int NF, int W, int kPF>
+__device__ inline void load_fwd_head(u16x8 (&af)[kPF][NF], const gu16x8* ffwd, int w, int ln) {
     constexpr int KSF = N / 16;
 #pragma unroll
     for (int p = 0; p < kPF; ++p)
 #pragma unroll
         for (int i = 0; i < NF; ++i) {
-            const int mt = (w + kWaves * i) / CT;
+            const int mt = (w + W * i) / CT;
             af[p][i] = ffwd[((size_t)mt * KSF + p) * 64 + ln];
         }
 }
@@ -151,9 +167,8 @@ __device__ inline void load_fwd_head(u16x8 (&af)[kPF][NF], const u16x8* __restri
 // R = P - y for one forward tile, written to LDS as bf16 (y from registers
 // or from global memory).
 template <int MP, int CT, bool YREG>
-__device__ inline void store_residual(const floatx16& acc, const floatx16& yv,
-                                      const float* __restrict__ yg, int nblk, int mt, int fct,
-                                      int ln, u16x8* Rb) {
+__device__ inline void store_residual(const floatx16& acc, const floatx16& yv, const gfloat* yg,
+                                      int nblk, int mt, int fct, int ln, u16x8* Rb) {
     const int h = ln >> 5, b = fct * 32 + (ln & 31);
     floatx16 rr = acc;
     if constexpr (YREG) {
@@ -161,8 +176,8 @@ __device__ inline void store_residual(const floatx16& acc, const floatx16& yv,
     } else if (b < nblk) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float4 y4 =
-                *reinterpret_cast<const float4*>(yg + (size_t)b * MP + mt * 32 + 8 * q + 4 * h);
+            const gfloat* yp = yg + (size_t)b * MP + mt * 32 + 8 * q + 4 * h;
+            const float4 y4 = make_float4(yp[0], yp[1], yp[2], yp[3]);
             rr[4 * q] -= y4.x;
             rr[4 * q + 1] -= y4.y;
             rr[4 * q + 2] -= y4.z;
@@ -173,23 +188,30 @@ __device__ inline void store_residual(const floatx16& acc, const floatx16& yv,
     Rb[((2 * mt + 1) * CT + fct) * 64 + ln] = pack_bf16(rr, 1);
 }
 
-template <int N, int MP, int CT>
-__global__ __launch_bounds__(64 * kWaves, 1) void fista_bf16_kernel(
+// SPL: accumulator tiles per wave whose s_{k-1} lives in LDS rather than in
+// registers (the registers go to deeper operator rings instead).
+template <int N, int MP, int CT, int W, int kPF, int kPA, int SPL>
+__global__ __launch_bounds__(64 * W, 1) void fista_bf16_kernel(
     const FusedTile* __restrict__ tiles, const int* __restrict__ qoff,
     const int* __restrict__ queue, int* __restrict__ counters) {
-    constexpr int W = kWaves;
     constexpr int RT = N / 32 / W;               // 32-row groups of n owned per wave
     constexpr int NG = RT * CT / 2;              // adjoint groups of two accumulator tiles
+    constexpr int UT = RT * CT;                  // accumulator tiles (rt, ct), u = rt * CT + ct
+    constexpr int SPR = UT - SPL;                // tiles whose s_{k-1} stays in registers
+    static_assert(SPL >= 0 && SPL <= UT, "bad LDS state split");
     constexpr int AR = CT == 1 ? 2 : 1;          // distinct operator rows per group
     constexpr int TT = (MP / 32) * CT;           // forward output tiles
     constexpr int FT = (TT + W - 1) / W;         // forward tiles per wave (max)
     constexpr int KSF = N / 16, KSA = MP / 16;   // K steps of forward / adjoint
     constexpr bool YREG = false;                 // y read from L2 in the epilogue (registers are the limit)
     static_assert(RT * CT >= 2 && (RT * CT) % 2 == 0 && W % CT == 0, "unsupported class");
-    static_assert(KSF % kPF == 0 && KSA % kPA == 0, "ring depth must divide the K steps");
+    static_assert(KSF % kPF == 0 && KSA % kPA == 0 && KSF >= kPF && KSA >= kPA,
+                  "ring depth must divide the K steps");
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     u16x8* Vb = reinterpret_cast<u16x8*>(lds);                            // [KSF][CT][64]
     u16x8* Rb = reinterpret_cast<u16x8*>(lds + (size_t)KSF * CT * 1024);  // [KSA][CT][64]
+    float4* Sl = reinterpret_cast<float4*>(lds + (size_t)(KSF + KSA) * CT * 1024);
+    // Sl: [W][SPL][4][64] float4, lane l's 16 values of a tile at q * 64 + l
     __shared__ int s_tile;
 
     const int tid = threadIdx.x, w = tid >> 6, ln = tid & 63, h = ln >> 5, col = ln & 31;
@@ -203,8 +225,9 @@ __global__ __launch_bounds__(64 * kWaves, 1) void fista_bf16_kernel(
         __syncthreads();
         if (t_id < 0) break;
         const FusedTile tl = tiles[t_id];
-        const u16x8* __restrict__ ffwd = reinterpret_cast<const u16x8*>(tl.frag_fwd);
-        const u16x8* __restrict__ fadj = reinterpret_cast<const u16x8*>(tl.frag_adj);
+        const gu16x8* ffwd = as_global<const gu16x8>(tl.frag_fwd);
+        const gu16x8* fadj = as_global<const gu16x8>(tl.frag_adj);
+        const gfloat* yg = as_global<const gfloat>(tl.y);
         const float inv_l = (float)(1.0 / tl.lip[0]);
         const int T = tl.T;
         const float* __restrict__ beta = tl.beta;
@@ -229,31 +252,38 @@ __global__ __launch_bounds__(64 * kWaves, 1) void fista_bf16_kernel(
                 }
             }
         }
-        floatx16 sp[RT][CT], vv[RT][CT];
+        floatx16 sp[SPR > 0 ? SPR : 1], vv[RT][CT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
-                sp[rt][ct] = floatx16{};
+                const int u = rt * CT + ct;
+                if (u < SPR) sp[u] = floatx16{};
                 vv[rt][ct] = floatx16{};
                 const int g = w * RT + rt;
                 const u16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
                 Vb[((2 * g) * CT + ct) * 64 + ln] = z;
                 Vb[((2 * g + 1) * CT + ct) * 64 + ln] = z;
             }
+#pragma unroll
+        for (int t = 0; t < SPL; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                Sl[((w * SPL + t) * 4 + q) * 64 + ln] = make_float4(0.f, 0.f, 0.f, 0.f);
         u16x8 af[kPF][FT];
         u16x8 aa[kPA][AR];
-        if (nft == FT) load_fwd_head<N, MP, CT, FT>(af, ffwd, w, ln);
+        if (nft == FT) load_fwd_head<N, MP, CT, FT, W, kPF>(af, ffwd, w, ln);
         __syncthreads();
 
         for (int k = 0; k < T; ++k) {
             // ---- forward: P = A V, R = P - y  (nft tiles for this wave)
             if (nft == FT) {
                 floatx16 acc[FT];
-                forward_tiles<N, MP, CT, FT, AR>(af, aa, acc, ffwd, fadj, Vb, w, ln, fct, w * RT);
+                forward_tiles<N, MP, CT, FT, AR, W, kPF, kPA>(af, aa, acc, ffwd, fadj, Vb, w, ln, fct,
+                                                              w * RT);
 #pragma unroll
                 for (int i = 0; i < FT; ++i)
-                    store_residual<MP, CT, YREG>(acc[i], yv[YREG ? i : 0], tl.y, tl.nblk,
+                    store_residual<MP, CT, YREG>(acc[i], yv[YREG ? i : 0], yg, tl.nblk,
                                                  (w + W * i) / CT, fct, ln, Rb);
             } else {
                 bool done = false;
@@ -261,12 +291,12 @@ __global__ __launch_bounds__(64 * kWaves, 1) void fista_bf16_kernel(
                     if (nft == FT - 1) {
                         u16x8 af2[kPF][FT - 1];
                         floatx16 acc[FT - 1];
-                        load_fwd_head<N, MP, CT, FT - 1>(af2, ffwd, w, ln);
-                        forward_tiles<N, MP, CT, FT - 1, AR>(af2, aa, acc, ffwd, fadj, Vb, w, ln,
-                                                             fct, w * RT);
+                        load_fwd_head<N, MP, CT, FT - 1, W, kPF>(af2, ffwd, w, ln);
+                        forward_tiles<N, MP, CT, FT - 1, AR, W, kPF, kPA>(af2, aa, acc, ffwd, fadj,
+                                                                          Vb, w, ln, fct, w * RT);
 #pragma unroll
                         for (int i = 0; i < FT - 1; ++i)
-                            store_residual<MP, CT, YREG>(acc[i], yv[YREG ? i : 0], tl.y, tl.nblk,
+                            store_residual<MP, CT, YREG>(acc[i], yv[YREG ? i : 0], yg, tl.nblk,
                                                          (w + W * i) / CT, fct, ln, Rb);
                         done = true;
                     }
@@ -291,7 +321,7 @@ __global__ __launch_bounds__(64 * kWaves, 1) void fista_bf16_kernel(
                 const int rt1 = (2 * g + 1) / CT, ct1 = (2 * g + 1) % CT;
                 floatx16 ga[2] = {floatx16{}, floatx16{}};
 #pragma unroll 1
-                for (int ks0 = 0; ks0 < KSA; ks0 += kPA) {
+                for (int ks0 = 0; ks0 < KSA - kPA; ks0 += kPA) {
 #pragma unroll
                     for (int j = 0; j < kPA; ++j) {
                         const int ks = ks0 + j;
@@ -303,30 +333,63 @@ __global__ __launch_bounds__(64 * kWaves, 1) void fista_bf16_kernel(
                         const bf16x8 a1 = AR == 2 ? __builtin_bit_cast(bf16x8, aa[j][AR - 1]) : a0;
                         ga[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, ga[0], 0, 0, 0);
                         ga[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, ga[1], 0, 0, 0);
-                        // fragments kPA steps ahead: this group, else the next group
-                        const bool same = ks + kPA < KSA;
-                        const int nks = same ? ks + kPA : ks + kPA - KSA;
-                        const int ng = same ? g : g + 1;
-                        if (ng < NG) {
 #pragma unroll
-                            for (int r = 0; r < AR; ++r)
-                                aa[j][r] =
-                                    fadj[((size_t)(w * RT + (2 * ng + r) / CT) * KSA + nks) * 64 + ln];
-                        }
+                        for (int r = 0; r < AR; ++r)
+                            aa[j][r] = fadj[((size_t)(w * RT + (2 * g + r) / CT) * KSA + ks + kPA) *
+                                                64 + ln];
                     }
                 }
-                if (g == NG - 1 && nft == FT) load_fwd_head<N, MP, CT, FT>(af, ffwd, w, ln);
+#pragma unroll
+                for (int j = 0; j < kPA; ++j) {   // last kPA steps: prefetch the next group's head
+                    const int ks = KSA - kPA + j;
+                    const bf16x8 b0 = __builtin_bit_cast(bf16x8, Rb[(ks * CT + ct0) * 64 + ln]);
+                    const bf16x8 b1 =
+                        ct1 == ct0 ? b0 : __builtin_bit_cast(bf16x8, Rb[(ks * CT + ct1) * 64 + ln]);
+                    const bf16x8 a0 = __builtin_bit_cast(bf16x8, aa[j][0]);
+                    const bf16x8 a1 = AR == 2 ? __builtin_bit_cast(bf16x8, aa[j][AR - 1]) : a0;
+                    ga[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, ga[0], 0, 0, 0);
+                    ga[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, ga[1], 0, 0, 0);
+                    if (g + 1 < NG) {
+#pragma unroll
+                        for (int r = 0; r < AR; ++r)
+                            aa[j][r] = fadj[((size_t)(w * RT + (2 * (g + 1) + r) / CT) * KSA + j) *
+                                                64 + ln];
+                    }
+                }
+                if (g == NG - 1 && nft == FT) load_fwd_head<N, MP, CT, FT, W, kPF>(af, ffwd, w, ln);
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const int rt = e ? rt1 : rt0, ct = e ? ct1 : ct0;
+                    const int ut = 2 * g + e;
                     const int gg = w * RT + rt;
                     const float tc = tau[ct];
+                    floatx16 spv;
+                    if (ut < SPR) {
+                        spv = sp[ut < SPR ? ut : 0];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const float4 t4 = Sl[((w * SPL + ut - SPR) * 4 + q) * 64 + ln];
+                            spv[4 * q] = t4.x;
+                            spv[4 * q + 1] = t4.y;
+                            spv[4 * q + 2] = t4.z;
+                            spv[4 * q + 3] = t4.w;
+                        }
+                    }
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const float u = fmaf(-ga[e][r], inv_l, vv[rt][ct][r]);
                         const float sn = u - __builtin_amdgcn_fmed3f(u, -tc, tc);
-                        vv[rt][ct][r] = fmaf(bk, sn - sp[rt][ct][r], sn);
-                        sp[rt][ct][r] = sn;
+                        vv[rt][ct][r] = fmaf(bk, sn - spv[r], sn);
+                        spv[r] = sn;
+                    }
+                    if (ut < SPR) {
+                        sp[ut < SPR ? ut : 0] = spv;
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            Sl[((w * SPL + ut - SPR) * 4 + q) * 64 + ln] =
+                                make_float4(spv[4 * q], spv[4 * q + 1], spv[4 * q + 2], spv[4 * q + 3]);
                     }
                     Vb[((2 * gg) * CT + ct) * 64 + ln] = pack_bf16(vv[rt][ct], 0);
                     Vb[((2 * gg + 1) * CT + ct) * 64 + ln] = pack_bf16(vv[rt][ct], 1);
@@ -340,51 +403,66 @@ __global__ __launch_bounds__(64 * kWaves, 1) void fista_bf16_kernel(
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
                 const int b = ct * 32 + col;
+                const int ut = rt * CT + ct;
+                floatx16 a;
+                if (ut < SPR) {
+                    a = sp[ut < SPR ? ut : 0];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const float4 t4 = Sl[((w * SPL + ut - SPR) * 4 + q) * 64 + ln];
+                        a[4 * q] = t4.x;
+                        a[4 * q + 1] = t4.y;
+                        a[4 * q + 2] = t4.z;
+                        a[4 * q + 3] = t4.w;
+                    }
+                }
                 if (b < tl.nblk) {
                     float* dst = tl.s + (size_t)b * N + (w * RT + rt) * 32 + 4 * h;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const floatx16& a = sp[rt][ct];
+                    for (int q = 0; q < 4; ++q)
                         *reinterpret_cast<float4*>(dst + 8 * q) =
                             make_float4(a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]);
-                    }
                 }
             }
     }
 }
 
-template <int N, int MP, int CT>
+template <int N, int MP, int CT, int W, int PF, int PA, int SPL>
 static void launch_class(const FusedTile* tiles, const int* qoff, const int* queue, int* counters,
                          int grid, hipStream_t st) {
-    const size_t lds = (size_t)(N / 16) * CT * 1024 + (size_t)(MP / 16) * CT * 1024;
+    const size_t lds = (size_t)(N / 16) * CT * 1024 + (size_t)(MP / 16) * CT * 1024 +
+                       (size_t)W * SPL * 4096;
+    auto* fn = &fista_bf16_kernel<N, MP, CT, W, PF, PA, SPL>;
     static bool attr_set = false;
     if (!attr_set) {
-        CSV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&fista_bf16_kernel<N, MP, CT>),
+        CSV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set = true;
     }
-    fista_bf16_kernel<N, MP, CT><<<dim3(grid), dim3(64 * kWaves), lds, st>>>(tiles, qoff, queue,
-                                                                             counters);
+    fn<<<dim3(grid), dim3(64 * W), lds, st>>>(tiles, qoff, queue, counters);
     CSV_HIP(hipGetLastError());
 }
 
+// Per class: column tiles CT, waves W and ring depths (forward, adjoint).
+// n = 1024 keeps one 32-block column tile (the iterates of 32 blocks fill
+// half the register file); n = 256 takes four (or two) column tiles.
 void launch_fista_bf16_class(int n, int Mp, const FusedTile* tiles, const int* qoff,
                              const int* queue, int* counters, int grid, hipStream_t st) {
-#define CSV_CLASS(NN, MM)                                                                   \
+#define CSV_CLASS(NN, MM, CT, W, PF, PA, SPL)                                               \
     if (n == NN && Mp == MM) {                                                              \
-        launch_class<NN, MM, (NN == 1024 ? 1 : (MM <= 64 ? 4 : 2))>(tiles, qoff, queue,     \
-                                                                   counters, grid, st);     \
+        launch_class<NN, MM, CT, W, PF, PA, SPL>(tiles, qoff, queue, counters, grid, st);   \
         return;                                                                             \
     }
-    CSV_CLASS(256, 32)
-    CSV_CLASS(256, 64)
-    CSV_CLASS(256, 96)
-    CSV_CLASS(256, 128)
-    CSV_CLASS(1024, 64)
-    CSV_CLASS(1024, 128)
-    CSV_CLASS(1024, 224)
-    CSV_CLASS(1024, 256)
-    CSV_CLASS(1024, 416)
+    CSV_CLASS(256, 32, 4, 8, 4, 2, 0)
+    CSV_CLASS(256, 64, 4, 8, 4, 2, 0)
+    CSV_CLASS(256, 96, 2, 8, 4, 2, 0)
+    CSV_CLASS(256, 128, 2, 8, 4, 2, 0)
+    CSV_CLASS(1024, 64, 1, 8, CSV_PF1024, 2, CSV_SPL1024)
+    CSV_CLASS(1024, 128, 1, 8, CSV_PF1024, CSV_PA1024, CSV_SPL1024)
+    CSV_CLASS(1024, 224, 1, 8, CSV_PF1024, 2, CSV_SPL1024)
+    CSV_CLASS(1024, 256, 1, 8, CSV_PF1024, CSV_PA1024, CSV_SPL1024)
+    CSV_CLASS(1024, 416, 1, 8, CSV_PF1024, 2, CSV_SPL1024)
 #undef CSV_CLASS
     throw Error{CSV_EUNSUPPORTED, "fused BF16 recovery has no kernel for n=" + std::to_string(n) +
                                       ", padded M=" + std::to_string(Mp)};

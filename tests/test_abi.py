@@ -1,0 +1,63 @@
+"""The C-ABI library loads without a GPU and exports every entry point that
+include/*.h declares; host-only entry points (validation, sizes,
+compression-ratio arithmetic) run on the CPU."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+INCLUDE = os.path.join(ROOT, "include")
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(INCLUDE):
+        if not fn.endswith(".h"):
+            continue
+        src = open(os.path.join(INCLUDE, fn)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*(?:int|const char\*|void)\s+\**(csv_\w+)\s*\(", src, re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1311_1419_amd import _native
+    lib = ctypes.CDLL(_native.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 20
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_declares_every_symbol():
+    from paper_1311_1419_amd import _native
+    assert _declared() <= set(_native._SIGS)
+
+
+def test_host_side_validation_and_sizes():
+    import paper_1311_1419_amd as P
+    p = P.Params(width=640, height=480, gop=16, block=32, m=256)
+    assert p.resolve() == (256, 300)
+    key, code, exp, bits = P.Context.encoded_size(p)
+    assert (key, code, exp, bits) == (640 * 480, 15 * 300 * 256, 15 * 300, 15 * 300 * (8 * 256 + 8))
+    assert P.Params(width=176, height=144, gop=4, block=32, m=0, rho=0.25).resolve() == (256, 30)
+    for bad in (dict(block=8), dict(width=170), dict(gop=0), dict(m=1025), dict(iters=0),
+                dict(key_qstep=24), dict(precision=7), dict(flags=64), dict(m=0, rho=0.0),
+                dict(lambda_frac=float("nan"))):
+        with pytest.raises(P.CsvError) as ei:
+            p.with_(**bad).resolve()
+        assert ei.value.code == -1
+
+
+def test_compression_ratio_identity():
+    import paper_1311_1419_amd as P
+    p = P.Params(width=176, height=144, gop=5, block=16, m=64)
+    cr = P.Context.compression_ratio(p, 40000, 4 * 99 * (8 * 64 + 8))
+    assert cr["total"] == pytest.approx(5 / (1 / cr["key"] + 4 / cr["cs"]), rel=1e-12)
+    raw = 8 * 176 * 144
+    assert cr["key"] == pytest.approx(raw / 40000)
+    assert math.isfinite(cr["total"])
