@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "recovered Mpixel/s at M/n=0.25, BF16-MFMA vs FP32, ≤0.1dB PSNR loss; p99 ms"
+KERNEL_SRC = os.path.join(ROOT, "paper_1311_1419_amd", "csrc", "k_fista_bf16.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "fista_bf16_vga640x480_m256_x16_pmc.md")
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
 WORKLOAD = "vga640x480-g16-b32-m256-t300-x16streams"
 
@@ -86,6 +88,22 @@ def run_path(ctx, P, torch, specs, frames_dev, precision, steps, warmup):
     ctx.profile(False)
     per_step = [a.elapsed_time(b) for a, b in evs]
     return wall, per_step, outs, streams
+
+
+def measured_traffic(streams):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on this kernel source and this workload size; else None."""
+    import hashlib
+    import re
+    if streams != 16 or not os.path.exists(PMC_SUMMARY):
+        return None
+    txt = open(PMC_SUMMARY).read()
+    sha = re.search(r"kernel_source_sha256: (\w+)", txt)
+    tb = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
+    cur = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if not sha or not tb or sha.group(1) != cur:
+        return None
+    return int(tb.group(1))
 
 
 def cpu_baseline(spec, gs_host, n_blocks):
@@ -187,7 +205,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2) if achieved else None,
                      "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_BF16_TFLOPS, 4) if achieved else None,
-                     "traffic": None, "kernel": "fista_bf16_kernel<1024,256,1>",
+                     "traffic": measured_traffic(args.streams), "traffic_unit": "bytes/launch",
+                     "kernel": "fista_bf16_kernel<1024,256,1,8,4,2,2>",
                      "kernel_ms": round(1e3 * avg_k_s, 4), "flops_per_launch": flops_launch},
         "fp32_path": fp32,
         "mean_psnr_db_bf16": round(mean_psnr, 3),
