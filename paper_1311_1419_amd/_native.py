@@ -37,6 +37,26 @@ class CsvGopStream(C.Structure):
                 ("exps", C.c_void_p), ("bits", C.c_void_p)]
 
 
+CSV_SERVER_FAKE_EXECUTOR = 1
+
+
+class CsvServerOpts(C.Structure):
+    _fields_ = [("mem_budget", C.c_size_t), ("max_queue", C.c_int32),
+                ("max_batch_blocks", C.c_int32), ("precision", C.c_int32),
+                ("hip_streams", C.c_int32), ("flags", C.c_int32),
+                ("fake_us_per_block", C.c_double), ("fake_fail_every", C.c_double)]
+
+
+class CsvStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("completed", C.c_uint64),
+                ("rejected", C.c_uint64), ("cancelled", C.c_uint64), ("failed", C.c_uint64),
+                ("recovered_pixels", C.c_uint64), ("p50_ms", C.c_double),
+                ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("max_ms", C.c_double),
+                ("mpix_per_s", C.c_double), ("bytes_in_flight", C.c_size_t),
+                ("peak_bytes", C.c_size_t), ("queue_depth", C.c_int32),
+                ("batches", C.c_int32), ("max_concurrent", C.c_int32)]
+
+
 class CsvError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"csv error {code}: {msg}")
@@ -79,6 +99,16 @@ _SIGS = {
     "csv_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "csv_profile_query": (C.c_int, [C.c_void_p, C.c_char_p, _P(C.c_double), _P(C.c_int64)]),
     "csv_profile_reset": (C.c_int, [C.c_void_p]),
+    "csv_clock": (C.c_double, []),
+    "csv_server_create": (C.c_int, [C.c_int, _P(CsvServerOpts), _P(C.c_void_p)]),
+    "csv_server_destroy": (C.c_int, [C.c_void_p]),
+    "csv_server_register_stream": (C.c_int, [C.c_void_p, _P(CsvParams), _P(C.c_uint32)]),
+    "csv_submit": (C.c_int, [C.c_void_p, C.c_uint32, _P(CsvGopStream), C.c_double,
+                             _P(C.c_uint64)]),
+    "csv_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, _P(C.c_int32)]),
+    "csv_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "csv_server_drain": (C.c_int, [C.c_void_p, C.c_double]),
+    "csv_server_stats": (C.c_int, [C.c_void_p, _P(CsvStats)]),
 }
 
 _lib = None

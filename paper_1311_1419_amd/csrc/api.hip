@@ -127,10 +127,37 @@ static void free_operator(Ctx* c, Operator* op) {
     c->used -= op->bytes;
 }
 
+void free_operators(Ctx* c) {
+    if (!c->cache || c->cache.use_count() > 1) return;
+    std::lock_guard<std::mutex> lk(c->cache->mu);
+    for (auto& kv : c->cache->ops) free_operator(c, kv.second.get());
+    c->cache->ops.clear();
+}
+
+void release_ctx(Ctx* c) {
+    (void)hipDeviceSynchronize();
+    free_operators(c);
+    for (auto& kv : c->scratch) ctx_free(c, kv.second.ptr, kv.second.bytes);
+    c->scratch.clear();
+    for (auto& kv : c->beta_tables) (void)hipFree(kv.second.first);
+    c->beta_tables.clear();
+    if (c->stage_host) (void)hipHostFree(c->stage_host);
+    c->stage_host = nullptr;
+    if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+    c->stage_done = nullptr;
+    for (auto& kv : c->prof_pending)
+        for (auto& ev : kv.second) {
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
+    c->prof_pending.clear();
+}
+
 Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
     const auto key = std::make_tuple(s.seed, s.sid, s.n, s.M);
-    auto it = c->ops.find(key);
-    if (it != c->ops.end()) return it->second.get();
+    std::lock_guard<std::mutex> lk(c->cache->mu);
+    auto it = c->cache->ops.find(key);
+    if (it != c->cache->ops.end()) return it->second.get();
     auto op = std::make_unique<Operator>();
     op->B = s.B;
     op->n = s.n;
@@ -175,7 +202,7 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
         throw;
     }
     Operator* raw = op.get();
-    c->ops.emplace(key, std::move(op));
+    c->cache->ops.emplace(key, std::move(op));
     return raw;
 }
 
@@ -368,6 +395,75 @@ ProfScope::~ProfScope() {
     if (hipEventRecord(b_, st_) == hipSuccess) c_->prof_pending[name_].push_back({a_, b_});
 }
 
+// Decode `count` GOPs.  Key frames first (Section 3.2: CS frames are decoded
+// only after the key frame), then one recovery pass over every CS block of
+// every GOP, then synthesis onto each decoded key frame (eq. (4)).
+void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* in,
+                 uint8_t* const* frames_out, float* const* cs_float_out, double* const* obj_out,
+                 hipStream_t st) {
+    struct Item {
+        Operator* op;
+        int nblk;
+        float* S;
+        float* lam;
+        const float* y;
+    };
+    std::vector<Item> items(count);
+    for (int i = 0; i < count; ++i) {
+        const Shape& s = shapes[i];
+        CSV_REQUIRE(in[i].key_levels && frames_out[i], CSV_EINVAL, "NULL key_levels or frames_out");
+        CSV_REQUIRE(s.G == 1 || (in[i].codes && in[i].exps), CSV_EINVAL, "codes/exps are NULL");
+        items[i].op = s.G > 1 ? get_operator(c, s, st) : nullptr;
+        items[i].nblk = (s.G - 1) * s.nb;
+    }
+    // scratch is sized before any launch that reads it
+    for (int i = 0; i < count; ++i) {
+        const Shape& s = shapes[i];
+        if (!items[i].nblk) continue;
+        const std::string tag = "#" + std::to_string(i);
+        items[i].S = static_cast<float*>(scratch(c, "S" + tag, (size_t)items[i].nblk * s.n * 4));
+        items[i].lam = static_cast<float*>(scratch(c, "lam" + tag, (size_t)items[i].nblk * 4));
+        scratch(c, "yhat" + tag, (size_t)items[i].nblk * s.Mp * 4);
+    }
+    for (int i = 0; i < count; ++i) {
+        const Shape& s = shapes[i];
+        ProfScope ps(c, "key_decode", st);
+        launch_key_decode(in[i].key_levels, s.W, s.H, s.qstep, frames_out[i], st);
+    }
+    std::vector<FusedJob> jobs;
+    for (int i = 0; i < count; ++i) {
+        const Shape& s = shapes[i];
+        Item& it = items[i];
+        if (!it.nblk) continue;
+        {
+            ProfScope ps(c, "prepare", st);
+            it.y = prepare(c, s, it.op, in[i].codes, in[i].exps, it.nblk, it.lam,
+                           "#" + std::to_string(i), st);
+        }
+        if (s.precision == CSV_FP32) {
+            ProfScope ps(c, "fista_fp32", st);
+            fista_fp32(c, s, it.op, it.y, it.lam, it.nblk, it.S, st);
+        } else {
+            jobs.push_back(FusedJob{&shapes[i], it.op, it.y, it.lam, it.S, it.nblk});
+        }
+    }
+    if (!jobs.empty()) fista_bf16(c, jobs, st);
+    for (int i = 0; i < count; ++i) {
+        const Shape& s = shapes[i];
+        const Item& it = items[i];
+        if (!it.nblk) continue;
+        if (obj_out && obj_out[i]) {
+            ProfScope ps(c, "final64", st);
+            launch_final64(it.op->a64t, it.S, in[i].codes, in[i].exps, it.lam, it.nblk, s.M, s.Mp,
+                           s.n, it.op->s_phi, obj_out[i], st);
+        }
+        ProfScope ps(c, "synth", st);
+        const size_t fs = (size_t)s.W * s.H;
+        launch_synth(it.S, it.op->dct, frames_out[i], s.W, s.H, s.B, s.nbx, s.nb, s.G - 1,
+                     frames_out[i] + fs, cs_float_out ? cs_float_out[i] : nullptr, st);
+    }
+}
+
 }  // namespace csv
 
 using namespace csv;
@@ -406,16 +502,7 @@ int csv_destroy(csv_ctx* ctx) {
     return guarded([&] {
         set_device(ctx);
         CSV_HIP(hipDeviceSynchronize());
-        for (auto& kv : ctx->impl.ops) free_operator(&ctx->impl, kv.second.get());
-        for (auto& kv : ctx->impl.scratch) ctx_free(&ctx->impl, kv.second.ptr, kv.second.bytes);
-        for (auto& kv : ctx->impl.beta_tables) (void)hipFree(kv.second.first);
-        if (ctx->impl.stage_host) (void)hipHostFree(ctx->impl.stage_host);
-        if (ctx->impl.stage_done) (void)hipEventDestroy(ctx->impl.stage_done);
-        for (auto& kv : ctx->impl.prof_pending)
-            for (auto& ev : kv.second) {
-                (void)hipEventDestroy(ev.first);
-                (void)hipEventDestroy(ev.second);
-            }
+        release_ctx(&ctx->impl);
         delete ctx;
     });
 }
@@ -501,75 +588,6 @@ int csv_encode_gop(csv_ctx* ctx, const csv_params* p, const uint8_t* frames,
         launch_measure(s, op->q, frames + fs, ncs, fs, keydec, y, st);
         launch_quantise(y, s.M, s.Mp, total, out->codes, out->exps, nullptr, st);
     });
-}
-
-// Decode `count` GOPs.  Key frames first (Section 3.2: CS frames are decoded
-// only after the key frame), then one recovery pass over every CS block of
-// every GOP, then synthesis onto each decoded key frame (eq. (4)).
-static void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* in,
-                        uint8_t* const* frames_out, float* const* cs_float_out,
-                        double* const* obj_out, hipStream_t st) {
-    struct Item {
-        Operator* op;
-        int nblk;
-        float* S;
-        float* lam;
-        const float* y;
-    };
-    std::vector<Item> items(count);
-    for (int i = 0; i < count; ++i) {
-        const Shape& s = shapes[i];
-        CSV_REQUIRE(in[i].key_levels && frames_out[i], CSV_EINVAL, "NULL key_levels or frames_out");
-        CSV_REQUIRE(s.G == 1 || (in[i].codes && in[i].exps), CSV_EINVAL, "codes/exps are NULL");
-        items[i].op = s.G > 1 ? get_operator(c, s, st) : nullptr;
-        items[i].nblk = (s.G - 1) * s.nb;
-    }
-    // scratch is sized before any launch that reads it
-    for (int i = 0; i < count; ++i) {
-        const Shape& s = shapes[i];
-        if (!items[i].nblk) continue;
-        const std::string tag = "#" + std::to_string(i);
-        items[i].S = static_cast<float*>(scratch(c, "S" + tag, (size_t)items[i].nblk * s.n * 4));
-        items[i].lam = static_cast<float*>(scratch(c, "lam" + tag, (size_t)items[i].nblk * 4));
-        scratch(c, "yhat" + tag, (size_t)items[i].nblk * s.Mp * 4);
-    }
-    for (int i = 0; i < count; ++i) {
-        const Shape& s = shapes[i];
-        ProfScope ps(c, "key_decode", st);
-        launch_key_decode(in[i].key_levels, s.W, s.H, s.qstep, frames_out[i], st);
-    }
-    std::vector<FusedJob> jobs;
-    for (int i = 0; i < count; ++i) {
-        const Shape& s = shapes[i];
-        Item& it = items[i];
-        if (!it.nblk) continue;
-        {
-            ProfScope ps(c, "prepare", st);
-            it.y = prepare(c, s, it.op, in[i].codes, in[i].exps, it.nblk, it.lam,
-                           "#" + std::to_string(i), st);
-        }
-        if (s.precision == CSV_FP32) {
-            ProfScope ps(c, "fista_fp32", st);
-            fista_fp32(c, s, it.op, it.y, it.lam, it.nblk, it.S, st);
-        } else {
-            jobs.push_back(FusedJob{&shapes[i], it.op, it.y, it.lam, it.S, it.nblk});
-        }
-    }
-    if (!jobs.empty()) fista_bf16(c, jobs, st);
-    for (int i = 0; i < count; ++i) {
-        const Shape& s = shapes[i];
-        const Item& it = items[i];
-        if (!it.nblk) continue;
-        if (obj_out && obj_out[i]) {
-            ProfScope ps(c, "final64", st);
-            launch_final64(it.op->a64t, it.S, in[i].codes, in[i].exps, it.lam, it.nblk, s.M, s.Mp,
-                           s.n, it.op->s_phi, obj_out[i], st);
-        }
-        ProfScope ps(c, "synth", st);
-        const size_t fs = (size_t)s.W * s.H;
-        launch_synth(it.S, it.op->dct, frames_out[i], s.W, s.H, s.B, s.nbx, s.nb, s.G - 1,
-                     frames_out[i] + fs, cs_float_out ? cs_float_out[i] : nullptr, st);
-    }
 }
 
 int csv_decode_gop(csv_ctx* ctx, const csv_params* p, const csv_gop_stream* in,

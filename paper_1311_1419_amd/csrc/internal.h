@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -74,8 +75,16 @@ struct Scratch {
     size_t bytes = 0;
 };
 
+// Per-stream operators, shareable between contexts (the server's batch
+// slots share one cache; each csv_ctx owns its own).
+struct OpCache {
+    std::mutex mu;
+    std::map<std::tuple<uint64_t, uint32_t, int, int>, std::unique_ptr<Operator>> ops;
+};
+
 struct Ctx {
     int device = 0;
+    std::shared_ptr<OpCache> cache = std::make_shared<OpCache>();
     size_t budget = 0;
     size_t used = 0;
     void* stage_host = nullptr;      // pinned staging for tile descriptors
@@ -84,7 +93,6 @@ struct Ctx {
     bool profiling = false;
     std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
     std::map<std::string, std::pair<double, long long>> prof_total;
-    std::map<std::tuple<uint64_t, uint32_t, int, int>, std::unique_ptr<Operator>> ops;
     std::map<std::string, Scratch> scratch;
     std::map<int, std::pair<float*, int>> beta_tables;   // key: T*2 + ista
     int gen = 0;   // bumps whenever a scratch buffer moves
@@ -110,6 +118,13 @@ void* ctx_alloc(Ctx* c, size_t bytes);
 void ctx_free(Ctx* c, void* p, size_t bytes);
 void* scratch(Ctx* c, const std::string& name, size_t bytes);
 Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st);
+void free_operators(Ctx* c);   // when c holds the last reference to its cache
+void release_ctx(Ctx* c);      // free everything c allocated
+// Decode `count` GOPs (key frames, recovery of every CS block in one pass,
+// synthesis); the body of csv_decode_gop / csv_decode_batch.
+void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* in,
+                 uint8_t* const* frames_out, float* const* cs_float_out, double* const* obj_out,
+                 hipStream_t st);
 const float* beta_table(Ctx* c, int T, bool ista, hipStream_t st);
 
 // ------------------------------------------------------------- kernels

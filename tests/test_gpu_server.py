@@ -1,0 +1,83 @@
+"""The serving loop on the GPU: every request decoded inside a mixed,
+continuously batched stream of requests equals the same GOP decoded alone
+(fused BF16 path; tiles never mix GOPs, so the results are bit-identical),
+and a Poisson arrival run completes every request with latency stats."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import synthvid as sv
+from tests.gpu_util import announce, ctx, dev, host  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16(spec):
+    import paper_1311_1419_amd as P
+    return P.Params.from_spec(spec, precision=P.CSV_BF16)
+
+
+def test_served_equals_alone(ctx):
+    import paper_1311_1419_amd as P
+    announce("server: served vs alone")
+    specs = [sv.qcif_tiny(), sv.cif_sweep(4, 0.1, stream=1), sv.vga_precision(0.25, gop=3, stream=2),
+             sv.qcif_tiny().with_(block=32, m=102, stream_id=9, phi_seed=99)]
+    items = []
+    for spec in specs:
+        p = _bf16(spec)
+        gs = ctx.encode_gop(dev(spec.video()), p)
+        alone = host(ctx.decode_gop(gs, p)[0])
+        items.append((p, gs, alone))
+    torch.cuda.synchronize()
+    with P.Server(0, hip_streams=2, max_batch_blocks=1500) as srv:
+        sids = [srv.register_stream(p) for p, _, _ in items]
+        tickets = []
+        for rep in range(3):
+            for i, (p, gs, _) in enumerate(items):
+                tickets.append((i, srv.submit(sids[i], gs, P.clock())))
+        outs = {}
+        deadline = time.time() + 60
+        while len(outs) < len(tickets) and time.time() < deadline:
+            for i, t in tickets:
+                if t in outs:
+                    continue
+                p = items[i][0]
+                buf = torch.empty((p.gop, p.height, p.width), dtype=torch.uint8, device="cuda")
+                if srv.poll(t, buf):
+                    outs[t] = (i, buf)
+            time.sleep(0.001)
+        assert len(outs) == len(tickets)
+        for t, (i, buf) in outs.items():
+            assert np.array_equal(host(buf), items[i][2]), f"request {t} of stream {i}"
+        st = srv.stats()
+        assert st["completed"] == len(tickets) and st["failed"] == 0
+        assert st["batches"] >= 2
+
+
+def test_poisson_load_completes(ctx):
+    import paper_1311_1419_amd as P
+    announce("server: poisson load")
+    rng = np.random.default_rng(5)
+    specs = [sv.qcif_tiny().with_(stream_id=k, phi_seed=1000 + k, iters=100) for k in range(6)]
+    gss = []
+    for spec in specs:
+        p = _bf16(spec)
+        gss.append((p, ctx.encode_gop(dev(spec.video()), p)))
+    torch.cuda.synchronize()
+    with P.Server(0, hip_streams=2) as srv:
+        sids = [srv.register_stream(p) for p, _ in gss]
+        t0 = P.clock()
+        arrivals = sorted((t0 + float(rng.exponential(0.004)) * k, k % len(gss)) for k in range(60))
+        tickets = []
+        for ta, i in arrivals:
+            while P.clock() < ta:
+                time.sleep(0.0002)
+            tickets.append(srv.submit(sids[i], gss[i][1], ta))
+        srv.drain(60.0)
+        for t in tickets:
+            assert srv.poll(t)
+        st = srv.stats()
+        assert st["completed"] == 60 and st["p99_ms"] >= st["p50_ms"] > 0
+        assert st["mpix_per_s"] > 0

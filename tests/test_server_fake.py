@@ -1,0 +1,172 @@
+"""Serving-loop logic on the CPU with the host-only fake executor:
+admission by memory budget, queue limits, cancellation, injected batch
+failures, latency bookkeeping and concurrent submitters."""
+import ctypes
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import paper_1311_1419_amd as P
+from paper_1311_1419_amd import _native as N
+
+
+class FakeGop:
+    """Non-null placeholders: the fake executor never dereferences them."""
+    def to_c(self):
+        return N.CsvGopStream(0x1000, 0x2000, 0x3000, None)
+
+
+PARAMS = P.Params(width=176, height=144, gop=4, block=16, m=64)   # 297 blocks, 101 376 output bytes
+REQ_BYTES = 4 * 176 * 144 + 3 * 99 * (256 * 4 + 64 * 4 + 4)
+
+
+def _server(**kw):
+    base = dict(fake_executor=True, fake_us_per_block=1.0, hip_streams=2)
+    base.update(kw)
+    return P.Server(**base)
+
+
+def _out():
+    return (ctypes.c_uint8 * (4 * 176 * 144))()
+
+
+def _poll_until(srv, t, out=None, timeout=10.0):
+    end = time.time() + timeout
+    while time.time() < end:
+        if srv.poll(t, out):
+            return True
+        time.sleep(0.001)
+    raise AssertionError("request did not complete")
+
+
+def test_submit_poll_and_stats():
+    with _server() as srv:
+        sid = srv.register_stream(PARAMS)
+        tickets = [srv.submit(sid, FakeGop(), P.clock()) for _ in range(12)]
+        srv.drain(10.0)
+        for t in tickets:
+            buf = _out()
+            assert _poll_until(srv, t, buf)
+            assert np.all(np.frombuffer(buf, dtype=np.uint8) == (t & 0xFF))
+        st = srv.stats()
+        assert st["submitted"] == st["admitted"] == st["completed"] == 12
+        assert st["recovered_pixels"] == 12 * 3 * 176 * 144
+        assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+        assert st["bytes_in_flight"] == 0 and st["batches"] >= 1
+
+
+def test_memory_budget_limits_admission():
+    with _server(mem_budget=2 * REQ_BYTES) as srv:
+        sid = srv.register_stream(PARAMS)
+        tickets = [srv.submit(sid, FakeGop()) for _ in range(5)]
+        time.sleep(0.05)
+        st = srv.stats()
+        assert st["admitted"] == 2 and st["queue_depth"] == 3
+        assert st["peak_bytes"] <= 2 * REQ_BYTES
+        with pytest.raises(N.CsvError) as ei:          # outputs held until polled
+            srv.drain(0.05)
+        assert ei.value.code == N.CSV_EAGAIN
+        for t in tickets:                               # polling frees memory, the rest admit
+            _poll_until(srv, t)
+        srv.drain(5.0)
+        st = srv.stats()
+        assert st["completed"] == 5 and st["peak_bytes"] <= 2 * REQ_BYTES
+
+
+def test_queue_full_and_oversized_request():
+    with _server(mem_budget=REQ_BYTES - 1, max_queue=3) as srv:
+        sid = srv.register_stream(PARAMS)
+        with pytest.raises(N.CsvError) as ei:
+            srv.submit(sid, FakeGop())
+        assert ei.value.code == N.CSV_ENOMEM
+    with _server(mem_budget=REQ_BYTES, max_queue=3) as srv:
+        sid = srv.register_stream(PARAMS)
+        first = srv.submit(sid, FakeGop())
+        time.sleep(0.02)                                # first admitted, holds the budget
+        for _ in range(3):
+            srv.submit(sid, FakeGop())
+        with pytest.raises(N.CsvError) as ei:
+            srv.submit(sid, FakeGop())
+        assert ei.value.code == N.CSV_EAGAIN
+        assert srv.stats()["rejected"] == 1
+        _poll_until(srv, first)
+
+
+def test_cancel_waiting_request():
+    with _server(mem_budget=REQ_BYTES) as srv:
+        sid = srv.register_stream(PARAMS)
+        a = srv.submit(sid, FakeGop())
+        b = srv.submit(sid, FakeGop())                  # waits: budget held by a
+        srv.cancel(b)
+        with pytest.raises(N.CsvError) as ei:
+            srv.poll(b)
+        assert ei.value.code == N.CSV_ECANCELED
+        _poll_until(srv, a)
+        assert srv.stats()["cancelled"] == 1
+
+
+def test_injected_batch_failures_fail_only_their_requests():
+    with _server(fake_fail_every=2, hip_streams=1, max_batch_blocks=297) as srv:
+        sid = srv.register_stream(PARAMS)
+        tickets = [srv.submit(sid, FakeGop()) for _ in range(6)]
+        srv.drain(5.0)
+        ok = failed = 0
+        for t in tickets:
+            try:
+                _poll_until(srv, t)
+                ok += 1
+            except N.CsvError as e:
+                assert e.code == N.CSV_EHIP and "injected" in str(e)
+                failed += 1
+        assert ok == 3 and failed == 3
+        st = srv.stats()
+        assert st["failed"] == 3 and st["completed"] == 3 and st["bytes_in_flight"] == 0
+
+
+def test_latency_includes_service_time_and_unknown_ids():
+    with _server(fake_us_per_block=200.0, hip_streams=1) as srv:
+        sid = srv.register_stream(PARAMS)
+        t = srv.submit(sid, FakeGop(), P.clock())
+        _poll_until(srv, t)
+        assert srv.stats()["max_ms"] >= 297 * 0.2 * 0.99
+        with pytest.raises(N.CsvError) as ei:
+            srv.submit(sid + 7, FakeGop())
+        assert ei.value.code == N.CSV_ENOTFOUND
+        with pytest.raises(N.CsvError) as ei:
+            srv.poll(123456)
+        assert ei.value.code == N.CSV_ENOTFOUND
+
+
+def test_concurrent_submitters():
+    with _server(fake_us_per_block=0.5) as srv:
+        sid = srv.register_stream(PARAMS)
+        tickets, lock = [], threading.Lock()
+
+        def work():
+            for _ in range(25):
+                t = srv.submit(sid, FakeGop())
+                with lock:
+                    tickets.append(t)
+
+        th = [threading.Thread(target=work) for _ in range(4)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        assert len(set(tickets)) == 100
+        srv.drain(10.0)
+        for t in tickets:
+            _poll_until(srv, t)
+        assert srv.stats()["completed"] == 100
+
+
+def test_bad_server_options():
+    with pytest.raises(N.CsvError):
+        P.Server(fake_executor=True, hip_streams=9)
+    with pytest.raises(N.CsvError):
+        P.Server(fake_executor=True, precision=5)
+    with _server() as srv:
+        with pytest.raises(N.CsvError):
+            srv.register_stream(PARAMS.with_(gop=1))
