@@ -202,6 +202,25 @@ int csv_recover_blocks(csv_ctx* ctx, const csv_params* p, int32_t n_blocks,
                        const int8_t* codes, const uint8_t* exps, float* s_out,
                        float* lambda_out, double* obj_out, void* stream);
 
+/* ------------------------------------------------------ graph replay */
+/* Capture the decode of a fixed batch (same arguments as csv_decode_batch)
+ * into a HIP graph: one eager decode first builds every per-stream operator
+ * and sizes the context's scratch, then the whole sequence (key frames,
+ * dequantisation, lambda, the persistent fused recovery launch with its
+ * tile table, synthesis, FP64 check) is stream-captured on `stream`
+ * (a non-default stream).  csv_graph_launch replays it over whatever the
+ * bound input buffers hold at launch time, writing the bound outputs.  The
+ * graph keeps using the context's scratch: replays and other decodes on
+ * that context must not overlap on the device.  Destroy the graph before
+ * its context. */
+typedef struct csv_graph csv_graph;
+int csv_graph_capture(csv_ctx* ctx, int32_t count, const csv_params* params,
+                      const csv_gop_stream* in, uint8_t* const* frames_out,
+                      float* const* cs_float_out, double* const* obj_out, void* stream,
+                      csv_graph** out);
+int csv_graph_launch(csv_graph* g, void* stream);
+int csv_graph_destroy(csv_graph* g);
+
 /* ------------------------------------------------------- measurement */
 /* Event timing of named kernel ranges on the stream they run on ("fista_bf16",
  * "fista_fp32", "prepare", "synth", "final64", "key_decode").  While enabled,

@@ -99,6 +99,11 @@ _SIGS = {
     "csv_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "csv_profile_query": (C.c_int, [C.c_void_p, C.c_char_p, _P(C.c_double), _P(C.c_int64)]),
     "csv_profile_reset": (C.c_int, [C.c_void_p]),
+    "csv_graph_capture": (C.c_int, [C.c_void_p, C.c_int32, _P(CsvParams), _P(CsvGopStream),
+                                    _P(C.c_void_p), _P(C.c_void_p), _P(C.c_void_p), C.c_void_p,
+                                    _P(C.c_void_p)]),
+    "csv_graph_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "csv_graph_destroy": (C.c_int, [C.c_void_p]),
     "csv_clock": (C.c_double, []),
     "csv_server_create": (C.c_int, [C.c_int, _P(CsvServerOpts), _P(C.c_void_p)]),
     "csv_server_destroy": (C.c_int, [C.c_void_p]),

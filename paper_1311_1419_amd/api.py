@@ -89,6 +89,29 @@ def _require_cuda(t: torch.Tensor, dtype, name: str):
         raise ValueError(f"{name} must be contiguous")
 
 
+class DecodeGraph:
+    """A captured batch decode (csv_graph); keeps its bound buffers alive."""
+
+    def __init__(self, handle, outputs, inputs):
+        self._h = handle
+        self.outputs = outputs
+        self._inputs = inputs
+
+    def launch(self, stream) -> None:
+        N.check(N.lib().csv_graph_launch(self._h, stream.cuda_stream))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            N.check(N.lib().csv_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """A csv_ctx: per-stream operator caches and scratch on one device."""
 
@@ -201,6 +224,40 @@ class Context:
                                          flptr if want_float else None,
                                          optr if want_obj else None, _stream(dev)))
         return outs
+
+    def capture_batch(self, items, stream, want_float: bool = False, want_obj: bool = False):
+        """Capture the decode of `items` (list of (GopStream, Params)) into a
+        HIP graph on `stream` (a torch.cuda.Stream).  Returns a DecodeGraph
+        whose launch() re-decodes whatever the bound GopStreams hold into
+        the bound output tensors (graph.outputs)."""
+        count = len(items)
+        dev = self.device
+        params = (N.CsvParams * count)()
+        streams = (N.CsvGopStream * count)()
+        fptr = (C.c_void_p * count)()
+        flptr = (C.c_void_p * count)()
+        optr = (C.c_void_p * count)()
+        outs = []
+        for i, (gs, p) in enumerate(items):
+            m, nb = p.resolve()
+            frames = torch.empty((p.gop, p.height, p.width), dtype=torch.uint8, device=dev)
+            fl = (torch.empty((p.gop - 1, p.height, p.width), dtype=torch.float32, device=dev)
+                  if want_float else None)
+            obj = (torch.empty((p.gop - 1, nb, 2), dtype=torch.float64, device=dev)
+                   if want_obj else None)
+            params[i] = p.to_c()
+            streams[i] = gs.to_c()
+            fptr[i] = frames.data_ptr()
+            flptr[i] = _ptr(fl)
+            optr[i] = _ptr(obj)
+            outs.append((frames, fl, obj))
+        h = C.c_void_p()
+        torch.cuda.synchronize(dev)
+        N.check(N.lib().csv_graph_capture(self._h, count, params, streams, fptr,
+                                          flptr if want_float else None,
+                                          optr if want_obj else None, stream.cuda_stream,
+                                          C.byref(h)))
+        return DecodeGraph(h, outs, [gs for gs, _ in items])
 
     # ---------------------------------------------------------- profiling
     def profile(self, on: bool = True) -> None:

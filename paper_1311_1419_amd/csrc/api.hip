@@ -108,6 +108,7 @@ void ctx_free(Ctx* c, void* p, size_t bytes) {
 void* scratch(Ctx* c, const std::string& name, size_t bytes) {
     Scratch& s = c->scratch[name];
     if (s.bytes >= bytes) return s.ptr;
+    CSV_REQUIRE(!c->capturing, CSV_EINVAL, "scratch would grow during graph capture");
     if (s.ptr) {
         CSV_HIP(hipDeviceSynchronize());   // earlier work may still read the old buffer
         ctx_free(c, s.ptr, s.bytes);
@@ -158,6 +159,7 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
     std::lock_guard<std::mutex> lk(c->cache->mu);
     auto it = c->cache->ops.find(key);
     if (it != c->cache->ops.end()) return it->second.get();
+    CSV_REQUIRE(!c->capturing, CSV_EINVAL, "operator setup during graph capture");
     auto op = std::make_unique<Operator>();
     op->B = s.B;
     op->n = s.n;
@@ -213,6 +215,7 @@ const float* beta_table(Ctx* c, int T, bool ista, hipStream_t st) {
     const int key = T * 2 + (ista ? 1 : 0);
     auto it = c->beta_tables.find(key);
     if (it != c->beta_tables.end()) return it->second.first;
+    CSV_REQUIRE(!c->capturing, CSV_EINVAL, "momentum table missing during graph capture");
     std::vector<float> h(T);
     double t = 1.0;
     for (int k = 0; k < T; ++k) {
@@ -302,20 +305,29 @@ static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st
         idx_ints += 9 + kv.second.size() + 8;
     }
     const size_t bytes = tiles_bytes + idx_ints * sizeof(int) + 64;
-    if (c->stage_bytes < bytes) {
-        if (c->stage_host) {
-            CSV_HIP(hipEventSynchronize(c->stage_done));
-            CSV_HIP(hipHostFree(c->stage_host));
+    char* host = nullptr;
+    c->last_table_bytes = bytes;
+    if (c->capturing) {
+        // the graph replays this upload from a buffer nobody else rewrites
+        CSV_REQUIRE(c->capture_host && bytes <= c->capture_bytes, CSV_EINVAL,
+                    "tile table larger than the capture buffer");
+        host = static_cast<char*>(c->capture_host);
+    } else {
+        if (c->stage_bytes < bytes) {
+            if (c->stage_host) {
+                CSV_HIP(hipEventSynchronize(c->stage_done));
+                CSV_HIP(hipHostFree(c->stage_host));
+            }
+            c->stage_host = nullptr;
+            c->stage_bytes = 0;
+            CSV_HIP(hipHostMalloc(&c->stage_host, bytes * 2, hipHostMallocDefault));
+            c->stage_bytes = bytes * 2;
+        } else if (c->stage_host) {
+            CSV_HIP(hipEventSynchronize(c->stage_done));   // previous upload has left the buffer
         }
-        c->stage_host = nullptr;
-        c->stage_bytes = 0;
-        CSV_HIP(hipHostMalloc(&c->stage_host, bytes * 2, hipHostMallocDefault));
-        c->stage_bytes = bytes * 2;
-    } else if (c->stage_host) {
-        CSV_HIP(hipEventSynchronize(c->stage_done));   // previous upload has left the buffer
+        if (!c->stage_done) CSV_HIP(hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming));
+        host = static_cast<char*>(c->stage_host);
     }
-    if (!c->stage_done) CSV_HIP(hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming));
-    char* host = static_cast<char*>(c->stage_host);
     char* dev = static_cast<char*>(scratch(c, "tiles", bytes));
     struct Launch {
         int n, Mp, grid;
@@ -344,7 +356,7 @@ static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st
         launches.push_back(L);
     }
     CSV_HIP(hipMemcpyAsync(dev, host, off_i, hipMemcpyHostToDevice, st));
-    CSV_HIP(hipEventRecord(c->stage_done, st));
+    if (!c->capturing) CSV_HIP(hipEventRecord(c->stage_done, st));
     for (const Launch& L : launches) {
         ProfScope ps(c, "fista_bf16", st);
         launch_fista_bf16_class(L.n, L.Mp, reinterpret_cast<const FusedTile*>(dev + L.tiles_off),
@@ -618,6 +630,98 @@ int csv_decode_batch(csv_ctx* ctx, int32_t count, const csv_params* params,
                         "one precision per batch");
         decode_gops(C(ctx), count, shapes.data(), in, frames_out, cs_float_out, obj_out,
                     static_cast<hipStream_t>(stream));
+    });
+}
+
+struct csv_graph {
+    csv_ctx* ctx;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<void*> keep;   // pinned tile tables the graph uploads from
+};
+
+int csv_graph_capture(csv_ctx* ctx, int32_t count, const csv_params* params,
+                      const csv_gop_stream* in, uint8_t* const* frames_out,
+                      float* const* cs_float_out, double* const* obj_out, void* stream,
+                      csv_graph** out) {
+    return guarded([&] {
+        CSV_REQUIRE(ctx && params && in && frames_out && out && count > 0, CSV_EINVAL,
+                    "NULL argument or empty batch");
+        CSV_REQUIRE(stream != nullptr, CSV_EINVAL, "graph capture needs a non-default stream");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        set_device(ctx);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        Ctx* c = C(ctx);
+        std::vector<Shape> shapes;
+        for (int i = 0; i < count; ++i) shapes.push_back(resolve(&params[i]));
+        for (int i = 1; i < count; ++i)
+            CSV_REQUIRE(shapes[i].precision == shapes[0].precision, CSV_EINVAL,
+                        "one precision per batch");
+        // eager pass: builds operators, momentum tables and scratch
+        decode_gops(c, count, shapes.data(), in, frames_out, cs_float_out, obj_out, st);
+        CSV_HIP(hipStreamSynchronize(st));
+        auto g = std::make_unique<csv_graph>();
+        g->ctx = ctx;
+        const bool prof = c->profiling;
+        if (c->last_table_bytes) {
+            void* keep = nullptr;
+            CSV_HIP(hipHostMalloc(&keep, c->last_table_bytes, hipHostMallocDefault));
+            g->keep.push_back(keep);
+            c->capture_host = keep;
+            c->capture_bytes = c->last_table_bytes;
+        }
+        c->profiling = false;
+        c->capturing = true;
+        hipError_t cap = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (cap == hipSuccess) {
+            try {
+                decode_gops(c, count, shapes.data(), in, frames_out, cs_float_out, obj_out, st);
+            } catch (...) {
+                hipGraph_t junk = nullptr;
+                (void)hipStreamEndCapture(st, &junk);
+                if (junk) (void)hipGraphDestroy(junk);
+                c->capturing = false;
+                c->capture_host = nullptr;
+                c->profiling = prof;
+                for (void* p : g->keep) (void)hipHostFree(p);
+                throw;
+            }
+            cap = hipStreamEndCapture(st, &g->graph);
+        }
+        c->capturing = false;
+        c->capture_host = nullptr;
+        c->profiling = prof;
+        if (cap != hipSuccess) {
+            for (void* p : g->keep) (void)hipHostFree(p);
+            throw Error{CSV_EHIP, std::string("stream capture failed: ") + hipGetErrorString(cap)};
+        }
+        const hipError_t e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g->graph);
+            for (void* p : g->keep) (void)hipHostFree(p);
+            throw Error{CSV_EHIP, std::string("graph instantiate failed: ") + hipGetErrorString(e)};
+        }
+        *out = g.release();
+    });
+}
+
+int csv_graph_launch(csv_graph* g, void* stream) {
+    return guarded([&] {
+        CSV_REQUIRE(g && g->exec, CSV_EINVAL, "NULL graph");
+        std::lock_guard<std::mutex> lk(g->ctx->mu);
+        set_device(g->ctx);
+        CSV_HIP(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+    });
+}
+
+int csv_graph_destroy(csv_graph* g) {
+    if (!g) return CSV_OK;
+    return guarded([&] {
+        (void)hipDeviceSynchronize();
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        for (void* p : g->keep) (void)hipHostFree(p);
+        delete g;
     });
 }
 

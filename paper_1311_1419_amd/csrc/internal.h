@@ -96,6 +96,13 @@ struct Ctx {
     std::map<std::string, Scratch> scratch;
     std::map<int, std::pair<float*, int>> beta_tables;   // key: T*2 + ista
     int gen = 0;   // bumps whenever a scratch buffer moves
+    // Stream capture: tile tables go to pinned buffers owned by the graph
+    // (capture_host) instead of the reusable staging buffer, and no host
+    // synchronisation or allocation may happen.
+    bool capturing = false;
+    void* capture_host = nullptr;     // pinned tile table owned by the graph
+    size_t capture_bytes = 0;
+    size_t last_table_bytes = 0;      // size of the latest tile table upload
 };
 
 // Records a pair of events around a named kernel range when profiling is on.
