@@ -8,8 +8,10 @@ marshals arguments: it loads libcsv.so and fails loudly if it is missing.
 """
 from ._native import (CSV_BF16, CSV_FP32, CSV_FLAG_ISTA, CSV_FLAG_LAMBDA_PIXEL_DOMAIN,
                       CsvError, lib)
-from .api import Context, GopStream, Params
+from .api import (Context, GopStream, Params, kernel_choice, load_kernel_choices,
+                  set_kernel_choice)
 from .server import Server, clock
 
-__all__ = ["Context", "GopStream", "Params", "Server", "clock", "CsvError", "CSV_BF16", "CSV_FP32",
+__all__ = ["Context", "GopStream", "Params", "Server", "clock", "kernel_choice",
+           "load_kernel_choices", "set_kernel_choice", "CsvError", "CSV_BF16", "CSV_FP32",
            "CSV_FLAG_ISTA", "CSV_FLAG_LAMBDA_PIXEL_DOMAIN", "lib"]

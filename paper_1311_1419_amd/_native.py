@@ -104,6 +104,12 @@ _SIGS = {
                                     _P(C.c_void_p)]),
     "csv_graph_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
     "csv_graph_destroy": (C.c_int, [C.c_void_p]),
+    "csv_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                               C.c_char_p, _P(C.c_double), _P(C.c_int32), _P(C.c_int32)]),
+    "csv_autotune_load": (C.c_int, [C.c_char_p]),
+    "csv_autotune_choice": (C.c_int, [C.c_int32, C.c_int32, C.c_char_p, C.c_size_t,
+                                      _P(C.c_int32), _P(C.c_int32)]),
+    "csv_autotune_set": (C.c_int, [C.c_int32, C.c_int32, C.c_int32]),
     "csv_clock": (C.c_double, []),
     "csv_server_create": (C.c_int, [C.c_int, _P(CsvServerOpts), _P(C.c_void_p)]),
     "csv_server_destroy": (C.c_int, [C.c_void_p]),

@@ -89,6 +89,22 @@ def _require_cuda(t: torch.Tensor, dtype, name: str):
         raise ValueError(f"{name} must be contiguous")
 
 
+def kernel_choice(block: int, m: int) -> tuple[str, int, int]:
+    """(variant name, index, number of variants) of the fused kernel class."""
+    buf = C.create_string_buffer(128)
+    idx, cnt = C.c_int32(), C.c_int32()
+    N.check(N.lib().csv_autotune_choice(block, m, buf, 128, C.byref(idx), C.byref(cnt)))
+    return buf.value.decode(), idx.value, cnt.value
+
+
+def set_kernel_choice(block: int, m: int, index: int) -> None:
+    N.check(N.lib().csv_autotune_set(block, m, index))
+
+
+def load_kernel_choices(json_path: str) -> None:
+    N.check(N.lib().csv_autotune_load(json_path.encode()))
+
+
 class DecodeGraph:
     """A captured batch decode (csv_graph); keeps its bound buffers alive."""
 
@@ -258,6 +274,19 @@ class Context:
                                           optr if want_obj else None, stream.cuda_stream,
                                           C.byref(h)))
         return DecodeGraph(h, outs, [gs for gs, _ in items])
+
+    # ------------------------------------------------------------ autotuning
+    def autotune(self, block: int, m: int, iters: int = 300, n_blocks: int = 8192,
+                 json_path: str | None = None) -> dict:
+        """Time every fused-kernel variant of the (block, m) class, make the
+        fastest the choice; returns {"times_ms": [...], "best": i, "choice": name}."""
+        ms = (C.c_double * 8)()
+        cnt, best = C.c_int32(), C.c_int32()
+        N.check(N.lib().csv_autotune(self._h, block, m, iters, n_blocks,
+                                     json_path.encode() if json_path else None, ms,
+                                     C.byref(cnt), C.byref(best)))
+        return {"times_ms": list(ms[:cnt.value]), "best": best.value,
+                "choice": kernel_choice(block, m)[0]}
 
     # ---------------------------------------------------------- profiling
     def profile(self, on: bool = True) -> None:

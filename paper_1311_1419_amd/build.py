@@ -16,7 +16,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libcsv.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "server.hip", "k_encode.hip", "k_decode.hip", "k_fista_bf16.hip"]
+SOURCES = ["api.hip", "server.hip", "autotune.hip", "k_encode.hip", "k_decode.hip",
+           "k_fista_bf16.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1,5 +1,6 @@
 // Host side of the C ABI: validation, context and per-stream operator
 // caches, scratch management and the encode / decode orchestration.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -272,14 +273,16 @@ struct FusedJob {
 // class is cut into eight contiguous runs, one per XCD queue (workgroup
 // b is dispatched to XCD b % 8), so tiles of one operator stay on few L2s;
 // idle workgroups steal from the other queues.
-static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st) {
+static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st,
+                       int variant = -1) {
     std::map<std::pair<int, int>, std::vector<FusedTile>> classes;
     for (const FusedJob& j : jobs) {
         const Shape& s = *j.s;
         CSV_REQUIRE(fused_class_supported(s.n, s.Mp), CSV_EUNSUPPORTED,
                     "fused BF16 recovery has no kernel for n=" + std::to_string(s.n) +
                         ", M padded to " + std::to_string(s.Mp));
-        const int nt = fused_tile_blocks(s.n, s.Mp);
+        const int nt = variant >= 0 ? 32 * fused_variants(s.n, s.Mp)[variant].ct
+                                    : fused_tile_blocks(s.n, s.Mp);
         const float* beta = beta_table(c, s.T, (s.flags & CSV_FLAG_ISTA) != 0, st);
         for (int b0 = 0; b0 < j.nblk; b0 += nt) {
             FusedTile t{};
@@ -362,12 +365,37 @@ static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st
         launch_fista_bf16_class(L.n, L.Mp, reinterpret_cast<const FusedTile*>(dev + L.tiles_off),
                                 reinterpret_cast<const int*>(dev + L.qoff_off),
                                 reinterpret_cast<const int*>(dev + L.queue_off),
-                                reinterpret_cast<int*>(dev + L.ctr_off), L.grid, st);
+                                reinterpret_cast<int*>(dev + L.ctr_off), L.grid, st, variant);
     }
 }
 
+// Time one fused launch over nblk blocks with kernel variant `variant`
+// (milliseconds, HIP events on `st`, median of `reps`).
+double time_fused_variant(Ctx* c, const Shape& s, Operator* op, const float* y, const float* lam,
+                          float* S, int nblk, int variant, int reps, hipStream_t st) {
+    std::vector<FusedJob> jobs{FusedJob{&s, op, y, lam, S, nblk}};
+    fista_bf16(c, jobs, st, variant);   // warm-up (also sets the kernel attributes)
+    hipEvent_t a, b;
+    CSV_HIP(hipEventCreate(&a));
+    CSV_HIP(hipEventCreate(&b));
+    std::vector<double> ms;
+    for (int r = 0; r < reps; ++r) {
+        CSV_HIP(hipEventRecord(a, st));
+        fista_bf16(c, jobs, st, variant);
+        CSV_HIP(hipEventRecord(b, st));
+        CSV_HIP(hipEventSynchronize(b));
+        float t = 0.f;
+        CSV_HIP(hipEventElapsedTime(&t, a, b));
+        ms.push_back(t);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    std::sort(ms.begin(), ms.end());
+    return ms[ms.size() / 2];
+}
+
 // Dequantise and compute lambda for nblk blocks of one operator; returns y^.
-static const float* prepare(Ctx* c, const Shape& s, Operator* op, const int8_t* codes,
+const float* prepare(Ctx* c, const Shape& s, Operator* op, const int8_t* codes,
                             const uint8_t* exps, int nblk, float* lam, const std::string& tag,
                             hipStream_t st) {
     float* y = static_cast<float*>(scratch(c, "yhat" + tag, (size_t)nblk * s.Mp * 4));
@@ -480,10 +508,6 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
 
 using namespace csv;
 
-struct csv_ctx {
-    Ctx impl;
-    std::mutex mu;
-};
 
 static Ctx* C(csv_ctx* c) { return &c->impl; }
 

@@ -129,6 +129,11 @@ void free_operators(Ctx* c);   // when c holds the last reference to its cache
 void release_ctx(Ctx* c);      // free everything c allocated
 // Decode `count` GOPs (key frames, recovery of every CS block in one pass,
 // synthesis); the body of csv_decode_gop / csv_decode_batch.
+double time_fused_variant(Ctx* c, const Shape& s, Operator* op, const float* y, const float* lam,
+                          float* S, int nblk, int variant, int reps, hipStream_t st);
+const float* prepare(Ctx* c, const Shape& s, Operator* op, const int8_t* codes,
+                     const uint8_t* exps, int nblk, float* lam, const std::string& tag,
+                     hipStream_t st);
 void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* in,
                  uint8_t* const* frames_out, float* const* cs_float_out, double* const* obj_out,
                  hipStream_t st);
@@ -180,11 +185,28 @@ struct FusedTile {
     int n, Mp;
 };
 void launch_bf16_frag_layout(Operator* op, hipStream_t st);
-int fused_tile_blocks(int n, int Mp);
+struct FusedVariant {
+    const char* name;
+    int ct;   // column tiles of 32 blocks per workgroup
+    void (*launch)(const FusedTile*, const int*, const int*, int*, int, hipStream_t);
+};
 bool fused_class_supported(int n, int Mp);
+const std::vector<FusedVariant>& fused_variants(int n, int Mp);
+int fused_choice(int n, int Mp);
+void set_fused_choice(int n, int Mp, int idx);
+std::vector<std::pair<int, int>> fused_classes();
+int fused_tile_blocks(int n, int Mp);   // blocks per tile of the chosen variant
 // one persistent launch over the tiles of one (n, Mp) class; qoff[0..8]
-// delimit eight per-XCD queues of tile indices, counters[8] start at zero
+// delimit eight per-XCD queues of tile indices, counters[8] start at zero;
+// variant < 0 selects the class's current choice
 void launch_fista_bf16_class(int n, int Mp, const FusedTile* tiles, const int* qoff,
-                             const int* queue, int* counters, int grid, hipStream_t st);
+                             const int* queue, int* counters, int grid, hipStream_t st,
+                             int variant = -1);
 
 }  // namespace csv
+
+// The opaque handle of csv.h.
+struct csv_ctx {
+    csv::Ctx impl;
+    std::mutex mu;
+};

@@ -76,20 +76,6 @@ void launch_bf16_frag_layout(Operator* op, hipStream_t st) {
     CSV_HIP(hipGetLastError());
 }
 
-#ifndef CSV_PF1024
-#define CSV_PF1024 4
-#define CSV_PA1024 2
-#define CSV_SPL1024 2
-#endif
-
-// Column tiles (of 32 blocks) per workgroup for a class (n, Mp).
-static int class_ct(int n, int Mp) {
-    if (n == 1024) return 1;
-    return Mp <= 64 ? 4 : 2;
-}
-
-int fused_tile_blocks(int n, int Mp) { return 32 * class_ct(n, Mp); }
-
 __device__ inline u16x8 pack_bf16(const floatx16& a, int s) {
     u16x8 o;
 #pragma unroll
@@ -444,36 +430,91 @@ static void launch_class(const FusedTile* tiles, const int* qoff, const int* que
     CSV_HIP(hipGetLastError());
 }
 
-// Per class: column tiles CT, waves W and ring depths (forward, adjoint).
-// n = 1024 keeps one 32-block column tile (the iterates of 32 blocks fill
-// half the register file); n = 256 takes four (or two) column tiles.
-void launch_fista_bf16_class(int n, int Mp, const FusedTile* tiles, const int* qoff,
-                             const int* queue, int* counters, int grid, hipStream_t st) {
-#define CSV_CLASS(NN, MM, CT, W, PF, PA, SPL)                                               \
-    if (n == NN && Mp == MM) {                                                              \
-        launch_class<NN, MM, CT, W, PF, PA, SPL>(tiles, qoff, queue, counters, grid, st);   \
-        return;                                                                             \
-    }
-    CSV_CLASS(256, 32, 4, 8, 4, 2, 0)
-    CSV_CLASS(256, 64, 4, 8, 4, 2, 0)
-    CSV_CLASS(256, 96, 2, 8, 4, 2, 0)
-    CSV_CLASS(256, 128, 2, 8, 4, 2, 0)
-    CSV_CLASS(1024, 64, 1, 8, CSV_PF1024, 2, CSV_SPL1024)
-    CSV_CLASS(1024, 128, 1, 8, CSV_PF1024, CSV_PA1024, CSV_SPL1024)
-    CSV_CLASS(1024, 224, 1, 8, CSV_PF1024, 2, CSV_SPL1024)
-    CSV_CLASS(1024, 256, 1, 8, CSV_PF1024, CSV_PA1024, CSV_SPL1024)
-    CSV_CLASS(1024, 416, 1, 8, CSV_PF1024, 2, CSV_SPL1024)
-#undef CSV_CLASS
-    throw Error{CSV_EUNSUPPORTED, "fused BF16 recovery has no kernel for n=" + std::to_string(n) +
-                                      ", padded M=" + std::to_string(Mp)};
+// Kernel variants per (n, Mp) class: column tiles CT, waves W, ring depths
+// (forward, adjoint) and LDS-resident state tiles.  Variant 0 is the
+// default; the autotuner (csv_autotune) times them and records a choice.
+template <int N, int MP, int CT, int W, int PF, int PA, int SPL>
+static void launch_variant(const FusedTile* tiles, const int* qoff, const int* queue,
+                           int* counters, int grid, hipStream_t st) {
+    launch_class<N, MP, CT, W, PF, PA, SPL>(tiles, qoff, queue, counters, grid, st);
 }
 
-bool fused_class_supported(int n, int Mp) {
-    static const int classes[][2] = {{256, 32},  {256, 64},   {256, 96},   {256, 128}, {1024, 64},
-                                     {1024, 128}, {1024, 224}, {1024, 256}, {1024, 416}};
-    for (const auto& c : classes)
-        if (c[0] == n && c[1] == Mp) return true;
-    return false;
+#define CSV_V(NN, MM, CT, W, PF, PA, SPL)                                          \
+    FusedVariant {                                                                 \
+        "ct" #CT "_w" #W "_pf" #PF "_pa" #PA "_spl" #SPL, CT,                    \
+            &launch_variant<NN, MM, CT, W, PF, PA, SPL>                            \
+    }
+
+struct ClassEntry {
+    int n, Mp;
+    std::vector<FusedVariant> v;
+    int choice;
+};
+
+static std::vector<ClassEntry>& class_table() {
+    static std::vector<ClassEntry> t = {
+        {256, 32, {CSV_V(256, 32, 4, 8, 4, 2, 0), CSV_V(256, 32, 2, 8, 4, 2, 0)}, 0},
+        {256, 64, {CSV_V(256, 64, 4, 8, 4, 2, 0), CSV_V(256, 64, 2, 8, 4, 2, 0)}, 0},
+        {256, 96, {CSV_V(256, 96, 2, 8, 4, 2, 0), CSV_V(256, 96, 4, 8, 4, 2, 0)}, 0},
+        {256, 128, {CSV_V(256, 128, 2, 8, 4, 2, 0), CSV_V(256, 128, 4, 8, 4, 2, 0)}, 0},
+        {1024, 64, {CSV_V(1024, 64, 1, 8, 4, 2, 2), CSV_V(1024, 64, 1, 8, 4, 2, 0)}, 0},
+        {1024, 128, {CSV_V(1024, 128, 1, 8, 4, 2, 2), CSV_V(1024, 128, 1, 8, 4, 2, 0)}, 0},
+        {1024, 224, {CSV_V(1024, 224, 1, 8, 4, 2, 2), CSV_V(1024, 224, 1, 8, 4, 2, 0)}, 0},
+        {1024, 256,
+         {CSV_V(1024, 256, 1, 8, 4, 2, 2), CSV_V(1024, 256, 1, 8, 4, 2, 0),
+          CSV_V(1024, 256, 1, 8, 8, 2, 2), CSV_V(1024, 256, 1, 8, 4, 2, 1)},
+         0},
+        {1024, 416, {CSV_V(1024, 416, 1, 8, 4, 2, 2), CSV_V(1024, 416, 1, 8, 4, 2, 0)}, 0},
+    };
+    return t;
+}
+#undef CSV_V
+
+static ClassEntry* find_class(int n, int Mp) {
+    for (auto& c : class_table())
+        if (c.n == n && c.Mp == Mp) return &c;
+    return nullptr;
+}
+
+bool fused_class_supported(int n, int Mp) { return find_class(n, Mp) != nullptr; }
+
+const std::vector<FusedVariant>& fused_variants(int n, int Mp) {
+    ClassEntry* c = find_class(n, Mp);
+    CSV_REQUIRE(c, CSV_EUNSUPPORTED,
+                "fused BF16 recovery has no kernel for n=" + std::to_string(n) +
+                    ", padded M=" + std::to_string(Mp));
+    return c->v;
+}
+
+int fused_choice(int n, int Mp) {
+    ClassEntry* c = find_class(n, Mp);
+    return c ? c->choice : 0;
+}
+
+void set_fused_choice(int n, int Mp, int idx) {
+    ClassEntry* c = find_class(n, Mp);
+    CSV_REQUIRE(c && idx >= 0 && idx < (int)c->v.size(), CSV_EINVAL, "no such kernel variant");
+    c->choice = idx;
+}
+
+std::vector<std::pair<int, int>> fused_classes() {
+    std::vector<std::pair<int, int>> out;
+    for (auto& c : class_table()) out.push_back({c.n, c.Mp});
+    return out;
+}
+
+int fused_tile_blocks(int n, int Mp) {
+    const auto& v = fused_variants(n, Mp);
+    return 32 * v[fused_choice(n, Mp)].ct;
+}
+
+void launch_fista_bf16_class(int n, int Mp, const FusedTile* tiles, const int* qoff,
+                             const int* queue, int* counters, int grid, hipStream_t st,
+                             int variant) {
+    const auto& v = fused_variants(n, Mp);
+    const int idx = variant >= 0 ? variant : fused_choice(n, Mp);
+    CSV_REQUIRE(idx < (int)v.size(), CSV_EINVAL, "no such kernel variant");
+    v[idx].launch(tiles, qoff, queue, counters, grid, st);
 }
 
 }  // namespace csv
