@@ -16,6 +16,7 @@ with HIP events on its own stream inside the timed region.
 from __future__ import annotations
 
 import argparse
+import collections
 import json
 import os
 import sys
@@ -241,14 +242,23 @@ def serve_main(args):
                 arr.sort()
                 base = srv.stats()
                 t0 = P.clock()
-                tickets = []
+                pending = collections.deque()
+
+                def collect():
+                    # a client takes decoded GOPs as they finish (in order),
+                    # which releases their frames from the server budget
+                    while pending and srv.poll(pending[0]):
+                        pending.popleft()
+
                 for ta, i in arr:
                     while P.clock() < t0 + ta:
+                        collect()
                         time.sleep(0.0002)
-                    tickets.append(srv.submit(sids[i], enc[i][1], t0 + ta))
-                srv.drain(600.0)
-                for t in tickets:
-                    srv.poll(t)
+                    pending.append(srv.submit(sids[i], enc[i][1], t0 + ta))
+                while pending:
+                    collect()
+                    time.sleep(0.0005)
+                srv.drain(60.0)
                 st = srv.stats()
             # the warm-up requests are included in the latency statistics only
             # through their (short) own latencies; 6 of several hundred
@@ -264,10 +274,15 @@ def serve_main(args):
                           "max_concurrent_batches": st["max_concurrent"]})
             print(json.dumps({"sweep_point": sweep[-1]}), flush=True)
     best = max(sweep, key=lambda r: r["served_mpix_s"])
+    # stable: the server keeps up with the offered load (served within 5% of
+    # offered); the highest such point is the load the server sustains
+    stable = [r for r in sweep if r["served_mpix_s"] >= 0.95 * r["offered_mpix_s"]]
+    top = max(stable, key=lambda r: r["load"]) if stable else None
     print(json.dumps({
         "metric": "served Mpixel/s and p99 latency, 256 cameras, Poisson GOP arrivals",
         "value": best["served_mpix_s"], "unit": "Mpixel/s", "n_gpus": 1,
         "p99_ms": best["p99_ms"], "p50_ms": best["p50_ms"],
+        "highest_stable_load": top,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": "serve256-vga/720p-b16-m/n0.1,0.25-g8..32-t300",

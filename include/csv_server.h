@@ -35,7 +35,10 @@ enum {
 };
 
 typedef struct {
-    size_t mem_budget;          /* bytes for admitted requests' outputs and working set (0: 4 GiB) */
+    size_t mem_budget;          /* device bytes charged to requests (0: 4 GiB): an admitted or
+                                   running request holds its decoded frames plus its recovery
+                                   working set; a finished one holds only its frames, until
+                                   csv_poll or csv_cancel releases them */
     int32_t max_queue;          /* waiting requests beyond which csv_submit returns CSV_EAGAIN (0: 4096) */
     int32_t max_batch_blocks;   /* recovery blocks per batch (0: 262144) */
     int32_t precision;          /* CSV_BF16 or CSV_FP32 for every request */
@@ -84,7 +87,10 @@ int csv_poll(csv_server* srv, uint64_t ticket, uint8_t* frames_out, int32_t* don
  * the device is discarded when its batch ends. */
 int csv_cancel(csv_server* srv, uint64_t ticket);
 
-/* Block until nothing waits or runs, or timeout_s elapses (CSV_EAGAIN). */
+/* Block until nothing waits or runs.  Returns CSV_EAGAIN when timeout_s
+ * elapses, and at once when the queue can make no progress: nothing runs and
+ * the next waiting request does not fit the budget left by finished requests
+ * that were not polled (poll or cancel them, then drain again). */
 int csv_server_drain(csv_server* srv, double timeout_s);
 
 int csv_server_stats(csv_server* srv, csv_stats* out);

@@ -333,7 +333,7 @@ static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st
     }
     char* dev = static_cast<char*>(scratch(c, "tiles", bytes));
     struct Launch {
-        int n, Mp, grid;
+        int n, Mp, count;
         size_t tiles_off, qoff_off, queue_off, ctr_off;
     };
     std::vector<Launch> launches;
@@ -341,7 +341,7 @@ static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st
     for (auto& kv : classes) {
         const auto& v = kv.second;
         const int count = (int)v.size();
-        Launch L{kv.first.first, kv.first.second, std::min(count, 256), off_t, 0, 0, 0};
+        Launch L{kv.first.first, kv.first.second, count, off_t, 0, 0, 0};
         std::memcpy(host + off_t, v.data(), v.size() * sizeof(FusedTile));
         off_t += v.size() * sizeof(FusedTile);
         int* qoff = reinterpret_cast<int*>(host + off_i);
@@ -365,7 +365,7 @@ static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st
         launch_fista_bf16_class(L.n, L.Mp, reinterpret_cast<const FusedTile*>(dev + L.tiles_off),
                                 reinterpret_cast<const int*>(dev + L.qoff_off),
                                 reinterpret_cast<const int*>(dev + L.queue_off),
-                                reinterpret_cast<int*>(dev + L.ctr_off), L.grid, st, variant);
+                                reinterpret_cast<int*>(dev + L.ctr_off), L.count, st, variant);
     }
 }
 

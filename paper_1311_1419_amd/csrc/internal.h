@@ -187,7 +187,8 @@ struct FusedTile {
 void launch_bf16_frag_layout(Operator* op, hipStream_t st);
 struct FusedVariant {
     const char* name;
-    int ct;   // column tiles of 32 blocks per workgroup
+    int ct;    // column tiles of 32 blocks per workgroup
+    int occ;   // workgroups resident per CU
     void (*launch)(const FusedTile*, const int*, const int*, int*, int, hipStream_t);
 };
 bool fused_class_supported(int n, int Mp);
@@ -196,11 +197,12 @@ int fused_choice(int n, int Mp);
 void set_fused_choice(int n, int Mp, int idx);
 std::vector<std::pair<int, int>> fused_classes();
 int fused_tile_blocks(int n, int Mp);   // blocks per tile of the chosen variant
-// one persistent launch over the tiles of one (n, Mp) class; qoff[0..8]
-// delimit eight per-XCD queues of tile indices, counters[8] start at zero;
-// variant < 0 selects the class's current choice
+// one persistent launch over the `count` tiles of one (n, Mp) class;
+// qoff[0..8] delimit eight per-XCD queues of tile indices, counters[8] start
+// at zero; variant < 0 selects the class's current choice.  The grid is
+// min(count, CUs x the variant's workgroups per CU).
 void launch_fista_bf16_class(int n, int Mp, const FusedTile* tiles, const int* qoff,
-                             const int* queue, int* counters, int grid, hipStream_t st,
+                             const int* queue, int* counters, int count, hipStream_t st,
                              int variant = -1);
 
 }  // namespace csv

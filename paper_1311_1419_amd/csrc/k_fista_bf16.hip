@@ -26,6 +26,9 @@
 // register 8 s + e of the accumulator.  The operator fragments are stored
 // with that same K order, so the products are exact permutations of the
 // plain sums.
+#include <algorithm>
+#include <atomic>
+
 #include "internal.h"
 #include "mfma.h"
 
@@ -175,9 +178,11 @@ __device__ inline void store_residual(const floatx16& acc, const floatx16& yv, c
 }
 
 // SPL: accumulator tiles per wave whose s_{k-1} lives in LDS rather than in
-// registers (the registers go to deeper operator rings instead).
-template <int N, int MP, int CT, int W, int kPF, int kPA, int SPL>
-__global__ __launch_bounds__(64 * W, 1) void fista_bf16_kernel(
+// registers (the registers go to deeper operator rings instead).  OCC
+// workgroups share a CU, so a wave gets 512 / (W OCC / 4) registers.
+template <int N, int MP, int CT, int W, int kPF, int kPA, int SPL, int OCC>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W * OCC / 4)))
+void fista_bf16_kernel(
     const FusedTile* __restrict__ tiles, const int* __restrict__ qoff,
     const int* __restrict__ queue, int* __restrict__ counters) {
     constexpr int RT = N / 32 / W;               // 32-row groups of n owned per wave
@@ -414,12 +419,16 @@ __global__ __launch_bounds__(64 * W, 1) void fista_bf16_kernel(
     }
 }
 
-template <int N, int MP, int CT, int W, int PF, int PA, int SPL>
+template <int N, int MP, int CT, int W, int PF, int PA, int SPL, int OCC>
 static void launch_class(const FusedTile* tiles, const int* qoff, const int* queue, int* counters,
                          int grid, hipStream_t st) {
+    static_assert(W * OCC % 4 == 0 && W * OCC <= 32, "waves per CU");
     const size_t lds = (size_t)(N / 16) * CT * 1024 + (size_t)(MP / 16) * CT * 1024 +
                        (size_t)W * SPL * 4096;
-    auto* fn = &fista_bf16_kernel<N, MP, CT, W, PF, PA, SPL>;
+    static_assert(((size_t)(N / 16) * CT * 1024 + (size_t)(MP / 16) * CT * 1024 +
+                   (size_t)W * SPL * 4096 + 64) * OCC <= 160 * 1024,
+                  "LDS of OCC workgroups exceeds a CU");
+    auto* fn = &fista_bf16_kernel<N, MP, CT, W, PF, PA, SPL, OCC>;
     static bool attr_set = false;
     if (!attr_set) {
         CSV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
@@ -431,18 +440,13 @@ static void launch_class(const FusedTile* tiles, const int* qoff, const int* que
 }
 
 // Kernel variants per (n, Mp) class: column tiles CT, waves W, ring depths
-// (forward, adjoint) and LDS-resident state tiles.  Variant 0 is the
-// default; the autotuner (csv_autotune) times them and records a choice.
-template <int N, int MP, int CT, int W, int PF, int PA, int SPL>
-static void launch_variant(const FusedTile* tiles, const int* qoff, const int* queue,
-                           int* counters, int grid, hipStream_t st) {
-    launch_class<N, MP, CT, W, PF, PA, SPL>(tiles, qoff, queue, counters, grid, st);
-}
-
-#define CSV_V(NN, MM, CT, W, PF, PA, SPL)                                          \
+// (forward, adjoint), LDS-resident state tiles and workgroups per CU.
+// Variant 0 is the default; the autotuner (csv_autotune) times them and
+// records a choice.
+#define CSV_V(NN, MM, CT, W, PF, PA, SPL, OCC)                                    \
     FusedVariant {                                                                 \
-        "ct" #CT "_w" #W "_pf" #PF "_pa" #PA "_spl" #SPL, CT,                    \
-            &launch_variant<NN, MM, CT, W, PF, PA, SPL>                            \
+        "ct" #CT "_w" #W "_pf" #PF "_pa" #PA "_spl" #SPL "_o" #OCC, CT, OCC,      \
+            &launch_class<NN, MM, CT, W, PF, PA, SPL, OCC>                         \
     }
 
 struct ClassEntry {
@@ -453,18 +457,33 @@ struct ClassEntry {
 
 static std::vector<ClassEntry>& class_table() {
     static std::vector<ClassEntry> t = {
-        {256, 32, {CSV_V(256, 32, 4, 8, 4, 2, 0), CSV_V(256, 32, 2, 8, 4, 2, 0)}, 0},
-        {256, 64, {CSV_V(256, 64, 4, 8, 4, 2, 0), CSV_V(256, 64, 2, 8, 4, 2, 0)}, 0},
-        {256, 96, {CSV_V(256, 96, 2, 8, 4, 2, 0), CSV_V(256, 96, 4, 8, 4, 2, 0)}, 0},
-        {256, 128, {CSV_V(256, 128, 2, 8, 4, 2, 0), CSV_V(256, 128, 4, 8, 4, 2, 0)}, 0},
-        {1024, 64, {CSV_V(1024, 64, 1, 8, 4, 2, 2), CSV_V(1024, 64, 1, 8, 4, 2, 0)}, 0},
-        {1024, 128, {CSV_V(1024, 128, 1, 8, 4, 2, 2), CSV_V(1024, 128, 1, 8, 4, 2, 0)}, 0},
-        {1024, 224, {CSV_V(1024, 224, 1, 8, 4, 2, 2), CSV_V(1024, 224, 1, 8, 4, 2, 0)}, 0},
-        {1024, 256,
-         {CSV_V(1024, 256, 1, 8, 4, 2, 2), CSV_V(1024, 256, 1, 8, 4, 2, 0),
-          CSV_V(1024, 256, 1, 8, 8, 2, 2), CSV_V(1024, 256, 1, 8, 4, 2, 1)},
+        {256, 32,
+         {CSV_V(256, 32, 2, 4, 4, 2, 0, 2), CSV_V(256, 32, 1, 4, 4, 2, 0, 3),
+          CSV_V(256, 32, 2, 8, 4, 2, 0, 1), CSV_V(256, 32, 4, 8, 4, 2, 0, 1)},
          0},
-        {1024, 416, {CSV_V(1024, 416, 1, 8, 4, 2, 2), CSV_V(1024, 416, 1, 8, 4, 2, 0)}, 0},
+        {256, 64,
+         {CSV_V(256, 64, 1, 4, 4, 2, 0, 3), CSV_V(256, 64, 2, 4, 4, 2, 0, 2),
+          CSV_V(256, 64, 2, 8, 4, 2, 0, 1), CSV_V(256, 64, 4, 8, 4, 2, 0, 1)},
+         0},
+        {256, 96,
+         {CSV_V(256, 96, 2, 8, 4, 2, 0, 1), CSV_V(256, 96, 4, 8, 4, 2, 0, 1),
+          CSV_V(256, 96, 2, 4, 2, 2, 0, 2), CSV_V(256, 96, 1, 4, 2, 2, 0, 3)},
+         0},
+        {256, 128,
+         {CSV_V(256, 128, 2, 4, 2, 2, 0, 2), CSV_V(256, 128, 1, 4, 2, 2, 0, 3),
+          CSV_V(256, 128, 2, 8, 4, 2, 0, 1), CSV_V(256, 128, 4, 8, 4, 2, 0, 1)},
+         0},
+        {1024, 64, {CSV_V(1024, 64, 1, 8, 4, 2, 2, 1), CSV_V(1024, 64, 1, 8, 4, 2, 0, 1)}, 0},
+        {1024, 128, {CSV_V(1024, 128, 1, 8, 4, 2, 2, 1), CSV_V(1024, 128, 1, 8, 4, 2, 0, 1)}, 0},
+        {1024, 224, {CSV_V(1024, 224, 1, 8, 4, 2, 2, 1), CSV_V(1024, 224, 1, 8, 4, 2, 0, 1)}, 0},
+        {1024, 256,
+         {CSV_V(1024, 256, 1, 8, 4, 2, 2, 1), CSV_V(1024, 256, 1, 8, 4, 2, 0, 1),
+          CSV_V(1024, 256, 1, 8, 8, 2, 2, 1), CSV_V(1024, 256, 1, 8, 4, 2, 1, 1)},
+         0},
+        {1024, 416,
+         {CSV_V(1024, 416, 1, 8, 2, 2, 2, 1), CSV_V(1024, 416, 1, 8, 4, 2, 2, 1),
+          CSV_V(1024, 416, 1, 8, 2, 2, 0, 1)},
+         0},
     };
     return t;
 }
@@ -508,12 +527,28 @@ int fused_tile_blocks(int n, int Mp) {
     return 32 * v[fused_choice(n, Mp)].ct;
 }
 
+// Compute units of the current device (cached per device).
+static int device_cus() {
+    static std::atomic<int> cus[64];
+    int dev = 0;
+    CSV_HIP(hipGetDevice(&dev));
+    CSV_REQUIRE(dev >= 0 && dev < 64, CSV_EINVAL, "device index out of range");
+    int c = cus[dev].load(std::memory_order_relaxed);
+    if (c <= 0) {
+        CSV_HIP(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
+        CSV_REQUIRE(c > 0, CSV_EHIP, "device reports no compute units");
+        cus[dev].store(c, std::memory_order_relaxed);
+    }
+    return c;
+}
+
 void launch_fista_bf16_class(int n, int Mp, const FusedTile* tiles, const int* qoff,
-                             const int* queue, int* counters, int grid, hipStream_t st,
+                             const int* queue, int* counters, int count, hipStream_t st,
                              int variant) {
     const auto& v = fused_variants(n, Mp);
     const int idx = variant >= 0 ? variant : fused_choice(n, Mp);
     CSV_REQUIRE(idx < (int)v.size(), CSV_EINVAL, "no such kernel variant");
+    const int grid = std::min(count, device_cus() * v[idx].occ);
     v[idx].launch(tiles, qoff, queue, counters, grid, st);
 }
 

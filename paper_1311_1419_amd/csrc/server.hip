@@ -222,6 +222,14 @@ struct Server {
         return b;
     }
 
+    // Nothing runs or waits for a slot, yet the head request cannot be
+    // admitted: only csv_poll (or csv_cancel) of finished requests frees
+    // the budget it needs.
+    bool stalled_locked() const {
+        return !waiting.empty() && admitted.empty() && busy_slots() == 0 &&
+               bytes + waiting.front()->bytes > o.mem_budget;
+    }
+
     // Admit in arrival order while the budget allows (head-of-line).
     void admit_locked() {
         while (!waiting.empty()) {
@@ -260,6 +268,10 @@ struct Server {
                 r->msg = msg;
                 ++st.failed;
             } else {
+                // the recovery working set is free once the batch is done;
+                // only the decoded frames stay charged until csv_poll
+                bytes -= r->bytes - r->out_bytes;
+                r->bytes = r->out_bytes;
                 r->state = DONE;
                 ++st.completed;
                 const StreamInfo& si = streams[r->sid];
@@ -546,6 +558,9 @@ int csv_server_drain(csv_server* srv, double timeout_s) {
         const auto until = std::chrono::steady_clock::now() +
                            std::chrono::microseconds((long long)(timeout_s * 1e6));
         while (!(s.waiting.empty() && s.admitted.empty() && s.busy_slots() == 0)) {
+            CSV_REQUIRE(!s.stalled_locked(), CSV_EAGAIN,
+                        "drain cannot finish: finished requests that were not polled hold the "
+                        "memory budget the next request needs");
             if (s.cv.wait_until(lk, until) == std::cv_status::timeout &&
                 !(s.waiting.empty() && s.admitted.empty() && s.busy_slots() == 0))
                 throw Error{CSV_EAGAIN, "drain timed out"};

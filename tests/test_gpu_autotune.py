@@ -16,7 +16,10 @@ pytestmark = pytest.mark.gpu
 SPECS = [(sv.qcif_tiny(), "b16-m64"), (sv.cif_sweep(4, 0.1), "b16-m26"),
          (sv.cif_sweep(4, 0.3), "b16-m77"), (sv.cif_sweep(4, 0.5), "b16-m128"),
          (sv.vga_precision(0.25, gop=3), "b32-m256"),
-         (sv.qcif_tiny().with_(block=32, m=102, gop=3, iters=300), "b32-m102")]
+         (sv.qcif_tiny().with_(block=32, m=102, gop=3, iters=300), "b32-m102"),
+         (sv.qcif_tiny().with_(block=32, m=51, gop=2, iters=300), "b32-m51"),
+         (sv.qcif_tiny().with_(block=32, m=205, gop=2, iters=300), "b32-m205"),
+         (sv.vga_precision(0.4, gop=2), "b32-m410")]
 
 
 @pytest.mark.parametrize("spec", [s for s, _ in SPECS], ids=[i for _, i in SPECS])
@@ -53,7 +56,7 @@ def test_autotune_records_and_reloads(ctx, tmp_path):
     assert table["arch"] == "gfx950"
     entry = [c for c in table["classes"] if c["n"] == 256 and c["Mp"] == 64][0]
     assert entry["variant"] == res["choice"] and len(entry["ms"]) == len(res["times_ms"])
-    P.set_kernel_choice(16, 64, 1 - res["best"])
+    P.set_kernel_choice(16, 64, (res["best"] + 1) % len(res["times_ms"]))
     P.load_kernel_choices(path)
     assert P.kernel_choice(16, 64)[0] == res["choice"]
     P.set_kernel_choice(16, 64, 0)

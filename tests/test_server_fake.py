@@ -19,7 +19,8 @@ class FakeGop:
 
 
 PARAMS = P.Params(width=176, height=144, gop=4, block=16, m=64)   # 297 blocks, 101 376 output bytes
-REQ_BYTES = 4 * 176 * 144 + 3 * 99 * (256 * 4 + 64 * 4 + 4)
+OUT_BYTES = 4 * 176 * 144
+REQ_BYTES = OUT_BYTES + 3 * 99 * (256 * 4 + 64 * 4 + 4)
 
 
 def _server(**kw):
@@ -58,21 +59,42 @@ def test_submit_poll_and_stats():
 
 
 def test_memory_budget_limits_admission():
-    with _server(mem_budget=2 * REQ_BYTES) as srv:
+    # 297 blocks at 100 us each: a request runs for about 30 ms
+    with _server(mem_budget=2 * REQ_BYTES, fake_us_per_block=100.0) as srv:
         sid = srv.register_stream(PARAMS)
         tickets = [srv.submit(sid, FakeGop()) for _ in range(5)]
-        time.sleep(0.05)
+        time.sleep(0.005)
         st = srv.stats()
         assert st["admitted"] == 2 and st["queue_depth"] == 3
-        assert st["peak_bytes"] <= 2 * REQ_BYTES
-        with pytest.raises(N.CsvError) as ei:          # outputs held until polled
-            srv.drain(0.05)
-        assert ei.value.code == N.CSV_EAGAIN
-        for t in tickets:                               # polling frees memory, the rest admit
-            _poll_until(srv, t)
-        srv.drain(5.0)
+        # finished requests keep only their frames charged, so all five fit
+        # without any poll
+        srv.drain(10.0)
         st = srv.stats()
         assert st["completed"] == 5 and st["peak_bytes"] <= 2 * REQ_BYTES
+        assert st["bytes_in_flight"] == 5 * OUT_BYTES
+        for t in tickets:
+            _poll_until(srv, t)
+        assert srv.stats()["bytes_in_flight"] == 0
+
+
+def test_drain_reports_a_budget_held_by_unpolled_outputs():
+    # room for one running request and one finished output: the third
+    # request cannot be admitted until a finished one is polled
+    with _server(mem_budget=REQ_BYTES + OUT_BYTES) as srv:
+        sid = srv.register_stream(PARAMS)
+        tickets = [srv.submit(sid, FakeGop()) for _ in range(3)]
+        t0 = time.time()
+        with pytest.raises(N.CsvError) as ei:
+            srv.drain(30.0)
+        assert ei.value.code == N.CSV_EAGAIN and "not polled" in str(ei.value)
+        assert time.time() - t0 < 5.0                   # reported, not timed out
+        st = srv.stats()
+        assert st["completed"] == 2 and st["queue_depth"] == 1
+        for t in tickets[:2]:
+            _poll_until(srv, t)
+        srv.drain(5.0)
+        _poll_until(srv, tickets[2])
+        assert srv.stats()["completed"] == 3
 
 
 def test_queue_full_and_oversized_request():
