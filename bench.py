@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--fp32-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the device-ceiling microbenchmarks")
     ap.add_argument("--cpu-blocks", type=int, default=3000,
                     help="blocks the oracle recovers for the CPU baseline")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -340,6 +342,14 @@ def main():
             fp32["psnr_loss_db_max"] = float(np.max(loss))
         mean_psnr = float(np.mean([psnr(v[t], fb[t]) for v, fb in zip(videos, bf16_frames)
                                    for t in range(1, v.shape[0])]))
+        ceilings = None if args.no_ceilings else ctx.probe_ceilings()
+    variant = P.kernel_choice(32, 256)[0]
+    # L2 -> CU bytes of the fused launch: every tile of 32 blocks reads both
+    # fragment layouts of its operator (2 x Mp x n bf16) once per iteration
+    tiles = sum(-(-((s.gop - 1) * ((s.height + 31) // 32) * ((s.width + 31) // 32)) // 32)
+                for s in specs)
+    l2_bytes = sum(-(-((s.gop - 1) * ((s.height + 31) // 32) * ((s.width + 31) // 32)) // 32)
+                   * s.iters * 2 * (-(-s.m // 32) * 32) * s.n * 2 for s in specs)
 
     value = px_per_step * args.steps / wall / 1e6
     avg_k_s = (k_ms / max(k_n, 1)) / 1e3
@@ -366,11 +376,22 @@ def main():
                      "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_BF16_TFLOPS, 4) if achieved else None,
                      "traffic": measured_traffic(args.streams), "traffic_unit": "bytes/launch",
-                     "kernel": "fista_bf16_kernel<1024,256,1,8,4,2,2>",
-                     "kernel_ms": round(1e3 * avg_k_s, 4), "flops_per_launch": flops_launch},
+                     "kernel": f"fista_bf16_kernel[n=1024,Mp=256] variant {variant}",
+                     "kernel_ms": round(1e3 * avg_k_s, 4), "flops_per_launch": flops_launch,
+                     "tiles_per_launch": tiles, "l2_bytes_per_launch": l2_bytes,
+                     "l2_tbs": round(l2_bytes / avg_k_s / 1e12, 2) if k_n else None},
         "fp32_path": fp32,
         "mean_psnr_db_bf16": round(mean_psnr, 3),
     }
+    if ceilings and k_n:
+        # the same kernel against what microbenchmarks reach on this device
+        line["roofline"]["achievable"] = {
+            "mfma_bf16_tflops": round(ceilings["mfma_bf16_tflops"], 1),
+            "l2_read_tbs": round(ceilings["l2_read_tbs"], 2),
+            "hbm_read_tbs": round(ceilings["hbm_read_tbs"], 2),
+            "lds_read_tbs": round(ceilings["lds_read_tbs"], 2),
+            "frac_mfma": round(achieved / ceilings["mfma_bf16_tflops"], 4),
+            "frac_l2": round(l2_bytes / avg_k_s / 1e12 / ceilings["l2_read_tbs"], 4)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(specs[0], codes_host, args.cpu_blocks)
     print(json.dumps(line), flush=True)

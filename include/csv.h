@@ -231,6 +231,22 @@ int csv_profile_enable(csv_ctx* ctx, int on);
 int csv_profile_query(csv_ctx* ctx, const char* name, double* total_ms, int64_t* launches);
 int csv_profile_reset(csv_ctx* ctx);
 
+/* Achievable ceilings of the context's device, from short microbenchmarks
+ * (synchronous, about 50 ms; allocates and frees 1 GiB + 2 MiB inside the
+ * context budget, CSV_ENOMEM if it does not fit).  A kernel's roofline
+ * fraction is read against these as well as against the datasheet peaks:
+ *   mfma_bf16_tflops  dense 32x32x16 BF16 MFMA chains on every CU;
+ *   l2_read_tbs       every CU streaming the same 1 MiB buffer, which stays
+ *                     resident in each XCD's L2 (L2 -> CU read bandwidth);
+ *   hbm_read_tbs      one pass over a 1 GiB buffer (HBM read bandwidth);
+ *   lds_read_tbs      16-byte LDS reads on every CU.
+ * Bandwidths are in 1e12 bytes/s, totals over the whole device. */
+typedef struct {
+    double mfma_bf16_tflops, l2_read_tbs, hbm_read_tbs, lds_read_tbs;
+    int32_t compute_units;
+} csv_ceilings;
+int csv_probe_ceilings(csv_ctx* ctx, csv_ceilings* out);
+
 #ifdef __cplusplus
 }
 #endif

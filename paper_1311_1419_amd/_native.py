@@ -57,6 +57,12 @@ class CsvStats(C.Structure):
                 ("batches", C.c_int32), ("max_concurrent", C.c_int32)]
 
 
+class CsvCeilings(C.Structure):
+    _fields_ = [("mfma_bf16_tflops", C.c_double), ("l2_read_tbs", C.c_double),
+                ("hbm_read_tbs", C.c_double), ("lds_read_tbs", C.c_double),
+                ("compute_units", C.c_int32)]
+
+
 class CsvError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"csv error {code}: {msg}")
@@ -99,6 +105,7 @@ _SIGS = {
     "csv_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "csv_profile_query": (C.c_int, [C.c_void_p, C.c_char_p, _P(C.c_double), _P(C.c_int64)]),
     "csv_profile_reset": (C.c_int, [C.c_void_p]),
+    "csv_probe_ceilings": (C.c_int, [C.c_void_p, _P(CsvCeilings)]),
     "csv_graph_capture": (C.c_int, [C.c_void_p, C.c_int32, _P(CsvParams), _P(CsvGopStream),
                                     _P(C.c_void_p), _P(C.c_void_p), _P(C.c_void_p), C.c_void_p,
                                     _P(C.c_void_p)]),

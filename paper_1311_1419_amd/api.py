@@ -302,6 +302,13 @@ class Context:
         N.check(N.lib().csv_profile_query(self._h, name.encode(), C.byref(ms), C.byref(cnt)))
         return ms.value, cnt.value
 
+    def probe_ceilings(self) -> dict:
+        """Achievable MFMA BF16 TFLOP/s and L2 / HBM / LDS read TB/s of the
+        device, from short microbenchmarks (synchronous)."""
+        r = N.CsvCeilings()
+        N.check(N.lib().csv_probe_ceilings(self._h, C.byref(r)))
+        return {f: getattr(r, f) for f, _ in N.CsvCeilings._fields_}
+
     # ------------------------------------------------------ single steps
     def phi_matrix(self, p: Params) -> torch.Tensor:
         m, _ = p.resolve()

@@ -797,6 +797,21 @@ int csv_profile_reset(csv_ctx* ctx) {
     });
 }
 
+int csv_probe_ceilings(csv_ctx* ctx, csv_ceilings* out) {
+    return guarded([&] {
+        CSV_REQUIRE(ctx && out, CSV_EINVAL, "NULL argument");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        set_device(ctx);
+        int cus = 0;
+        CSV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                      ctx->impl.device));
+        CSV_REQUIRE(cus > 0, CSV_EHIP, "device reports no compute units");
+        csv_ceilings r{};
+        probe_ceilings(C(ctx), cus, &r);
+        *out = r;
+    });
+}
+
 int csv_phi_matrix(csv_ctx* ctx, const csv_params* p, int8_t* q_out, void* stream) {
     return guarded([&] {
         CSV_REQUIRE(ctx && q_out, CSV_EINVAL, "NULL argument");

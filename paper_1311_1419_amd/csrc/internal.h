@@ -171,6 +171,9 @@ void launch_final64(const double* a64t, const float* s, const int8_t* codes, con
                     const float* lam, int nblk, int M, int Mp, int n, double s_phi, double* obj,
                     hipStream_t st);
 
+// device ceilings (k_probe.hip); synchronous
+void probe_ceilings(Ctx* c, int cus, csv_ceilings* out);
+
 // fused BF16 recovery (k_fista_bf16.hip)
 struct FusedTile {
     const uint16_t* frag_fwd;

@@ -109,3 +109,17 @@ def test_encode_deterministic(ctx):
     b = ctx.encode_gop(frames, p)
     assert np.array_equal(host(a.codes), host(b.codes))
     assert np.array_equal(host(a.exps), host(b.exps))
+
+
+def test_probe_ceilings_are_plausible(ctx):
+    announce("probe_ceilings")
+    held = ctx.bytes_held()
+    c = ctx.probe_ceilings()
+    assert ctx.bytes_held() == held            # probe buffers are freed again
+    assert c["compute_units"] > 0
+    # MI355X: 2.5 PF dense BF16, 8 TB/s HBM; the probes reach a large part
+    # of those and L2/LDS stream faster than HBM
+    assert 500.0 < c["mfma_bf16_tflops"] < 2600.0
+    assert 1.0 < c["hbm_read_tbs"] < 8.5
+    assert c["l2_read_tbs"] > c["hbm_read_tbs"]
+    assert c["lds_read_tbs"] > c["l2_read_tbs"]
