@@ -153,6 +153,14 @@ void release_ctx(Ctx* c) {
             (void)hipEventDestroy(ev.second);
         }
     c->prof_pending.clear();
+    for (int i = 0; i < Ctx::kAux; ++i) {
+        if (c->aux[i]) (void)hipStreamDestroy(c->aux[i]);
+        if (c->aux_done[i]) (void)hipEventDestroy(c->aux_done[i]);
+        c->aux[i] = nullptr;
+        c->aux_done[i] = nullptr;
+    }
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    c->fork_ev = nullptr;
 }
 
 Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
@@ -233,8 +241,8 @@ const float* beta_table(Ctx* c, int T, bool ista, hipStream_t st) {
 
 // --------------------------------------------------------- recovery core
 static void lambda_pass(Ctx* c, const Shape& s, Operator* op, const float* y, int nblk, float* lam,
-                        hipStream_t st) {
-    float* g0 = static_cast<float*>(scratch(c, "g0", (size_t)nblk * s.n * 4));
+                        hipStream_t st, const std::string& g0name) {
+    float* g0 = static_cast<float*>(scratch(c, g0name, (size_t)nblk * s.n * 4));
     const float* opm = (s.flags & CSV_FLAG_LAMBDA_PIXEL_DOMAIN) ? op->phi32 : op->a32;
     launch_gemm_nn(y, opm, g0, nblk, s.n, s.Mp, s.Mp, s.n, s.n, st);
     launch_row_absmax(g0, nblk, s.n, s.n, s.lambda_frac, lam, st);
@@ -397,10 +405,10 @@ double time_fused_variant(Ctx* c, const Shape& s, Operator* op, const float* y, 
 // Dequantise and compute lambda for nblk blocks of one operator; returns y^.
 const float* prepare(Ctx* c, const Shape& s, Operator* op, const int8_t* codes,
                             const uint8_t* exps, int nblk, float* lam, const std::string& tag,
-                            hipStream_t st) {
+                            hipStream_t st, const std::string& g0name) {
     float* y = static_cast<float*>(scratch(c, "yhat" + tag, (size_t)nblk * s.Mp * 4));
     launch_dequant(codes, exps, nblk, s.M, s.Mp, op->s_phi, y, st);
-    lambda_pass(c, s, op, y, nblk, lam, st);
+    lambda_pass(c, s, op, y, nblk, lam, st, g0name);
     return y;
 }
 
@@ -438,6 +446,31 @@ ProfScope::~ProfScope() {
 // Decode `count` GOPs.  Key frames first (Section 3.2: CS frames are decoded
 // only after the key frame), then one recovery pass over every CS block of
 // every GOP, then synthesis onto each decoded key frame (eq. (4)).
+// Fork: the auxiliary streams wait for everything enqueued on st so far.
+// Join: st waits for everything enqueued on the auxiliary streams.  Both are
+// event edges, so they also hold inside a stream capture.
+static void ensure_aux(Ctx* c) {
+    if (c->fork_ev) return;
+    CSV_REQUIRE(!c->capturing, CSV_EINVAL, "auxiliary streams created during graph capture");
+    for (int i = 0; i < Ctx::kAux; ++i) {
+        CSV_HIP(hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking));
+        CSV_HIP(hipEventCreateWithFlags(&c->aux_done[i], hipEventDisableTiming));
+    }
+    CSV_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+}
+
+static void fork_aux(Ctx* c, hipStream_t st) {
+    CSV_HIP(hipEventRecord(c->fork_ev, st));
+    for (int i = 0; i < Ctx::kAux; ++i) CSV_HIP(hipStreamWaitEvent(c->aux[i], c->fork_ev, 0));
+}
+
+static void join_aux(Ctx* c, hipStream_t st) {
+    for (int i = 0; i < Ctx::kAux; ++i) {
+        CSV_HIP(hipEventRecord(c->aux_done[i], c->aux[i]));
+        CSV_HIP(hipStreamWaitEvent(st, c->aux_done[i], 0));
+    }
+}
+
 void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* in,
                  uint8_t* const* frames_out, float* const* cs_float_out, double* const* obj_out,
                  hipStream_t st) {
@@ -456,6 +489,12 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
         items[i].op = s.G > 1 ? get_operator(c, s, st) : nullptr;
         items[i].nblk = (s.G - 1) * s.nb;
     }
+    // GOP i's per-GOP kernels run on auxiliary stream i % kAux (one GOP
+    // alone stays on st); each auxiliary stream has its own lambda scratch
+    const bool spread = count > 1;
+    if (spread) ensure_aux(c);
+    auto lane_of = [&](int i) { return spread ? c->aux[i % Ctx::kAux] : st; };
+    auto g0_of = [&](int i) { return spread ? "g0@" + std::to_string(i % Ctx::kAux) : std::string("g0"); };
     // scratch is sized before any launch that reads it
     for (int i = 0; i < count; ++i) {
         const Shape& s = shapes[i];
@@ -464,44 +503,53 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
         items[i].S = static_cast<float*>(scratch(c, "S" + tag, (size_t)items[i].nblk * s.n * 4));
         items[i].lam = static_cast<float*>(scratch(c, "lam" + tag, (size_t)items[i].nblk * 4));
         scratch(c, "yhat" + tag, (size_t)items[i].nblk * s.Mp * 4);
+        scratch(c, g0_of(i), (size_t)items[i].nblk * s.n * 4);
     }
+    if (spread) fork_aux(c, st);
     for (int i = 0; i < count; ++i) {
         const Shape& s = shapes[i];
-        ProfScope ps(c, "key_decode", st);
-        launch_key_decode(in[i].key_levels, s.W, s.H, s.qstep, frames_out[i], st);
+        Item& it = items[i];
+        const hipStream_t ls = lane_of(i);
+        {
+            ProfScope ps(c, "key_decode", ls);
+            launch_key_decode(in[i].key_levels, s.W, s.H, s.qstep, frames_out[i], ls);
+        }
+        if (!it.nblk) continue;
+        ProfScope ps(c, "prepare", ls);
+        it.y = prepare(c, s, it.op, in[i].codes, in[i].exps, it.nblk, it.lam,
+                       "#" + std::to_string(i), ls, g0_of(i));
     }
+    if (spread) join_aux(c, st);
     std::vector<FusedJob> jobs;
     for (int i = 0; i < count; ++i) {
         const Shape& s = shapes[i];
         Item& it = items[i];
         if (!it.nblk) continue;
-        {
-            ProfScope ps(c, "prepare", st);
-            it.y = prepare(c, s, it.op, in[i].codes, in[i].exps, it.nblk, it.lam,
-                           "#" + std::to_string(i), st);
-        }
         if (s.precision == CSV_FP32) {
-            ProfScope ps(c, "fista_fp32", st);
+            ProfScope ps(c, "fista_fp32", st);   // shares the context's FP32 scratch: serial
             fista_fp32(c, s, it.op, it.y, it.lam, it.nblk, it.S, st);
         } else {
             jobs.push_back(FusedJob{&shapes[i], it.op, it.y, it.lam, it.S, it.nblk});
         }
     }
     if (!jobs.empty()) fista_bf16(c, jobs, st);
+    if (spread) fork_aux(c, st);
     for (int i = 0; i < count; ++i) {
         const Shape& s = shapes[i];
         const Item& it = items[i];
         if (!it.nblk) continue;
+        const hipStream_t ls = lane_of(i);
         if (obj_out && obj_out[i]) {
-            ProfScope ps(c, "final64", st);
+            ProfScope ps(c, "final64", ls);
             launch_final64(it.op->a64t, it.S, in[i].codes, in[i].exps, it.lam, it.nblk, s.M, s.Mp,
-                           s.n, it.op->s_phi, obj_out[i], st);
+                           s.n, it.op->s_phi, obj_out[i], ls);
         }
-        ProfScope ps(c, "synth", st);
+        ProfScope ps(c, "synth", ls);
         const size_t fs = (size_t)s.W * s.H;
         launch_synth(it.S, it.op->dct, frames_out[i], s.W, s.H, s.B, s.nbx, s.nb, s.G - 1,
-                     frames_out[i] + fs, cs_float_out ? cs_float_out[i] : nullptr, st);
+                     frames_out[i] + fs, cs_float_out ? cs_float_out[i] : nullptr, ls);
     }
+    if (spread) join_aux(c, st);
 }
 
 }  // namespace csv

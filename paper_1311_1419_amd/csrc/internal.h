@@ -103,6 +103,13 @@ struct Ctx {
     void* capture_host = nullptr;     // pinned tile table owned by the graph
     size_t capture_bytes = 0;
     size_t last_table_bytes = 0;      // size of the latest tile table upload
+    // Auxiliary streams: per-GOP kernels of a batch decode (key frames,
+    // lambda, FP64 check, synthesis) are spread over them, forked from and
+    // joined back into the caller's stream with events.
+    static constexpr int kAux = 3;
+    hipStream_t aux[kAux] = {};
+    hipEvent_t aux_done[kAux] = {};
+    hipEvent_t fork_ev = nullptr;
 };
 
 // Records a pair of events around a named kernel range when profiling is on.
@@ -131,9 +138,10 @@ void release_ctx(Ctx* c);      // free everything c allocated
 // synthesis); the body of csv_decode_gop / csv_decode_batch.
 double time_fused_variant(Ctx* c, const Shape& s, Operator* op, const float* y, const float* lam,
                           float* S, int nblk, int variant, int reps, hipStream_t st);
+// lambda's adjoint product goes to scratch buffer `g0name`
 const float* prepare(Ctx* c, const Shape& s, Operator* op, const int8_t* codes,
                      const uint8_t* exps, int nblk, float* lam, const std::string& tag,
-                     hipStream_t st);
+                     hipStream_t st, const std::string& g0name = "g0");
 void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* in,
                  uint8_t* const* frames_out, float* const* cs_float_out, double* const* obj_out,
                  hipStream_t st);
