@@ -141,6 +141,14 @@ int csv_compression_ratio(const csv_params* p, uint64_t bits_key, uint64_t bits_
 int csv_encode_gop(csv_ctx* ctx, const csv_params* p, const uint8_t* frames,
                    const csv_gop_stream* out, void* stream);
 
+/* Encode `count` GOPs, possibly of different streams and sizes, with the
+ * same results as `count` csv_encode_gop calls.  params[i], frames[i] and
+ * out[i] describe GOP i (host arrays of `count` entries; frames[i] and the
+ * buffers of out[i] are device memory as for csv_encode_gop).  The GOPs'
+ * kernels overlap on the device.  Asynchronous on `stream`. */
+int csv_encode_batch(csv_ctx* ctx, int32_t count, const csv_params* params,
+                     const uint8_t* const* frames, const csv_gop_stream* out, void* stream);
+
 /* Decode one GOP (Section 3.2, Fig. 4, eqs. (1) and (4)).
  *   frames_out:   device, G*H*W uint8; frame 0 = decoded key frame;
  *   cs_float_out: device, (G-1)*H*W float (decoded key + recovered

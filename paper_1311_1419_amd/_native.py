@@ -84,6 +84,8 @@ _SIGS = {
                                         _P(C.c_double), _P(C.c_double), _P(C.c_double)]),
     "csv_encode_gop": (C.c_int, [C.c_void_p, _P(CsvParams), C.c_void_p,
                                  _P(CsvGopStream), C.c_void_p]),
+    "csv_encode_batch": (C.c_int, [C.c_void_p, C.c_int32, _P(CsvParams), _P(C.c_void_p),
+                                   _P(CsvGopStream), C.c_void_p]),
     "csv_decode_gop": (C.c_int, [C.c_void_p, _P(CsvParams), _P(CsvGopStream), C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_void_p]),
     "csv_decode_batch": (C.c_int, [C.c_void_p, C.c_int32, _P(CsvParams), _P(CsvGopStream),

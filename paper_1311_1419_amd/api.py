@@ -198,6 +198,28 @@ class Context:
                                        C.byref(out.to_c()), _stream(self.device)))
         return out
 
+    def encode_batch(self, items, outs=None):
+        """items: list of (frames G x H x W uint8 tensor, Params).  Encodes
+        every GOP (same results as encode_gop per item) with overlapping
+        kernels; returns the GopStreams (`outs`, if given, are filled)."""
+        count = len(items)
+        params = (N.CsvParams * max(count, 1))()
+        fptr = (C.c_void_p * max(count, 1))()
+        streams = (N.CsvGopStream * max(count, 1))()
+        res = []
+        for i, (frames, p) in enumerate(items):
+            _require_cuda(frames, torch.uint8, "frames")
+            if tuple(frames.shape) != (p.gop, p.height, p.width):
+                raise ValueError("frames must be G x H x W")
+            gs = outs[i] if outs is not None else self.alloc_stream(p)
+            params[i] = p.to_c()
+            fptr[i] = frames.data_ptr()
+            streams[i] = gs.to_c()
+            res.append(gs)
+        N.check(N.lib().csv_encode_batch(self._h, count, params, fptr, streams,
+                                         _stream(self.device)))
+        return res
+
     def decode_gop(self, gs: GopStream, p: Params, want_float: bool = False,
                    want_obj: bool = False):
         m, nb = p.resolve()

@@ -446,6 +446,57 @@ ProfScope::~ProfScope() {
 // Decode `count` GOPs.  Key frames first (Section 3.2: CS frames are decoded
 // only after the key frame), then one recovery pass over every CS block of
 // every GOP, then synthesis onto each decoded key frame (eq. (4)).
+// Forward declarations of the batch helpers below.
+static void ensure_aux(Ctx* c);
+static void fork_aux(Ctx* c, hipStream_t st);
+static void join_aux(Ctx* c, hipStream_t st);
+
+// Encode `count` GOPs (Section 3.1, Fig. 3): key frame coded and decoded,
+// every CS frame's residual against the decoded key frame (eqs. (2)-(3))
+// measured per block and quantised.  GOP i runs on auxiliary stream
+// i % kAux with scratch of its own (one GOP alone runs on st).
+void encode_gops(Ctx* c, int count, const Shape* shapes, const uint8_t* const* frames,
+                 const csv_gop_stream* out, hipStream_t st) {
+    std::vector<Operator*> ops(count, nullptr);
+    for (int i = 0; i < count; ++i) {
+        const Shape& s = shapes[i];
+        CSV_REQUIRE(frames[i] && out[i].key_levels, CSV_EINVAL, "NULL frames or key_levels");
+        CSV_REQUIRE(s.G == 1 || (out[i].codes && out[i].exps), CSV_EINVAL, "codes/exps are NULL");
+        if (s.G > 1) ops[i] = get_operator(c, s, st);
+    }
+    const bool spread = count > 1;
+    if (spread) ensure_aux(c);
+    std::vector<uint8_t*> keydec(count, nullptr);
+    std::vector<int32_t*> ymeas(count, nullptr);
+    for (int i = 0; i < count; ++i) {   // scratch is sized before any launch
+        const Shape& s = shapes[i];
+        if (s.G == 1) continue;
+        const std::string tag = spread ? "#" + std::to_string(i) : std::string();
+        keydec[i] = static_cast<uint8_t*>(scratch(c, "keydec" + tag, (size_t)s.W * s.H));
+        ymeas[i] = static_cast<int32_t*>(
+            scratch(c, "ymeas" + tag, (size_t)(s.G - 1) * s.nb * s.Mp * 4));
+    }
+    if (spread) fork_aux(c, st);
+    for (int i = 0; i < count; ++i) {
+        const Shape& s = shapes[i];
+        const hipStream_t ls = spread ? c->aux[i % Ctx::kAux] : st;
+        const int ncs = s.G - 1;
+        unsigned long long* bits = reinterpret_cast<unsigned long long*>(out[i].bits);
+        if (bits) {
+            launch_fill_u64(bits, 0ull, 1, ls);
+            launch_fill_u64(bits + 1, (unsigned long long)ncs * s.nb * (8ull * s.M + 8ull), 1, ls);
+        }
+        launch_key_encode(frames[i], s.W, s.H, s.qshift, out[i].key_levels, bits, ls);
+        if (!ncs) continue;
+        launch_key_decode(out[i].key_levels, s.W, s.H, s.qstep, keydec[i], ls);
+        const size_t fs = (size_t)s.W * s.H;
+        const int total = ncs * s.nb;
+        launch_measure(s, ops[i]->q, frames[i] + fs, ncs, fs, keydec[i], ymeas[i], ls);
+        launch_quantise(ymeas[i], s.M, s.Mp, total, out[i].codes, out[i].exps, nullptr, ls);
+    }
+    if (spread) join_aux(c, st);
+}
+
 // Fork: the auxiliary streams wait for everything enqueued on st so far.
 // Join: st waits for everything enqueued on the auxiliary streams.  Both are
 // event edges, so they also hold inside a stream capture.
@@ -648,29 +699,24 @@ int csv_encode_gop(csv_ctx* ctx, const csv_params* p, const uint8_t* frames,
                    const csv_gop_stream* out, void* stream) {
     return guarded([&] {
         CSV_REQUIRE(ctx && frames && out, CSV_EINVAL, "NULL argument");
-        CSV_REQUIRE(out->key_levels, CSV_EINVAL, "out->key_levels is NULL");
         std::lock_guard<std::mutex> lk(ctx->mu);
         set_device(ctx);
         const Shape s = resolve(p);
-        hipStream_t st = static_cast<hipStream_t>(stream);
-        const int ncs = s.G - 1;
-        CSV_REQUIRE(ncs == 0 || (out->codes && out->exps), CSV_EINVAL, "codes/exps are NULL");
-        Ctx* c = C(ctx);
-        Operator* op = ncs ? get_operator(c, s, st) : nullptr;
-        unsigned long long* bits = reinterpret_cast<unsigned long long*>(out->bits);
-        if (bits) {
-            launch_fill_u64(bits, 0ull, 1, st);
-            launch_fill_u64(bits + 1, (unsigned long long)ncs * s.nb * (8ull * s.M + 8ull), 1, st);
-        }
-        launch_key_encode(frames, s.W, s.H, s.qshift, out->key_levels, bits, st);
-        if (!ncs) return;
-        uint8_t* keydec = static_cast<uint8_t*>(scratch(c, "keydec", (size_t)s.W * s.H));
-        launch_key_decode(out->key_levels, s.W, s.H, s.qstep, keydec, st);
-        const size_t fs = (size_t)s.W * s.H;
-        const int total = ncs * s.nb;
-        int32_t* y = static_cast<int32_t*>(scratch(c, "ymeas", (size_t)total * s.Mp * 4));
-        launch_measure(s, op->q, frames + fs, ncs, fs, keydec, y, st);
-        launch_quantise(y, s.M, s.Mp, total, out->codes, out->exps, nullptr, st);
+        encode_gops(C(ctx), 1, &s, &frames, out, static_cast<hipStream_t>(stream));
+    });
+}
+
+int csv_encode_batch(csv_ctx* ctx, int32_t count, const csv_params* params,
+                     const uint8_t* const* frames, const csv_gop_stream* out, void* stream) {
+    return guarded([&] {
+        CSV_REQUIRE(count >= 0, CSV_EINVAL, "negative count");
+        if (count == 0) return;
+        CSV_REQUIRE(ctx && params && frames && out, CSV_EINVAL, "NULL argument");
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        set_device(ctx);
+        std::vector<Shape> shapes;
+        for (int i = 0; i < count; ++i) shapes.push_back(resolve(&params[i]));
+        encode_gops(C(ctx), count, shapes.data(), frames, out, static_cast<hipStream_t>(stream));
     });
 }
 

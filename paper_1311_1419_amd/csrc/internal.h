@@ -142,6 +142,9 @@ double time_fused_variant(Ctx* c, const Shape& s, Operator* op, const float* y, 
 const float* prepare(Ctx* c, const Shape& s, Operator* op, const int8_t* codes,
                      const uint8_t* exps, int nblk, float* lam, const std::string& tag,
                      hipStream_t st, const std::string& g0name = "g0");
+// Encode `count` GOPs; the body of csv_encode_gop / csv_encode_batch.
+void encode_gops(Ctx* c, int count, const Shape* shapes, const uint8_t* const* frames,
+                 const csv_gop_stream* out, hipStream_t st);
 void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* in,
                  uint8_t* const* frames_out, float* const* cs_float_out, double* const* obj_out,
                  hipStream_t st);

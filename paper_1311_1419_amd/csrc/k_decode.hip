@@ -444,18 +444,27 @@ __global__ __launch_bounds__(256) void final64_kernel(const double* __restrict__
     for (int i = 0; i < RTW; ++i) acc[i] = doublex4{0.0, 0.0, 0.0, 0.0};
     double l1 = 0.0;   // sum |s| over the staged entries of this thread
     const int sb = tid >> 4, sk = (tid & 15) * 2;   // staging: block sb, k sk, sk+1
-    for (int k0 = 0; k0 < n; k0 += F64_KC) {
-        // issue every operator load of the chunk first (latency overlap)
-        double av[F64_KC / 4][RTW];
+    // operator fragments of one K chunk; the next chunk's loads are issued
+    // before this chunk's products so their latency overlaps the MFMAs
+    double av[F64_KC / 4][RTW], an[F64_KC / 4][RTW];
+    auto load_chunk = [&](double (&dst)[F64_KC / 4][RTW], int k0) {
 #pragma unroll
         for (int kk = 0; kk < F64_KC / 4; ++kk) {
             const size_t krow = (size_t)(k0 + 4 * kk + kq) * Mp;
 #pragma unroll
             for (int i = 0; i < RTW; ++i) {
                 const int rt = wv + 4 * i;
-                av[kk][i] = rt < nrt ? a64t[krow + rt * 16 + j] : 0.0;
+                dst[kk][i] = rt < nrt ? a64t[krow + rt * 16 + j] : 0.0;
             }
         }
+    };
+    load_chunk(an, 0);
+    for (int k0 = 0; k0 < n; k0 += F64_KC) {
+#pragma unroll
+        for (int kk = 0; kk < F64_KC / 4; ++kk)
+#pragma unroll
+            for (int i = 0; i < RTW; ++i) av[kk][i] = an[kk][i];
+        if (k0 + F64_KC < n) load_chunk(an, k0 + F64_KC);
         float2 v = make_float2(0.f, 0.f);
         if (b0 + sb < nblk) v = *reinterpret_cast<const float2*>(s + (size_t)(b0 + sb) * n + k0 + sk);
         __syncthreads();

@@ -123,3 +123,23 @@ def test_probe_ceilings_are_plausible(ctx):
     assert 1.0 < c["hbm_read_tbs"] < 8.5
     assert c["l2_read_tbs"] > c["hbm_read_tbs"]
     assert c["lds_read_tbs"] > c["l2_read_tbs"]
+
+
+def test_encode_batch_equals_oracle_per_gop(ctx):
+    """A batch of GOPs of different sizes, block sizes, M and GOP lengths
+    (including a key-only GOP) encodes to exactly the oracle's streams."""
+    specs = [sv.qcif_tiny(), sv.cif_sweep(4, 0.1, stream=1), sv.qcif_tiny().with_(gop=1),
+             sv.qcif_tiny().with_(block=32, m=102, gop=3), sv.cif_sweep(4, 0.5, stream=2),
+             sv.qcif_tiny(stream=3)]
+    announce(f"encode_batch of {len(specs)} GOPs")
+    vids = [s.video() for s in specs]
+    items = [(dev(v), _params(s)) for v, s in zip(vids, specs)]
+    outs = ctx.encode_batch(items)
+    for spec, v, gs in zip(specs, vids, outs):
+        ref = codec.encode_gop(v, codec.Params.from_spec(spec))
+        assert np.array_equal(host(gs.key_levels).astype(np.int64), ref.key_levels)
+        if spec.gop > 1:
+            assert np.array_equal(host(gs.codes), ref.codes)
+            assert np.array_equal(host(gs.exps), ref.exps)
+        bits = host(gs.bits)
+        assert int(bits[0]) == ref.bits_key and int(bits[1]) == ref.bits_cs
