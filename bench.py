@@ -49,9 +49,10 @@ def parse():
                     help="blocks the oracle recovers for the CPU baseline")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
-    ap.add_argument("--mode", choices=["headline", "mixed", "serve"], default="headline",
+    ap.add_argument("--mode", choices=["headline", "mixed", "serve", "encode"], default="headline",
                     help="headline: the metric above; mixed: 64 mixed streams decoded by one "
-                         "graph-captured batch; serve: 256 cameras under a Poisson load sweep")
+                         "graph-captured batch; serve: 256 cameras under a Poisson load sweep; "
+                         "encode: the headline cameras encoded in each measurement form")
     ap.add_argument("--serve-window", type=float, default=2.0, help="seconds per sweep point")
     ap.add_argument("--serve-loads", type=str, default="0.01,0.02,0.04,0.08",
                     help="fractions of the cameras' nominal GOP rates")
@@ -291,6 +292,58 @@ def serve_main(args):
         "sweep": sweep}), flush=True)
 
 
+def encode_main(args):
+    """The headline cameras' GOPs encoded as one batch in each measurement
+    form (exact integer product on BF16 MFMA, INT8 split-residual MFMA, FP8
+    E4M3 MFMA); reports CS pixels encoded per second and the measurement
+    kernel's algorithmic rate (2 M n operations per block)."""
+    import torch
+    import paper_1311_1419_amd as P
+    specs = make_streams(args.streams)
+    frames_dev = [torch.from_numpy(s.video()).cuda() for s in specs]
+    px = sum((s.gop - 1) * s.height * s.width for s in specs)
+    blocks = sum((s.gop - 1) * ((s.height + 31) // 32) * ((s.width + 31) // 32) for s in specs)
+    ops_step = sum((s.gop - 1) * ((s.height + 31) // 32) * ((s.width + 31) // 32) * 2.0 * s.m * s.n
+                   for s in specs)
+    forms = {"exact_bf16": 0, "int8": P.CSV_FLAG_MEASURE_INT8, "fp8": P.CSV_FLAG_MEASURE_FP8}
+    peaks = {"exact_bf16": 2500.0, "int8": 5000.0, "fp8": 5000.0}   # dense TFLOP/s or TOP/s
+    res = {}
+    with P.Context(0) as ctx:
+        for name, flag in forms.items():
+            params = [P.Params.from_spec(s, precision=P.CSV_BF16, flags=flag) for s in specs]
+            outs = [ctx.alloc_stream(p) for p in params]
+            items = list(zip(frames_dev, params))
+            for _ in range(args.warmup):
+                ctx.encode_batch(items, outs=outs)
+            torch.cuda.synchronize()
+            ctx.profile_reset()
+            ctx.profile(True)
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                ctx.encode_batch(items, outs=outs)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            ctx.profile(False)
+            m_ms, m_n = ctx.profile_query("measure")
+            kernel_ms = m_ms / max(m_n, 1)                 # per GOP launch
+            per_gop_ops = ops_step / len(specs)
+            res[name] = {"mpix_per_s": round(px * args.steps / wall / 1e6, 1),
+                         "ms_per_step": round(1e3 * wall / args.steps, 4),
+                         "measure_kernel_us_per_gop": round(1e3 * kernel_ms, 2),
+                         "measure_tops": round(per_gop_ops / (kernel_ms * 1e-3) / 1e12, 2),
+                         "measure_frac_of_peak": round(per_gop_ops / (kernel_ms * 1e-3) / 1e12
+                                                       / peaks[name], 4)}
+    print(json.dumps({
+        "metric": "encoded CS Mpixel/s per measurement form, 16 cameras 640x480 GOP 16, M/n=0.25",
+        "value": res["exact_bf16"]["mpix_per_s"], "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int8/fp8/bf16", "data": "synthetic",
+        "config": {"workload": WORKLOAD + "-encode", "blocks_per_step": blocks,
+                   "note": "measure kernel timed per GOP launch while the batch's GOPs overlap "
+                           "on three streams"},
+        "forms": res}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -302,6 +355,8 @@ def main():
         return mixed_main(args)
     if args.mode == "serve":
         return serve_main(args)
+    if args.mode == "encode":
+        return encode_main(args)
     import torch
     import paper_1311_1419_amd as P
 

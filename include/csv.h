@@ -61,7 +61,18 @@ enum {
 
 enum {
     CSV_FLAG_ISTA = 1,                 /* no momentum (t_k = 1): proximal gradient */
-    CSV_FLAG_LAMBDA_PIXEL_DOMAIN = 2   /* lambda = frac*||Phi^T y||_inf instead of ||(Phi Psi)^T y||_inf */
+    CSV_FLAG_LAMBDA_PIXEL_DOMAIN = 2,  /* lambda = frac*||Phi^T y||_inf instead of ||(Phi Psi)^T y||_inf */
+    /* Encoder measurement forms (a low-complexity encoder, Sections 1 and 3;
+     * at most one of the two):
+     *   INT8: y~ = 16 Q h + Q l with r = 16 h + l, l in [0, 15], on int8
+     *         MFMA with int32 accumulation; identical to the exact y~ = Q r;
+     *   FP8:  y~ = e4m3(Q) e4m3(r), OCP E4M3 operands (round to nearest
+     *         even) on FP8 MFMA; every E4M3 value of these integers is an
+     *         integer and the FP32 sums stay below 2^24, so y~ is that exact
+     *         integer sum, a few percent away from Q r.
+     * The decoder ignores these flags. */
+    CSV_FLAG_MEASURE_INT8 = 4,
+    CSV_FLAG_MEASURE_FP8 = 8
 };
 
 /* ------------------------------------------------------------ params */
@@ -231,7 +242,7 @@ int csv_graph_destroy(csv_graph* g);
 
 /* ------------------------------------------------------- measurement */
 /* Event timing of named kernel ranges on the stream they run on ("fista_bf16",
- * "fista_fp32", "prepare", "synth", "final64", "key_decode").  While enabled,
+ * "fista_fp32", "prepare", "synth", "final64", "key_decode", "measure").  While enabled,
  * every such range records a pair of HIP events.  csv_profile_query waits
  * for the recorded events and returns the summed milliseconds and the number
  * of ranges for `name` since the last reset. */

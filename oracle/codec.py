@@ -16,7 +16,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import cs, keyframe, philox
+from . import cs, fp8, keyframe, philox
 
 
 @dataclass(frozen=True)
@@ -34,6 +34,7 @@ class Params:
     solver: str = "fista"           # fista | ista | mfista | direct
     pixel_domain_lambda: bool = False
     no_quant: bool = False          # test hook: y^ = s_Phi y~ exactly
+    measure_form: str = "exact"     # exact | int8 | fp8 (encoder product, see fp8.py)
 
     @property
     def n(self) -> int:
@@ -75,7 +76,15 @@ def encode_gop(frames: np.ndarray, p: Params) -> GopStream:
     y_all = np.zeros((g - 1, nb, p.m), dtype=np.int64)
     for t in range(1, g):
         res = frames[t].astype(np.int64) - key_dec.astype(np.int64)
-        y_int = cs.measure(q, cs.gather_blocks(res, p.block))
+        r_cols = cs.gather_blocks(res, p.block)
+        if p.measure_form == "exact":
+            y_int = cs.measure(q, r_cols)
+        elif p.measure_form == "int8":
+            y_int = fp8.measure_int8(q, r_cols)
+        elif p.measure_form == "fp8":
+            y_int = fp8.measure_fp8(q, r_cols)
+        else:
+            raise ValueError(f"unknown measurement form {p.measure_form!r}")
         c, e = cs.quantise(y_int)
         codes[t - 1] = c.T
         exps[t - 1] = e

@@ -21,6 +21,8 @@ CSV_FP32 = 0
 CSV_BF16 = 1
 CSV_FLAG_ISTA = 1
 CSV_FLAG_LAMBDA_PIXEL_DOMAIN = 2
+CSV_FLAG_MEASURE_INT8 = 4
+CSV_FLAG_MEASURE_FP8 = 8
 
 
 class CsvParams(C.Structure):

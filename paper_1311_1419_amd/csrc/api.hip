@@ -53,8 +53,12 @@ Shape resolve(const csv_params* p) {
                 "lambda_frac must be finite and >= 0");
     CSV_REQUIRE(p->precision == CSV_FP32 || p->precision == CSV_BF16, CSV_EINVAL,
                 "precision must be CSV_FP32 or CSV_BF16");
-    CSV_REQUIRE((p->flags & ~(CSV_FLAG_ISTA | CSV_FLAG_LAMBDA_PIXEL_DOMAIN)) == 0, CSV_EINVAL,
-                "unknown flag bits");
+    CSV_REQUIRE((p->flags & ~(CSV_FLAG_ISTA | CSV_FLAG_LAMBDA_PIXEL_DOMAIN |
+                              CSV_FLAG_MEASURE_INT8 | CSV_FLAG_MEASURE_FP8)) == 0,
+                CSV_EINVAL, "unknown flag bits");
+    CSV_REQUIRE((p->flags & (CSV_FLAG_MEASURE_INT8 | CSV_FLAG_MEASURE_FP8)) !=
+                    (CSV_FLAG_MEASURE_INT8 | CSV_FLAG_MEASURE_FP8),
+                CSV_EINVAL, "at most one measurement form flag");
     s.W = p->width;
     s.H = p->height;
     s.G = p->gop;
@@ -182,7 +186,7 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
     const size_t sz_q = Mp * n, sz_a64 = Mp * n * 8, sz_a32 = Mp * n * 4;
     const size_t sz_frag = Mp * n * 2, sz_lip = 64, sz_dct = n * 4, sz_dct64 = n * 8;
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
-    const size_t total = al(sz_q) + 2 * al(sz_a64) + 2 * al(sz_a32) + 2 * al(sz_frag) +
+    const size_t total = 2 * al(sz_q) + 2 * al(sz_a64) + 2 * al(sz_a32) + 2 * al(sz_frag) +
                          al(sz_lip) + al(sz_dct) + al(sz_dct64);
     char* base = static_cast<char*>(ctx_alloc(c, total));
     op->bytes = total;
@@ -193,6 +197,7 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
         return p;
     };
     op->q = reinterpret_cast<int8_t*>(take(sz_q));
+    op->q8 = reinterpret_cast<uint8_t*>(take(sz_q));
     op->a64 = reinterpret_cast<double*>(take(sz_a64));
     op->a64t = reinterpret_cast<double*>(take(sz_a64));
     op->a32 = reinterpret_cast<float*>(take(sz_a32));
@@ -204,6 +209,7 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
     op->dct64 = reinterpret_cast<double*>(take(sz_dct64));
     try {
         launch_phi_q(op->q, s.M, s.Mp, s.n, s.seed, (uint64_t)s.sid, st);
+        launch_q_e4m3(op->q, op->q8, s.Mp * s.n, st);
         launch_operator_setup(op.get(), st);
         launch_bf16_frag_layout(op.get(), st);
         double* gram = static_cast<double*>(scratch(c, "gram", (size_t)s.M * s.M * 8));
@@ -491,7 +497,11 @@ void encode_gops(Ctx* c, int count, const Shape* shapes, const uint8_t* const* f
         launch_key_decode(out[i].key_levels, s.W, s.H, s.qstep, keydec[i], ls);
         const size_t fs = (size_t)s.W * s.H;
         const int total = ncs * s.nb;
-        launch_measure(s, ops[i]->q, frames[i] + fs, ncs, fs, keydec[i], ymeas[i], ls);
+        {
+            ProfScope ps(c, "measure", ls);
+            launch_measure(s, ops[i]->q, ops[i]->q8, frames[i] + fs, ncs, fs, keydec[i], ymeas[i],
+                           ls);
+        }
         launch_quantise(ymeas[i], s.M, s.Mp, total, out[i].codes, out[i].exps, nullptr, ls);
     }
     if (spread) join_aux(c, st);
@@ -993,7 +1003,7 @@ int csv_measure_frame(csv_ctx* ctx, const csv_params* p, const uint8_t* frame,
         Ctx* c = C(ctx);
         Operator* op = get_operator(c, s, st);
         int32_t* y = static_cast<int32_t*>(scratch(c, "ymeas", (size_t)s.nb * s.Mp * 4));
-        launch_measure(s, op->q, frame, 1, (size_t)s.W * s.H, key_decoded, y, st);
+        launch_measure(s, op->q, op->q8, frame, 1, (size_t)s.W * s.H, key_decoded, y, st);
         launch_quantise(y, s.M, s.Mp, s.nb, codes, exps, y_out, st);
     });
 }

@@ -57,6 +57,7 @@ struct Operator {
     uint32_t sid = 0;
     double s_phi = 0;
     int8_t* q = nullptr;          // Mp x n, rows >= M zero
+    uint8_t* q8 = nullptr;        // Mp x n, Q as OCP E4M3 bytes (FP8 measurement form)
     double* a64 = nullptr;        // Mp x n, A = s_phi Q Psi
     double* a64t = nullptr;       // n x Mp, A transposed (final FP64 check)
     float* a32 = nullptr;         // Mp x n
@@ -156,10 +157,13 @@ void launch_phi_q(int8_t* q, int M, int Mp, int n, uint64_t k0, uint64_t k1, hip
 void launch_key_encode(const uint8_t* frame, int W, int H, int qshift, int16_t* levels,
                        unsigned long long* bits, hipStream_t st);
 void launch_key_decode(const int16_t* levels, int W, int H, int qstep, uint8_t* out, hipStream_t st);
-void launch_measure(const Shape& s, const int8_t* q, const uint8_t* frames, int n_frames,
-                    size_t frame_stride, const uint8_t* key, int32_t* y_scratch, hipStream_t st);
+// exact BF16-MFMA product, or the INT8 / FP8 form selected by s.flags
+void launch_measure(const Shape& s, const int8_t* q, const uint8_t* q8, const uint8_t* frames,
+                    int n_frames, size_t frame_stride, const uint8_t* key, int32_t* y_scratch,
+                    hipStream_t st);
 void launch_quantise(const int32_t* y, int M, int Mp, int total, int8_t* codes, uint8_t* exps,
                      int32_t* y_out, hipStream_t st);
+void launch_q_e4m3(const int8_t* q, uint8_t* q8, size_t count, hipStream_t st);
 void launch_fill_u64(unsigned long long* p, unsigned long long v, int count, hipStream_t st);
 
 // decode side (k_decode.hip)

@@ -191,71 +191,237 @@ void launch_key_decode(const int16_t* levels, int W, int H, int qstep, uint8_t* 
     CSV_HIP(hipGetLastError());
 }
 
+// OCP FP8 E4M3 byte of an integer |v| <= 448: 1 sign bit, 4 exponent bits
+// (bias 7), 3 mantissa bits, round to nearest, ties to even.  Integers below
+// 16 are exact; above, the significand keeps its top 4 bits.
+__device__ inline uint32_t int_to_e4m3(int v) {
+    const uint32_t sgn = v < 0 ? 0x80u : 0u;
+    const uint32_t a = (uint32_t)(v < 0 ? -v : v);
+    if (a == 0u) return sgn;
+    int e = 31 - __builtin_clz(a);   // a in [2^e, 2^(e+1))
+    uint32_t m;                      // significand with 3 fraction bits, in [8, 16)
+    if (e <= 3) {
+        m = a << (3 - e);
+    } else {
+        const int sh = e - 3;
+        m = a >> sh;
+        const uint32_t rem = a & ((1u << sh) - 1u), half = 1u << (sh - 1);
+        if (rem > half || (rem == half && (m & 1u))) ++m;
+        if (m == 16u) {
+            m = 8u;
+            ++e;
+        }
+    }
+    return sgn | ((uint32_t)(e + 7) << 3) | (m & 7u);
+}
+
+__global__ void q_e4m3_kernel(const int8_t* __restrict__ q, uint8_t* __restrict__ q8, size_t count) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) q8[i] = (uint8_t)int_to_e4m3((int)q[i]);
+}
+
+void launch_q_e4m3(const int8_t* q, uint8_t* q8, size_t count, hipStream_t st) {
+    if (!count) return;
+    q_e4m3_kernel<<<dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st>>>(q, q8, count);
+    CSV_HIP(hipGetLastError());
+}
+
 // ------------------------------------------------------------ measurement
-// y~ = Q r for a tile of 32 blocks: the residual (frame - decoded key,
-// zero-padded outside the frame) is staged in LDS as bf16, Q streams from
-// global memory as int8 and is widened to bf16; both are exact (|r| <= 255,
-// |Q| <= 32), and so is the FP32 accumulation (every partial sum < 2^24 for
-// n <= 2048).  Each wave computes 32-row M tiles with 32x32x16 MFMA.
-template <int B>
-__global__ __launch_bounds__(256) void measure_kernel(const int8_t* __restrict__ q, int Mp,
-                                                     const uint8_t* __restrict__ frames,
-                                                     int n_frames, size_t frame_stride,
-                                                     const uint8_t* __restrict__ key, int W, int H,
-                                                     int nbx, int nb, int32_t* __restrict__ y) {
-    constexpr int n = B * B;
-    constexpr int LD = n + 8;   // bf16 row stride (16-byte pad against bank conflicts)
-    extern __shared__ uint16_t res[];   // [32][LD]
+// y~ = Q r for a tile of 32 blocks, in one of three forms:
+//   FORM 0 (exact): the residual (frame - decoded key, zero outside the
+//          frame) is staged in LDS as bf16 and Q (int8) is widened to bf16
+//          in registers; both are exact (|r| <= 255, |Q| <= 32) and so is
+//          the FP32 accumulation (every partial sum < 2^24 for n <= 2048);
+//   FORM 1 (int8): two byte planes, the digits h = r >> 4 (in [-16, 15]) and
+//          l = r & 15 (in [0, 15]) of r = 16 h + l; Q times each plane on
+//          int8 MFMA with int32 accumulation, y~ = 16 Q h + Q l = Q r;
+//   FORM 2 (fp8): one plane of E4M3 residuals times the E4M3 copy of Q on
+//          FP8 MFMA; every operand is an integer and every partial sum is
+//          below 2^24, so the FP32 accumulator holds the exact integer sum
+//          of e4m3(Q) e4m3(r).
+// Staging moves 8 pixels per load (W % 8 == 0 keeps a group inside or
+// outside the frame and aligned) with the loads of four groups in flight.
+// Each wave computes 32-row M tiles with 32x32x16 MFMA; operand layout of
+// the 32x32x16 MFMA: lane l, elements e = 0..7 carry row (A) or column (B)
+// l % 32 and K index 8 (l / 32) + e.
+template <int B, int FORM>
+struct MeasureLayout {
+    static constexpr int n = B * B;
+    static constexpr int EB = FORM == 0 ? 2 : 1;                  // staged bytes per residual
+    static constexpr int LD = FORM == 0 ? 2 * n + 16 : n + 8;     // bytes per block; pads spread banks
+    static constexpr int PLANES = FORM == 1 ? 2 : 1;
+    static constexpr size_t PLANE = (size_t)32 * LD;
+    static constexpr size_t LDS = PLANE * PLANES;
+};
+
+__device__ inline int byte_of(uint2 w, int i) {
+    return (int)(((i < 4 ? w.x : w.y) >> (8 * (i & 3))) & 0xffu);
+}
+
+template <int B, int FORM>
+__global__ __launch_bounds__(256) void measure_kernel(const int8_t* __restrict__ q,
+                                                      const uint8_t* __restrict__ q8, int Mp,
+                                                      const uint8_t* __restrict__ frames,
+                                                      int n_frames, size_t frame_stride,
+                                                      const uint8_t* __restrict__ key, int W, int H,
+                                                      int nbx, int nb, int32_t* __restrict__ y) {
+    using L = MeasureLayout<B, FORM>;
+    constexpr int n = L::n;
+    extern __shared__ __attribute__((aligned(16))) uint8_t res[];   // [PLANES][32][LD]
     const int tid = threadIdx.x;
     const int total = n_frames * nb;
     const int gb0 = blockIdx.x * 32;
-    // stage residuals: groups of 4 pixels along a block row
-    for (int e = tid; e < 32 * n / 4; e += 256) {
-        const int j = e / (n / 4);
-        const int rem = e - j * (n / 4);
-        const int r = rem / (B / 4), c4 = (rem - r * (B / 4)) * 4;
-        const int gb = gb0 + j;
-        uint16_t v[4] = {0, 0, 0, 0};
-        if (gb < total) {
-            const int t = gb / nb, b = gb - t * nb;
-            const int py = (b / nbx) * B + r, px = (b % nbx) * B + c4;
-            if (py < H && px < W) {   // W % 8 == 0: a 4-pixel group is all in or all out
-                const uchar4 f = *reinterpret_cast<const uchar4*>(frames + t * frame_stride + (size_t)py * W + px);
-                const uchar4 k = *reinterpret_cast<const uchar4*>(key + (size_t)py * W + px);
-                v[0] = int_to_bf16_exact((int)f.x - (int)k.x);
-                v[1] = int_to_bf16_exact((int)f.y - (int)k.y);
-                v[2] = int_to_bf16_exact((int)f.z - (int)k.z);
-                v[3] = int_to_bf16_exact((int)f.w - (int)k.w);
+    constexpr int PER = 32 * n / 8 / 256;   // 8-pixel groups per thread: 16 (B=32) or 4 (B=16)
+    constexpr int U = 4;
+    static_assert(PER % U == 0, "staging rounds");
+#pragma unroll 1
+    for (int base = 0; base < PER; base += U) {
+        uint2 fv[U], kv[U];
+        size_t dst[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int item = tid + 256 * (base + u);
+            const int j = item / (n / 8);
+            const int rem = item - j * (n / 8);
+            const int r = rem / (B / 8), c8 = (rem - r * (B / 8)) * 8;
+            const int gb = gb0 + j;
+            fv[u] = make_uint2(0u, 0u);
+            kv[u] = make_uint2(0u, 0u);
+            if (gb < total) {
+                const int t = gb / nb, b = gb - t * nb;
+                const int py = (b / nbx) * B + r, px = (b % nbx) * B + c8;
+                if (py < H && px < W) {
+                    fv[u] = *reinterpret_cast<const uint2*>(frames + t * frame_stride + (size_t)py * W + px);
+                    kv[u] = *reinterpret_cast<const uint2*>(key + (size_t)py * W + px);
+                }
+            }
+            dst[u] = (size_t)j * L::LD + (size_t)(r * B + c8) * L::EB;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = byte_of(fv[u], i) - byte_of(kv[u], i);
+            if constexpr (FORM == 0) {
+                u16x8 o;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) o[i] = int_to_bf16_exact(v[i]);
+                *reinterpret_cast<u16x8*>(res + dst[u]) = o;
+            } else if constexpr (FORM == 1) {
+                uint2 wh = make_uint2(0u, 0u), wl = make_uint2(0u, 0u);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    wh.x |= ((uint32_t)(v[i] >> 4) & 0xffu) << (8 * i);
+                    wh.y |= ((uint32_t)(v[4 + i] >> 4) & 0xffu) << (8 * i);
+                    wl.x |= ((uint32_t)(v[i] & 15)) << (8 * i);
+                    wl.y |= ((uint32_t)(v[4 + i] & 15)) << (8 * i);
+                }
+                *reinterpret_cast<uint2*>(res + dst[u]) = wh;
+                *reinterpret_cast<uint2*>(res + L::PLANE + dst[u]) = wl;
+            } else {
+                uint2 w8 = make_uint2(0u, 0u);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    w8.x |= int_to_e4m3(v[i]) << (8 * i);
+                    w8.y |= int_to_e4m3(v[4 + i]) << (8 * i);
+                }
+                *reinterpret_cast<uint2*>(res + dst[u]) = w8;
             }
         }
-        uint16_t* dst = res + j * LD + r * B + c4;
-        dst[0] = v[0];
-        dst[1] = v[1];
-        dst[2] = v[2];
-        dst[3] = v[3];
     }
     __syncthreads();
     const int wv = tid >> 6, ln = tid & 63, col = ln & 31, half = ln >> 5;
     for (int mt = wv; mt < Mp / 32; mt += 4) {
-        floatx16 acc = {};
-        const int8_t* qrow = q + (size_t)(mt * 32 + col) * n + 8 * half;
-        const uint16_t* rrow = res + col * LD + 8 * half;
-#pragma unroll 4
-        for (int s = 0; s < n / 16; ++s) {
-            const uint2 qq = *reinterpret_cast<const uint2*>(qrow + 16 * s);
-            const bf16x8 a = int8x8_to_bf16x8(qq);
-            const bf16x8 b = *reinterpret_cast<const bf16x8*>(rrow + 16 * s);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        const size_t qoff = (size_t)(mt * 32 + col) * n + 8 * half;
+        const uint8_t* rrow = res + (size_t)col * L::LD + (size_t)8 * half * L::EB;
+        int32_t out[16];
+        if constexpr (FORM == 0) {
+            floatx16 acc = {};
+#pragma unroll 8
+            for (int s = 0; s < n / 16; ++s) {
+                const bf16x8 a = int8x8_to_bf16x8(*reinterpret_cast<const uint2*>(q + qoff + 16 * s));
+                const bf16x8 b = *reinterpret_cast<const bf16x8*>(rrow + 16 * s * L::EB);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) out[r] = (int32_t)acc[r];
+        } else if constexpr (FORM == 1) {
+            intx16 ah = {}, al = {};
+#pragma unroll 8
+            for (int s = 0; s < n / 16; ++s) {
+                const long a = *reinterpret_cast<const long*>(q + qoff + 16 * s);
+                const long bh = *reinterpret_cast<const long*>(rrow + 16 * s);
+                const long bl = *reinterpret_cast<const long*>(rrow + L::PLANE + 16 * s);
+                ah = __builtin_amdgcn_mfma_i32_32x32x16_i8(a, bh, ah, 0, 0, 0);
+                al = __builtin_amdgcn_mfma_i32_32x32x16_i8(a, bl, al, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) out[r] = 16 * ah[r] + al[r];
+        } else {
+            floatx16 acc = {};
+#pragma unroll 8
+            for (int s = 0; s < n / 16; ++s) {
+                const long a = *reinterpret_cast<const long*>(q8 + qoff + 16 * s);
+                const long b = *reinterpret_cast<const long*>(rrow + 16 * s);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, b, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) out[r] = (int32_t)acc[r];
         }
         const int gb = gb0 + col;
         if (gb < total) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int m = mt * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-                y[(size_t)gb * Mp + m] = (int32_t)acc[r];
+                y[(size_t)gb * Mp + m] = out[r];
             }
         }
     }
+}
+
+template <int B, int FORM>
+static void launch_measure_form(const Shape& s, const int8_t* q, const uint8_t* q8,
+                                const uint8_t* frames, int n_frames, size_t frame_stride,
+                                const uint8_t* key, int32_t* y, hipStream_t st) {
+    const int total = n_frames * s.nb;
+    const size_t lds = MeasureLayout<B, FORM>::LDS;
+    auto* fn = &measure_kernel<B, FORM>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        CSV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = true;
+    }
+    fn<<<dim3(ceil_div(total, 32)), dim3(256), lds, st>>>(q, q8, s.Mp, frames, n_frames,
+                                                           frame_stride, key, s.W, s.H, s.nbx,
+                                                           s.nb, y);
+    CSV_HIP(hipGetLastError());
+}
+
+template <int B>
+static void launch_measure_b(const Shape& s, const int8_t* q, const uint8_t* q8,
+                             const uint8_t* frames, int n_frames, size_t frame_stride,
+                             const uint8_t* key, int32_t* y, hipStream_t st) {
+    if (s.flags & CSV_FLAG_MEASURE_INT8)
+        launch_measure_form<B, 1>(s, q, q8, frames, n_frames, frame_stride, key, y, st);
+    else if (s.flags & CSV_FLAG_MEASURE_FP8)
+        launch_measure_form<B, 2>(s, q, q8, frames, n_frames, frame_stride, key, y, st);
+    else
+        launch_measure_form<B, 0>(s, q, q8, frames, n_frames, frame_stride, key, y, st);
+}
+
+void launch_measure(const Shape& s, const int8_t* q, const uint8_t* q8, const uint8_t* frames,
+                    int n_frames, size_t frame_stride, const uint8_t* key, int32_t* y_scratch,
+                    hipStream_t st) {
+    // y_scratch: (n_frames * nb) x Mp int32
+    const int total = n_frames * s.nb;
+    if (total == 0) return;
+    CSV_REQUIRE((reinterpret_cast<uintptr_t>(frames) | reinterpret_cast<uintptr_t>(key)) % 8 == 0,
+                CSV_EINVAL, "frame buffers must be 8-byte aligned");
+    if (s.B == 16)
+        launch_measure_b<16>(s, q, q8, frames, n_frames, frame_stride, key, y_scratch, st);
+    else
+        launch_measure_b<32>(s, q, q8, frames, n_frames, frame_stride, key, y_scratch, st);
 }
 
 // Block-floating-point 8-bit quantiser, one wave per block: m = max|y~|,
@@ -283,31 +449,6 @@ __global__ __launch_bounds__(256) void quantise_kernel(const int32_t* __restrict
         if (y_out) y_out[(size_t)gb * M + m] = v;
     }
     if (ln == 0) exps[gb] = (uint8_t)e;
-}
-
-void launch_measure(const Shape& s, const int8_t* q, const uint8_t* frames, int n_frames,
-                    size_t frame_stride, const uint8_t* key, int32_t* y_scratch, hipStream_t st) {
-    // y_scratch: (n_frames * nb) x Mp int32
-    const int total = n_frames * s.nb;
-    if (total == 0) return;
-    const dim3 grid(ceil_div(total, 32));
-    static bool attr_set = false;
-    if (!attr_set) {
-        CSV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&measure_kernel<32>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    32 * (1024 + 8) * (int)sizeof(uint16_t)));
-        attr_set = true;
-    }
-    if (s.B == 16) {
-        const size_t lds = 32 * (256 + 8) * sizeof(uint16_t);
-        measure_kernel<16><<<grid, dim3(256), lds, st>>>(q, s.Mp, frames, n_frames, frame_stride,
-                                                         key, s.W, s.H, s.nbx, s.nb, y_scratch);
-    } else {
-        const size_t lds = 32 * (1024 + 8) * sizeof(uint16_t);
-        measure_kernel<32><<<grid, dim3(256), lds, st>>>(q, s.Mp, frames, n_frames, frame_stride,
-                                                         key, s.W, s.H, s.nbx, s.nb, y_scratch);
-    }
-    CSV_HIP(hipGetLastError());
 }
 
 void launch_quantise(const int32_t* y, int M, int Mp, int total, int8_t* codes, uint8_t* exps,

@@ -10,6 +10,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef int intx16 __attribute__((ext_vector_type(16)));
 
 // bf16 bit pattern of a small integer (|v| <= 256): exact, the low half of
 // its float encoding is zero.

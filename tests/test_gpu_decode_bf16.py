@@ -124,3 +124,26 @@ def test_bf16_full_size_sampled_blocks(ctx):
         sl = (slice(by * 32, by * 32 + 32), slice(bx * 32, bx * 32 + 32))
         ref = key[sl] + x
         assert np.max(np.abs(fl[t][sl] - ref)) <= MAXABS_TOL, (t, b)
+
+
+@pytest.mark.parametrize("spec", [sv.qcif_tiny(), sv.vga_precision(0.25, gop=3)],
+                         ids=["qcif-b16-m64", "vga-b32-m256"])
+def test_decode_of_fp8_measured_gop(ctx, spec):
+    """A GOP measured in the FP8 form decodes like the oracle's decode of
+    the same FP8 codes (the BF16 bars), and within 0.25 dB of the GOP
+    measured exactly (the FP8 operands perturb the measurements by a few
+    percent; the oracle shows -0.04..+0.09 dB on these inputs)."""
+    import paper_1311_1419_amd as P
+    announce(f"decode of fp8-measured {spec.width}x{spec.height} B={spec.block}")
+    frames = spec.video()
+    op8 = codec.Params.from_spec(spec, measure_form="fp8")
+    ref8 = codec.decode_gop(codec.encode_gop(frames, op8), op8)
+    p8 = _bf16(spec, flags=P.CSV_FLAG_MEASURE_FP8)
+    out8, fl8, _ = ctx.decode_gop(ctx.encode_gop(dev(frames), p8), p8, want_float=True)
+    p = _bf16(spec)
+    out, _, _ = ctx.decode_gop(ctx.encode_gop(dev(frames), p), p)
+    out8, fl8, out = host(out8), host(fl8), host(out)
+    for t in range(1, spec.gop):
+        assert np.max(np.abs(fl8[t - 1].astype(np.float64) - ref8.cs_float[t - 1])) <= MAXABS_TOL
+        assert abs(psnr(frames[t], out8[t]) - psnr(frames[t], ref8.frames[t])) <= PSNR_TOL
+        assert abs(psnr(frames[t], out8[t]) - psnr(frames[t], out[t])) <= 0.25

@@ -143,3 +143,31 @@ def test_encode_batch_equals_oracle_per_gop(ctx):
             assert np.array_equal(host(gs.exps), ref.exps)
         bits = host(gs.bits)
         assert int(bits[0]) == ref.bits_key and int(bits[1]) == ref.bits_cs
+
+
+FORM_SPECS = [(sv.qcif_tiny(), "qcif-b16"), (sv.cif_sweep(4, 0.3), "cif-m77"),
+              (sv.vga_precision(0.25, gop=3), "vga-b32-m256"),
+              (sv.qcif_tiny().with_(block=32, m=410, gop=2), "qcif-b32-m410-padded")]
+
+
+@pytest.mark.parametrize("form", ["int8", "fp8"])
+@pytest.mark.parametrize("spec", [s for s, _ in FORM_SPECS], ids=[i for _, i in FORM_SPECS])
+def test_measurement_forms_bit_exact(ctx, spec, form):
+    """INT8 (split residual) and FP8 (E4M3) measurement forms equal the
+    oracle's definition of each form bit for bit: measurements, codes,
+    exponents and bit counts."""
+    import paper_1311_1419_amd as P
+    announce(f"measure form {form} {spec.width}x{spec.height} B={spec.block} M={spec.m}")
+    flag = P.CSV_FLAG_MEASURE_INT8 if form == "int8" else P.CSV_FLAG_MEASURE_FP8
+    frames = spec.video()
+    p = _params(spec, flags=flag)
+    gs = ctx.encode_gop(dev(frames), p)
+    ref = codec.encode_gop(frames, codec.Params.from_spec(spec, measure_form=form))
+    assert np.array_equal(host(gs.codes), ref.codes)
+    assert np.array_equal(host(gs.exps), ref.exps)
+    bits = host(gs.bits)
+    assert int(bits[0]) == ref.bits_key and int(bits[1]) == ref.bits_cs
+    # the raw integer measurements of one CS frame
+    key = dev(ref.key_decoded)
+    y, codes, exps = ctx.measure_frame(p, dev(frames[1]), key)
+    assert np.array_equal(host(y).astype(np.int64), ref.y_int[0])
