@@ -49,10 +49,14 @@ def parse():
                     help="blocks the oracle recovers for the CPU baseline")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
-    ap.add_argument("--mode", choices=["headline", "mixed", "serve", "encode"], default="headline",
+    ap.add_argument("--mode", choices=["headline", "mixed", "serve", "encode", "configure"],
+                    default="headline",
                     help="headline: the metric above; mixed: 64 mixed streams decoded by one "
                          "graph-captured batch; serve: 256 cameras under a Poisson load sweep; "
-                         "encode: the headline cameras encoded in each measurement form")
+                         "encode: the headline cameras encoded in each measurement form; "
+                         "configure: the (G, M) configurator sweep")
+    ap.add_argument("--psnr-floor", type=float, default=32.0,
+                    help="configure mode: PSNR floor standing in for the tracking requirement")
     ap.add_argument("--serve-window", type=float, default=2.0, help="seconds per sweep point")
     ap.add_argument("--serve-loads", type=str, default="0.01,0.02,0.04,0.08",
                     help="fractions of the cameras' nominal GOP rates")
@@ -344,6 +348,44 @@ def encode_main(args):
         "forms": res}), flush=True)
 
 
+def configure_main(args):
+    """The configurator's sweep (Fig. 6, Table I): a synthetic 352x288 clip
+    of 105 frames, B = 32, GOP sizes 3/5/7 and M = 256/102/51/25/16/12 (CS
+    frame CR 1024/(M+1) = 4.0 ... 78.8; 39.4/60.2/78.8 are the paper's
+    40/60/80), every candidate coded and decoded on the GPU; the choice
+    under a PSNR floor."""
+    import torch
+    import paper_1311_1419_amd as P
+    import synthvid as sv
+    spec = sv.cif_sweep(4, 0.25).with_(block=32, iters=300)
+    clip = torch.from_numpy(spec.video(105)).cuda()
+    gops, ms = [3, 5, 7], [256, 102, 51, 25, 16, 12]
+    with P.Context(0) as ctx:
+        base = P.Params.from_spec(spec, precision=P.CSV_BF16)
+        ctx.configure(clip[:7], base, [3], [25], args.psnr_floor)   # warm-up: operators
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.configure(clip, base, gops, ms, args.psnr_floor)
+        wall = time.perf_counter() - t0
+    pts = res["points"]
+    # Fig. 6(a) with the paper's key-frame CR of 23 (Section 4), for comparison
+    for p in pts:
+        p["cr_total_at_key_cr_23"] = p["gop"] / (1.0 / 23.0 + (p["gop"] - 1) / p["cr_cs"])
+        for k in ("cr_total", "cr_key", "cr_cs", "psnr_all", "psnr_cs", "cr_total_at_key_cr_23"):
+            p[k] = round(p[k], 3)
+    px = 105 * spec.height * spec.width * len(pts)
+    print(json.dumps({
+        "metric": "configurator sweep: (G, M) candidates coded and decoded per second, "
+                  "352x288 clip of 105 frames",
+        "value": round(len(pts) / wall, 3), "unit": "candidates/s", "n_gpus": 1,
+        "ms_per_sweep": round(1e3 * wall, 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "cif352x288-f105-b32-g3,5,7-m256..12-t300",
+                   "psnr_floor_db": args.psnr_floor, "pixels_coded_per_sweep": px},
+        "best": res["best"], "chosen": pts[res["best"]] if res["best"] >= 0 else None,
+        "points": pts}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -357,6 +399,8 @@ def main():
         return serve_main(args)
     if args.mode == "encode":
         return encode_main(args)
+    if args.mode == "configure":
+        return configure_main(args)
     import torch
     import paper_1311_1419_amd as P
 

@@ -65,6 +65,13 @@ class CsvCeilings(C.Structure):
                 ("compute_units", C.c_int32)]
 
 
+class CsvConfigPoint(C.Structure):
+    _fields_ = [("gop", C.c_int32), ("m", C.c_int32), ("bits_key", C.c_uint64),
+                ("bits_cs", C.c_uint64), ("cr_total", C.c_double), ("cr_key", C.c_double),
+                ("cr_cs", C.c_double), ("psnr_all", C.c_double), ("psnr_cs", C.c_double),
+                ("meets_floor", C.c_int32)]
+
+
 class CsvError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"csv error {code}: {msg}")
@@ -121,6 +128,11 @@ _SIGS = {
     "csv_autotune_choice": (C.c_int, [C.c_int32, C.c_int32, C.c_char_p, C.c_size_t,
                                       _P(C.c_int32), _P(C.c_int32)]),
     "csv_autotune_set": (C.c_int, [C.c_int32, C.c_int32, C.c_int32]),
+    "csv_configure": (C.c_int, [C.c_void_p, _P(CsvParams), C.c_void_p, C.c_int32,
+                                _P(C.c_int32), C.c_int32, _P(C.c_int32), C.c_int32, C.c_double,
+                                _P(CsvConfigPoint), _P(C.c_int32), C.c_void_p]),
+    "csv_frame_sse": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                C.c_int32, C.c_void_p, C.c_void_p]),
     "csv_clock": (C.c_double, []),
     "csv_server_create": (C.c_int, [C.c_int, _P(CsvServerOpts), _P(C.c_void_p)]),
     "csv_server_destroy": (C.c_int, [C.c_void_p]),

@@ -324,6 +324,38 @@ class Context:
         N.check(N.lib().csv_profile_query(self._h, name.encode(), C.byref(ms), C.byref(cnt)))
         return ms.value, cnt.value
 
+    def configure(self, clip: torch.Tensor, base: Params, gops, ms, psnr_floor: float) -> dict:
+        """Sweep (G, M) candidates over a calibration clip (F x H x W uint8
+        device tensor) with the coder itself and choose the largest total CR
+        whose mean PSNR meets the floor.  Returns {"points": [dict per
+        candidate, G-major], "best": index or -1}."""
+        _require_cuda(clip, torch.uint8, "clip")
+        if clip.dim() != 3 or tuple(clip.shape[1:]) != (base.height, base.width):
+            raise ValueError("clip must be F x H x W")
+        ng, nm = len(gops), len(ms)
+        g_arr = (C.c_int32 * ng)(*gops)
+        m_arr = (C.c_int32 * nm)(*ms)
+        pts = (N.CsvConfigPoint * (ng * nm))()
+        best = C.c_int32()
+        N.check(N.lib().csv_configure(self._h, C.byref(base.to_c()), clip.data_ptr(),
+                                      clip.shape[0], g_arr, ng, m_arr, nm, psnr_floor, pts,
+                                      C.byref(best), _stream(self.device)))
+        return {"points": [{f: getattr(p, f) for f, _ in N.CsvConfigPoint._fields_} for p in pts],
+                "best": best.value}
+
+    def frame_sse(self, a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+        """Exact per-frame sums of squared differences of two F x H x W uint8
+        device stacks (uint64 as int64)."""
+        _require_cuda(a, torch.uint8, "a")
+        _require_cuda(b, torch.uint8, "b")
+        if a.shape != b.shape or a.dim() != 3:
+            raise ValueError("a and b must both be F x H x W")
+        out = torch.empty((a.shape[0],), dtype=torch.int64, device=self.device)
+        N.check(N.lib().csv_frame_sse(self._h, a.data_ptr(), b.data_ptr(), a.shape[0],
+                                      a.shape[2], a.shape[1], out.data_ptr(),
+                                      _stream(self.device)))
+        return out
+
     def probe_ceilings(self) -> dict:
         """Achievable MFMA BF16 TFLOP/s and L2 / HBM / LDS read TB/s of the
         device, from short microbenchmarks (synchronous)."""
