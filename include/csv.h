@@ -72,7 +72,16 @@ enum {
      *         integer sum, a few percent away from Q r.
      * The decoder ignores these flags. */
     CSV_FLAG_MEASURE_INT8 = 4,
-    CSV_FLAG_MEASURE_FP8 = 8
+    CSV_FLAG_MEASURE_FP8 = 8,
+    /* Decoder: total-variation recovery (the paper's TVAL3-style solver,
+     * Section 4) instead of l1 in the DCT basis: per block, in the pixel
+     * domain, min lam TV(x) + 1/2 ||Phi x - y^||^2 with isotropic TV over
+     * forward differences inside the block, by the linearised alternating-
+     * direction iteration (w = shrink(D x + nu/beta, lam/beta); one gradient
+     * step on x with step 1/(L + 8 beta); nu += beta (D x - w)); beta = 0.03
+     * lam; lam = lambda_frac ||Phi^T y^||_inf.  FP32 only (CSV_EUNSUPPORTED
+     * with CSV_BF16); obj_out then holds the TV objective. */
+    CSV_FLAG_TV = 16
 };
 
 /* ------------------------------------------------------------ params */
@@ -242,7 +251,7 @@ int csv_graph_destroy(csv_graph* g);
 
 /* ------------------------------------------------------- measurement */
 /* Event timing of named kernel ranges on the stream they run on ("fista_bf16",
- * "fista_fp32", "prepare", "synth", "final64", "key_decode", "measure").  While enabled,
+ * "fista_fp32", "tv_fp32", "prepare", "synth", "final64", "key_decode", "measure").  While enabled,
  * every such range records a pair of HIP events.  csv_profile_query waits
  * for the recorded events and returns the summed milliseconds and the number
  * of ranges for `name` since the last reset. */

@@ -16,7 +16,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import cs, fp8, keyframe, philox
+from . import cs, fp8, keyframe, philox, tv
 
 
 @dataclass(frozen=True)
@@ -31,7 +31,7 @@ class Params:
     iters: int = 300
     key_qstep: int = 16
     lambda_frac: float = 0.01
-    solver: str = "fista"           # fista | ista | mfista | direct
+    solver: str = "fista"           # fista | ista | mfista | direct | tv
     pixel_domain_lambda: bool = False
     no_quant: bool = False          # test hook: y^ = s_Phi y~ exactly
     measure_form: str = "exact"     # exact | int8 | fp8 (encoder product, see fp8.py)
@@ -124,6 +124,22 @@ def decode_gop(gs: GopStream, p: Params) -> Decoded:
             y_hat = s_phi * gs.y_int[t - 1].T.astype(np.float64)
         else:
             y_hat = cs.dequantise(gs.codes[t - 1].T, gs.exps[t - 1], s_phi)
+        if p.solver == "tv":
+            # total-variation recovery in the pixel domain (oracle/tv.py);
+            # s holds the pixel-domain residual x, the objective is TV's
+            phi = s_phi * q.astype(np.float64)
+            lam = tv.lambdas(phi, y_hat, p.lambda_frac)
+            xr = tv.recover(phi, y_hat, lam, L, b, p.iters)
+            f = key_dec.astype(np.float64) + cs.scatter_blocks(xr, h, w, b)
+            cs_f[t - 1] = f
+            frames[t] = cs.round_to_u8(f)
+            obj[t - 1] = tv.objective(phi, y_hat, xr, lam, b)
+            rn = np.linalg.norm(phi @ xr - y_hat, axis=0)
+            yn = np.linalg.norm(y_hat, axis=0)
+            relr[t - 1] = np.where(yn > 0, rn / np.where(yn > 0, yn, 1.0), 0.0)
+            lam_all[t - 1] = lam
+            s_all[t - 1] = xr.T
+            continue
         if p.solver == "direct":
             # least squares on a square operator (M = n, lam = 0)
             s = np.linalg.solve(a, y_hat)

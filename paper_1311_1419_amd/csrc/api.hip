@@ -54,7 +54,7 @@ Shape resolve(const csv_params* p) {
     CSV_REQUIRE(p->precision == CSV_FP32 || p->precision == CSV_BF16, CSV_EINVAL,
                 "precision must be CSV_FP32 or CSV_BF16");
     CSV_REQUIRE((p->flags & ~(CSV_FLAG_ISTA | CSV_FLAG_LAMBDA_PIXEL_DOMAIN |
-                              CSV_FLAG_MEASURE_INT8 | CSV_FLAG_MEASURE_FP8)) == 0,
+                              CSV_FLAG_MEASURE_INT8 | CSV_FLAG_MEASURE_FP8 | CSV_FLAG_TV)) == 0,
                 CSV_EINVAL, "unknown flag bits");
     CSV_REQUIRE((p->flags & (CSV_FLAG_MEASURE_INT8 | CSV_FLAG_MEASURE_FP8)) !=
                     (CSV_FLAG_MEASURE_INT8 | CSV_FLAG_MEASURE_FP8),
@@ -249,9 +249,31 @@ const float* beta_table(Ctx* c, int T, bool ista, hipStream_t st) {
 static void lambda_pass(Ctx* c, const Shape& s, Operator* op, const float* y, int nblk, float* lam,
                         hipStream_t st, const std::string& g0name) {
     float* g0 = static_cast<float*>(scratch(c, g0name, (size_t)nblk * s.n * 4));
-    const float* opm = (s.flags & CSV_FLAG_LAMBDA_PIXEL_DOMAIN) ? op->phi32 : op->a32;
+    const float* opm =
+        (s.flags & (CSV_FLAG_LAMBDA_PIXEL_DOMAIN | CSV_FLAG_TV)) ? op->phi32 : op->a32;
     launch_gemm_nn(y, opm, g0, nblk, s.n, s.Mp, s.Mp, s.n, s.n, st);
     launch_row_absmax(g0, nblk, s.n, s.n, s.lambda_frac, lam, st);
+}
+
+// Total-variation recovery (k_tv.hip): x in S (pixel domain), FP32.
+static void tv_fp32(Ctx* c, const Shape& s, Operator* op, const float* y, const float* lam,
+                    int nblk, float* S, hipStream_t st) {
+    const size_t nn = (size_t)nblk * s.n;
+    float* nuh = static_cast<float*>(scratch(c, "tv_nuh", nn * 4));
+    float* nuv = static_cast<float*>(scratch(c, "tv_nuv", nn * 4));
+    float* wh = static_cast<float*>(scratch(c, "tv_wh", nn * 4));
+    float* wv = static_cast<float*>(scratch(c, "tv_wv", nn * 4));
+    float* ph = static_cast<float*>(scratch(c, "tv_ph", nn * 4));
+    float* pv = static_cast<float*>(scratch(c, "tv_pv", nn * 4));
+    float* Gd = static_cast<float*>(scratch(c, "Gd", nn * 4));
+    float* R = static_cast<float*>(scratch(c, "Rm", (size_t)nblk * s.Mp * 4));
+    for (float* p : {S, nuh, nuv, wh, wv}) launch_fill_f32(p, 0.f, nn, st);
+    for (int k = 0; k < s.T; ++k) {
+        launch_tv_dual(S, nuh, nuv, wh, wv, ph, pv, lam, nblk, s.B, st);
+        launch_gemm_nt(S, op->phi32, R, nblk, s.Mp, s.n, s.n, s.n, s.Mp, y, s.Mp, s.M, st);
+        launch_gemm_nn(R, op->phi32, Gd, nblk, s.n, s.Mp, s.Mp, s.n, s.n, st);
+        launch_tv_primal(S, Gd, ph, pv, lam, op->lip, nblk, s.B, st);
+    }
 }
 
 static void fista_fp32(Ctx* c, const Shape& s, Operator* op, const float* y, const float* lam,
@@ -422,8 +444,14 @@ void recover(Ctx* c, const Shape& s, Operator* op, const int8_t* codes, const ui
              int nblk, float* S, float* lam_out, double* obj_out, hipStream_t st) {
     if (nblk <= 0) return;
     float* lam = lam_out ? lam_out : static_cast<float*>(scratch(c, "lam", (size_t)nblk * 4));
+    const bool tv = (s.flags & CSV_FLAG_TV) != 0;
+    CSV_REQUIRE(!tv || s.precision == CSV_FP32, CSV_EUNSUPPORTED,
+                "TV recovery has an FP32 path only");
     const float* y = prepare(c, s, op, codes, exps, nblk, lam, "", st);
-    if (s.precision == CSV_FP32) {
+    if (tv) {
+        ProfScope ps(c, "tv_fp32", st);
+        tv_fp32(c, s, op, y, lam, nblk, S, st);
+    } else if (s.precision == CSV_FP32) {
         ProfScope ps(c, "fista_fp32", st);
         fista_fp32(c, s, op, y, lam, nblk, S, st);
     } else {
@@ -431,8 +459,11 @@ void recover(Ctx* c, const Shape& s, Operator* op, const int8_t* codes, const ui
     }
     if (obj_out) {
         ProfScope ps(c, "final64", st);
-        launch_final64(op->a64t, S, codes, exps, lam, nblk, s.M, s.Mp, s.n, op->s_phi, obj_out,
-                       st);
+        if (tv)
+            launch_tv_final64(op->q, S, codes, exps, lam, nblk, s.M, s.B, op->s_phi, obj_out, st);
+        else
+            launch_final64(op->a64t, S, codes, exps, lam, nblk, s.M, s.Mp, s.n, op->s_phi,
+                           obj_out, st);
     }
 }
 
@@ -546,6 +577,8 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
     for (int i = 0; i < count; ++i) {
         const Shape& s = shapes[i];
         CSV_REQUIRE(in[i].key_levels && frames_out[i], CSV_EINVAL, "NULL key_levels or frames_out");
+        CSV_REQUIRE(!(s.flags & CSV_FLAG_TV) || s.precision == CSV_FP32, CSV_EUNSUPPORTED,
+                    "TV recovery has an FP32 path only");
         CSV_REQUIRE(s.G == 1 || (in[i].codes && in[i].exps), CSV_EINVAL, "codes/exps are NULL");
         items[i].op = s.G > 1 ? get_operator(c, s, st) : nullptr;
         items[i].nblk = (s.G - 1) * s.nb;
@@ -586,7 +619,10 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
         const Shape& s = shapes[i];
         Item& it = items[i];
         if (!it.nblk) continue;
-        if (s.precision == CSV_FP32) {
+        if (s.flags & CSV_FLAG_TV) {
+            ProfScope ps(c, "tv_fp32", st);      // shares the context's FP32 scratch: serial
+            tv_fp32(c, s, it.op, it.y, it.lam, it.nblk, it.S, st);
+        } else if (s.precision == CSV_FP32) {
             ProfScope ps(c, "fista_fp32", st);   // shares the context's FP32 scratch: serial
             fista_fp32(c, s, it.op, it.y, it.lam, it.nblk, it.S, st);
         } else {
@@ -600,15 +636,21 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
         const Item& it = items[i];
         if (!it.nblk) continue;
         const hipStream_t ls = lane_of(i);
+        const bool tv = (s.flags & CSV_FLAG_TV) != 0;
         if (obj_out && obj_out[i]) {
             ProfScope ps(c, "final64", ls);
-            launch_final64(it.op->a64t, it.S, in[i].codes, in[i].exps, it.lam, it.nblk, s.M, s.Mp,
-                           s.n, it.op->s_phi, obj_out[i], ls);
+            if (tv)
+                launch_tv_final64(it.op->q, it.S, in[i].codes, in[i].exps, it.lam, it.nblk, s.M,
+                                  s.B, it.op->s_phi, obj_out[i], ls);
+            else
+                launch_final64(it.op->a64t, it.S, in[i].codes, in[i].exps, it.lam, it.nblk, s.M,
+                               s.Mp, s.n, it.op->s_phi, obj_out[i], ls);
         }
         ProfScope ps(c, "synth", ls);
         const size_t fs = (size_t)s.W * s.H;
-        launch_synth(it.S, it.op->dct, frames_out[i], s.W, s.H, s.B, s.nbx, s.nb, s.G - 1,
-                     frames_out[i] + fs, cs_float_out ? cs_float_out[i] : nullptr, ls);
+        // TV recovers pixel-domain residuals: no basis to synthesise
+        launch_synth(it.S, tv ? nullptr : it.op->dct, frames_out[i], s.W, s.H, s.B, s.nbx, s.nb,
+                     s.G - 1, frames_out[i] + fs, cs_float_out ? cs_float_out[i] : nullptr, ls);
     }
     if (spread) join_aux(c, st);
 }

@@ -189,6 +189,15 @@ void launch_final64(const double* a64t, const float* s, const int8_t* codes, con
 // device ceilings (k_probe.hip); synchronous
 void probe_ceilings(Ctx* c, int cus, csv_ceilings* out);
 
+// total-variation recovery (k_tv.hip)
+void launch_tv_dual(const float* x, float* nuh, float* nuv, float* wh, float* wv, float* ph,
+                    float* pv, const float* lam, int nblk, int B, hipStream_t st);
+void launch_tv_primal(float* x, const float* g, const float* ph, const float* pv,
+                      const float* lam, const double* lip, int nblk, int B, hipStream_t st);
+void launch_tv_final64(const int8_t* q, const float* x, const int8_t* codes, const uint8_t* exps,
+                       const float* lam, int nblk, int M, int B, double s_phi, double* obj,
+                       hipStream_t st);
+
 // fused BF16 recovery (k_fista_bf16.hip)
 struct FusedTile {
     const uint16_t* frag_fwd;

@@ -364,8 +364,9 @@ void launch_prox(float* s, float* v, const float* g, const float* lam, const dou
 }
 
 // ------------------------------------------------------------- synthesis
-// Residual block X = C^T S C (eq. (4) adds it to the decoded key frame);
-// float output = key + X, uint8 output = clip(round-half-even(key + X)).
+// Residual block X = C^T S C (eq. (4) adds it to the decoded key frame), or
+// X = S itself when dct is NULL (pixel-domain recovery); float output =
+// key + X, uint8 output = clip(round-half-even(key + X)).
 // One workgroup per block, one thread per pixel.
 template <int B>
 __global__ __launch_bounds__(B * B) void synth_kernel(const float* __restrict__ s,
@@ -379,18 +380,23 @@ __global__ __launch_bounds__(B * B) void synth_kernel(const float* __restrict__ 
     __shared__ float C[n];
     const int gb = blockIdx.x, t = gb / nb, b = gb % nb;
     const int tid = threadIdx.x;
-    S[tid] = s[(size_t)gb * n + tid];
-    C[tid] = dct[tid];
-    __syncthreads();
     const int r = tid / B, c = tid % B;
-    float u = 0.f;   // U[r][l = c] = sum_k C[k][r] S[k][l]
+    float x;
+    if (dct == nullptr) {   // pixel-domain residual (TV recovery)
+        x = s[(size_t)gb * n + tid];
+    } else {
+        S[tid] = s[(size_t)gb * n + tid];
+        C[tid] = dct[tid];
+        __syncthreads();
+        float u = 0.f;   // U[r][l = c] = sum_k C[k][r] S[k][l]
 #pragma unroll 8
-    for (int k = 0; k < B; ++k) u = fmaf(C[k * B + r], S[k * B + c], u);
-    U[tid] = u;
-    __syncthreads();
-    float x = 0.f;   // X[r][c] = sum_l U[r][l] C[l][c]
+        for (int k = 0; k < B; ++k) u = fmaf(C[k * B + r], S[k * B + c], u);
+        U[tid] = u;
+        __syncthreads();
+        x = 0.f;   // X[r][c] = sum_l U[r][l] C[l][c]
 #pragma unroll 8
-    for (int l = 0; l < B; ++l) x = fmaf(U[r * B + l], C[l * B + c], x);
+        for (int l = 0; l < B; ++l) x = fmaf(U[r * B + l], C[l * B + c], x);
+    }
     const int py = (b / nbx) * B + r, px = (b % nbx) * B + c;
     if (py < H && px < W) {
         const size_t pix = (size_t)py * W + px;
