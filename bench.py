@@ -49,12 +49,14 @@ def parse():
                     help="blocks the oracle recovers for the CPU baseline")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
-    ap.add_argument("--mode", choices=["headline", "mixed", "serve", "encode", "configure"],
+    ap.add_argument("--mode", choices=["headline", "mixed", "serve", "encode", "configure", "tv",
+                                       "whole"],
                     default="headline",
                     help="headline: the metric above; mixed: 64 mixed streams decoded by one "
                          "graph-captured batch; serve: 256 cameras under a Poisson load sweep; "
                          "encode: the headline cameras encoded in each measurement form; "
-                         "configure: the (G, M) configurator sweep")
+                         "configure: the (G, M) configurator sweep; tv: TV recovery vs l1; "
+                         "whole: whole-frame measurement with Q regenerated on the fly")
     ap.add_argument("--psnr-floor", type=float, default=32.0,
                     help="configure mode: PSNR floor standing in for the tracking requirement")
     ap.add_argument("--serve-window", type=float, default=2.0, help="seconds per sweep point")
@@ -386,6 +388,117 @@ def configure_main(args):
         "points": pts}), flush=True)
 
 
+def tv_main(args):
+    """Total-variation recovery (the paper's TVAL3-style solver) against the
+    l1-DCT path on the same GOPs: 4 synthetic 352x288 cameras, GOP 16, B =
+    16, M/n = 0.25 (M = 64), T = 300; one step = decode the 4 GOPs as one
+    batch.  Reports recovered Mpixel/s of each path and the PSNR each
+    reaches on the same codes."""
+    import torch
+    import paper_1311_1419_amd as P
+    import synthvid as sv
+    specs = [sv.cif_sweep(16, 0.25, stream=s) for s in range(4)]
+    videos = [s.video() for s in specs]
+    px = sum((s.gop - 1) * s.height * s.width for s in specs)
+    res = {}
+    with P.Context(0) as ctx:
+        for name, prec, flags in [("tv_fp32", P.CSV_FP32, P.CSV_FLAG_TV),
+                                  ("l1_fp32", P.CSV_FP32, 0), ("l1_bf16", P.CSV_BF16, 0)]:
+            params = [P.Params.from_spec(s, precision=prec, flags=flags) for s in specs]
+            items = [(ctx.encode_gop(torch.from_numpy(v).cuda(), p), p)
+                     for v, p in zip(videos, params)]
+            for _ in range(args.warmup):
+                outs = ctx.decode_batch(items)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                outs = ctx.decode_batch(items)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / args.steps
+            ps = [psnr(v[t], o[0][t].cpu().numpy()) for v, o in zip(videos, outs)
+                  for t in range(1, v.shape[0])]
+            res[name] = {"mpix_per_s": round(px / wall / 1e6, 2), "ms_per_step": round(1e3 * wall, 3),
+                         "mean_psnr_db": round(float(np.mean(ps)), 3)}
+    # unfused TV moves about 72 bytes per pixel per iteration through HBM
+    # (dual step: x, nu, w in, nu, w, P out; primal step: x, G, P in, x out;
+    # the two products' x/R/G traffic), so HBM bounds it at
+    # 8 TB/s / (72 B x T) pixels/s
+    ceiling = 8.0e12 / (72.0 * 300) / 1e6
+    print(json.dumps({
+        "metric": "recovered Mpixel/s, TV recovery vs l1-DCT on the same codes, 4 cameras 352x288 "
+                  "GOP 16, M/n=0.25, T=300",
+        "value": res["tv_fp32"]["mpix_per_s"], "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": "cif352x288-g16-b16-m64-t300-x4streams-tv"},
+        "roofline": {"bound": "hbm", "unit": "Mpixel/s", "peak": round(ceiling, 1),
+                     "achieved": res["tv_fp32"]["mpix_per_s"],
+                     "frac": round(res["tv_fp32"]["mpix_per_s"] / ceiling, 4),
+                     "note": "unfused TV: about 72 HBM bytes per pixel per iteration at 8 TB/s"},
+        "paths": res}), flush=True)
+
+
+def whole_main(args):
+    """Whole-frame measurement (eq. (1) literal): 8 synthetic 176x144
+    cameras, GOP 5 (the paper's key frame + four CS frames), each CS frame
+    measured as one 25 344-pixel vector by Q regenerated in the kernel; at
+    the paper's CS compression ratio of 50 (M = 506) and at M/n = 0.25
+    (M = 6336).  One step = the 8 GOPs encoded as one batch.  The kernel is
+    integer-ALU bound: 332 VALU instructions per Philox block of four Q
+    entries plus 7 per CS frame (counted in its gfx950 code), against
+    256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s."""
+    import torch
+    import paper_1311_1419_amd as P
+    import synthvid as sv
+    specs = [sv.qcif_tiny(stream=s).with_(gop=5) for s in range(8)]
+    frames = [torch.from_numpy(s.video()).cuda() for s in specs]
+    n = 176 * 144
+    peak = 256 * 4 * 16 * 2.4e9
+    res = {}
+    with P.Context(0) as ctx:
+        for label, m in [("cr50_m506", 506), ("rho0.25_m6336", 6336)]:
+            params = [P.Params.from_spec(s, m=m, precision=P.CSV_FP32,
+                                         flags=P.CSV_FLAG_WHOLE_FRAME) for s in specs]
+            outs = [ctx.alloc_stream(p) for p in params]
+            items = list(zip(frames, params))
+            for _ in range(args.warmup):
+                ctx.encode_batch(items, outs=outs)
+            torch.cuda.synchronize()
+            ctx.profile_reset()
+            ctx.profile(True)
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                ctx.encode_batch(items, outs=outs)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / args.steps
+            ctx.profile(False)
+            k_ms, k_n = ctx.profile_query("measure")
+            k_s = k_ms / max(k_n, 1) / 1e3                      # per GOP launch
+            entries = m * n                                     # Q entries per GOP
+            ops = entries / 4 * (332 + 7 * 4)                   # VALU lane-ops per GOP
+            px = len(specs) * 4 * n
+            cr_cs = 8.0 * n / (8 * m + 8)
+            res[label] = {"m": m, "cs_cr": round(cr_cs, 2),
+                          "cs_mpix_per_s": round(px / wall / 1e6, 2),
+                          "ms_per_step": round(1e3 * wall, 3),
+                          "measure_ms_per_gop": round(1e3 * k_s, 4),
+                          "q_entries_per_s": round(entries / k_s, 1),
+                          "valu_tops": round(ops / k_s / 1e12, 2),
+                          "valu_frac": round(ops / k_s / peak, 4)}
+    print(json.dumps({
+        "metric": "whole-frame CS Mpixel/s encoded (Q regenerated on the fly), 8 cameras 176x144 "
+                  "GOP 5",
+        "value": res["cr50_m506"]["cs_mpix_per_s"], "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32/int64", "data": "synthetic",
+        "config": {"workload": "qcif176x144-g5-whole-frame-x8streams",
+                   "note": "measure kernel timed per GOP while the batch's GOPs overlap"},
+        "roofline": {"bound": "alu", "unit": "T lane-ops/s", "peak": round(peak / 1e12, 1),
+                     "achieved": res["rho0.25_m6336"]["valu_tops"],
+                     "frac": res["rho0.25_m6336"]["valu_frac"]},
+        "rates": res}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -401,6 +514,10 @@ def main():
         return encode_main(args)
     if args.mode == "configure":
         return configure_main(args)
+    if args.mode == "tv":
+        return tv_main(args)
+    if args.mode == "whole":
+        return whole_main(args)
     import torch
     import paper_1311_1419_amd as P
 

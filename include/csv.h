@@ -81,7 +81,15 @@ enum {
      * step on x with step 1/(L + 8 beta); nu += beta (D x - w)); beta = 0.03
      * lam; lam = lambda_frac ||Phi^T y^||_inf.  FP32 only (CSV_EUNSUPPORTED
      * with CSV_BF16); obj_out then holds the TV objective. */
-    CSV_FLAG_TV = 16
+    CSV_FLAG_TV = 16,
+    /* Encoder: whole-frame measurement, eq. (1) read literally: each CS
+     * frame's residual is one vector of n = W H pixels (block is ignored,
+     * N_b = 1, M up to W H, m = 0 takes M = floor(rho W H + 0.5)), measured
+     * by the M x (W H) matrix of the same counter generator, regenerated
+     * inside the kernel and never stored, in exact 64-bit integer sums, and
+     * quantised as one block per frame.  GOPs of at most 32 frames; exact
+     * integer form only; decoding such streams returns CSV_EUNSUPPORTED. */
+    CSV_FLAG_WHOLE_FRAME = 32
 };
 
 /* ------------------------------------------------------------ params */

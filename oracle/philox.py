@@ -94,3 +94,18 @@ def measurement_matrix_q(m: int, n: int, phi_seed: int, stream_id: int) -> np.nd
 def phi_scale(m: int) -> float:
     """s_Phi = 1 / (4 sqrt(M)), so that Phi = s_Phi * Q has variance 1/M."""
     return 1.0 / (4.0 * np.sqrt(m))
+
+
+def measurement_rows_q(rows, n: int, phi_seed: int, stream_id: int) -> np.ndarray:
+    """Selected rows of Q (len(rows) x n) with the same entries as
+    `measurement_matrix_q`: entry (i, j) is word (i n + j) mod 4 of the
+    Philox block at counter (i n + j) div 4."""
+    rows = np.asarray(rows, dtype=np.int64)
+    idx = (rows[:, None] * n + np.arange(n, dtype=np.int64)[None, :]).reshape(-1)
+    ctr = (idx // 4).astype(np.uint64)
+    zeros = np.zeros_like(ctr)
+    w = philox4x64_10(ctr, np.full(ctr.shape, n, dtype=np.uint64), zeros, zeros,
+                      int(phi_seed) & MASK64, int(stream_id) & MASK64)
+    words = np.stack(w, axis=1)[np.arange(idx.size), idx % 4]
+    q = np.bitwise_count(words).astype(np.int64) - 32
+    return q.reshape(rows.size, n)

@@ -24,6 +24,7 @@ CSV_FLAG_LAMBDA_PIXEL_DOMAIN = 2
 CSV_FLAG_MEASURE_INT8 = 4
 CSV_FLAG_MEASURE_FP8 = 8
 CSV_FLAG_TV = 16
+CSV_FLAG_WHOLE_FRAME = 32
 
 
 class CsvParams(C.Structure):

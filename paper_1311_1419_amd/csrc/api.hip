@@ -54,8 +54,14 @@ Shape resolve(const csv_params* p) {
     CSV_REQUIRE(p->precision == CSV_FP32 || p->precision == CSV_BF16, CSV_EINVAL,
                 "precision must be CSV_FP32 or CSV_BF16");
     CSV_REQUIRE((p->flags & ~(CSV_FLAG_ISTA | CSV_FLAG_LAMBDA_PIXEL_DOMAIN |
-                              CSV_FLAG_MEASURE_INT8 | CSV_FLAG_MEASURE_FP8 | CSV_FLAG_TV)) == 0,
+                              CSV_FLAG_MEASURE_INT8 | CSV_FLAG_MEASURE_FP8 | CSV_FLAG_TV |
+                              CSV_FLAG_WHOLE_FRAME)) == 0,
                 CSV_EINVAL, "unknown flag bits");
+    CSV_REQUIRE(!(p->flags & CSV_FLAG_WHOLE_FRAME) ||
+                    !(p->flags & (CSV_FLAG_MEASURE_INT8 | CSV_FLAG_MEASURE_FP8)),
+                CSV_EINVAL, "whole-frame measurement is exact integer only");
+    CSV_REQUIRE(!(p->flags & CSV_FLAG_WHOLE_FRAME) || p->gop <= 32, CSV_EUNSUPPORTED,
+                "whole-frame measurement supports GOPs of at most 32 frames");
     CSV_REQUIRE((p->flags & (CSV_FLAG_MEASURE_INT8 | CSV_FLAG_MEASURE_FP8)) !=
                     (CSV_FLAG_MEASURE_INT8 | CSV_FLAG_MEASURE_FP8),
                 CSV_EINVAL, "at most one measurement form flag");
@@ -63,18 +69,20 @@ Shape resolve(const csv_params* p) {
     s.H = p->height;
     s.G = p->gop;
     s.B = p->block;
-    s.n = s.B * s.B;
-    CSV_REQUIRE(s.n <= 2048, CSV_EUNSUPPORTED, "n > 2048 breaks exact FP32 measurement");
+    const bool whole = (p->flags & CSV_FLAG_WHOLE_FRAME) != 0;
+    // whole frame: one vector of W H pixels, measured in exact int64 sums
+    s.n = whole ? p->width * p->height : s.B * s.B;
+    CSV_REQUIRE(whole || s.n <= 2048, CSV_EUNSUPPORTED, "n > 2048 breaks exact FP32 measurement");
     int M = p->m;
     if (M == 0) {
         CSV_REQUIRE(p->rho > 0.f && p->rho <= 1.f, CSV_EINVAL, "rho must be in (0, 1] when m == 0");
         M = (int)std::floor((double)p->rho * s.n + 0.5);
     }
-    CSV_REQUIRE(M >= 1 && M <= s.n, CSV_EINVAL, "m must be in [1, block*block]");
+    CSV_REQUIRE(M >= 1 && M <= s.n, CSV_EINVAL, "m must be in [1, n]");
     s.M = M;
     s.Mp = round_up(M, 32);
-    s.nbx = ceil_div(s.W, s.B);
-    s.nby = ceil_div(s.H, s.B);
+    s.nbx = whole ? 1 : ceil_div(s.W, s.B);
+    s.nby = whole ? 1 : ceil_div(s.H, s.B);
     s.nb = s.nbx * s.nby;
     s.qstep = p->key_qstep;
     s.qshift = 20;
@@ -499,7 +507,7 @@ void encode_gops(Ctx* c, int count, const Shape* shapes, const uint8_t* const* f
         const Shape& s = shapes[i];
         CSV_REQUIRE(frames[i] && out[i].key_levels, CSV_EINVAL, "NULL frames or key_levels");
         CSV_REQUIRE(s.G == 1 || (out[i].codes && out[i].exps), CSV_EINVAL, "codes/exps are NULL");
-        if (s.G > 1) ops[i] = get_operator(c, s, st);
+        if (s.G > 1 && !(s.flags & CSV_FLAG_WHOLE_FRAME)) ops[i] = get_operator(c, s, st);
     }
     const bool spread = count > 1;
     if (spread) ensure_aux(c);
@@ -510,8 +518,9 @@ void encode_gops(Ctx* c, int count, const Shape* shapes, const uint8_t* const* f
         if (s.G == 1) continue;
         const std::string tag = spread ? "#" + std::to_string(i) : std::string();
         keydec[i] = static_cast<uint8_t*>(scratch(c, "keydec" + tag, (size_t)s.W * s.H));
+        // int32 per padded row, or int64 per row for whole frames
         ymeas[i] = static_cast<int32_t*>(
-            scratch(c, "ymeas" + tag, (size_t)(s.G - 1) * s.nb * s.Mp * 4));
+            scratch(c, "ymeas" + tag, (size_t)(s.G - 1) * s.nb * s.Mp * 8));
     }
     if (spread) fork_aux(c, st);
     for (int i = 0; i < count; ++i) {
@@ -528,6 +537,15 @@ void encode_gops(Ctx* c, int count, const Shape* shapes, const uint8_t* const* f
         launch_key_decode(out[i].key_levels, s.W, s.H, s.qstep, keydec[i], ls);
         const size_t fs = (size_t)s.W * s.H;
         const int total = ncs * s.nb;
+        if (s.flags & CSV_FLAG_WHOLE_FRAME) {
+            long long* y64 = reinterpret_cast<long long*>(ymeas[i]);
+            {
+                ProfScope ps(c, "measure", ls);
+                launch_whole_measure(s, frames[i] + fs, ncs, fs, keydec[i], y64, ls);
+            }
+            launch_whole_quantise(y64, s.M, ncs, out[i].codes, out[i].exps, nullptr, ls);
+            continue;
+        }
         {
             ProfScope ps(c, "measure", ls);
             launch_measure(s, ops[i]->q, ops[i]->q8, frames[i] + fs, ncs, fs, keydec[i], ymeas[i],
@@ -579,6 +597,8 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
         CSV_REQUIRE(in[i].key_levels && frames_out[i], CSV_EINVAL, "NULL key_levels or frames_out");
         CSV_REQUIRE(!(s.flags & CSV_FLAG_TV) || s.precision == CSV_FP32, CSV_EUNSUPPORTED,
                     "TV recovery has an FP32 path only");
+        CSV_REQUIRE(!(s.flags & CSV_FLAG_WHOLE_FRAME) || s.G == 1, CSV_EUNSUPPORTED,
+                    "recovery of whole-frame measurements is not available");
         CSV_REQUIRE(s.G == 1 || (in[i].codes && in[i].exps), CSV_EINVAL, "codes/exps are NULL");
         items[i].op = s.G > 1 ? get_operator(c, s, st) : nullptr;
         items[i].nblk = (s.G - 1) * s.nb;
@@ -1043,6 +1063,15 @@ int csv_measure_frame(csv_ctx* ctx, const csv_params* p, const uint8_t* frame,
         const Shape s = resolve(p);
         hipStream_t st = static_cast<hipStream_t>(stream);
         Ctx* c = C(ctx);
+        if (s.flags & CSV_FLAG_WHOLE_FRAME) {
+            // |y~| <= n 255 32 must fit y_out's int32
+            CSV_REQUIRE(!y_out || (long long)s.n * 255 * 32 < (1ll << 31), CSV_EUNSUPPORTED,
+                        "whole-frame measurements of this frame size exceed int32");
+            long long* y = static_cast<long long*>(scratch(c, "ymeas", (size_t)s.M * 8));
+            launch_whole_measure(s, frame, 1, (size_t)s.W * s.H, key_decoded, y, st);
+            launch_whole_quantise(y, s.M, 1, codes, exps, y_out, st);
+            return;
+        }
         Operator* op = get_operator(c, s, st);
         int32_t* y = static_cast<int32_t*>(scratch(c, "ymeas", (size_t)s.nb * s.Mp * 4));
         launch_measure(s, op->q, op->q8, frame, 1, (size_t)s.W * s.H, key_decoded, y, st);

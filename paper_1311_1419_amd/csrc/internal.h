@@ -189,6 +189,12 @@ void launch_final64(const double* a64t, const float* s, const int8_t* codes, con
 // device ceilings (k_probe.hip); synchronous
 void probe_ceilings(Ctx* c, int cus, csv_ceilings* out);
 
+// whole-frame measurement (k_whole.hip): y (n_frames x M, int64)
+void launch_whole_measure(const Shape& s, const uint8_t* frames, int n_frames, size_t frame_stride,
+                          const uint8_t* key, long long* y, hipStream_t st);
+void launch_whole_quantise(const long long* y, int M, int n_frames, int8_t* codes, uint8_t* exps,
+                           int32_t* y32, hipStream_t st);
+
 // total-variation recovery (k_tv.hip)
 void launch_tv_dual(const float* x, float* nuh, float* nuv, float* wh, float* wv, float* ph,
                     float* pv, const float* lam, int nblk, int B, hipStream_t st);

@@ -46,8 +46,9 @@ def test_host_side_validation_and_sizes():
     assert (key, code, exp, bits) == (640 * 480, 15 * 300 * 256, 15 * 300, 15 * 300 * (8 * 256 + 8))
     assert P.Params(width=176, height=144, gop=4, block=32, m=0, rho=0.25).resolve() == (256, 30)
     for bad in (dict(block=8), dict(width=170), dict(gop=0), dict(m=1025), dict(iters=0),
-                dict(key_qstep=24), dict(precision=7), dict(flags=64), dict(flags=32), dict(m=0, rho=0.0),
+                dict(key_qstep=24), dict(precision=7), dict(flags=64), dict(flags=128), dict(m=0, rho=0.0),
                 dict(flags=P.CSV_FLAG_MEASURE_INT8 | P.CSV_FLAG_MEASURE_FP8),
+                dict(flags=P.CSV_FLAG_WHOLE_FRAME | P.CSV_FLAG_MEASURE_FP8),
                 dict(lambda_frac=float("nan"))):
         with pytest.raises(P.CsvError) as ei:
             p.with_(**bad).resolve()
@@ -55,6 +56,13 @@ def test_host_side_validation_and_sizes():
     for ok in (P.CSV_FLAG_MEASURE_INT8, P.CSV_FLAG_MEASURE_FP8,
                P.CSV_FLAG_MEASURE_FP8 | P.CSV_FLAG_ISTA, P.CSV_FLAG_TV):
         assert p.with_(flags=ok).resolve() == (256, 300)
+    # whole frame: n = W H, one block per frame, M from rho over W H
+    pw = p.with_(flags=P.CSV_FLAG_WHOLE_FRAME, m=0, rho=0.25)
+    assert pw.resolve() == (76800, 1)
+    assert P.Context.encoded_size(pw)[1:] == (15 * 76800, 15, 15 * (8 * 76800 + 8))
+    with pytest.raises(P.CsvError) as ei:
+        pw.with_(gop=33).resolve()
+    assert ei.value.code == -2
 
 
 def test_compression_ratio_identity():

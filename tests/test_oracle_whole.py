@@ -1,0 +1,56 @@
+"""Pins of the oracle's whole-frame measurement (eq. (1) literal): the row
+sampler against the full generator, linearity and the integer bound, and the
+reduction to the block form when a frame is a single block."""
+import numpy as np
+
+import synthvid as sv
+from oracle import codec, cs, keyframe, philox, whole
+
+
+def test_rows_equal_full_matrix():
+    q = philox.measurement_matrix_q(37, 104, 9, 4)
+    rows = [0, 5, 36, 17]
+    assert np.array_equal(philox.measurement_rows_q(rows, 104, 9, 4), q[rows])
+
+
+def test_single_block_frame_equals_block_form():
+    # a 16 x 16 frame is one block of B = 16: the whole-frame and block
+    # measurements coincide (same counter layout, n = 256)
+    rng = np.random.default_rng(1)
+    frames = rng.integers(0, 256, size=(3, 16, 16), dtype=np.uint8)
+    lev = keyframe.encode_levels(frames[0], 16)
+    key = keyframe.decode_levels(lev, 16)
+    y = whole.measure(frames, key, 40, 11, 2)
+    q = philox.measurement_matrix_q(40, 256, 11, 2)
+    for t in (1, 2):
+        r = cs.gather_blocks(frames[t].astype(np.int64) - key.astype(np.int64), 16)
+        assert np.array_equal(y[t - 1], cs.measure(q, r)[:, 0])
+
+
+def test_linearity_bound_and_sampled_rows():
+    spec = sv.qcif_tiny().with_(gop=3)
+    frames = spec.video()
+    lev = keyframe.encode_levels(frames[0], 16)
+    key = keyframe.decode_levels(lev, 16)
+    m = 300
+    y = whole.measure(frames, key, m, 5, 1)
+    n = 176 * 144
+    r = frames[1:].astype(np.int64) - key.astype(np.int64)[None]
+    assert np.all(np.abs(y) <= 32 * np.abs(r).reshape(2, -1).sum(axis=1)[:, None])
+    rows = [0, 7, 299, 150]
+    assert np.array_equal(whole.measure_rows(frames, key, rows, 5, 1), y[:, rows])
+    # linearity in the residual: doubling the CS frames' residual doubles y~
+    q = philox.measurement_matrix_q(m, n, 5, 1)
+    assert np.array_equal(q @ (2 * r.reshape(2, -1).T), 2 * y.T)
+
+
+def test_encode_gop_bits():
+    spec = sv.qcif_tiny().with_(gop=4)
+    frames = spec.video()
+    e = whole.encode_gop(frames, 500, 16, 3, 0)
+    assert e["codes"].shape == (3, 500) and e["exps"].shape == (3,)
+    assert e["bits_cs"] == 3 * (8 * 500 + 8)
+    ref = codec.encode_gop(frames, codec.Params.from_spec(spec))
+    assert e["bits_key"] == ref.bits_key
+    # the quantiser: largest code magnitude is 127 when y~ != 0
+    assert np.abs(e["codes"].astype(np.int64)).max() <= 127
