@@ -79,8 +79,10 @@ enum {
      * forward differences inside the block, by the linearised alternating-
      * direction iteration (w = shrink(D x + nu/beta, lam/beta); one gradient
      * step on x with step 1/(L + 8 beta); nu += beta (D x - w)); beta = 0.03
-     * lam; lam = lambda_frac ||Phi^T y^||_inf.  FP32 only (CSV_EUNSUPPORTED
-     * with CSV_BF16); obj_out then holds the TV objective. */
+     * lam; lam = lambda_frac ||Phi^T y^||_inf.  CSV_FP32: any block size;
+     * CSV_BF16 (fused, BF16 products, FP32 iterates): 16 x 16 blocks with
+     * M up to 128, CSV_EUNSUPPORTED otherwise.  obj_out then holds the TV
+     * objective. */
     CSV_FLAG_TV = 16,
     /* Encoder: whole-frame measurement, eq. (1) read literally: each CS
      * frame's residual is one vector of n = W H pixels (block is ignored,
@@ -259,7 +261,7 @@ int csv_graph_destroy(csv_graph* g);
 
 /* ------------------------------------------------------- measurement */
 /* Event timing of named kernel ranges on the stream they run on ("fista_bf16",
- * "fista_fp32", "tv_fp32", "prepare", "synth", "final64", "key_decode", "measure").  While enabled,
+ * "fista_fp32", "tv_fp32", "tv_bf16", "prepare", "synth", "final64", "key_decode", "measure").  While enabled,
  * every such range records a pair of HIP events.  csv_profile_query waits
  * for the recorded events and returns the summed milliseconds and the number
  * of ranges for `name` since the last reset. */

@@ -194,7 +194,7 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
     const size_t sz_q = Mp * n, sz_a64 = Mp * n * 8, sz_a32 = Mp * n * 4;
     const size_t sz_frag = Mp * n * 2, sz_lip = 64, sz_dct = n * 4, sz_dct64 = n * 8;
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
-    const size_t total = 2 * al(sz_q) + 2 * al(sz_a64) + 2 * al(sz_a32) + 2 * al(sz_frag) +
+    const size_t total = 2 * al(sz_q) + 2 * al(sz_a64) + 2 * al(sz_a32) + 4 * al(sz_frag) +
                          al(sz_lip) + al(sz_dct) + al(sz_dct64);
     char* base = static_cast<char*>(ctx_alloc(c, total));
     op->bytes = total;
@@ -212,6 +212,8 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
     op->phi32 = reinterpret_cast<float*>(take(sz_a32));
     op->frag_fwd = reinterpret_cast<uint16_t*>(take(sz_frag));
     op->frag_adj = reinterpret_cast<uint16_t*>(take(sz_frag));
+    op->phi_frag_fwd = reinterpret_cast<uint16_t*>(take(sz_frag));
+    op->phi_frag_adj = reinterpret_cast<uint16_t*>(take(sz_frag));
     op->lip = reinterpret_cast<double*>(take(sz_lip));
     op->dct = reinterpret_cast<float*>(take(sz_dct));
     op->dct64 = reinterpret_cast<double*>(take(sz_dct64));
@@ -310,6 +312,7 @@ struct FusedJob {
     const float* lam;
     float* S;
     int nblk;
+    bool tv = false;   // total-variation recovery (Phi fragments, k_tv_bf16.hip)
 };
 
 // Split every job into tiles of 32*CT blocks, group the tiles by (n, Mp)
@@ -319,19 +322,27 @@ struct FusedJob {
 // idle workgroups steal from the other queues.
 static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st,
                        int variant = -1) {
-    std::map<std::pair<int, int>, std::vector<FusedTile>> classes;
+    // class key (n, Mp, tv); TV tiles are 32 blocks and use the Phi fragments
+    std::map<std::tuple<int, int, int>, std::vector<FusedTile>> classes;
     for (const FusedJob& j : jobs) {
         const Shape& s = *j.s;
-        CSV_REQUIRE(fused_class_supported(s.n, s.Mp), CSV_EUNSUPPORTED,
-                    "fused BF16 recovery has no kernel for n=" + std::to_string(s.n) +
-                        ", M padded to " + std::to_string(s.Mp));
-        const int nt = variant >= 0 ? 32 * fused_variants(s.n, s.Mp)[variant].ct
-                                    : fused_tile_blocks(s.n, s.Mp);
+        if (j.tv) {
+            CSV_REQUIRE(tv_class_supported(s.n, s.Mp), CSV_EUNSUPPORTED,
+                        "fused BF16 TV recovery runs on 16 x 16 blocks with M up to 128; "
+                        "use CSV_FP32 otherwise");
+        } else {
+            CSV_REQUIRE(fused_class_supported(s.n, s.Mp), CSV_EUNSUPPORTED,
+                        "fused BF16 recovery has no kernel for n=" + std::to_string(s.n) +
+                            ", M padded to " + std::to_string(s.Mp));
+        }
+        const int nt = j.tv ? 32
+                            : variant >= 0 ? 32 * fused_variants(s.n, s.Mp)[variant].ct
+                                           : fused_tile_blocks(s.n, s.Mp);
         const float* beta = beta_table(c, s.T, (s.flags & CSV_FLAG_ISTA) != 0, st);
         for (int b0 = 0; b0 < j.nblk; b0 += nt) {
             FusedTile t{};
-            t.frag_fwd = j.op->frag_fwd;
-            t.frag_adj = j.op->frag_adj;
+            t.frag_fwd = j.tv ? j.op->phi_frag_fwd : j.op->frag_fwd;
+            t.frag_adj = j.tv ? j.op->phi_frag_adj : j.op->frag_adj;
             t.lip = j.op->lip;
             t.y = j.y + (size_t)b0 * s.Mp;
             t.lam = j.lam + b0;
@@ -341,7 +352,7 @@ static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st
             t.T = s.T;
             t.n = s.n;
             t.Mp = s.Mp;
-            classes[{s.n, s.Mp}].push_back(t);
+            classes[{s.n, s.Mp, j.tv ? 1 : 0}].push_back(t);
         }
     }
     if (classes.empty()) return;
@@ -377,7 +388,7 @@ static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st
     }
     char* dev = static_cast<char*>(scratch(c, "tiles", bytes));
     struct Launch {
-        int n, Mp, count;
+        int n, Mp, tv, count;
         size_t tiles_off, qoff_off, queue_off, ctr_off;
     };
     std::vector<Launch> launches;
@@ -385,7 +396,8 @@ static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st
     for (auto& kv : classes) {
         const auto& v = kv.second;
         const int count = (int)v.size();
-        Launch L{kv.first.first, kv.first.second, count, off_t, 0, 0, 0};
+        Launch L{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), count,
+                 off_t, 0, 0, 0};
         std::memcpy(host + off_t, v.data(), v.size() * sizeof(FusedTile));
         off_t += v.size() * sizeof(FusedTile);
         int* qoff = reinterpret_cast<int*>(host + off_i);
@@ -405,11 +417,17 @@ static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st
     CSV_HIP(hipMemcpyAsync(dev, host, off_i, hipMemcpyHostToDevice, st));
     if (!c->capturing) CSV_HIP(hipEventRecord(c->stage_done, st));
     for (const Launch& L : launches) {
-        ProfScope ps(c, "fista_bf16", st);
-        launch_fista_bf16_class(L.n, L.Mp, reinterpret_cast<const FusedTile*>(dev + L.tiles_off),
-                                reinterpret_cast<const int*>(dev + L.qoff_off),
-                                reinterpret_cast<const int*>(dev + L.queue_off),
-                                reinterpret_cast<int*>(dev + L.ctr_off), L.count, st, variant);
+        const auto* tiles = reinterpret_cast<const FusedTile*>(dev + L.tiles_off);
+        const auto* qoff = reinterpret_cast<const int*>(dev + L.qoff_off);
+        const auto* queue = reinterpret_cast<const int*>(dev + L.queue_off);
+        auto* ctr = reinterpret_cast<int*>(dev + L.ctr_off);
+        if (L.tv) {
+            ProfScope ps(c, "tv_bf16", st);
+            launch_tv_bf16_class(L.n, L.Mp, tiles, qoff, queue, ctr, L.count, device_cus(), st);
+        } else {
+            ProfScope ps(c, "fista_bf16", st);
+            launch_fista_bf16_class(L.n, L.Mp, tiles, qoff, queue, ctr, L.count, st, variant);
+        }
     }
 }
 
@@ -453,12 +471,14 @@ void recover(Ctx* c, const Shape& s, Operator* op, const int8_t* codes, const ui
     if (nblk <= 0) return;
     float* lam = lam_out ? lam_out : static_cast<float*>(scratch(c, "lam", (size_t)nblk * 4));
     const bool tv = (s.flags & CSV_FLAG_TV) != 0;
-    CSV_REQUIRE(!tv || s.precision == CSV_FP32, CSV_EUNSUPPORTED,
-                "TV recovery has an FP32 path only");
     const float* y = prepare(c, s, op, codes, exps, nblk, lam, "", st);
-    if (tv) {
+    if (tv && s.precision == CSV_FP32) {
         ProfScope ps(c, "tv_fp32", st);
         tv_fp32(c, s, op, y, lam, nblk, S, st);
+    } else if (tv) {
+        FusedJob j{&s, op, y, lam, S, nblk};
+        j.tv = true;
+        fista_bf16(c, {j}, st);
     } else if (s.precision == CSV_FP32) {
         ProfScope ps(c, "fista_fp32", st);
         fista_fp32(c, s, op, y, lam, nblk, S, st);
@@ -595,8 +615,10 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
     for (int i = 0; i < count; ++i) {
         const Shape& s = shapes[i];
         CSV_REQUIRE(in[i].key_levels && frames_out[i], CSV_EINVAL, "NULL key_levels or frames_out");
-        CSV_REQUIRE(!(s.flags & CSV_FLAG_TV) || s.precision == CSV_FP32, CSV_EUNSUPPORTED,
-                    "TV recovery has an FP32 path only");
+        CSV_REQUIRE(!(s.flags & CSV_FLAG_TV) || s.precision == CSV_FP32 ||
+                        tv_class_supported(s.n, s.Mp),
+                    CSV_EUNSUPPORTED,
+                    "BF16 TV recovery runs on 16 x 16 blocks with M up to 128; use CSV_FP32");
         CSV_REQUIRE(!(s.flags & CSV_FLAG_WHOLE_FRAME) || s.G == 1, CSV_EUNSUPPORTED,
                     "recovery of whole-frame measurements is not available");
         CSV_REQUIRE(s.G == 1 || (in[i].codes && in[i].exps), CSV_EINVAL, "codes/exps are NULL");
@@ -639,9 +661,13 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
         const Shape& s = shapes[i];
         Item& it = items[i];
         if (!it.nblk) continue;
-        if (s.flags & CSV_FLAG_TV) {
+        if ((s.flags & CSV_FLAG_TV) && s.precision == CSV_FP32) {
             ProfScope ps(c, "tv_fp32", st);      // shares the context's FP32 scratch: serial
             tv_fp32(c, s, it.op, it.y, it.lam, it.nblk, it.S, st);
+        } else if (s.flags & CSV_FLAG_TV) {
+            FusedJob j{&shapes[i], it.op, it.y, it.lam, it.S, it.nblk};
+            j.tv = true;
+            jobs.push_back(j);
         } else if (s.precision == CSV_FP32) {
             ProfScope ps(c, "fista_fp32", st);   // shares the context's FP32 scratch: serial
             fista_fp32(c, s, it.op, it.y, it.lam, it.nblk, it.S, st);

@@ -64,6 +64,8 @@ struct Operator {
     float* phi32 = nullptr;       // Mp x n, s_phi Q
     uint16_t* frag_fwd = nullptr; // bf16 A in forward-product fragment order
     uint16_t* frag_adj = nullptr; // bf16 A in adjoint-product fragment order
+    uint16_t* phi_frag_fwd = nullptr;   // bf16 Phi, forward fragment order (TV)
+    uint16_t* phi_frag_adj = nullptr;   // bf16 Phi, adjoint fragment order (TV)
     double* lip = nullptr;        // device: [0] L_used, [1] Rayleigh quotient, [2] iterations
     float* dct = nullptr;         // B x B orthonormal DCT-II, C[k][i]
     double* dct64 = nullptr;      // same in FP64
@@ -237,6 +239,11 @@ int fused_tile_blocks(int n, int Mp);   // blocks per tile of the chosen variant
 void launch_fista_bf16_class(int n, int Mp, const FusedTile* tiles, const int* qoff,
                              const int* queue, int* counters, int count, hipStream_t st,
                              int variant = -1);
+int device_cus();
+// fused BF16 TV recovery (k_tv_bf16.hip): 16 x 16 blocks, tiles of 32
+bool tv_class_supported(int n, int Mp);
+void launch_tv_bf16_class(int n, int Mp, const FusedTile* tiles, const int* qoff,
+                          const int* queue, int* counters, int count, int cus, hipStream_t st);
 
 }  // namespace csv
 

@@ -29,26 +29,10 @@
 #include <algorithm>
 #include <atomic>
 
-#include "internal.h"
-#include "mfma.h"
+#include "fused_common.h"
 
 namespace csv {
 
-
-// Pointers into global memory.  Tile descriptors are read from memory, so
-// without the address space the compiler emits flat loads, which count on
-// the LDS counter too and force a full wait before every LDS read.
-typedef __attribute__((address_space(1))) const u16x8 gu16x8;
-typedef __attribute__((address_space(1))) const float gfloat;
-template <class T>
-__device__ inline T* as_global(const void* p) {
-    return (T*)(p);
-}
-
-// K index inside a 32-group carried by (K step s, lane half h, element e).
-__host__ __device__ inline int kappa(int s, int h, int e) {
-    return 16 * s + 8 * (e / 4) + 4 * h + (e % 4);
-}
 
 // frag_fwd[mt][ks][lane][e] = A[mt*32 + lane%32][32*(ks/2) + kappa(ks%2, lane/32, e)]
 // frag_adj[nt][ks][lane][e] = A[32*(ks/2) + kappa(ks%2, lane/32, e)][nt*32 + lane%32]
@@ -77,104 +61,10 @@ void launch_bf16_frag_layout(Operator* op, hipStream_t st) {
     frag_layout_kernel<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st>>>(
         op->a32, op->n, op->Mp, op->frag_fwd, op->frag_adj);
     CSV_HIP(hipGetLastError());
-}
-
-__device__ inline u16x8 pack_bf16(const floatx16& a, int s) {
-    u16x8 o;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) o[e] = __builtin_bit_cast(uint16_t, (__bf16)a[8 * s + e]);
-    return o;
-}
-
-__device__ inline int next_tile(const int* __restrict__ qoff, const int* __restrict__ queue,
-                                int* __restrict__ counters) {
-    const int x0 = blockIdx.x & 7;
-    for (int d = 0; d < 8; ++d) {
-        const int x = (x0 + d) & 7;
-        const int len = qoff[x + 1] - qoff[x];
-        if (len <= 0) continue;
-        const int i = atomicAdd(&counters[x], 1);
-        if (i < len) return queue[qoff[x] + i];
-    }
-    return -1;
-}
-
-
-// Forward product for this wave's NF output tiles (mt_i, fct), mt_i =
-// (w + W i) / CT.  af holds the first kPF K steps on entry.  Loads the first
-// kPA adjoint steps (rows rt0 + r / CT) into aa before returning.
-template <int N, int MP, int CT, int NF, int AR, int W, int kPF, int kPA>
-__device__ inline void forward_tiles(u16x8 (&af)[kPF][NF], u16x8 (&aa)[kPA][AR],
-                                     floatx16 (&acc)[NF], const gu16x8* ffwd, const gu16x8* fadj,
-                                     const u16x8* Vb, int w, int ln, int fct, int rt0) {
-    constexpr int KSF = N / 16, KSA = MP / 16;
-#pragma unroll
-    for (int i = 0; i < NF; ++i) acc[i] = floatx16{};
-#pragma unroll 1
-    for (int ks0 = 0; ks0 < KSF - kPF; ks0 += kPF) {
-#pragma unroll
-        for (int j = 0; j < kPF; ++j) {
-            const int ks = ks0 + j;
-            const bf16x8 b = __builtin_bit_cast(bf16x8, Vb[(ks * CT + fct) * 64 + ln]);
-#pragma unroll
-            for (int i = 0; i < NF; ++i) {
-                acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[j][i]),
-                                                                 b, acc[i], 0, 0, 0);
-                const int mt = (w + W * i) / CT;
-                af[j][i] = ffwd[((size_t)mt * KSF + ks + kPF) * 64 + ln];
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < kPF; ++j) {   // last kPF steps: no further forward loads
-        const int ks = KSF - kPF + j;
-        const bf16x8 b = __builtin_bit_cast(bf16x8, Vb[(ks * CT + fct) * 64 + ln]);
-#pragma unroll
-        for (int i = 0; i < NF; ++i)
-            acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[j][i]), b,
-                                                             acc[i], 0, 0, 0);
-        if (j < kPA) {
-#pragma unroll
-            for (int r = 0; r < AR; ++r)
-                aa[j][r] = fadj[((size_t)(rt0 + r / CT) * KSA + j) * 64 + ln];
-        }
-    }
-}
-
-template <int N, int MP, int CT, int NF, int W, int kPF>
-__device__ inline void load_fwd_head(u16x8 (&af)[kPF][NF], const gu16x8* ffwd, int w, int ln) {
-    constexpr int KSF = N / 16;
-#pragma unroll
-    for (int p = 0; p < kPF; ++p)
-#pragma unroll
-        for (int i = 0; i < NF; ++i) {
-            const int mt = (w + W * i) / CT;
-            af[p][i] = ffwd[((size_t)mt * KSF + p) * 64 + ln];
-        }
-}
-
-// R = P - y for one forward tile, written to LDS as bf16 (y from registers
-// or from global memory).
-template <int MP, int CT, bool YREG>
-__device__ inline void store_residual(const floatx16& acc, const floatx16& yv, const gfloat* yg,
-                                      int nblk, int mt, int fct, int ln, u16x8* Rb) {
-    const int h = ln >> 5, b = fct * 32 + (ln & 31);
-    floatx16 rr = acc;
-    if constexpr (YREG) {
-        rr -= yv;
-    } else if (b < nblk) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const gfloat* yp = yg + (size_t)b * MP + mt * 32 + 8 * q + 4 * h;
-            const float4 y4 = make_float4(yp[0], yp[1], yp[2], yp[3]);
-            rr[4 * q] -= y4.x;
-            rr[4 * q + 1] -= y4.y;
-            rr[4 * q + 2] -= y4.z;
-            rr[4 * q + 3] -= y4.w;
-        }
-    }
-    Rb[((2 * mt) * CT + fct) * 64 + ln] = pack_bf16(rr, 0);
-    Rb[((2 * mt + 1) * CT + fct) * 64 + ln] = pack_bf16(rr, 1);
+    // Phi itself (pixel-domain products of the TV solver)
+    frag_layout_kernel<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st>>>(
+        op->phi32, op->n, op->Mp, op->phi_frag_fwd, op->phi_frag_adj);
+    CSV_HIP(hipGetLastError());
 }
 
 // SPL: accumulator tiles per wave whose s_{k-1} lives in LDS rather than in
@@ -529,7 +419,7 @@ int fused_tile_blocks(int n, int Mp) {
 }
 
 // Compute units of the current device (cached per device).
-static int device_cus() {
+int device_cus() {
     static std::atomic<int> cus[64];
     int dev = 0;
     CSV_HIP(hipGetDevice(&dev));

@@ -1,8 +1,9 @@
 """Total-variation recovery (CSV_FLAG_TV, the TVAL3-style solver of
-Section 4) on the GPU against the FP64 oracle: same FP32 bars as the plain
-FISTA path (per-frame PSNR within 0.01 dB, float frames within 0.05, FP64
-TV objective within 1e-5 relative); BF16 is refused; a batch mixing TV and
-l1 GOPs decodes each as if alone."""
+Section 4) on the GPU against the FP64 oracle: the FP32 path with the bars
+of the plain FISTA path (per-frame PSNR within 0.01 dB, float frames within
+0.05, FP64 TV objective within 1e-5 relative); the fused BF16 kernel for
+16 x 16 blocks with the BF16 bars; B = 32 in BF16 is refused; a batch
+mixing TV and l1 GOPs decodes each as if alone."""
 import numpy as np
 import pytest
 
@@ -44,23 +45,53 @@ def test_tv_decode_matches_oracle(ctx, spec):
     assert np.max(rr) <= 2e-5
 
 
-def test_tv_refuses_bf16_and_mixed_batch(ctx):
+BF16_CASES = [(sv.qcif_tiny(), "qcif-b16-m64"), (sv.cif_sweep(4, 0.1), "cif-b16-m26"),
+              (sv.cif_sweep(4, 0.3), "cif-b16-m77"), (sv.cif_sweep(4, 0.5), "cif-b16-m128")]
+
+
+@pytest.mark.parametrize("spec", [c[0] for c in BF16_CASES], ids=[c[1] for c in BF16_CASES])
+def test_tv_bf16_matches_oracle(ctx, spec):
+    """The fused BF16 TV kernel (BF16 Phi products, FP32 iterates) against
+    the FP64 oracle, with the BF16 bars of the l1 path: PSNR within 0.1 dB,
+    float frames within 4 grey levels, TV objective within 1e-2."""
     import paper_1311_1419_amd as P
-    announce("tv bf16 refused, mixed batch")
-    spec = sv.qcif_tiny()
-    frames = dev(spec.video())
-    pb = P.Params.from_spec(spec, precision=P.CSV_BF16, flags=P.CSV_FLAG_TV)
-    gs = ctx.encode_gop(frames, pb)
+    announce(f"tv bf16 {spec.width}x{spec.height} M={spec.m}")
+    frames = spec.video()
+    op = codec.Params.from_spec(spec, solver="tv")
+    ref = codec.decode_gop(codec.encode_gop(frames, op), op)
+    p = P.Params.from_spec(spec, precision=P.CSV_BF16, flags=P.CSV_FLAG_TV)
+    gs = ctx.encode_gop(dev(frames), p)
+    out, fl, obj = ctx.decode_gop(gs, p, want_float=True, want_obj=True)
+    out, fl, obj = host(out), host(fl), host(obj)
+    for t in range(1, spec.gop):
+        err = np.max(np.abs(fl[t - 1].astype(np.float64) - ref.cs_float[t - 1]))
+        assert err <= 4.0, f"frame {t}: max abs {err}"
+        dp = abs(psnr(frames[t], out[t]) - psnr(frames[t], ref.frames[t]))
+        assert dp <= 0.1, f"frame {t}: PSNR differs by {dp}"
+    rel = np.abs(obj[..., 0] - ref.objective) / np.maximum(ref.objective, 1e-300)
+    assert np.max(rel) <= 1e-2
+
+
+def test_tv_bf16_b32_refused_and_mixed_batch(ctx):
+    import paper_1311_1419_amd as P
+    announce("tv bf16 B=32 refused, mixed batch")
+    big = sv.qcif_tiny().with_(block=32, m=102, gop=2)
+    pb = P.Params.from_spec(big, precision=P.CSV_BF16, flags=P.CSV_FLAG_TV)
+    gs = ctx.encode_gop(dev(big.video()), pb)
     with pytest.raises(P.CsvError) as ei:
         ctx.decode_gop(gs, pb)
     assert ei.value.code == P._native.CSV_EUNSUPPORTED
-    p_tv = _tv(spec)
-    p_l1 = P.Params.from_spec(spec, precision=P.CSV_FP32)
-    g_tv = ctx.encode_gop(frames, p_tv)
-    g_l1 = ctx.encode_gop(frames, p_l1)
-    both = ctx.decode_batch([(g_tv, p_tv), (g_l1, p_l1)], want_float=True)
-    a_tv = ctx.decode_gop(g_tv, p_tv, want_float=True)
-    a_l1 = ctx.decode_gop(g_l1, p_l1, want_float=True)
-    assert np.array_equal(host(both[0][1]), host(a_tv[1]))
-    assert np.array_equal(host(both[1][1]), host(a_l1[1]))
-    assert not np.array_equal(host(a_tv[1]), host(a_l1[1]))
+    # one batch (one precision) holding fused TV and fused l1 GOPs of two
+    # streams: each decodes as if alone
+    spec = sv.qcif_tiny()
+    frames = dev(spec.video())
+    params = [P.Params.from_spec(spec, precision=P.CSV_BF16, flags=P.CSV_FLAG_TV),
+              P.Params.from_spec(spec, precision=P.CSV_BF16),
+              P.Params.from_spec(sv.cif_sweep(4, 0.25).with_(height=144, width=176), precision=P.CSV_BF16,
+                                 flags=P.CSV_FLAG_TV)]
+    streams = [ctx.encode_gop(frames, p) for p in params]
+    both = ctx.decode_batch(list(zip(streams, params)), want_float=True)
+    for (g, p), b in zip(zip(streams, params), both):
+        alone = ctx.decode_gop(g, p, want_float=True)
+        assert np.array_equal(host(b[1]), host(alone[1]))
+    assert not np.array_equal(host(both[0][1]), host(both[1][1]))
