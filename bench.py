@@ -459,7 +459,9 @@ def whole_main(args):
     cameras, GOP 5 (the paper's key frame + four CS frames), each CS frame
     measured as one 25 344-pixel vector by Q regenerated in the kernel; at
     the paper's CS compression ratio of 50 (M = 506) and at M/n = 0.25
-    (M = 6336).  One step = the 8 GOPs encoded as one batch.  The kernel is
+    (M = 6336).  One step = the 8 GOPs encoded as one batch.  Then the
+    same GOPs at M = 506 decoded by whole-frame TV recovery (reported
+    beside the measurement rate, not as the headline value).  The kernel is
     integer-ALU bound: 332 VALU instructions per Philox block of four Q
     entries plus 7 per CS frame (counted in its gfx950 code), against
     256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s."""
@@ -501,6 +503,38 @@ def whole_main(args):
                           "q_entries_per_s": round(entries / k_s, 1),
                           "valu_tops": round(ops / k_s / 1e12, 2),
                           "valu_frac": round(ops / k_s / peak, 4)}
+        # decode: each CS frame recovered as one 176x144 image by the TV
+        # solver (FP32, T = 300) at CR 50, the 8 GOPs as one batch
+        params = [P.Params.from_spec(s, m=506, precision=P.CSV_FP32, iters=300,
+                                     flags=P.CSV_FLAG_WHOLE_FRAME | P.CSV_FLAG_TV) for s in specs]
+        items = [(ctx.encode_gop(f, p), p) for f, p in zip(frames, params)]
+        for _ in range(max(args.warmup, 1)):
+            outs = ctx.decode_batch(items)
+        torch.cuda.synchronize()
+        ctx.profile_reset()
+        ctx.profile(True)
+        dsteps = max(1, min(args.steps, 5))
+        t0 = time.perf_counter()
+        for _ in range(dsteps):
+            outs = ctx.decode_batch(items)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / dsteps
+        ctx.profile(False)
+        k_ms, k_n = ctx.profile_query("tv_whole")
+        it_s = k_ms / max(k_n, 1) / 1e3 / 300               # one iteration of one GOP
+        ps = [psnr(s.video()[t], o[0][t].cpu().numpy()) for s, o in zip(specs, outs)
+              for t in range(1, 5)]
+        # algorithmic HBM bytes per iteration: Q read by both products
+        # (2 M n int8) and the FP32 state of the 4 CS frames (dual step: x,
+        # nu, w in, nu, w, P out = 11 words; primal step: x, g, P in, x out
+        # = 5 words per pixel)
+        byt = 2.0 * 506 * n + 4 * n * 4 * 16
+        res["decode_tv_cr50_m506"] = {
+            "cs_mpix_per_s": round(len(specs) * 4 * n / wall / 1e6, 3),
+            "ms_per_step": round(1e3 * wall, 3), "iters": 300,
+            "ms_per_gop_iteration": round(1e3 * it_s, 5),
+            "gbps_algorithmic": round(byt / it_s / 1e9, 1),
+            "mean_psnr_db": round(float(np.mean(ps)), 3)}
     print(json.dumps({
         "metric": "whole-frame CS Mpixel/s encoded (Q regenerated on the fly), 8 cameras 176x144 "
                   "GOP 5",

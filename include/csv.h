@@ -90,7 +90,12 @@ enum {
      * by the M x (W H) matrix of the same counter generator, regenerated
      * inside the kernel and never stored, in exact 64-bit integer sums, and
      * quantised as one block per frame.  GOPs of at most 32 frames; exact
-     * integer form only; decoding such streams returns CSV_EUNSUPPORTED. */
+     * integer form only.  Decoder: each CS frame is recovered as one H x W
+     * image by the TV solver above (needs CSV_FLAG_TV and CSV_FP32;
+     * CSV_EUNSUPPORTED otherwise), with Q (M x W H int8)
+     * resident on the device and L from the FP64 power iteration on Q Q^T
+     * (M <= 16384); obj_out holds one (objective, relative residual) pair per
+     * CS frame.  csv_recover_blocks and csv_operator_matrix refuse it. */
     CSV_FLAG_WHOLE_FRAME = 32
 };
 
@@ -261,8 +266,9 @@ int csv_graph_destroy(csv_graph* g);
 
 /* ------------------------------------------------------- measurement */
 /* Event timing of named kernel ranges on the stream they run on ("fista_bf16",
- * "fista_fp32", "tv_fp32", "tv_bf16", "prepare", "synth", "final64", "key_decode", "measure").  While enabled,
- * every such range records a pair of HIP events.  csv_profile_query waits
+ * "fista_fp32", "tv_fp32", "tv_bf16", "tv_whole", "prepare", "synth",
+ * "final64", "key_decode", "measure").  While enabled, every such range
+ * records a pair of HIP events.  csv_profile_query waits
  * for the recorded events and returns the summed milliseconds and the number
  * of ranges for `name` since the last reset. */
 int csv_profile_enable(csv_ctx* ctx, int on);

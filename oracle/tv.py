@@ -29,7 +29,9 @@ fixed by the data alone.  Parameters: lam_b = frac ||Phi^T y^_b||_inf per
 block and beta_b = 0.03 lam_b (1 where lam_b = 0).
 
 D: horizontal and vertical forward differences inside the block with a zero
-difference across the last column and the last row (Neumann boundary).
+difference across the last column and the last row (Neumann boundary).  The
+same functions take a whole H x W frame as one column when b = (H, W) (the
+whole-frame reading of eq. (1), oracle/whole.py).
 """
 from __future__ import annotations
 
@@ -38,35 +40,43 @@ import numpy as np
 BETA_RATIO = 0.03
 
 
-def grad(x: np.ndarray, b: int) -> tuple[np.ndarray, np.ndarray]:
-    """D x for block columns x (n x N): horizontal and vertical differences."""
-    X = x.reshape(b, b, -1)
+def _hw(b) -> tuple[int, int]:
+    """Image shape of a column: b (a B x B block) or (height, width)."""
+    return (b, b) if isinstance(b, (int, np.integer)) else (int(b[0]), int(b[1]))
+
+
+def grad(x: np.ndarray, b) -> tuple[np.ndarray, np.ndarray]:
+    """D x for image columns x (n x N; each a B x B block, or an H x W frame
+    when b = (H, W)): horizontal and vertical differences."""
+    hh, ww = _hw(b)
+    X = x.reshape(hh, ww, -1)
     dh = np.zeros_like(X)
     dv = np.zeros_like(X)
     dh[:, :-1] = X[:, 1:] - X[:, :-1]
     dv[:-1, :] = X[1:, :] - X[:-1, :]
-    return dh.reshape(b * b, -1), dv.reshape(b * b, -1)
+    return dh.reshape(hh * ww, -1), dv.reshape(hh * ww, -1)
 
 
-def grad_adj(ph: np.ndarray, pv: np.ndarray, b: int) -> np.ndarray:
+def grad_adj(ph: np.ndarray, pv: np.ndarray, b) -> np.ndarray:
     """D^T (ph, pv): the adjoint of `grad`."""
-    Ph = ph.reshape(b, b, -1)
-    Pv = pv.reshape(b, b, -1)
+    hh, ww = _hw(b)
+    Ph = ph.reshape(hh, ww, -1)
+    Pv = pv.reshape(hh, ww, -1)
     out = np.zeros_like(Ph)
     out[:, :-1] -= Ph[:, :-1]
     out[:, 1:] += Ph[:, :-1]
     out[:-1, :] -= Pv[:-1, :]
     out[1:, :] += Pv[:-1, :]
-    return out.reshape(b * b, -1)
+    return out.reshape(hh * ww, -1)
 
 
-def tv_norm(x: np.ndarray, b: int) -> np.ndarray:
+def tv_norm(x: np.ndarray, b) -> np.ndarray:
     """Isotropic TV of each block column."""
     dh, dv = grad(x, b)
     return np.sum(np.sqrt(dh * dh + dv * dv), axis=0)
 
 
-def objective(phi: np.ndarray, y: np.ndarray, x: np.ndarray, lam: np.ndarray, b: int) -> np.ndarray:
+def objective(phi: np.ndarray, y: np.ndarray, x: np.ndarray, lam: np.ndarray, b) -> np.ndarray:
     r = phi @ x - y
     return 0.5 * np.sum(r * r, axis=0) + lam * tv_norm(x, b)
 
@@ -75,7 +85,7 @@ def betas(lam: np.ndarray) -> np.ndarray:
     return np.where(lam > 0, BETA_RATIO * lam, 1.0)
 
 
-def recover(phi: np.ndarray, y: np.ndarray, lam: np.ndarray, L: float, b: int, iters: int,
+def recover(phi: np.ndarray, y: np.ndarray, lam: np.ndarray, L: float, b, iters: int,
             return_dual: bool = False):
     """The iteration of the module docstring; x (n x N) and optionally the
     multipliers (nu_h, nu_v)."""

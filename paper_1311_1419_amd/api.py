@@ -35,6 +35,9 @@ class Params:
 
     @property
     def n(self) -> int:
+        """Pixels per measured vector: a B x B block, or the whole frame."""
+        if self.flags & N.CSV_FLAG_WHOLE_FRAME:
+            return self.width * self.height
         return self.block * self.block
 
     def resolve(self) -> tuple[int, int]:

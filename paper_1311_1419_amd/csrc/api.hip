@@ -176,7 +176,8 @@ void release_ctx(Ctx* c) {
 }
 
 Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
-    const auto key = std::make_tuple(s.seed, s.sid, s.n, s.M);
+    const bool whole = (s.flags & CSV_FLAG_WHOLE_FRAME) != 0;
+    const auto key = std::make_tuple(s.seed, s.sid, s.n, s.M, whole);
     std::lock_guard<std::mutex> lk(c->cache->mu);
     auto it = c->cache->ops.find(key);
     if (it != c->cache->ops.end()) return it->second.get();
@@ -189,7 +190,30 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
     op->seed = s.seed;
     op->sid = s.sid;
     op->s_phi = 1.0 / (4.0 * std::sqrt((double)s.M));
+    op->whole = whole;
     const size_t n = s.n, Mp = s.Mp;
+    if (whole) {
+        // Q (M x W H int8, read by the whole-frame products) and the step
+        // constant; no transform, no FP32 or BF16 copies
+        CSV_REQUIRE(s.n % 64 == 0, CSV_EUNSUPPORTED,
+                    "whole-frame recovery needs W H to be a multiple of 64");
+        const size_t sz_q = (Mp * n + 255) / 256 * 256;
+        char* base = static_cast<char*>(ctx_alloc(c, sz_q + 256));
+        op->bytes = sz_q + 256;
+        op->q = reinterpret_cast<int8_t*>(base);
+        op->lip = reinterpret_cast<double*>(base + sz_q);
+        try {
+            launch_phi_q(op->q, s.M, s.Mp, s.n, s.seed, (uint64_t)s.sid, st);
+            double* gram = static_cast<double*>(scratch(c, "gram", (size_t)s.M * s.M * 8));
+            launch_power_iteration(op.get(), gram, st);
+        } catch (...) {
+            free_operator(c, op.get());
+            throw;
+        }
+        Operator* raw = op.get();
+        c->cache->ops.emplace(key, std::move(op));
+        return raw;
+    }
     // one allocation, carved into 256-byte aligned pieces
     const size_t sz_q = Mp * n, sz_a64 = Mp * n * 8, sz_a32 = Mp * n * 4;
     const size_t sz_frag = Mp * n * 2, sz_lip = 64, sz_dct = n * 4, sz_dct64 = n * 8;
@@ -279,10 +303,10 @@ static void tv_fp32(Ctx* c, const Shape& s, Operator* op, const float* y, const 
     float* R = static_cast<float*>(scratch(c, "Rm", (size_t)nblk * s.Mp * 4));
     for (float* p : {S, nuh, nuv, wh, wv}) launch_fill_f32(p, 0.f, nn, st);
     for (int k = 0; k < s.T; ++k) {
-        launch_tv_dual(S, nuh, nuv, wh, wv, ph, pv, lam, nblk, s.B, st);
+        launch_tv_dual(S, nuh, nuv, wh, wv, ph, pv, lam, nblk, s.B, s.B, st);
         launch_gemm_nt(S, op->phi32, R, nblk, s.Mp, s.n, s.n, s.n, s.Mp, y, s.Mp, s.M, st);
         launch_gemm_nn(R, op->phi32, Gd, nblk, s.n, s.Mp, s.Mp, s.n, s.n, st);
-        launch_tv_primal(S, Gd, ph, pv, lam, op->lip, nblk, s.B, st);
+        launch_tv_primal(S, Gd, 1, 1.f, ph, pv, lam, op->lip, nblk, s.B, s.B, st);
     }
 }
 
@@ -601,11 +625,68 @@ static void join_aux(Ctx* c, hipStream_t st) {
     }
 }
 
+// Whole-frame recovery (eq. (1) with the TV solver): every CS frame of the
+// GOP is one H x W image measured by Phi = s_Phi Q (M x W H).  FP32 iterates,
+// products with the resident int8 Q in fixed-order partial sums, the same
+// dual and primal steps as the block TV solver; FP64 objective per frame.
+static void decode_whole(Ctx* c, const Shape& s, Operator* op, const csv_gop_stream& in,
+                         uint8_t* frames, float* cs_float, double* obj, hipStream_t st) {
+    {
+        ProfScope ps(c, "key_decode", st);
+        launch_key_decode(in.key_levels, s.W, s.H, s.qstep, frames, st);
+    }
+    const int F = s.G - 1, n = s.n, M = s.M;
+    if (F <= 0) return;
+    const size_t nn = (size_t)F * n;
+    const int nk = whole_fwd_parts(n), nj = ceil_div(M, whole_adj_rows(M));
+    float* y = static_cast<float*>(scratch(c, "w_y", (size_t)F * M * 4));
+    float* r = static_cast<float*>(scratch(c, "w_r", (size_t)F * M * 4));
+    float* pf = static_cast<float*>(scratch(c, "w_pf", (size_t)nk * F * M * 4));
+    float* pa = static_cast<float*>(scratch(c, "w_pa", (size_t)nj * nn * 4));
+    float* lam = static_cast<float*>(scratch(c, "w_lam", (size_t)F * 4));
+    float* x = static_cast<float*>(scratch(c, "w_x", nn * 4));
+    float* nuh = static_cast<float*>(scratch(c, "tv_nuh", nn * 4));
+    float* nuv = static_cast<float*>(scratch(c, "tv_nuv", nn * 4));
+    float* wh = static_cast<float*>(scratch(c, "tv_wh", nn * 4));
+    float* wv = static_cast<float*>(scratch(c, "tv_wv", nn * 4));
+    float* ph = static_cast<float*>(scratch(c, "tv_ph", nn * 4));
+    float* pv = static_cast<float*>(scratch(c, "tv_pv", nn * 4));
+    double* rr = obj ? static_cast<double*>(scratch(c, "w_rr", (size_t)F * M * 8)) : nullptr;
+    double* yy = obj ? static_cast<double*>(scratch(c, "w_yy", (size_t)F * M * 8)) : nullptr;
+    const float sphi = (float)op->s_phi;
+    {
+        ProfScope ps(c, "prepare", st);
+        launch_dequant(in.codes, in.exps, F, M, M, op->s_phi, y, st);
+        // lam_f = frac ||Phi^T y^_f||_inf
+        launch_whole_adj(op->q, y, F, n, M, pa, st);
+        launch_sum_parts(pa, nj, nn, sphi, x, st);
+        launch_row_absmax(x, F, n, n, s.lambda_frac, lam, st);
+    }
+    {
+        ProfScope ps(c, "tv_whole", st);
+        for (float* p : {x, nuh, nuv, wh, wv}) launch_fill_f32(p, 0.f, nn, st);
+        for (int k = 0; k < s.T; ++k) {
+            launch_tv_dual(x, nuh, nuv, wh, wv, ph, pv, lam, F, s.H, s.W, st);
+            launch_whole_fwd(op->q, x, F, n, M, sphi, y, pf, r, st);
+            launch_whole_adj(op->q, r, F, n, M, pa, st);
+            launch_tv_primal(x, pa, nj, sphi, ph, pv, lam, op->lip, F, s.H, s.W, st);
+        }
+    }
+    if (obj) {
+        ProfScope ps(c, "final64", st);
+        launch_whole_objective(op->q, x, F, s.H, s.W, M, op->s_phi, in.codes, in.exps, lam, rr,
+                               yy, obj, st);
+    }
+    ProfScope ps(c, "synth", st);
+    launch_whole_place(x, frames, F, n, frames + n, cs_float, st);
+}
+
 void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* in,
                  uint8_t* const* frames_out, float* const* cs_float_out, double* const* obj_out,
                  hipStream_t st) {
     struct Item {
         Operator* op;
+        bool whole = false;
         int nblk;
         float* S;
         float* lam;
@@ -619,12 +700,28 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
                         tv_class_supported(s.n, s.Mp),
                     CSV_EUNSUPPORTED,
                     "BF16 TV recovery runs on 16 x 16 blocks with M up to 128; use CSV_FP32");
-        CSV_REQUIRE(!(s.flags & CSV_FLAG_WHOLE_FRAME) || s.G == 1, CSV_EUNSUPPORTED,
-                    "recovery of whole-frame measurements is not available");
+        CSV_REQUIRE(!(s.flags & CSV_FLAG_WHOLE_FRAME) ||
+                        ((s.flags & CSV_FLAG_TV) && s.precision == CSV_FP32),
+                    CSV_EUNSUPPORTED,
+                    "whole-frame measurements are recovered by TV in FP32 only "
+                    "(CSV_FLAG_TV, CSV_FP32)");
         CSV_REQUIRE(s.G == 1 || (in[i].codes && in[i].exps), CSV_EINVAL, "codes/exps are NULL");
         items[i].op = s.G > 1 ? get_operator(c, s, st) : nullptr;
         items[i].nblk = (s.G - 1) * s.nb;
     }
+    // whole-frame GOPs run alone on st (their scratch is the context's)
+    bool any_block = false;
+    for (int i = 0; i < count; ++i) {
+        if (!(shapes[i].flags & CSV_FLAG_WHOLE_FRAME)) {
+            any_block = true;
+            continue;
+        }
+        decode_whole(c, shapes[i], items[i].op, in[i], frames_out[i],
+                     cs_float_out ? cs_float_out[i] : nullptr, obj_out ? obj_out[i] : nullptr, st);
+        items[i].whole = true;
+        items[i].nblk = 0;   // nothing left for the block passes below
+    }
+    if (!any_block) return;
     // GOP i's per-GOP kernels run on auxiliary stream i % kAux (one GOP
     // alone stays on st); each auxiliary stream has its own lambda scratch
     const bool spread = count > 1;
@@ -646,6 +743,7 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
         const Shape& s = shapes[i];
         Item& it = items[i];
         const hipStream_t ls = lane_of(i);
+        if (it.whole) continue;
         {
             ProfScope ps(c, "key_decode", ls);
             launch_key_decode(in[i].key_levels, s.W, s.H, s.qstep, frames_out[i], ls);
@@ -1023,6 +1121,8 @@ int csv_operator_matrix(csv_ctx* ctx, const csv_params* p, double* a_out, void* 
         set_device(ctx);
         const Shape s = resolve(p);
         hipStream_t st = static_cast<hipStream_t>(stream);
+        CSV_REQUIRE(!(s.flags & CSV_FLAG_WHOLE_FRAME), CSV_EUNSUPPORTED,
+                    "whole-frame operators have no transform basis");
         Operator* op = get_operator(C(ctx), s, st);
         CSV_HIP(hipMemcpyAsync(a_out, op->a64, (size_t)s.M * s.n * 8, hipMemcpyDeviceToDevice, st));
     });
@@ -1116,6 +1216,8 @@ int csv_recover_blocks(csv_ctx* ctx, const csv_params* p, int32_t n_blocks, cons
         const Shape s = resolve(p);
         hipStream_t st = static_cast<hipStream_t>(stream);
         Ctx* c = C(ctx);
+        CSV_REQUIRE(!(s.flags & CSV_FLAG_WHOLE_FRAME), CSV_EUNSUPPORTED,
+                    "whole-frame measurements are recovered by csv_decode_gop");
         Operator* op = get_operator(c, s, st);
         recover(c, s, op, codes, exps, n_blocks, s_out, lambda_out, obj_out, st);
     });

@@ -53,6 +53,7 @@ Shape resolve(const csv_params* p);
 // Per-stream operator state, resident in HBM while the context lives.
 struct Operator {
     int B = 0, n = 0, M = 0, Mp = 0;
+    bool whole = false;           // whole-frame operator: q and lip only
     uint64_t seed = 0;
     uint32_t sid = 0;
     double s_phi = 0;
@@ -82,7 +83,8 @@ struct Scratch {
 // slots share one cache; each csv_ctx owns its own).
 struct OpCache {
     std::mutex mu;
-    std::map<std::tuple<uint64_t, uint32_t, int, int>, std::unique_ptr<Operator>> ops;
+    // (seed, stream, n, M, whole frame)
+    std::map<std::tuple<uint64_t, uint32_t, int, int, bool>, std::unique_ptr<Operator>> ops;
 };
 
 struct Ctx {
@@ -196,12 +198,31 @@ void launch_whole_measure(const Shape& s, const uint8_t* frames, int n_frames, s
                           const uint8_t* key, long long* y, hipStream_t st);
 void launch_whole_quantise(const long long* y, int M, int n_frames, int8_t* codes, uint8_t* exps,
                            int32_t* y32, hipStream_t st);
+// whole-frame recovery: products with the resident int8 Q, output, FP64 check
+// forward: r = s_Phi Q x - y^ via whole_fwd_parts(n) partials, each F M
+// floats; adjoint: ceil(M / whole_adj_rows(M)) partials of Q^T r, each F n
+// floats, added (in order, times s_Phi) by launch_tv_primal
+int whole_fwd_parts(int n);
+int whole_adj_rows(int M);
+void launch_whole_fwd(const int8_t* q, const float* x, int F, int n, int M, float s_phi,
+                      const float* y, float* part, float* r, hipStream_t st);
+void launch_whole_adj(const int8_t* q, const float* r, int F, int n, int M, float* part,
+                      hipStream_t st);
+void launch_sum_parts(const float* part, int nparts, size_t count, float scale, float* out,
+                      hipStream_t st);
+void launch_whole_place(const float* x, const uint8_t* key, int F, int n, uint8_t* out,
+                        float* out_f32, hipStream_t st);
+void launch_whole_objective(const int8_t* q, const float* x, int F, int H, int W, int M,
+                            double s_phi, const int8_t* codes, const uint8_t* exps,
+                            const float* lam, double* rr, double* yy, double* obj,
+                            hipStream_t st);
 
 // total-variation recovery (k_tv.hip)
 void launch_tv_dual(const float* x, float* nuh, float* nuv, float* wh, float* wv, float* ph,
-                    float* pv, const float* lam, int nblk, int B, hipStream_t st);
-void launch_tv_primal(float* x, const float* g, const float* ph, const float* pv,
-                      const float* lam, const double* lip, int nblk, int B, hipStream_t st);
+                    float* pv, const float* lam, int nblk, int BH, int BW, hipStream_t st);
+void launch_tv_primal(float* x, const float* g, int gparts, float gscale, const float* ph,
+                      const float* pv, const float* lam, const double* lip, int nblk, int BH,
+                      int BW, hipStream_t st);
 void launch_tv_final64(const int8_t* q, const float* x, const int8_t* codes, const uint8_t* exps,
                        const float* lam, int nblk, int M, int B, double s_phi, double* obj,
                        hipStream_t st);

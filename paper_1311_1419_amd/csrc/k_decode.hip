@@ -98,31 +98,46 @@ __device__ inline double block_sum_1024(double v, double* red) {
 
 // Power iteration on G (FP64): v0 = 1/sqrt(M); w = G v; Rayleigh quotient
 // rq = v.w; stop once |rq - rq_prev| <= tol rq (from the second step), else
-// v = w / ||w||.  One workgroup of 1024 threads, thread i owns row i.
+// v = w / ||w||.  One workgroup of 1024 threads; thread t owns rows t,
+// t + 1024, ... (M <= 16384), v lives in LDS.
+constexpr int kPowRows = 16;
 __global__ __launch_bounds__(1024) void power_kernel(const double* __restrict__ g, int M,
                                                     double s_phi, double tol, int max_iter,
                                                     double* __restrict__ lip) {
-    __shared__ double v[1024];
+    extern __shared__ double v[];   // M
     __shared__ double red[16];
-    const int i = threadIdx.x;
-    if (i < M) v[i] = 1.0 / sqrt((double)M);
+    const int tid = threadIdx.x;
+    for (int i = tid; i < M; i += 1024) v[i] = 1.0 / sqrt((double)M);
     __syncthreads();
     double rq = 0.0, rq_prev = 0.0;
     int it = 0;
     for (it = 1; it <= max_iter; ++it) {
-        double w = 0.0;
-        if (i < M)
-            for (int j = 0; j < M; ++j) w += g[(size_t)j * M + i] * v[j];   // G symmetric
-        rq = block_sum_1024(i < M ? v[i] * w : 0.0, red);
+        double w[kPowRows];
+        double pv = 0.0, pw = 0.0;
+#pragma unroll
+        for (int k = 0; k < kPowRows; ++k) {
+            const int i = tid + 1024 * k;
+            w[k] = 0.0;
+            if (i < M) {
+                for (int j = 0; j < M; ++j) w[k] += g[(size_t)j * M + i] * v[j];   // G symmetric
+                pv += v[i] * w[k];
+                pw += w[k] * w[k];
+            }
+        }
+        rq = block_sum_1024(pv, red);
         if (it > 1 && fabs(rq - rq_prev) <= tol * rq) break;
         rq_prev = rq;
-        const double nw = sqrt(block_sum_1024(i < M ? w * w : 0.0, red));
+        const double nw = sqrt(block_sum_1024(pw, red));
         if (nw == 0.0) break;
         __syncthreads();
-        if (i < M) v[i] = w / nw;
+#pragma unroll
+        for (int k = 0; k < kPowRows; ++k) {
+            const int i = tid + 1024 * k;
+            if (i < M) v[i] = w[k] / nw;
+        }
         __syncthreads();
     }
-    if (i == 0) {
+    if (tid == 0) {
         lip[0] = 1.001 * s_phi * s_phi * rq;
         lip[1] = rq;
         lip[2] = (double)(it > max_iter ? max_iter : it);
@@ -145,7 +160,16 @@ void launch_power_iteration(Operator* op, double* gram, hipStream_t st) {
     gram_kernel<<<dim3(ceil_div(M, 16), ceil_div(M, 16)), dim3(256), 0, st>>>(op->q, M, op->n,
                                                                              gram);
     CSV_HIP(hipGetLastError());
-    power_kernel<<<dim3(1), dim3(1024), 0, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip);
+    CSV_REQUIRE(M <= 1024 * kPowRows, CSV_EUNSUPPORTED, "step constant: M above 16384");
+    const size_t lds = (size_t)M * sizeof(double);
+    static bool attr_set = false;
+    if (!attr_set) {
+        CSV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&power_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    1024 * kPowRows * (int)sizeof(double)));
+        attr_set = true;
+    }
+    power_kernel<<<dim3(1), dim3(1024), lds, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip);
     CSV_HIP(hipGetLastError());
 }
 

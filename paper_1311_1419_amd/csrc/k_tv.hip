@@ -1,6 +1,6 @@
 // Total-variation recovery of block residuals (the TVAL3-style solver of
-// Section 4, reference [14]), FP32, pixel domain, blocks as rows (nblk x n,
-// a block's B x B pixels row-major):
+// Section 4, reference [14]), FP32, pixel domain, images as rows (nblk x n,
+// each a BH x BW image row-major: a B x B block, or a whole frame):
 //   min_x lam TV(x) + 1/2 ||Phi x - y^||^2,  TV(x) = sum_i ||D_i x||_2,
 // by the linearised alternating-direction iteration, x_0 = 0, nu_0 = 0:
 //   w   = shrink(D x + nu / beta, lam / beta)
@@ -28,16 +28,17 @@ __global__ __launch_bounds__(256) void tv_dual_kernel(const float* __restrict__ 
                                                       float* __restrict__ nuh, float* __restrict__ nuv,
                                                       float* __restrict__ wh, float* __restrict__ wv,
                                                       float* __restrict__ ph, float* __restrict__ pv,
-                                                      const float* __restrict__ lam, int nblk, int B) {
-    const int n = B * B;
+                                                      const float* __restrict__ lam, int nblk, int BH,
+                                                      int BW) {
+    const int n = BH * BW;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (size_t)nblk * n) return;
     const int b = (int)(idx / n), k = (int)(idx - (size_t)b * n);
-    const int i = k / B, j = k - i * B;
+    const int i = k / BW, j = k - i * BW;
     const float* xb = x + (size_t)b * n;
     const float xv = xb[k];
-    const float dh = j + 1 < B ? xb[k + 1] - xv : 0.f;
-    const float dv = i + 1 < B ? xb[k + B] - xv : 0.f;
+    const float dh = j + 1 < BW ? xb[k + 1] - xv : 0.f;
+    const float dv = i + 1 < BH ? xb[k + BW] - xv : 0.f;
     const float l = lam[b], beta = tv_beta(l);
     // multiplier update of the previous iteration, with the current x
     const float nh = nuh[idx] + beta * (dh - wh[idx]);
@@ -56,28 +57,34 @@ __global__ __launch_bounds__(256) void tv_dual_kernel(const float* __restrict__ 
 
 // x <- x - alpha (g + D^T p), D^T p at (i, j) =
 //   - ph(i, j)[j < B-1] + ph(i, j-1)[j > 0] - pv(i, j)[i < B-1] + pv(i-1, j)[i > 0].
+// g = gscale (g_0 + ... + g_{gparts-1}) for gradients delivered as partial
+// sums (the whole-frame adjoint), each nblk x n; gparts = 1, gscale = 1 is g.
 __global__ __launch_bounds__(256) void tv_primal_kernel(float* __restrict__ x,
-                                                        const float* __restrict__ g,
+                                                        const float* __restrict__ g, int gparts,
+                                                        float gscale,
                                                         const float* __restrict__ ph,
                                                         const float* __restrict__ pv,
                                                         const float* __restrict__ lam,
                                                         const double* __restrict__ lip, int nblk,
-                                                        int B) {
-    const int n = B * B;
+                                                        int BH, int BW) {
+    const int n = BH * BW;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (size_t)nblk * n) return;
     const int b = (int)(idx / n), k = (int)(idx - (size_t)b * n);
-    const int i = k / B, j = k - i * B;
+    const int i = k / BW, j = k - i * BW;
     const float* phb = ph + (size_t)b * n;
     const float* pvb = pv + (size_t)b * n;
     float dt = 0.f;
-    if (j + 1 < B) dt -= phb[k];
+    if (j + 1 < BW) dt -= phb[k];
     if (j > 0) dt += phb[k - 1];
-    if (i + 1 < B) dt -= pvb[k];
-    if (i > 0) dt += pvb[k - B];
+    if (i + 1 < BH) dt -= pvb[k];
+    if (i > 0) dt += pvb[k - BW];
     const float beta = tv_beta(lam[b]);
     const float alpha = (float)(1.0 / (lip[0] + 8.0 * (double)beta));
-    x[idx] -= alpha * (g[idx] + dt);
+    const size_t stride = (size_t)nblk * n;
+    float gv = g[idx];
+    for (int k = 1; k < gparts; ++k) gv += g[k * stride + idx];
+    x[idx] -= alpha * (gscale * gv + dt);
 }
 
 // FP64 check per block (one workgroup): r = s_Phi Q x - y^ with y^ =
@@ -133,20 +140,21 @@ __global__ __launch_bounds__(256) void tv_final64_kernel(const int8_t* __restric
 }
 
 void launch_tv_dual(const float* x, float* nuh, float* nuv, float* wh, float* wv, float* ph,
-                    float* pv, const float* lam, int nblk, int B, hipStream_t st) {
-    const size_t t = (size_t)nblk * B * B;
+                    float* pv, const float* lam, int nblk, int BH, int BW, hipStream_t st) {
+    const size_t t = (size_t)nblk * BH * BW;
     if (!t) return;
     tv_dual_kernel<<<dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st>>>(x, nuh, nuv, wh, wv,
-                                                                           ph, pv, lam, nblk, B);
+                                                                           ph, pv, lam, nblk, BH, BW);
     CSV_HIP(hipGetLastError());
 }
 
-void launch_tv_primal(float* x, const float* g, const float* ph, const float* pv,
-                      const float* lam, const double* lip, int nblk, int B, hipStream_t st) {
-    const size_t t = (size_t)nblk * B * B;
+void launch_tv_primal(float* x, const float* g, int gparts, float gscale, const float* ph,
+                      const float* pv, const float* lam, const double* lip, int nblk, int BH,
+                      int BW, hipStream_t st) {
+    const size_t t = (size_t)nblk * BH * BW;
     if (!t) return;
-    tv_primal_kernel<<<dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st>>>(x, g, ph, pv, lam,
-                                                                             lip, nblk, B);
+    tv_primal_kernel<<<dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st>>>(
+        x, g, gparts, gscale, ph, pv, lam, lip, nblk, BH, BW);
     CSV_HIP(hipGetLastError());
 }
 
