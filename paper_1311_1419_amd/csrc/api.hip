@@ -193,17 +193,19 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
     op->whole = whole;
     const size_t n = s.n, Mp = s.Mp;
     if (whole) {
-        // Q (M x W H int8, read by the whole-frame products) and the step
-        // constant; no transform, no FP32 or BF16 copies
+        // Q (Mp x W H int8) for the forward product, Q^T (W H x Mp) for the
+        // adjoint, and the step constant; no transform, no FP32 or BF16 copies
         CSV_REQUIRE(s.n % 64 == 0, CSV_EUNSUPPORTED,
                     "whole-frame recovery needs W H to be a multiple of 64");
         const size_t sz_q = (Mp * n + 255) / 256 * 256;
-        char* base = static_cast<char*>(ctx_alloc(c, sz_q + 256));
-        op->bytes = sz_q + 256;
+        char* base = static_cast<char*>(ctx_alloc(c, 2 * sz_q + 256));
+        op->bytes = 2 * sz_q + 256;
         op->q = reinterpret_cast<int8_t*>(base);
-        op->lip = reinterpret_cast<double*>(base + sz_q);
+        op->qt = reinterpret_cast<int8_t*>(base + sz_q);
+        op->lip = reinterpret_cast<double*>(base + 2 * sz_q);
         try {
             launch_phi_q(op->q, s.M, s.Mp, s.n, s.seed, (uint64_t)s.sid, st);
+            launch_transpose_q(op->q, s.Mp, s.n, op->qt, st);
             double* gram = static_cast<double*>(scratch(c, "gram", (size_t)s.M * s.M * 8));
             launch_power_iteration(op.get(), gram, st);
         } catch (...) {
@@ -306,7 +308,7 @@ static void tv_fp32(Ctx* c, const Shape& s, Operator* op, const float* y, const 
         launch_tv_dual(S, nuh, nuv, wh, wv, ph, pv, lam, nblk, s.B, s.B, st);
         launch_gemm_nt(S, op->phi32, R, nblk, s.Mp, s.n, s.n, s.n, s.Mp, y, s.Mp, s.M, st);
         launch_gemm_nn(R, op->phi32, Gd, nblk, s.n, s.Mp, s.Mp, s.n, s.n, st);
-        launch_tv_primal(S, Gd, 1, 1.f, ph, pv, lam, op->lip, nblk, s.B, s.B, st);
+        launch_tv_primal(S, Gd, ph, pv, lam, op->lip, nblk, s.B, s.B, st);
     }
 }
 
@@ -625,60 +627,95 @@ static void join_aux(Ctx* c, hipStream_t st) {
     }
 }
 
-// Whole-frame recovery (eq. (1) with the TV solver): every CS frame of the
-// GOP is one H x W image measured by Phi = s_Phi Q (M x W H).  FP32 iterates,
-// products with the resident int8 Q in fixed-order partial sums, the same
-// dual and primal steps as the block TV solver; FP64 objective per frame.
-static void decode_whole(Ctx* c, const Shape& s, Operator* op, const csv_gop_stream& in,
-                         uint8_t* frames, float* cs_float, double* obj, hipStream_t st) {
+// Whole-frame recovery (eq. (1) with the TV solver): every CS frame of a
+// GOP is one H x W image measured by Phi = s_Phi Q (M x W H).  FP32
+// iterates, products with the resident int8 Q in fixed-order partial sums,
+// the same dual and primal steps as the block TV solver, FP64 objective per
+// frame.  A group of GOPs of one shape (at most kWholeBatch) shares every
+// launch of the iteration: the images are [GOP][frame] rows.
+struct WholeItem {
+    Operator* op;
+    const csv_gop_stream* in;
+    uint8_t* frames;
+    float* cs_float;
+    double* obj;
+};
+
+static void decode_whole(Ctx* c, const Shape& s, const std::vector<WholeItem>& its,
+                         hipStream_t st) {
+    const int ng = (int)its.size();
+    CSV_REQUIRE(ng >= 1 && ng <= kWholeBatch, CSV_EINVAL, "whole-frame group size");
     {
         ProfScope ps(c, "key_decode", st);
-        launch_key_decode(in.key_levels, s.W, s.H, s.qstep, frames, st);
+        for (const WholeItem& w : its)
+            launch_key_decode(w.in->key_levels, s.W, s.H, s.qstep, w.frames, st);
     }
     const int F = s.G - 1, n = s.n, M = s.M;
     if (F <= 0) return;
-    const size_t nn = (size_t)F * n;
-    const int nk = whole_fwd_parts(n), nj = ceil_div(M, whole_adj_rows(M));
-    float* y = static_cast<float*>(scratch(c, "w_y", (size_t)F * M * 4));
-    float* r = static_cast<float*>(scratch(c, "w_r", (size_t)F * M * 4));
-    float* pf = static_cast<float*>(scratch(c, "w_pf", (size_t)nk * F * M * 4));
-    float* pa = static_cast<float*>(scratch(c, "w_pa", (size_t)nj * nn * 4));
-    float* lam = static_cast<float*>(scratch(c, "w_lam", (size_t)F * 4));
+    const int nimg = ng * F;
+    const size_t nn = (size_t)nimg * n, fm = (size_t)nimg * M;
+    const int nk = whole_fwd_parts(n);
+    float* y = static_cast<float*>(scratch(c, "w_y", fm * 4));
+    float* r = static_cast<float*>(scratch(c, "w_r", fm * 4));
+    float* pf = static_cast<float*>(scratch(c, "w_pf", (size_t)nk * fm * 4));
+    float* lam = static_cast<float*>(scratch(c, "w_lam", (size_t)nimg * 4));
+    double* lipv = static_cast<double*>(scratch(c, "w_lip", (size_t)ng * 8));
     float* x = static_cast<float*>(scratch(c, "w_x", nn * 4));
-    float* nuh = static_cast<float*>(scratch(c, "tv_nuh", nn * 4));
-    float* nuv = static_cast<float*>(scratch(c, "tv_nuv", nn * 4));
-    float* wh = static_cast<float*>(scratch(c, "tv_wh", nn * 4));
-    float* wv = static_cast<float*>(scratch(c, "tv_wv", nn * 4));
-    float* ph = static_cast<float*>(scratch(c, "tv_ph", nn * 4));
-    float* pv = static_cast<float*>(scratch(c, "tv_pv", nn * 4));
-    double* rr = obj ? static_cast<double*>(scratch(c, "w_rr", (size_t)F * M * 8)) : nullptr;
-    double* yy = obj ? static_cast<double*>(scratch(c, "w_yy", (size_t)F * M * 8)) : nullptr;
-    const float sphi = (float)op->s_phi;
+    WholeTv tv{x,
+               static_cast<float*>(scratch(c, "tv_nuh", nn * 4)),
+               static_cast<float*>(scratch(c, "tv_nuv", nn * 4)),
+               static_cast<float*>(scratch(c, "tv_wh", nn * 4)),
+               static_cast<float*>(scratch(c, "tv_wv", nn * 4)),
+               static_cast<float*>(scratch(c, "tv_ph", nn * 4)),
+               static_cast<float*>(scratch(c, "tv_pv", nn * 4)),
+               lam,
+               lipv};
+    bool any_obj = false;
+    for (const WholeItem& w : its) any_obj = any_obj || w.obj;
+    double* rr = any_obj ? static_cast<double*>(scratch(c, "w_rr", (size_t)F * M * 8)) : nullptr;
+    double* yy = any_obj ? static_cast<double*>(scratch(c, "w_yy", (size_t)F * M * 8)) : nullptr;
+    WholeQ qs{}, qts{};
+    WholeLip ls{};
+    for (int g = 0; g < ng; ++g) {
+        qs.q[g] = its[g].op->q;
+        qts.q[g] = its[g].op->qt;
+        ls.lip[g] = its[g].op->lip;
+    }
+    const double s_phi = its[0].op->s_phi;
+    const float sphi = (float)s_phi;
+    const WholeTv plain{};
     {
         ProfScope ps(c, "prepare", st);
-        launch_dequant(in.codes, in.exps, F, M, M, op->s_phi, y, st);
-        // lam_f = frac ||Phi^T y^_f||_inf
-        launch_whole_adj(op->q, y, F, n, M, pa, st);
-        launch_sum_parts(pa, nj, nn, sphi, x, st);
-        launch_row_absmax(x, F, n, n, s.lambda_frac, lam, st);
+        for (int g = 0; g < ng; ++g)
+            launch_dequant(its[g].in->codes, its[g].in->exps, F, M, M, s_phi,
+                           y + (size_t)g * F * M, st);
+        launch_gather_lip(ls, ng, lipv, st);
+        // lam = frac ||Phi^T y^||_inf per frame
+        launch_whole_adj(qts, ng, y, F, s.H, s.W, M, s.Mp, sphi, x, plain, st);
+        launch_row_absmax(x, nimg, n, n, s.lambda_frac, lam, st);
     }
     {
+        // per iteration: forward product with the dual step (x -> nu, w, P
+        // and the partials), the partials' sum (r), adjoint with the primal
+        // step (x); x, nu, w start at zero
         ProfScope ps(c, "tv_whole", st);
-        for (float* p : {x, nuh, nuv, wh, wv}) launch_fill_f32(p, 0.f, nn, st);
+        for (float* p : {x, tv.nuh, tv.nuv, tv.wh, tv.wv}) launch_fill_f32(p, 0.f, nn, st);
         for (int k = 0; k < s.T; ++k) {
-            launch_tv_dual(x, nuh, nuv, wh, wv, ph, pv, lam, F, s.H, s.W, st);
-            launch_whole_fwd(op->q, x, F, n, M, sphi, y, pf, r, st);
-            launch_whole_adj(op->q, r, F, n, M, pa, st);
-            launch_tv_primal(x, pa, nj, sphi, ph, pv, lam, op->lip, F, s.H, s.W, st);
+            launch_whole_fwd(qs, ng, x, F, s.H, s.W, M, sphi, y, pf, r, tv, st);
+            launch_whole_adj(qts, ng, r, F, s.H, s.W, M, s.Mp, sphi, nullptr, tv, st);
         }
     }
-    if (obj) {
-        ProfScope ps(c, "final64", st);
-        launch_whole_objective(op->q, x, F, s.H, s.W, M, op->s_phi, in.codes, in.exps, lam, rr,
-                               yy, obj, st);
+    for (int g = 0; g < ng; ++g) {
+        const WholeItem& w = its[g];
+        const float* xg = x + (size_t)g * F * n;
+        if (w.obj) {
+            ProfScope ps(c, "final64", st);
+            launch_whole_objective(w.op->q, xg, F, s.H, s.W, M, s_phi, w.in->codes, w.in->exps,
+                                   lam + (size_t)g * F, rr, yy, w.obj, st);
+        }
+        ProfScope ps(c, "synth", st);
+        launch_whole_place(xg, w.frames, F, n, w.frames + n, w.cs_float, st);
     }
-    ProfScope ps(c, "synth", st);
-    launch_whole_place(x, frames, F, n, frames + n, cs_float, st);
 }
 
 void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* in,
@@ -709,17 +746,32 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
         items[i].op = s.G > 1 ? get_operator(c, s, st) : nullptr;
         items[i].nblk = (s.G - 1) * s.nb;
     }
-    // whole-frame GOPs run alone on st (their scratch is the context's)
+    // whole-frame GOPs: grouped by shape (frame size, M, G, T, lambda_frac),
+    // each group's iterations batched on st (their scratch is the context's)
     bool any_block = false;
+    std::map<std::tuple<int, int, int, int, int, float>, std::vector<int>> groups;
     for (int i = 0; i < count; ++i) {
-        if (!(shapes[i].flags & CSV_FLAG_WHOLE_FRAME)) {
+        const Shape& s = shapes[i];
+        if (!(s.flags & CSV_FLAG_WHOLE_FRAME)) {
             any_block = true;
             continue;
         }
-        decode_whole(c, shapes[i], items[i].op, in[i], frames_out[i],
-                     cs_float_out ? cs_float_out[i] : nullptr, obj_out ? obj_out[i] : nullptr, st);
+        groups[std::make_tuple(s.W, s.H, s.M, s.G, s.T, s.lambda_frac)].push_back(i);
         items[i].whole = true;
         items[i].nblk = 0;   // nothing left for the block passes below
+    }
+    for (const auto& kv : groups) {
+        const std::vector<int>& idx = kv.second;
+        for (size_t a = 0; a < idx.size(); a += kWholeBatch) {
+            std::vector<WholeItem> its;
+            for (size_t b = a; b < idx.size() && b < a + kWholeBatch; ++b) {
+                const int i = idx[b];
+                its.push_back(WholeItem{items[i].op, &in[i], frames_out[i],
+                                        cs_float_out ? cs_float_out[i] : nullptr,
+                                        obj_out ? obj_out[i] : nullptr});
+            }
+            decode_whole(c, shapes[idx[a]], its, st);
+        }
     }
     if (!any_block) return;
     // GOP i's per-GOP kernels run on auxiliary stream i % kAux (one GOP

@@ -53,7 +53,8 @@ Shape resolve(const csv_params* p);
 // Per-stream operator state, resident in HBM while the context lives.
 struct Operator {
     int B = 0, n = 0, M = 0, Mp = 0;
-    bool whole = false;           // whole-frame operator: q and lip only
+    bool whole = false;           // whole-frame operator: q, qt and lip only
+    int8_t* qt = nullptr;         // whole frame: n x Mp, Q transposed
     uint64_t seed = 0;
     uint32_t sid = 0;
     double s_phi = 0;
@@ -199,17 +200,36 @@ void launch_whole_measure(const Shape& s, const uint8_t* frames, int n_frames, s
 void launch_whole_quantise(const long long* y, int M, int n_frames, int8_t* codes, uint8_t* exps,
                            int32_t* y32, hipStream_t st);
 // whole-frame recovery: products with the resident int8 Q, output, FP64 check
-// forward: r = s_Phi Q x - y^ via whole_fwd_parts(n) partials, each F M
-// floats; adjoint: ceil(M / whole_adj_rows(M)) partials of Q^T r, each F n
-// floats, added (in order, times s_Phi) by launch_tv_primal
+// A batch of up to kWholeBatch GOPs of one shape, each with its own Q
+// (passed by value as a kernel argument); x, y, r are [GOP][F][.] arrays.
+constexpr int kWholeBatch = 16;
+struct WholeQ {
+    const int8_t* q[kWholeBatch];
+};
+struct WholeLip {
+    const double* lip[kWholeBatch];
+};
+// TV state of a batch ([GOP][F][n] arrays, lam [GOP][F], lip [GOP]); all
+// null for a plain product
+struct WholeTv {
+    float* x;
+    float *nuh, *nuv, *wh, *wv, *ph, *pv;
+    const float* lam;
+    const double* lip;
+};
 int whole_fwd_parts(int n);
-int whole_adj_rows(int M);
-void launch_whole_fwd(const int8_t* q, const float* x, int F, int n, int M, float s_phi,
-                      const float* y, float* part, float* r, hipStream_t st);
-void launch_whole_adj(const int8_t* q, const float* r, int F, int n, int M, float* part,
+// forward: r = s_Phi Q x - y^ through whole_fwd_parts(n) partials (part:
+// that many x GOPs x F x M floats), with the TV dual step when tv.nuh is set
+void launch_whole_fwd(const WholeQ& qs, int ngop, const float* x, int F, int H, int W, int M,
+                      float s_phi, const float* y, float* part, float* r, const WholeTv& tv,
                       hipStream_t st);
-void launch_sum_parts(const float* part, int nparts, size_t count, float scale, float* out,
-                      hipStream_t st);
+// adjoint from Q^T (n x Mp): gout = s_Phi Q^T r, or with tv.nuh set the TV
+// primal step x <- x - alpha (s_Phi Q^T r + D^T P)
+void launch_whole_adj(const WholeQ& qts, int ngop, const float* r, int F, int H, int W, int M,
+                      int Mp, float s_phi, float* gout, const WholeTv& tv, hipStream_t st);
+void launch_transpose_q(const int8_t* q, int Mp, int n, int8_t* qt, hipStream_t st);
+// out[g] = lip_g[0] (the step constants of a batch, one per GOP)
+void launch_gather_lip(const WholeLip& ls, int ngop, double* out, hipStream_t st);
 void launch_whole_place(const float* x, const uint8_t* key, int F, int n, uint8_t* out,
                         float* out_f32, hipStream_t st);
 void launch_whole_objective(const int8_t* q, const float* x, int F, int H, int W, int M,
@@ -220,9 +240,8 @@ void launch_whole_objective(const int8_t* q, const float* x, int F, int H, int W
 // total-variation recovery (k_tv.hip)
 void launch_tv_dual(const float* x, float* nuh, float* nuv, float* wh, float* wv, float* ph,
                     float* pv, const float* lam, int nblk, int BH, int BW, hipStream_t st);
-void launch_tv_primal(float* x, const float* g, int gparts, float gscale, const float* ph,
-                      const float* pv, const float* lam, const double* lip, int nblk, int BH,
-                      int BW, hipStream_t st);
+void launch_tv_primal(float* x, const float* g, const float* ph, const float* pv,
+                      const float* lam, const double* lip, int nblk, int BH, int BW, hipStream_t st);
 void launch_tv_final64(const int8_t* q, const float* x, const int8_t* codes, const uint8_t* exps,
                        const float* lam, int nblk, int M, int B, double s_phi, double* obj,
                        hipStream_t st);

@@ -15,12 +15,9 @@
 #include <cmath>
 
 #include "internal.h"
+#include "tv_step.h"
 
 namespace csv {
-
-constexpr float kTvBetaRatio = 0.03f;
-
-__device__ inline float tv_beta(float lam) { return lam > 0.f ? kTvBetaRatio * lam : 1.f; }
 
 // One thread per pixel.  nu, w: (nblk x n) pairs (horizontal, vertical);
 // on entry w holds the previous iteration's w (zero before the first).
@@ -35,33 +32,12 @@ __global__ __launch_bounds__(256) void tv_dual_kernel(const float* __restrict__ 
     if (idx >= (size_t)nblk * n) return;
     const int b = (int)(idx / n), k = (int)(idx - (size_t)b * n);
     const int i = k / BW, j = k - i * BW;
-    const float* xb = x + (size_t)b * n;
-    const float xv = xb[k];
-    const float dh = j + 1 < BW ? xb[k + 1] - xv : 0.f;
-    const float dv = i + 1 < BH ? xb[k + BW] - xv : 0.f;
-    const float l = lam[b], beta = tv_beta(l);
-    // multiplier update of the previous iteration, with the current x
-    const float nh = nuh[idx] + beta * (dh - wh[idx]);
-    const float nv = nuv[idx] + beta * (dv - wv[idx]);
-    const float vh = dh + nh / beta, vv = dv + nv / beta;
-    const float mag = sqrtf(vh * vh + vv * vv);
-    const float sc = mag > 0.f ? fmaxf(mag - l / beta, 0.f) / mag : 0.f;
-    const float w1 = sc * vh, w2 = sc * vv;
-    nuh[idx] = nh;
-    nuv[idx] = nv;
-    wh[idx] = w1;
-    wv[idx] = w2;
-    ph[idx] = nh + beta * (dh - w1);
-    pv[idx] = nv + beta * (dv - w2);
+    tv_dual_at(x + (size_t)b * n, k, i, j, BH, BW, idx, lam[b], nuh, nuv, wh, wv, ph, pv);
 }
 
-// x <- x - alpha (g + D^T p), D^T p at (i, j) =
-//   - ph(i, j)[j < B-1] + ph(i, j-1)[j > 0] - pv(i, j)[i < B-1] + pv(i-1, j)[i > 0].
-// g = gscale (g_0 + ... + g_{gparts-1}) for gradients delivered as partial
-// sums (the whole-frame adjoint), each nblk x n; gparts = 1, gscale = 1 is g.
+// x <- x - alpha (g + D^T p), one thread per pixel.
 __global__ __launch_bounds__(256) void tv_primal_kernel(float* __restrict__ x,
-                                                        const float* __restrict__ g, int gparts,
-                                                        float gscale,
+                                                        const float* __restrict__ g,
                                                         const float* __restrict__ ph,
                                                         const float* __restrict__ pv,
                                                         const float* __restrict__ lam,
@@ -72,19 +48,9 @@ __global__ __launch_bounds__(256) void tv_primal_kernel(float* __restrict__ x,
     if (idx >= (size_t)nblk * n) return;
     const int b = (int)(idx / n), k = (int)(idx - (size_t)b * n);
     const int i = k / BW, j = k - i * BW;
-    const float* phb = ph + (size_t)b * n;
-    const float* pvb = pv + (size_t)b * n;
-    float dt = 0.f;
-    if (j + 1 < BW) dt -= phb[k];
-    if (j > 0) dt += phb[k - 1];
-    if (i + 1 < BH) dt -= pvb[k];
-    if (i > 0) dt += pvb[k - BW];
-    const float beta = tv_beta(lam[b]);
-    const float alpha = (float)(1.0 / (lip[0] + 8.0 * (double)beta));
-    const size_t stride = (size_t)nblk * n;
-    float gv = g[idx];
-    for (int k = 1; k < gparts; ++k) gv += g[k * stride + idx];
-    x[idx] -= alpha * (gscale * gv + dt);
+    const float dt = tv_dtp_at(ph + (size_t)b * n, pv + (size_t)b * n, k, i, j, BH, BW);
+    const float alpha = tv_alpha(lip[0], tv_beta(lam[b]));
+    x[idx] -= alpha * (g[idx] + dt);
 }
 
 // FP64 check per block (one workgroup): r = s_Phi Q x - y^ with y^ =
@@ -148,13 +114,12 @@ void launch_tv_dual(const float* x, float* nuh, float* nuv, float* wh, float* wv
     CSV_HIP(hipGetLastError());
 }
 
-void launch_tv_primal(float* x, const float* g, int gparts, float gscale, const float* ph,
-                      const float* pv, const float* lam, const double* lip, int nblk, int BH,
-                      int BW, hipStream_t st) {
+void launch_tv_primal(float* x, const float* g, const float* ph, const float* pv,
+                      const float* lam, const double* lip, int nblk, int BH, int BW, hipStream_t st) {
     const size_t t = (size_t)nblk * BH * BW;
     if (!t) return;
-    tv_primal_kernel<<<dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st>>>(
-        x, g, gparts, gscale, ph, pv, lam, lip, nblk, BH, BW);
+    tv_primal_kernel<<<dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st>>>(x, g, ph, pv, lam,
+                                                                             lip, nblk, BH, BW);
     CSV_HIP(hipGetLastError());
 }
 

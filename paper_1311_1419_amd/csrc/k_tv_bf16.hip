@@ -35,10 +35,9 @@
 #include <algorithm>
 
 #include "fused_common.h"
+#include "tv_step.h"
 
 namespace csv {
-
-constexpr float kTvBetaRatioBf16 = 0.03f;
 
 // Values of the partner lane (l ^ 32) at registers 0, 4, 8, 12 (c = 0) or
 // 3, 7, 11, 15 (c = 3).
@@ -141,9 +140,9 @@ void tv_bf16_kernel(const FusedTile* __restrict__ tiles, const int* __restrict__
         const gu16x8* fadj = as_global<const gu16x8>(tl.frag_adj);
         const gfloat* yg = as_global<const gfloat>(tl.y);
         const float lam = col < tl.nblk ? tl.lam[col] : 0.f;
-        const float beta = lam > 0.f ? kTvBetaRatioBf16 * lam : 1.f;
+        const float beta = tv_beta(lam);
         const float inv_beta = 1.f / beta, thr = lam / beta;
-        const float alpha = (float)(1.0 / (tl.lip[0] + 8.0 * (double)beta));
+        const float alpha = tv_alpha(tl.lip[0], beta);
         const int T = tl.T;
 
         floatx16 x = {}, mh = {}, mv = {};

@@ -8,6 +8,7 @@
 // per four entries of Q, each entry multiplied into every CS frame.
 #include "internal.h"
 #include "philox.h"
+#include "tv_step.h"
 
 namespace csv {
 
@@ -130,138 +131,265 @@ void launch_whole_quantise(const long long* y, int M, int n_frames, int8_t* code
 // Whole-frame recovery (eq. (1) with the TV solver of k_tv.hip, each CS frame
 // one W x H image): Phi = s_Phi Q with Q (M x n int8) resident; F frames.
 
-// Both products split the long sum into fixed chunks, write one partial per
-// chunk and add the partials in chunk order in the consumer: the result
-// depends only on the shapes, never on scheduling.
-constexpr int kFwdRows = 64;    // rows of Q per forward workgroup
+// Both products stage a 512-column chunk of the dense operand (x or r) in
+// LDS, column c at lds_col(c) in rows of 640 floats: the eight 16-float
+// pieces that one load instruction of a wave reads (lanes 16 part + 128 u
+// for part 0..7) then start in eight different groups of four banks, free of
+// conflicts.  Each thread takes R rows of Q (R pixel rows of Q^T), so every
+// value read from LDS feeds R multiply-adds; FM bounds the frames of a GOP
+// (F <= FM), fixing the accumulator count.
 constexpr int kFwdCols = 512;   // pixels per forward workgroup (one sum chunk)
-constexpr int kAdjCols = 1024;  // pixels per adjoint workgroup (4 per thread)
+constexpr int kAdjRows = 512;   // rows of Q^T staged per adjoint step
+constexpr int kLdsRow = 640;    // floats per staged row (512 columns, swizzled)
+static_assert(kAdjRows == 512, "one staged row of r per thread of the adjoint workgroup");
 
-// Forward partials: P[k][f][m] = sum over the pixels p of chunk k of
-// Q[m][p] x[f][p].  Grid (ceil(M / 64), ceil(n / 512)); the chunk of every
-// frame is staged in LDS (F x 512 floats; the last chunk may be shorter, a
-// multiple of 64 since n is); thread (row tid / 4, part tid % 4) takes 16
-// pixels at 64 c + 16 part and the four parts meet by lane shuffles.
-__global__ __launch_bounds__(256) void whole_fwd_kernel(const int8_t* __restrict__ q,
-                                                        const float* __restrict__ x, int F, int n,
-                                                        int M, float* __restrict__ part_out) {
-    extern __shared__ float xs[];   // F x kFwdCols
-    const int tid = threadIdx.x, col0 = blockIdx.y * kFwdCols;
-    const int ncols = min(kFwdCols, n - col0);
-    for (int e = tid; e < F * (kFwdCols / 4); e += 256) {
-        const int f = e / (kFwdCols / 4), c4 = (e - f * (kFwdCols / 4)) * 4;
-        if (c4 < ncols)
-            *reinterpret_cast<float4*>(xs + f * kFwdCols + c4) =
-                *reinterpret_cast<const float4*>(x + (size_t)f * n + col0 + c4);
-    }
-    __syncthreads();
-    const int m = blockIdx.x * kFwdRows + (tid >> 2), part = tid & 3;
-    float acc[kWMaxF];
+__device__ inline int lds_col(int c) { return (c >> 7) * 160 + (c & 127) + 4 * ((c >> 4) & 7); }
+
+// Unpack 16 signed bytes to floats (exact).
+__device__ inline void unpack16(const int4& qq, float* qv) {
 #pragma unroll
-    for (int f = 0; f < kWMaxF; ++f) acc[f] = 0.f;
-    if (m < M) {
-        const int8_t* qr = q + (size_t)m * n + col0;
-#pragma unroll 2
-        for (int c = 16 * part; c < ncols; c += 64) {
-            const int4 qq = *reinterpret_cast<const int4*>(qr + c);
-            float qv[16];
+    for (int e = 0; e < 4; ++e) {
+        const int wd = e == 0 ? qq.x : e == 1 ? qq.y : e == 2 ? qq.z : qq.w;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) qv[4 * e + b] = (float)(int8_t)((wd >> (8 * b)) & 0xff);
+    }
+}
+
+// acc[rho][f] += sum of the 16 products of piece (qv[rho], staged row f at
+// physical column base) over rho < R, f < F.
+template <int FM, int R>
+__device__ inline void piece_fma(const float (&qv)[R][16], const float* __restrict__ st, int base,
+                                 int F, float (&acc)[R][FM]) {
+#pragma unroll
+    for (int f = 0; f < FM; ++f) {
+        if (f < F) {
+            const float4* sf = reinterpret_cast<const float4*>(st + f * kLdsRow + base);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int wd = e == 0 ? qq.x : e == 1 ? qq.y : e == 2 ? qq.z : qq.w;
+                const float4 v = sf[e];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) qv[4 * e + b] = (float)(int8_t)((wd >> (8 * b)) & 0xff);
-            }
-#pragma unroll
-            for (int f = 0; f < kWMaxF; ++f) {
-                if (f < F) {
-                    const float4* xf = reinterpret_cast<const float4*>(xs + f * kFwdCols + c);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const float4 xv = xf[e];
-                        acc[f] = fmaf(qv[4 * e], xv.x, acc[f]);
-                        acc[f] = fmaf(qv[4 * e + 1], xv.y, acc[f]);
-                        acc[f] = fmaf(qv[4 * e + 2], xv.z, acc[f]);
-                        acc[f] = fmaf(qv[4 * e + 3], xv.w, acc[f]);
-                    }
+                for (int rho = 0; rho < R; ++rho) {
+                    acc[rho][f] = fmaf(qv[rho][4 * e], v.x, acc[rho][f]);
+                    acc[rho][f] = fmaf(qv[rho][4 * e + 1], v.y, acc[rho][f]);
+                    acc[rho][f] = fmaf(qv[rho][4 * e + 2], v.z, acc[rho][f]);
+                    acc[rho][f] = fmaf(qv[rho][4 * e + 3], v.w, acc[rho][f]);
                 }
             }
         }
     }
-    float* out = part_out + (size_t)blockIdx.y * F * M;
+}
+
+// Forward product with the dual step.  Partials P[k][g][f][m] = sum over
+// the pixels p of chunk k (512 pixels) of Q_g[m][p] x[g][f][p] for the GOPs g
+// of a batch (one Q each, same shape), added in chunk order by
+// whole_fwd_reduce_kernel: the sums depend only on the shapes.  Grid
+// (ceil(M / 64 R), ceil(n / 512), GOPs), 512 threads: eight lanes share a
+// row of Q (rows m0 + 64 rho), each reading 16 bytes at 128 u + 16 part (a
+// wave reads whole 128-byte lines); all of a thread's pieces are requested
+// before the chunk of x is staged.  The last chunk may be shorter (a
+// multiple of 64, as n is).  With tv set, the workgroups of a chunk also
+// take the dual step of its pixels (each row tile a slice): it reads x only
+// and writes nu, w, P, which the adjoint launch reads.
+template <int FM, int R>
+__global__ __launch_bounds__(512) void whole_fwd_kernel(WholeQ qs, const float* __restrict__ xall,
+                                                        int F, int H, int W, int M,
+                                                        float* __restrict__ part_out, WholeTv tv) {
+    extern __shared__ float xs[];   // F x kLdsRow
+    const int n = H * W;
+    const int tid = threadIdx.x, col0 = blockIdx.y * kFwdCols, g = blockIdx.z;
+    const int ncols = min(kFwdCols, n - col0);
+    const int8_t* __restrict__ q = qs.q[g];
+    const float* __restrict__ x = xall + (size_t)g * F * n;
+    const int part = tid & 7, mb = blockIdx.x * (64 * R) + (tid >> 3);
+    int4 qq[R][kFwdCols / 128];
 #pragma unroll
-    for (int f = 0; f < kWMaxF; ++f) {
-        float v = acc[f];
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
-        if (f < F && part == 0 && m < M) out[(size_t)f * M + m] = v;
+    for (int rho = 0; rho < R; ++rho) {
+        const int m = mb + 64 * rho;
+#pragma unroll
+        for (int u = 0; u < kFwdCols / 128; ++u) {
+            const int c = 16 * part + 128 * u;
+            qq[rho][u] = m < M && c < ncols
+                             ? *reinterpret_cast<const int4*>(q + (size_t)m * n + col0 + c)
+                             : make_int4(0, 0, 0, 0);
+        }
+    }
+    {
+        // F x 128 float4 over 512 threads (frames 4 s .. 4 s + 3 in step s),
+        // loaded from clamped in-range addresses so that all are in flight
+        const int c4 = (tid % (kFwdCols / 4)) * 4, fr = tid / (kFwdCols / 4);
+        const int cc = c4 < ncols ? c4 : 0;
+        float4 xv[(FM + 3) / 4];
+#pragma unroll
+        for (int s4 = 0; s4 < (FM + 3) / 4; ++s4) {
+            const int f = min(4 * s4 + fr, F - 1);
+            xv[s4] = 4 * s4 < F ? *reinterpret_cast<const float4*>(x + (size_t)f * n + col0 + cc)
+                                : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < (FM + 3) / 4; ++s4)
+            if (4 * s4 + fr < F && c4 < ncols)
+                *reinterpret_cast<float4*>(xs + (4 * s4 + fr) * kLdsRow + lds_col(c4)) = xv[s4];
+    }
+    __syncthreads();
+    float acc[R][FM];
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho)
+#pragma unroll
+        for (int f = 0; f < FM; ++f) acc[rho][f] = 0.f;
+#pragma unroll
+    for (int u = 0; u < kFwdCols / 128; ++u) {
+        const int c = 16 * part + 128 * u;
+        if (c >= ncols) break;
+        float qv[R][16];
+#pragma unroll
+        for (int rho = 0; rho < R; ++rho) unpack16(qq[rho][u], qv[rho]);
+        piece_fma<FM, R>(qv, xs, lds_col(c), F, acc);
+    }
+    float* out = part_out + ((size_t)blockIdx.y * gridDim.z + g) * F * M;
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho) {
+        const int m = mb + 64 * rho;
+#pragma unroll
+        for (int f = 0; f < FM; ++f) {
+            float v = acc[rho][f];
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            // every lane of the row holds the sum: lane f % 8 stores frame f
+            if (f < F && (f & 7) == part && m < M) out[(size_t)f * M + m] = v;
+        }
+    }
+    if (tv.nuh) {
+        const int tiles = gridDim.x, t = blockIdx.x;
+        const int lo = ncols * t / tiles, hi = ncols * (t + 1) / tiles, cnt = hi - lo;
+        for (int e = tid; e < F * cnt; e += 512) {
+            const int f = e / cnt, k = col0 + lo + (e - f * cnt);
+            const int i = k / W, j = k - i * W;
+            const int b = g * F + f;
+            tv_dual_at(xall + (size_t)b * n, k, i, j, H, W, (size_t)b * n + k, tv.lam[b], tv.nuh,
+                       tv.nuv, tv.wh, tv.wv, tv.ph, tv.pv);
+        }
     }
 }
 
-// r[f][m] = s_Phi sum_k P[k][f][m] - y^[f][m] (chunks in order).
-__global__ void whole_fwd_reduce_kernel(const float* __restrict__ part, int nk, int F, int M,
-                                        float s_phi, const float* __restrict__ y,
-                                        float* __restrict__ r) {
+// r[i] = s_Phi sum_k P[k][i] - y^[i] over i = (g, f, m) (chunks in order).
+__global__ __launch_bounds__(256) void whole_fwd_reduce_kernel(const float* __restrict__ part,
+                                                               int nk, int count, float s_phi,
+                                                               const float* __restrict__ y,
+                                                               float* __restrict__ r) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= F * M) return;
+    if (idx >= count) return;
     float v = 0.f;
-    for (int k = 0; k < nk; ++k) v += part[(size_t)k * F * M + idx];
+#pragma unroll 8
+    for (int k = 0; k < nk; ++k) v += part[(size_t)k * count + idx];
     r[idx] = fmaf(s_phi, v, -y[idx]);
 }
 
-// Adjoint partials: G[j][f][p] = sum over the rows m of chunk j (mc rows) of
-// Q[m][p] r[f][m].  Grid (ceil(n / 1024), ceil(M / mc)); r of the chunk is
-// staged in LDS; each thread takes four consecutive pixels (one 32-bit load
-// of Q per row, a wave reading 256 contiguous bytes).
-__global__ __launch_bounds__(256) void whole_adj_kernel(const int8_t* __restrict__ q,
-                                                        const float* __restrict__ r, int F, int n,
-                                                        int M, int mc, float* __restrict__ part_out) {
-    extern __shared__ float rs[];   // F x mc
-    const int tid = threadIdx.x, m0 = blockIdx.y * mc;
-    const int mend = min(M, m0 + mc);
-    for (int e = tid; e < F * mc; e += 256) {
-        const int f = e / mc, mm = e - f * mc;
-        rs[e] = m0 + mm < M ? r[(size_t)f * M + m0 + mm] : 0.f;
+// Adjoint product with the primal step.  g[g][f][p] = s_Phi sum_m Q_g[m][p]
+// r[g][f][m], read from the transposed copy Q^T (n x Mp, rows zero-padded):
+// grid (ceil(n / 64 R), GOPs), 512 threads, eight lanes per pixel row
+// (rows p0 + 64 rho) reading 16 bytes each at 128 u + 16 part, r staged in
+// LDS 512 rows at a time after the thread's pieces of Q^T are requested,
+// the eight lanes meeting by lane shuffles (fixed order).  With tv set the
+// gradient never leaves the registers: x <- x - alpha (g + D^T P) at once
+// (P from the dual step of the forward launch); else g is written to gout.
+template <int FM, int R>
+__global__ __launch_bounds__(512) void whole_adj_kernel(WholeQ qts, const float* __restrict__ rall,
+                                                        int F, int H, int W, int M, int Mp,
+                                                        float s_phi, float* __restrict__ gout,
+                                                        WholeTv tv) {
+    extern __shared__ float rs[];   // F x kLdsRow
+    const int n = H * W;
+    const int tid = threadIdx.x, g = blockIdx.y, part = tid & 7;
+    const int pb = blockIdx.x * (64 * R) + (tid >> 3);
+    const int8_t* __restrict__ qt = qts.q[g];
+    const float* __restrict__ r = rall + (size_t)g * F * M;
+    float acc[R][FM];
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho)
+#pragma unroll
+        for (int f = 0; f < FM; ++f) acc[rho][f] = 0.f;
+    for (int m0 = 0; m0 < Mp; m0 += kAdjRows) {
+        const int mch = min(kAdjRows, Mp - m0);   // a multiple of 32
+        int4 qq[R][kAdjRows / 128];
+#pragma unroll
+        for (int rho = 0; rho < R; ++rho) {
+            const int p = pb + 64 * rho;
+#pragma unroll
+            for (int u = 0; u < kAdjRows / 128; ++u) {
+                const int c = 16 * part + 128 * u;
+                qq[rho][u] = p < n && c < mch
+                                 ? *reinterpret_cast<const int4*>(qt + (size_t)p * Mp + m0 + c)
+                                 : make_int4(0, 0, 0, 0);
+            }
+        }
+        if (m0) __syncthreads();
+        {
+            float rv[FM];   // thread tid stages row m0 + tid of every frame
+            const int mm = tid;
+            const int mr = m0 + mm < M ? m0 + mm : M - 1;
+#pragma unroll
+            for (int f = 0; f < FM; ++f) rv[f] = f < F ? r[(size_t)f * M + mr] : 0.f;
+#pragma unroll
+            for (int f = 0; f < FM; ++f)
+                if (f < F && mm < mch) rs[f * kLdsRow + lds_col(mm)] = m0 + mm < M ? rv[f] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kAdjRows / 128; ++u) {
+            const int c = 16 * part + 128 * u;
+            if (c >= mch) break;
+            float qv[R][16];
+#pragma unroll
+            for (int rho = 0; rho < R; ++rho) unpack16(qq[rho][u], qv[rho]);
+            piece_fma<FM, R>(qv, rs, lds_col(c), F, acc);
+        }
     }
-    __syncthreads();
-    const int p = blockIdx.x * kAdjCols + tid * 4;
-    if (p >= n) return;   // n % 64 == 0: the four pixels are all in range
-    float acc[kWMaxF][4];
 #pragma unroll
-    for (int f = 0; f < kWMaxF; ++f)
+    for (int rho = 0; rho < R; ++rho) {
+        const int p = pb + 64 * rho;
+        const int i = p / W, j = p - i * W;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[f][b] = 0.f;
-    const int8_t* qc = q + p;
-    for (int m = m0; m < mend; ++m) {
-        const int wd = *reinterpret_cast<const int*>(qc + (size_t)m * n);
-        float qv[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) qv[b] = (float)(int8_t)((wd >> (8 * b)) & 0xff);
-        const float* rm = rs + (m - m0);
-#pragma unroll
-        for (int f = 0; f < kWMaxF; ++f) {
-            if (f < F) {
-                const float rv = rm[f * mc];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[f][b] = fmaf(qv[b], rv, acc[f][b]);
+        for (int f = 0; f < FM; ++f) {
+            float v = acc[rho][f];
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            if (f < F && (f & 7) == part && p < n) {   // lane f % 8 keeps frame f
+                const int b = g * F + f;
+                const float gv = s_phi * v;
+                if (!tv.nuh) {
+                    gout[(size_t)b * n + p] = gv;
+                } else {
+                    const float dt = tv_dtp_at(tv.ph + (size_t)b * n, tv.pv + (size_t)b * n, p, i,
+                                               j, H, W);
+                    const float alpha = tv_alpha(tv.lip[g], tv_beta(tv.lam[b]));
+                    tv.x[(size_t)b * n + p] -= alpha * (gv + dt);
+                }
             }
         }
     }
-    float* out = part_out + (size_t)blockIdx.y * F * n;
-#pragma unroll
-    for (int f = 0; f < kWMaxF; ++f)
-        if (f < F)
-            *reinterpret_cast<float4*>(out + (size_t)f * n + p) =
-                make_float4(acc[f][0], acc[f][1], acc[f][2], acc[f][3]);
 }
 
-// out[i] = scale (part[0][i] + ... + part[nparts-1][i]) (parts in order).
-__global__ void sum_parts_kernel(const float* __restrict__ part, int nparts, size_t count,
-                                 float scale, float* __restrict__ out) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    float v = part[i];
-    for (int k = 1; k < nparts; ++k) v += part[k * count + i];
-    out[i] = scale * v;
+// Q^T (n x Mp) from Q (Mp x n): 32 x 64 tiles through LDS.
+__global__ __launch_bounds__(256) void transpose_q_kernel(const int8_t* __restrict__ q, int Mp,
+                                                          int n, int8_t* __restrict__ qt) {
+    __shared__ int8_t t[32][65];
+    const int m0 = blockIdx.y * 32, p0 = blockIdx.x * 64, tid = threadIdx.x;
+    for (int e = tid; e < 32 * 64; e += 256) {
+        const int r = e / 64, c = e % 64;
+        t[r][c] = q[(size_t)(m0 + r) * n + p0 + c];
+    }
+    __syncthreads();
+    for (int e = tid; e < 32 * 64; e += 256) {
+        const int c = e / 32, r = e % 32;
+        qt[(size_t)(p0 + c) * Mp + m0 + r] = t[r][c];
+    }
+}
+
+__global__ void gather_lip_kernel(WholeLip ls, int ngop, double* __restrict__ out) {
+    const int g = threadIdx.x;
+    if (g < ngop) out[g] = ls.lip[g][0];
 }
 
 // Decoded CS frames: out[f][p] = clip(round-half-even(key[p] + x[f][p])).
@@ -345,36 +473,66 @@ __global__ __launch_bounds__(256) void whole_obj_final_kernel(const double* __re
 
 int whole_fwd_parts(int n) { return ceil_div(n, kFwdCols); }
 
-int whole_adj_rows(int M) { return M <= 2048 ? 64 : 256; }
-
-void launch_whole_fwd(const int8_t* q, const float* x, int F, int n, int M, float s_phi,
-                      const float* y, float* part, float* r, hipStream_t st) {
-    if (F <= 0) return;
-    CSV_REQUIRE(F <= kWMaxF && n % 64 == 0, CSV_EUNSUPPORTED, "whole-frame product shape");
+void launch_whole_fwd(const WholeQ& qs, int ngop, const float* x, int F, int H, int W, int M,
+                      float s_phi, const float* y, float* part, float* r, const WholeTv& tv,
+                      hipStream_t st) {
+    const int n = H * W;
+    if (F <= 0 || ngop <= 0) return;
+    CSV_REQUIRE(F <= kWMaxF && n % 64 == 0 && ngop <= kWholeBatch, CSV_EUNSUPPORTED,
+                "whole-frame product shape");
     const int nk = whole_fwd_parts(n);
-    whole_fwd_kernel<<<dim3(ceil_div(M, kFwdRows), nk), dim3(256),
-                       (size_t)F * kFwdCols * sizeof(float), st>>>(q, x, F, n, M, part);
+    const size_t lds = (size_t)F * kLdsRow * sizeof(float);
+    auto go = [&](auto kern, int R) {
+        kern<<<dim3(ceil_div(M, 64 * R), nk, ngop), dim3(512), lds, st>>>(qs, x, F, H, W, M, part,
+                                                                         tv);
+    };
+    if (F <= 4)
+        go(whole_fwd_kernel<4, 2>, 2);
+    else if (F <= 8)
+        go(whole_fwd_kernel<8, 2>, 2);
+    else if (F <= 16)
+        go(whole_fwd_kernel<16, 1>, 1);
+    else
+        go(whole_fwd_kernel<32, 1>, 1);
     CSV_HIP(hipGetLastError());
-    whole_fwd_reduce_kernel<<<dim3(ceil_div(F * M, 256)), dim3(256), 0, st>>>(part, nk, F, M,
+    const int count = ngop * F * M;
+    whole_fwd_reduce_kernel<<<dim3(ceil_div(count, 256)), dim3(256), 0, st>>>(part, nk, count,
                                                                              s_phi, y, r);
     CSV_HIP(hipGetLastError());
 }
 
-void launch_whole_adj(const int8_t* q, const float* r, int F, int n, int M, float* part,
-                      hipStream_t st) {
-    if (F <= 0) return;
-    CSV_REQUIRE(F <= kWMaxF && n % 64 == 0, CSV_EUNSUPPORTED, "whole-frame product shape");
-    const int mc = whole_adj_rows(M);
-    whole_adj_kernel<<<dim3(ceil_div(n, kAdjCols), ceil_div(M, mc)), dim3(256),
-                       (size_t)F * mc * sizeof(float), st>>>(q, r, F, n, M, mc, part);
+void launch_whole_adj(const WholeQ& qts, int ngop, const float* r, int F, int H, int W, int M,
+                      int Mp, float s_phi, float* gout, const WholeTv& tv, hipStream_t st) {
+    const int n = H * W;
+    if (F <= 0 || ngop <= 0) return;
+    CSV_REQUIRE(F <= kWMaxF && n % 64 == 0 && Mp % 32 == 0 && Mp >= M && ngop <= kWholeBatch,
+                CSV_EUNSUPPORTED, "whole-frame product shape");
+    const size_t lds = (size_t)F * kLdsRow * sizeof(float);
+    auto go = [&](auto kern, int R) {
+        kern<<<dim3(ceil_div(n, 64 * R), ngop), dim3(512), lds, st>>>(qts, r, F, H, W, M, Mp,
+                                                                     s_phi, gout, tv);
+    };
+    if (F <= 4)
+        go(whole_adj_kernel<4, 2>, 2);
+    else if (F <= 8)
+        go(whole_adj_kernel<8, 2>, 2);
+    else if (F <= 16)
+        go(whole_adj_kernel<16, 1>, 1);
+    else
+        go(whole_adj_kernel<32, 1>, 1);
     CSV_HIP(hipGetLastError());
 }
 
-void launch_sum_parts(const float* part, int nparts, size_t count, float scale, float* out,
-                      hipStream_t st) {
-    if (!count) return;
-    sum_parts_kernel<<<dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st>>>(part, nparts,
-                                                                                count, scale, out);
+void launch_transpose_q(const int8_t* q, int Mp, int n, int8_t* qt, hipStream_t st) {
+    CSV_REQUIRE(Mp % 32 == 0 && n % 64 == 0, CSV_EUNSUPPORTED, "transpose shape");
+    transpose_q_kernel<<<dim3(n / 64, Mp / 32), dim3(256), 0, st>>>(q, Mp, n, qt);
+    CSV_HIP(hipGetLastError());
+}
+
+void launch_gather_lip(const WholeLip& ls, int ngop, double* out, hipStream_t st) {
+    if (ngop <= 0) return;
+    CSV_REQUIRE(ngop <= kWholeBatch, CSV_EINVAL, "whole-frame batch too large");
+    gather_lip_kernel<<<dim3(1), dim3(64), 0, st>>>(ls, ngop, out);
     CSV_HIP(hipGetLastError());
 }
 
