@@ -521,19 +521,20 @@ def whole_main(args):
         wall = (time.perf_counter() - t0) / dsteps
         ctx.profile(False)
         k_ms, k_n = ctx.profile_query("tv_whole")
-        it_s = k_ms / max(k_n, 1) / 1e3 / 300               # one iteration of one GOP
+        it_s = k_ms / max(k_n, 1) / 1e3 / 300               # one iteration, all 8 GOPs
         ps = [psnr(s.video()[t], o[0][t].cpu().numpy()) for s, o in zip(specs, outs)
               for t in range(1, 5)]
-        # algorithmic HBM bytes per iteration: Q read by both products
-        # (2 M n int8) and the FP32 state of the 4 CS frames (dual step: x,
-        # nu, w in, nu, w, P out = 11 words; primal step: x, g, P in, x out
-        # = 5 words per pixel)
-        byt = 2.0 * 506 * n + 4 * n * 4 * 16
+        # algorithmic HBM bytes per iteration and GOP: Q read by both
+        # products (2 M n int8) and 16 FP32 words of state per pixel and CS
+        # frame (dual step: x, nu, w in, nu, w, P out = 11; forward: x = 1;
+        # primal step: x, P in, x out = 4)
+        byt = len(specs) * (2.0 * 506 * n + 4 * n * 4 * 16)
         res["decode_tv_cr50_m506"] = {
             "cs_mpix_per_s": round(len(specs) * 4 * n / wall / 1e6, 3),
             "ms_per_step": round(1e3 * wall, 3), "iters": 300,
-            "ms_per_gop_iteration": round(1e3 * it_s, 5),
-            "gbps_algorithmic": round(byt / it_s / 1e9, 1),
+            "us_per_iteration_8gops": round(1e6 * it_s, 2),
+            "algorithmic_tbs": round(byt / it_s / 1e12, 3),
+            "hbm_frac": round(byt / it_s / 8e12, 4),
             "mean_psnr_db": round(float(np.mean(ps)), 3)}
     print(json.dumps({
         "metric": "whole-frame CS Mpixel/s encoded (Q regenerated on the fly), 8 cameras 176x144 "

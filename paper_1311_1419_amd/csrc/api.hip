@@ -206,7 +206,7 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
         try {
             launch_phi_q(op->q, s.M, s.Mp, s.n, s.seed, (uint64_t)s.sid, st);
             launch_transpose_q(op->q, s.Mp, s.n, op->qt, st);
-            double* gram = static_cast<double*>(scratch(c, "gram", (size_t)s.M * s.M * 8));
+            int* gram = static_cast<int*>(scratch(c, "gram", (size_t)s.M * s.M * 4));
             launch_power_iteration(op.get(), gram, st);
         } catch (...) {
             free_operator(c, op.get());
@@ -248,7 +248,7 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
         launch_q_e4m3(op->q, op->q8, s.Mp * s.n, st);
         launch_operator_setup(op.get(), st);
         launch_bf16_frag_layout(op.get(), st);
-        double* gram = static_cast<double*>(scratch(c, "gram", (size_t)s.M * s.M * 8));
+        int* gram = static_cast<int*>(scratch(c, "gram", (size_t)s.M * s.M * 4));
         launch_power_iteration(op.get(), gram, st);
     } catch (...) {
         free_operator(c, op.get());
@@ -659,7 +659,7 @@ static void decode_whole(Ctx* c, const Shape& s, const std::vector<WholeItem>& i
     float* r = static_cast<float*>(scratch(c, "w_r", fm * 4));
     float* pf = static_cast<float*>(scratch(c, "w_pf", (size_t)nk * fm * 4));
     float* lam = static_cast<float*>(scratch(c, "w_lam", (size_t)nimg * 4));
-    double* lipv = static_cast<double*>(scratch(c, "w_lip", (size_t)ng * 8));
+    float* alpha = static_cast<float*>(scratch(c, "w_alpha", (size_t)nimg * 4));
     float* x = static_cast<float*>(scratch(c, "w_x", nn * 4));
     WholeTv tv{x,
                static_cast<float*>(scratch(c, "tv_nuh", nn * 4)),
@@ -669,7 +669,7 @@ static void decode_whole(Ctx* c, const Shape& s, const std::vector<WholeItem>& i
                static_cast<float*>(scratch(c, "tv_ph", nn * 4)),
                static_cast<float*>(scratch(c, "tv_pv", nn * 4)),
                lam,
-               lipv};
+               alpha};
     bool any_obj = false;
     for (const WholeItem& w : its) any_obj = any_obj || w.obj;
     double* rr = any_obj ? static_cast<double*>(scratch(c, "w_rr", (size_t)F * M * 8)) : nullptr;
@@ -689,10 +689,10 @@ static void decode_whole(Ctx* c, const Shape& s, const std::vector<WholeItem>& i
         for (int g = 0; g < ng; ++g)
             launch_dequant(its[g].in->codes, its[g].in->exps, F, M, M, s_phi,
                            y + (size_t)g * F * M, st);
-        launch_gather_lip(ls, ng, lipv, st);
-        // lam = frac ||Phi^T y^||_inf per frame
+        // lam = frac ||Phi^T y^||_inf per frame, then the step per frame
         launch_whole_adj(qts, ng, y, F, s.H, s.W, M, s.Mp, sphi, x, plain, st);
         launch_row_absmax(x, nimg, n, n, s.lambda_frac, lam, st);
+        launch_whole_alpha(ls, lam, F, ng, alpha, st);
     }
     {
         // per iteration: forward product with the dual step (x -> nu, w, P

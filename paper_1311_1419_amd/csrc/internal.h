@@ -173,7 +173,7 @@ void launch_fill_u64(unsigned long long* p, unsigned long long v, int count, hip
 
 // decode side (k_decode.hip)
 void launch_operator_setup(Operator* op, hipStream_t st);
-void launch_power_iteration(Operator* op, double* gram, hipStream_t st);
+void launch_power_iteration(Operator* op, int* gram, hipStream_t st);   // gram: M x M int32 scratch
 void launch_dequant(const int8_t* codes, const uint8_t* exps, int nblk, int M, int Mp,
                     double s_phi, float* y, hipStream_t st);
 void launch_gemm_nt(const float* X, const float* WT, float* C, int R, int N, int K,
@@ -215,7 +215,7 @@ struct WholeTv {
     float* x;
     float *nuh, *nuv, *wh, *wv, *ph, *pv;
     const float* lam;
-    const double* lip;
+    const float* alpha;   // per image: 1 / (L_g + 8 beta)
 };
 int whole_fwd_parts(int n);
 // forward: r = s_Phi Q x - y^ through whole_fwd_parts(n) partials (part:
@@ -228,8 +228,9 @@ void launch_whole_fwd(const WholeQ& qs, int ngop, const float* x, int F, int H, 
 void launch_whole_adj(const WholeQ& qts, int ngop, const float* r, int F, int H, int W, int M,
                       int Mp, float s_phi, float* gout, const WholeTv& tv, hipStream_t st);
 void launch_transpose_q(const int8_t* q, int Mp, int n, int8_t* qt, hipStream_t st);
-// out[g] = lip_g[0] (the step constants of a batch, one per GOP)
-void launch_gather_lip(const WholeLip& ls, int ngop, double* out, hipStream_t st);
+// alpha[b] = 1 / (L_g + 8 beta(lam[b])) for image b = g F + f of a batch
+void launch_whole_alpha(const WholeLip& ls, const float* lam, int F, int ngop, float* alpha,
+                        hipStream_t st);
 void launch_whole_place(const float* x, const uint8_t* key, int F, int n, uint8_t* out,
                         float* out_f32, hipStream_t st);
 void launch_whole_objective(const int8_t* q, const float* x, int F, int H, int W, int M,

@@ -60,9 +60,9 @@ __global__ __launch_bounds__(256) void operator_kernel(const int8_t* __restrict_
 }
 
 // Integer Gram matrix G = Q Q^T (M x M), exact in 32-bit integers
-// (|G_ij| <= 32*32*n), stored as FP64.
+// (|G_ij| <= 32*32*n < 2^31, checked by the launcher).
 __global__ __launch_bounds__(256) void gram_kernel(const int8_t* __restrict__ q, int M, int n,
-                                                  double* __restrict__ g) {
+                                                  int* __restrict__ g) {
     __shared__ int Qa[16][65];
     __shared__ int Qb[16][65];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -80,48 +80,75 @@ __global__ __launch_bounds__(256) void gram_kernel(const int8_t* __restrict__ q,
         for (int c = 0; c < 64; ++c) acc += Qa[ty][c] * Qb[tx][c];
         __syncthreads();
     }
-    if (i < M && j < M) g[(size_t)i * M + j] = (double)acc;
+    if (i < M && j < M) g[(size_t)i * M + j] = acc;
 }
 
+// Deterministic sum over the 1024 threads: wave shuffles, then the 16 wave
+// partials in order; every thread gets the total.
 __device__ inline double block_sum_1024(double v, double* red) {
-    // deterministic tree: wave shuffles, then the 16 wave partials in order
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
     __syncthreads();
     if (ln == 0) red[wv] = v;
     __syncthreads();
     double t = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    for (int w = 0; w < 16; ++w) t += red[w];
     return t;
 }
 
 // Power iteration on G (FP64): v0 = 1/sqrt(M); w = G v; Rayleigh quotient
 // rq = v.w; stop once |rq - rq_prev| <= tol rq (from the second step), else
-// v = w / ||w||.  One workgroup of 1024 threads; thread t owns rows t,
-// t + 1024, ... (M <= 16384), v lives in LDS.
-constexpr int kPowRows = 16;
-__global__ __launch_bounds__(1024) void power_kernel(const double* __restrict__ g, int M,
+// v = w / ||w||.  One workgroup of 16 waves, v in LDS (M <= 16384).  Wave
+// w takes rows i = w + 16 k, eight at a time; its lanes split each row
+// (j = lane + 64 s, coalesced int32 reads of G, FP64 products) and meet by
+// a fixed shuffle tree; row k's result stays in lane k % 64, register k / 64.
+constexpr int kPowSlots = 16;   // rows per lane per wave: M <= 16 x 64 x 16
+__global__ __launch_bounds__(1024) void power_kernel(const int* __restrict__ g, int M,
                                                     double s_phi, double tol, int max_iter,
                                                     double* __restrict__ lip) {
     extern __shared__ double v[];   // M
     __shared__ double red[16];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
     for (int i = tid; i < M; i += 1024) v[i] = 1.0 / sqrt((double)M);
     __syncthreads();
+    const int rows = (M - wv + 15) / 16;   // rows of this wave
     double rq = 0.0, rq_prev = 0.0;
     int it = 0;
     for (it = 1; it <= max_iter; ++it) {
-        double w[kPowRows];
+        double w[kPowSlots];
         double pv = 0.0, pw = 0.0;
 #pragma unroll
-        for (int k = 0; k < kPowRows; ++k) {
-            const int i = tid + 1024 * k;
-            w[k] = 0.0;
-            if (i < M) {
-                for (int j = 0; j < M; ++j) w[k] += g[(size_t)j * M + i] * v[j];   // G symmetric
-                pv += v[i] * w[k];
-                pw += w[k] * w[k];
+        for (int t = 0; t < kPowSlots; ++t) {
+            w[t] = 0.0;
+            // eight rows at a time: eight independent loads and FMA chains
+            for (int kk0 = 0; kk0 < 64; kk0 += 8) {
+                const int k0 = 64 * t + kk0;
+                if (k0 >= rows) break;   // wave-uniform
+                const int* gr[8];
+                double acc[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    gr[r] = g + (size_t)(wv + 16 * min(k0 + r, rows - 1)) * M;
+                    acc[r] = 0.0;
+                }
+                for (int j = ln; j < M; j += 64) {
+                    const double vj = v[j];
+#pragma unroll
+                    for (int r = 0; r < 8; ++r) acc[r] = fma((double)gr[r][j], vj, acc[r]);
+                }
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    double a = acc[r];
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+                    const int k = k0 + r;
+                    if (k < rows && ln == kk0 + r) {
+                        w[t] = a;
+                        pv = fma(v[wv + 16 * k], a, pv);
+                        pw = fma(a, a, pw);
+                    }
+                }
             }
         }
         rq = block_sum_1024(pv, red);
@@ -129,11 +156,11 @@ __global__ __launch_bounds__(1024) void power_kernel(const double* __restrict__ 
         rq_prev = rq;
         const double nw = sqrt(block_sum_1024(pw, red));
         if (nw == 0.0) break;
-        __syncthreads();
+        __syncthreads();   // every wave has finished reading v
 #pragma unroll
-        for (int k = 0; k < kPowRows; ++k) {
-            const int i = tid + 1024 * k;
-            if (i < M) v[i] = w[k] / nw;
+        for (int t = 0; t < kPowSlots; ++t) {
+            const int k = 64 * t + ln;
+            if (k < rows) v[wv + 16 * k] = w[t] / nw;
         }
         __syncthreads();
     }
@@ -155,20 +182,22 @@ void launch_operator_setup(Operator* op, hipStream_t st) {
     CSV_HIP(hipGetLastError());
 }
 
-void launch_power_iteration(Operator* op, double* gram, hipStream_t st) {
+void launch_power_iteration(Operator* op, int* gram, hipStream_t st) {
     const int M = op->M;
+    CSV_REQUIRE(M <= 16 * 64 * kPowSlots, CSV_EUNSUPPORTED, "step constant: M above 16384");
+    CSV_REQUIRE(1024ll * op->n < (1ll << 31), CSV_EUNSUPPORTED,
+                "step constant: n too large for the exact int32 Gram matrix");
     gram_kernel<<<dim3(ceil_div(M, 16), ceil_div(M, 16)), dim3(256), 0, st>>>(op->q, M, op->n,
                                                                              gram);
     CSV_HIP(hipGetLastError());
-    CSV_REQUIRE(M <= 1024 * kPowRows, CSV_EUNSUPPORTED, "step constant: M above 16384");
-    const size_t lds = (size_t)M * sizeof(double);
-    static bool attr_set = false;
+    static bool attr_set = false;   // v in LDS beyond the 64 KB default
     if (!attr_set) {
         CSV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&power_kernel),
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    1024 * kPowRows * (int)sizeof(double)));
+                                    16 * 64 * kPowSlots * (int)sizeof(double)));
         attr_set = true;
     }
+    const size_t lds = (size_t)M * sizeof(double);
     power_kernel<<<dim3(1), dim3(1024), lds, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip);
     CSV_HIP(hipGetLastError());
 }

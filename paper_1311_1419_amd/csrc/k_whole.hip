@@ -141,9 +141,22 @@ void launch_whole_quantise(const long long* y, int M, int n_frames, int8_t* code
 constexpr int kFwdCols = 512;   // pixels per forward workgroup (one sum chunk)
 constexpr int kAdjRows = 512;   // rows of Q^T staged per adjoint step
 constexpr int kLdsRow = 640;    // floats per staged row (512 columns, swizzled)
-static_assert(kAdjRows == 512, "one staged row of r per thread of the adjoint workgroup");
+constexpr int kNT = 256;        // threads per product workgroup
+static_assert(kNT % (kFwdCols / 4) == 0 && kAdjRows % kNT == 0,
+              "the staging loops need whole steps of the workgroup");
 
 __device__ inline int lds_col(int c) { return (c >> 7) * 160 + (c & 127) + 4 * ((c >> 4) & 7); }
+
+// a / d for 0 <= a < 2^21 and 0 < d (pixel indices of the whole-frame
+// decoder, whose exact int32 Gram matrix bounds W H below 2^21): the float
+// estimate a * (1 / d) is within one of the quotient; an exact integer
+// correction follows.
+__device__ inline int div_small(int a, int d, float inv_d) {
+    int qd = (int)((float)a * inv_d);
+    qd -= qd * d > a ? 1 : 0;
+    qd += (qd + 1) * d <= a ? 1 : 0;
+    return qd;
+}
 
 // Unpack 16 signed bytes to floats (exact).
 __device__ inline void unpack16(const int4& qq, float* qv) {
@@ -183,28 +196,29 @@ __device__ inline void piece_fma(const float (&qv)[R][16], const float* __restri
 // the pixels p of chunk k (512 pixels) of Q_g[m][p] x[g][f][p] for the GOPs g
 // of a batch (one Q each, same shape), added in chunk order by
 // whole_fwd_reduce_kernel: the sums depend only on the shapes.  Grid
-// (ceil(M / 64 R), ceil(n / 512), GOPs), 512 threads: eight lanes share a
-// row of Q (rows m0 + 64 rho), each reading 16 bytes at 128 u + 16 part (a
-// wave reads whole 128-byte lines); all of a thread's pieces are requested
-// before the chunk of x is staged.  The last chunk may be shorter (a
-// multiple of 64, as n is).  With tv set, the workgroups of a chunk also
+// (ceil(M / (NT / 8) R), ceil(n / 512), GOPs), NT threads: eight lanes share
+// a row of Q (rows m0 + (NT / 8) rho), each reading 16 bytes at 128 u +
+// 16 part (a wave reads whole 128-byte lines); all of a thread's pieces are
+// requested before the chunk of x is staged.  The last chunk may be shorter
+// (a multiple of 64, as n is).  With tv set, the workgroups of a chunk also
 // take the dual step of its pixels (each row tile a slice): it reads x only
 // and writes nu, w, P, which the adjoint launch reads.
-template <int FM, int R>
-__global__ __launch_bounds__(512) void whole_fwd_kernel(WholeQ qs, const float* __restrict__ xall,
-                                                        int F, int H, int W, int M,
-                                                        float* __restrict__ part_out, WholeTv tv) {
+template <int FM, int R, int NT>
+__global__ __launch_bounds__(NT) void whole_fwd_kernel(WholeQ qs, const float* __restrict__ xall,
+                                                       int F, int H, int W, int M,
+                                                       float* __restrict__ part_out, WholeTv tv) {
+    constexpr int RS = NT / 8;   // row stride between a thread's rows
     extern __shared__ float xs[];   // F x kLdsRow
     const int n = H * W;
     const int tid = threadIdx.x, col0 = blockIdx.y * kFwdCols, g = blockIdx.z;
     const int ncols = min(kFwdCols, n - col0);
     const int8_t* __restrict__ q = qs.q[g];
     const float* __restrict__ x = xall + (size_t)g * F * n;
-    const int part = tid & 7, mb = blockIdx.x * (64 * R) + (tid >> 3);
+    const int part = tid & 7, mb = blockIdx.x * (RS * R) + (tid >> 3);
     int4 qq[R][kFwdCols / 128];
 #pragma unroll
     for (int rho = 0; rho < R; ++rho) {
-        const int m = mb + 64 * rho;
+        const int m = mb + RS * rho;
 #pragma unroll
         for (int u = 0; u < kFwdCols / 128; ++u) {
             const int c = 16 * part + 128 * u;
@@ -214,21 +228,22 @@ __global__ __launch_bounds__(512) void whole_fwd_kernel(WholeQ qs, const float* 
         }
     }
     {
-        // F x 128 float4 over 512 threads (frames 4 s .. 4 s + 3 in step s),
-        // loaded from clamped in-range addresses so that all are in flight
+        // F x 128 float4 over NT threads (FS frames per step), loaded from
+        // clamped in-range addresses so that all are in flight
+        constexpr int FS = NT / (kFwdCols / 4);
         const int c4 = (tid % (kFwdCols / 4)) * 4, fr = tid / (kFwdCols / 4);
         const int cc = c4 < ncols ? c4 : 0;
-        float4 xv[(FM + 3) / 4];
+        float4 xv[(FM + FS - 1) / FS];
 #pragma unroll
-        for (int s4 = 0; s4 < (FM + 3) / 4; ++s4) {
-            const int f = min(4 * s4 + fr, F - 1);
-            xv[s4] = 4 * s4 < F ? *reinterpret_cast<const float4*>(x + (size_t)f * n + col0 + cc)
-                                : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int s4 = 0; s4 < (FM + FS - 1) / FS; ++s4) {
+            const int f = min(FS * s4 + fr, F - 1);
+            xv[s4] = FS * s4 < F ? *reinterpret_cast<const float4*>(x + (size_t)f * n + col0 + cc)
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
         }
 #pragma unroll
-        for (int s4 = 0; s4 < (FM + 3) / 4; ++s4)
-            if (4 * s4 + fr < F && c4 < ncols)
-                *reinterpret_cast<float4*>(xs + (4 * s4 + fr) * kLdsRow + lds_col(c4)) = xv[s4];
+        for (int s4 = 0; s4 < (FM + FS - 1) / FS; ++s4)
+            if (FS * s4 + fr < F && c4 < ncols)
+                *reinterpret_cast<float4*>(xs + (FS * s4 + fr) * kLdsRow + lds_col(c4)) = xv[s4];
     }
     __syncthreads();
     float acc[R][FM];
@@ -248,7 +263,7 @@ __global__ __launch_bounds__(512) void whole_fwd_kernel(WholeQ qs, const float* 
     float* out = part_out + ((size_t)blockIdx.y * gridDim.z + g) * F * M;
 #pragma unroll
     for (int rho = 0; rho < R; ++rho) {
-        const int m = mb + 64 * rho;
+        const int m = mb + RS * rho;
 #pragma unroll
         for (int f = 0; f < FM; ++f) {
             float v = acc[rho][f];
@@ -262,9 +277,10 @@ __global__ __launch_bounds__(512) void whole_fwd_kernel(WholeQ qs, const float* 
     if (tv.nuh) {
         const int tiles = gridDim.x, t = blockIdx.x;
         const int lo = ncols * t / tiles, hi = ncols * (t + 1) / tiles, cnt = hi - lo;
-        for (int e = tid; e < F * cnt; e += 512) {
-            const int f = e / cnt, k = col0 + lo + (e - f * cnt);
-            const int i = k / W, j = k - i * W;
+        const float invc = 1.f / (float)cnt, invW = 1.f / (float)W;
+        for (int e = tid; e < F * cnt; e += NT) {
+            const int f = div_small(e, cnt, invc), k = col0 + lo + (e - f * cnt);
+            const int i = div_small(k, W, invW), j = k - i * W;
             const int b = g * F + f;
             tv_dual_at(xall + (size_t)b * n, k, i, j, H, W, (size_t)b * n + k, tv.lam[b], tv.nuh,
                        tv.nuv, tv.wh, tv.wv, tv.ph, tv.pv);
@@ -287,21 +303,23 @@ __global__ __launch_bounds__(256) void whole_fwd_reduce_kernel(const float* __re
 
 // Adjoint product with the primal step.  g[g][f][p] = s_Phi sum_m Q_g[m][p]
 // r[g][f][m], read from the transposed copy Q^T (n x Mp, rows zero-padded):
-// grid (ceil(n / 64 R), GOPs), 512 threads, eight lanes per pixel row
-// (rows p0 + 64 rho) reading 16 bytes each at 128 u + 16 part, r staged in
+// grid (ceil(n / (NT / 8) R), GOPs), NT threads, eight lanes per pixel row
+// (rows p0 + (NT / 8) rho) reading 16 bytes each at 128 u + 16 part, r staged in
 // LDS 512 rows at a time after the thread's pieces of Q^T are requested,
 // the eight lanes meeting by lane shuffles (fixed order).  With tv set the
 // gradient never leaves the registers: x <- x - alpha (g + D^T P) at once
 // (P from the dual step of the forward launch); else g is written to gout.
-template <int FM, int R>
-__global__ __launch_bounds__(512) void whole_adj_kernel(WholeQ qts, const float* __restrict__ rall,
-                                                        int F, int H, int W, int M, int Mp,
-                                                        float s_phi, float* __restrict__ gout,
-                                                        WholeTv tv) {
+template <int FM, int R, int NT>
+__global__ __launch_bounds__(NT) void whole_adj_kernel(WholeQ qts, const float* __restrict__ rall,
+                                                       int F, int H, int W, int M, int Mp,
+                                                       float s_phi, float* __restrict__ gout,
+                                                       WholeTv tv) {
+    constexpr int RS = NT / 8;   // pixel-row stride between a thread's rows
     extern __shared__ float rs[];   // F x kLdsRow
     const int n = H * W;
     const int tid = threadIdx.x, g = blockIdx.y, part = tid & 7;
-    const int pb = blockIdx.x * (64 * R) + (tid >> 3);
+    const int pb = blockIdx.x * (RS * R) + (tid >> 3);
+    const float invW = 1.f / (float)W;
     const int8_t* __restrict__ qt = qts.q[g];
     const float* __restrict__ r = rall + (size_t)g * F * M;
     float acc[R][FM];
@@ -314,7 +332,7 @@ __global__ __launch_bounds__(512) void whole_adj_kernel(WholeQ qts, const float*
         int4 qq[R][kAdjRows / 128];
 #pragma unroll
         for (int rho = 0; rho < R; ++rho) {
-            const int p = pb + 64 * rho;
+            const int p = pb + RS * rho;
 #pragma unroll
             for (int u = 0; u < kAdjRows / 128; ++u) {
                 const int c = 16 * part + 128 * u;
@@ -324,9 +342,10 @@ __global__ __launch_bounds__(512) void whole_adj_kernel(WholeQ qts, const float*
             }
         }
         if (m0) __syncthreads();
-        {
-            float rv[FM];   // thread tid stages row m0 + tid of every frame
-            const int mm = tid;
+#pragma unroll
+        for (int h = 0; h < kAdjRows / NT; ++h) {
+            float rv[FM];   // thread tid stages rows m0 + tid + NT h of every frame
+            const int mm = tid + NT * h;
             const int mr = m0 + mm < M ? m0 + mm : M - 1;
 #pragma unroll
             for (int f = 0; f < FM; ++f) rv[f] = f < F ? r[(size_t)f * M + mr] : 0.f;
@@ -347,15 +366,25 @@ __global__ __launch_bounds__(512) void whole_adj_kernel(WholeQ qts, const float*
     }
 #pragma unroll
     for (int rho = 0; rho < R; ++rho) {
-        const int p = pb + 64 * rho;
-        const int i = p / W, j = p - i * W;
+        const int p = pb + RS * rho;
+        const int i = div_small(p, W, invW), j = p - i * W;
+        float sums[FM];
 #pragma unroll
         for (int f = 0; f < FM; ++f) {
             float v = acc[rho][f];
             v += __shfl_xor(v, 1);
             v += __shfl_xor(v, 2);
             v += __shfl_xor(v, 4);
-            if (f < F && (f & 7) == part && p < n) {   // lane f % 8 keeps frame f
+            sums[f] = v;   // every lane of the row holds every frame's sum
+        }
+        // lane part finishes frames part, part + 8, ...
+#pragma unroll
+        for (int f0 = 0; f0 < FM; f0 += 8) {
+            const int f = f0 + part;
+            float v = 0.f;
+#pragma unroll
+            for (int ff = 0; ff < 8 && f0 + ff < FM; ++ff) v = part == ff ? sums[f0 + ff] : v;
+            if (f < F && p < n) {
                 const int b = g * F + f;
                 const float gv = s_phi * v;
                 if (!tv.nuh) {
@@ -363,8 +392,7 @@ __global__ __launch_bounds__(512) void whole_adj_kernel(WholeQ qts, const float*
                 } else {
                     const float dt = tv_dtp_at(tv.ph + (size_t)b * n, tv.pv + (size_t)b * n, p, i,
                                                j, H, W);
-                    const float alpha = tv_alpha(tv.lip[g], tv_beta(tv.lam[b]));
-                    tv.x[(size_t)b * n + p] -= alpha * (gv + dt);
+                    tv.x[(size_t)b * n + p] -= tv.alpha[b] * (gv + dt);
                 }
             }
         }
@@ -387,9 +415,10 @@ __global__ __launch_bounds__(256) void transpose_q_kernel(const int8_t* __restri
     }
 }
 
-__global__ void gather_lip_kernel(WholeLip ls, int ngop, double* __restrict__ out) {
-    const int g = threadIdx.x;
-    if (g < ngop) out[g] = ls.lip[g][0];
+__global__ void whole_alpha_kernel(WholeLip ls, const float* __restrict__ lam, int F, int nimg,
+                                   float* __restrict__ alpha) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nimg) alpha[b] = tv_alpha(ls.lip[b / F][0], tv_beta(lam[b]));
 }
 
 // Decoded CS frames: out[f][p] = clip(round-half-even(key[p] + x[f][p])).
@@ -483,17 +512,17 @@ void launch_whole_fwd(const WholeQ& qs, int ngop, const float* x, int F, int H, 
     const int nk = whole_fwd_parts(n);
     const size_t lds = (size_t)F * kLdsRow * sizeof(float);
     auto go = [&](auto kern, int R) {
-        kern<<<dim3(ceil_div(M, 64 * R), nk, ngop), dim3(512), lds, st>>>(qs, x, F, H, W, M, part,
-                                                                         tv);
+        kern<<<dim3(ceil_div(M, kNT / 8 * R), nk, ngop), dim3(kNT), lds, st>>>(qs, x, F, H, W, M,
+                                                                              part, tv);
     };
     if (F <= 4)
-        go(whole_fwd_kernel<4, 2>, 2);
+        go(whole_fwd_kernel<4, 2, kNT>, 2);
     else if (F <= 8)
-        go(whole_fwd_kernel<8, 2>, 2);
+        go(whole_fwd_kernel<8, 2, kNT>, 2);
     else if (F <= 16)
-        go(whole_fwd_kernel<16, 1>, 1);
+        go(whole_fwd_kernel<16, 1, kNT>, 1);
     else
-        go(whole_fwd_kernel<32, 1>, 1);
+        go(whole_fwd_kernel<32, 1, kNT>, 1);
     CSV_HIP(hipGetLastError());
     const int count = ngop * F * M;
     whole_fwd_reduce_kernel<<<dim3(ceil_div(count, 256)), dim3(256), 0, st>>>(part, nk, count,
@@ -509,17 +538,17 @@ void launch_whole_adj(const WholeQ& qts, int ngop, const float* r, int F, int H,
                 CSV_EUNSUPPORTED, "whole-frame product shape");
     const size_t lds = (size_t)F * kLdsRow * sizeof(float);
     auto go = [&](auto kern, int R) {
-        kern<<<dim3(ceil_div(n, 64 * R), ngop), dim3(512), lds, st>>>(qts, r, F, H, W, M, Mp,
-                                                                     s_phi, gout, tv);
+        kern<<<dim3(ceil_div(n, kNT / 8 * R), ngop), dim3(kNT), lds, st>>>(qts, r, F, H, W, M, Mp,
+                                                                          s_phi, gout, tv);
     };
     if (F <= 4)
-        go(whole_adj_kernel<4, 2>, 2);
+        go(whole_adj_kernel<4, 4, kNT>, 4);
     else if (F <= 8)
-        go(whole_adj_kernel<8, 2>, 2);
+        go(whole_adj_kernel<8, 2, kNT>, 2);
     else if (F <= 16)
-        go(whole_adj_kernel<16, 1>, 1);
+        go(whole_adj_kernel<16, 1, kNT>, 1);
     else
-        go(whole_adj_kernel<32, 1>, 1);
+        go(whole_adj_kernel<32, 1, kNT>, 1);
     CSV_HIP(hipGetLastError());
 }
 
@@ -529,10 +558,12 @@ void launch_transpose_q(const int8_t* q, int Mp, int n, int8_t* qt, hipStream_t 
     CSV_HIP(hipGetLastError());
 }
 
-void launch_gather_lip(const WholeLip& ls, int ngop, double* out, hipStream_t st) {
-    if (ngop <= 0) return;
+void launch_whole_alpha(const WholeLip& ls, const float* lam, int F, int ngop, float* alpha,
+                        hipStream_t st) {
+    if (ngop <= 0 || F <= 0) return;
     CSV_REQUIRE(ngop <= kWholeBatch, CSV_EINVAL, "whole-frame batch too large");
-    gather_lip_kernel<<<dim3(1), dim3(64), 0, st>>>(ls, ngop, out);
+    whole_alpha_kernel<<<dim3(ceil_div(ngop * F, 256)), dim3(256), 0, st>>>(ls, lam, F, ngop * F,
+                                                                           alpha);
     CSV_HIP(hipGetLastError());
 }
 
