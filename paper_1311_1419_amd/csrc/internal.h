@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <map>
 #include <memory>
@@ -280,6 +281,21 @@ int fused_tile_blocks(int n, int Mp);   // blocks per tile of the chosen variant
 void launch_fista_bf16_class(int n, int Mp, const FusedTile* tiles, const int* qoff,
                              const int* queue, int* counters, int count, hipStream_t st,
                              int variant = -1);
+// Raise kernel FN's dynamic LDS limit to `bytes` on the current device, once
+// per device (the attribute is per device; concurrent first calls may both
+// set it, which is harmless).
+template <auto FN>
+inline void ensure_lds_limit(size_t bytes) {
+    static std::atomic<uint64_t> done{0};   // one bit per device ordinal < 64
+    int dev = 0;
+    CSV_HIP(hipGetDevice(&dev));
+    const uint64_t bit = 1ull << (dev & 63);
+    if (done.load(std::memory_order_acquire) & bit) return;
+    CSV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(FN),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    done.fetch_or(bit, std::memory_order_release);
+}
+
 int device_cus();
 // fused BF16 TV recovery (k_tv_bf16.hip): 16 x 16 blocks, tiles of 32
 bool tv_class_supported(int n, int Mp);

@@ -83,84 +83,80 @@ __global__ __launch_bounds__(256) void gram_kernel(const int8_t* __restrict__ q,
     if (i < M && j < M) g[(size_t)i * M + j] = acc;
 }
 
-// Deterministic sum over the 1024 threads: wave shuffles, then the 16 wave
-// partials in order; every thread gets the total.
-__device__ inline double block_sum_1024(double v, double* red) {
+// Deterministic sums of two values over the 1024 threads: wave shuffles,
+// then the 16 wave partials in order; every thread gets both totals.  Its
+// first barrier also orders every earlier LDS read before later writes.
+__device__ inline void block_sum2_1024(double& a, double& b, double (*red)[16]) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+    }
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
     __syncthreads();
-    if (ln == 0) red[wv] = v;
+    if (ln == 0) {
+        red[0][wv] = a;
+        red[1][wv] = b;
+    }
     __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < 16; ++w) t += red[w];
-    return t;
+    double ta = 0.0, tb = 0.0;
+    for (int w = 0; w < 16; ++w) {
+        ta += red[0][w];
+        tb += red[1][w];
+    }
+    a = ta;
+    b = tb;
 }
 
 // Power iteration on G (FP64): v0 = 1/sqrt(M); w = G v; Rayleigh quotient
 // rq = v.w; stop once |rq - rq_prev| <= tol rq (from the second step), else
-// v = w / ||w||.  One workgroup of 16 waves, v in LDS (M <= 16384).  Wave
-// w takes rows i = w + 16 k, eight at a time; its lanes split each row
-// (j = lane + 64 s, coalesced int32 reads of G, FP64 products) and meet by
-// a fixed shuffle tree; row k's result stays in lane k % 64, register k / 64.
-constexpr int kPowSlots = 16;   // rows per lane per wave: M <= 16 x 64 x 16
-__global__ __launch_bounds__(1024) void power_kernel(const int* __restrict__ g, int M,
+// v = w / ||w||.  One workgroup of 1024 threads, v in LDS (M <= 16384).  S
+// adjacent threads share a row (S = 1024 / M rounded down to a power of
+// two, at most 64): thread s of the group sums j = s, s + S, ... of
+// G[j][i] v[j] (G symmetric: consecutive groups read consecutive i), the S
+// partial sums meet by a fixed shuffle tree, and the group's first thread
+// keeps w_i.  With S = 1 a thread takes rows t, t + 1024, ... (up to 16).
+constexpr int kPowRows = 16;
+__global__ __launch_bounds__(1024) void power_kernel(const int* __restrict__ g, int M, int S,
                                                     double s_phi, double tol, int max_iter,
                                                     double* __restrict__ lip) {
     extern __shared__ double v[];   // M
-    __shared__ double red[16];
-    const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+    __shared__ double red[2][16];
+    const int tid = threadIdx.x, grp = tid / S, sl = tid - grp * S, per_pass = 1024 / S;
     for (int i = tid; i < M; i += 1024) v[i] = 1.0 / sqrt((double)M);
     __syncthreads();
-    const int rows = (M - wv + 15) / 16;   // rows of this wave
     double rq = 0.0, rq_prev = 0.0;
     int it = 0;
     for (it = 1; it <= max_iter; ++it) {
-        double w[kPowSlots];
+        double w[kPowRows];
         double pv = 0.0, pw = 0.0;
 #pragma unroll
-        for (int t = 0; t < kPowSlots; ++t) {
-            w[t] = 0.0;
-            // eight rows at a time: eight independent loads and FMA chains
-            for (int kk0 = 0; kk0 < 64; kk0 += 8) {
-                const int k0 = 64 * t + kk0;
-                if (k0 >= rows) break;   // wave-uniform
-                const int* gr[8];
-                double acc[8];
-#pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    gr[r] = g + (size_t)(wv + 16 * min(k0 + r, rows - 1)) * M;
-                    acc[r] = 0.0;
-                }
-                for (int j = ln; j < M; j += 64) {
-                    const double vj = v[j];
-#pragma unroll
-                    for (int r = 0; r < 8; ++r) acc[r] = fma((double)gr[r][j], vj, acc[r]);
-                }
-#pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    double a = acc[r];
-#pragma unroll
-                    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
-                    const int k = k0 + r;
-                    if (k < rows && ln == kk0 + r) {
-                        w[t] = a;
-                        pv = fma(v[wv + 16 * k], a, pv);
-                        pw = fma(a, a, pw);
-                    }
-                }
+        for (int k = 0; k < kPowRows; ++k) {
+            if (per_pass * k >= M) break;   // uniform
+            const int i = grp + per_pass * k;
+            double acc = 0.0;
+            if (i < M) {
+#pragma unroll 16
+                for (int j = sl; j < M; j += S) acc = fma((double)g[(size_t)j * M + i], v[j], acc);
+            }
+            for (int off = S >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+            w[k] = acc;
+            if (i < M && sl == 0) {
+                pv = fma(v[i], acc, pv);
+                pw = fma(acc, acc, pw);
             }
         }
-        rq = block_sum_1024(pv, red);
+        block_sum2_1024(pv, pw, red);   // also: every thread has finished reading v
+        rq = pv;
         if (it > 1 && fabs(rq - rq_prev) <= tol * rq) break;
         rq_prev = rq;
-        const double nw = sqrt(block_sum_1024(pw, red));
+        const double nw = sqrt(pw);
         if (nw == 0.0) break;
-        __syncthreads();   // every wave has finished reading v
 #pragma unroll
-        for (int t = 0; t < kPowSlots; ++t) {
-            const int k = 64 * t + ln;
-            if (k < rows) v[wv + 16 * k] = w[t] / nw;
+        for (int k = 0; k < kPowRows; ++k) {
+            if (per_pass * k >= M) break;
+            const int i = grp + per_pass * k;
+            if (i < M && sl == 0) v[i] = w[k] / nw;
         }
         __syncthreads();
     }
@@ -184,21 +180,19 @@ void launch_operator_setup(Operator* op, hipStream_t st) {
 
 void launch_power_iteration(Operator* op, int* gram, hipStream_t st) {
     const int M = op->M;
-    CSV_REQUIRE(M <= 16 * 64 * kPowSlots, CSV_EUNSUPPORTED, "step constant: M above 16384");
+    CSV_REQUIRE(M <= 1024 * kPowRows, CSV_EUNSUPPORTED, "step constant: M above 16384");
     CSV_REQUIRE(1024ll * op->n < (1ll << 31), CSV_EUNSUPPORTED,
                 "step constant: n too large for the exact int32 Gram matrix");
     gram_kernel<<<dim3(ceil_div(M, 16), ceil_div(M, 16)), dim3(256), 0, st>>>(op->q, M, op->n,
                                                                              gram);
     CSV_HIP(hipGetLastError());
-    static bool attr_set = false;   // v in LDS beyond the 64 KB default
-    if (!attr_set) {
-        CSV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&power_kernel),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    16 * 64 * kPowSlots * (int)sizeof(double)));
-        attr_set = true;
-    }
+    // v in LDS, beyond the 64 KB default
+    ensure_lds_limit<&power_kernel>((size_t)1024 * kPowRows * sizeof(double));
+    int S = 1;   // threads per row: 1024 / M rounded down to a power of two, <= 64
+    while (S < 64 && 2 * S * M <= 1024) S *= 2;
     const size_t lds = (size_t)M * sizeof(double);
-    power_kernel<<<dim3(1), dim3(1024), lds, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip);
+    power_kernel<<<dim3(1), dim3(1024), lds, st>>>(gram, M, S, op->s_phi, 1e-12, 10000,
+                                                   op->lip);
     CSV_HIP(hipGetLastError());
 }
 

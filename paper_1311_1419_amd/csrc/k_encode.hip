@@ -363,12 +363,7 @@ static void launch_measure_form(const Shape& s, const int8_t* q, const uint8_t* 
     const int total = n_frames * s.nb;
     const size_t lds = MeasureLayout<B, FORM>::LDS;
     auto* fn = &measure_kernel<B, FORM>;
-    static bool attr_set = false;
-    if (!attr_set) {
-        CSV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_set = true;
-    }
+    ensure_lds_limit<&measure_kernel<B, FORM>>(lds);
     fn<<<dim3(ceil_div(total, 32)), dim3(256), lds, st>>>(q, q8, s.Mp, frames, n_frames,
                                                            frame_stride, key, s.W, s.H, s.nbx,
                                                            s.nb, y);

@@ -319,12 +319,7 @@ static void launch_class(const FusedTile* tiles, const int* qoff, const int* que
                    (size_t)W * SPL * 4096 + 64) * OCC <= 160 * 1024,
                   "LDS of OCC workgroups exceeds a CU");
     auto* fn = &fista_bf16_kernel<N, MP, CT, W, PF, PA, SPL, OCC>;
-    static bool attr_set = false;
-    if (!attr_set) {
-        CSV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_set = true;
-    }
+    ensure_lds_limit<&fista_bf16_kernel<N, MP, CT, W, PF, PA, SPL, OCC>>(lds);
     fn<<<dim3(grid), dim3(64 * W), lds, st>>>(tiles, qoff, queue, counters);
     CSV_HIP(hipGetLastError());
 }

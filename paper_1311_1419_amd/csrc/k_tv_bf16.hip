@@ -257,12 +257,7 @@ static void launch_tv_class(const FusedTile* tiles, const int* qoff, const int* 
     constexpr size_t lds = (size_t)16 * 1024 + (size_t)(MP / 16) * 1024 + 2 * 8 * 8 * 64 * 4;
     static_assert((lds + 64) * OCC <= 160 * 1024, "LDS of OCC workgroups exceeds a CU");
     auto* fn = &tv_bf16_kernel<MP, PF, PA, OCC>;
-    static bool attr_set = false;
-    if (!attr_set) {
-        CSV_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_set = true;
-    }
+    ensure_lds_limit<&tv_bf16_kernel<MP, PF, PA, OCC>>(lds);
     fn<<<dim3(grid), dim3(512), lds, st>>>(tiles, qoff, queue, counters);
     CSV_HIP(hipGetLastError());
 }
