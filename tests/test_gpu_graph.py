@@ -37,3 +37,60 @@ def test_graph_replays_match_eager(ctx):
             assert np.array_equal(host(f), ef), f"replay {rep}"
             assert np.array_equal(host(fl), efl), f"replay {rep}"
     g.close()
+
+
+def _replays_match(ctx, specs_params, make_video, reps=3):
+    """Capture the decode of (spec, params) items, then replay it `reps`
+    times with new GOPs encoded into the bound buffers in between; every
+    replay must equal an eager decode of the same inputs."""
+    bufs = [ctx.alloc_stream(p) for _, p in specs_params]
+    for (s, p), b in zip(specs_params, bufs):
+        ctx.encode_gop(dev(make_video(s, 0)), p, out=b)
+    items = [(b, p) for b, (_, p) in zip(bufs, specs_params)]
+    st = torch.cuda.Stream()
+    g = ctx.capture_batch(items, st, want_float=True, want_obj=True)
+    for rep in range(reps):
+        for (s, p), b in zip(specs_params, bufs):
+            ctx.encode_gop(dev(make_video(s, rep + 1)), p, out=b)
+        torch.cuda.synchronize()
+        eager = ctx.decode_batch(items, want_float=True, want_obj=True)
+        eager = [(host(f), host(fl), host(ob)) for f, fl, ob in eager]
+        g.launch(st)
+        st.synchronize()
+        for (f, fl, ob), (ef, efl, eob) in zip(g.outputs, eager):
+            assert np.array_equal(host(f), ef), f"replay {rep}"
+            assert np.array_equal(host(fl), efl), f"replay {rep}"
+            assert np.array_equal(host(ob), eob), f"replay {rep}"
+    g.close()
+
+
+def _shifted(s, k):
+    return sv.surveillance_video(sv.VideoSpec(s.height, s.width, s.gop, s.n_objects,
+                                              s.video_seed + 17 * k))
+
+
+def test_graph_replays_tv_bf16_batch(ctx):
+    """The fused BF16 TV kernel and the fused l1 kernel in one captured batch."""
+    import paper_1311_1419_amd as P
+    announce("graph capture + replays: BF16 TV and l1")
+    specs = [sv.qcif_tiny(), sv.cif_sweep(4, 0.3, stream=3)]
+    items = [(specs[0], P.Params.from_spec(specs[0], precision=P.CSV_BF16, flags=P.CSV_FLAG_TV)),
+             (specs[1], P.Params.from_spec(specs[1], precision=P.CSV_BF16, flags=P.CSV_FLAG_TV)),
+             (specs[0], P.Params.from_spec(specs[0].with_(stream_id=11), precision=P.CSV_BF16))]
+    _replays_match(ctx, items, _shifted)
+
+
+def test_graph_replays_fp32_tv_and_whole_frame_batch(ctx):
+    """FP32 batch: two whole-frame TV GOPs of one shape (shared launches), a
+    block TV GOP and an l1 GOP."""
+    import paper_1311_1419_amd as P
+    announce("graph capture + replays: FP32 whole-frame TV, block TV, l1")
+    spec = sv.qcif_tiny().with_(gop=3)
+    whole = dict(precision=P.CSV_FP32, flags=P.CSV_FLAG_TV | P.CSV_FLAG_WHOLE_FRAME, m=300,
+                 iters=40)
+    items = [(spec, P.Params.from_spec(spec, **whole)),
+             (spec, P.Params.from_spec(spec.with_(stream_id=21), **whole)),
+             (spec, P.Params.from_spec(spec.with_(stream_id=22), precision=P.CSV_FP32,
+                                       flags=P.CSV_FLAG_TV, iters=60)),
+             (spec, P.Params.from_spec(spec.with_(stream_id=23), precision=P.CSV_FP32, iters=60))]
+    _replays_match(ctx, items, _shifted)
