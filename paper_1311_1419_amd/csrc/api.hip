@@ -285,16 +285,37 @@ const float* beta_table(Ctx* c, int T, bool ista, hipStream_t st) {
 static void lambda_pass(Ctx* c, const Shape& s, Operator* op, const float* y, int nblk, float* lam,
                         hipStream_t st, const std::string& g0name) {
     float* g0 = static_cast<float*>(scratch(c, g0name, (size_t)nblk * s.n * 4));
-    const float* opm =
-        (s.flags & (CSV_FLAG_LAMBDA_PIXEL_DOMAIN | CSV_FLAG_TV)) ? op->phi32 : op->a32;
-    launch_gemm_nn(y, opm, g0, nblk, s.n, s.Mp, s.Mp, s.n, s.n, st);
+    F32Batch bt{};
+    bt.j[0].op = (s.flags & (CSV_FLAG_LAMBDA_PIXEL_DOMAIN | CSV_FLAG_TV)) ? op->phi32 : op->a32;
+    bt.j[0].R = const_cast<float*>(y);   // read only: the adjoint's input
+    bt.j[0].G = g0;
+    bt.j[0].nblk = nblk;
+    launch_f32_adjoint(bt, 1, s.n, s.Mp, st);   // g0 = y^ A (or y^ Phi)
     launch_row_absmax(g0, nblk, s.n, s.n, s.lambda_frac, lam, st);
 }
 
-// Total-variation recovery (k_tv.hip): x in S (pixel domain), FP32.
-static void tv_fp32(Ctx* c, const Shape& s, Operator* op, const float* y, const float* lam,
-                    int nblk, float* S, hipStream_t st) {
-    const size_t nn = (size_t)nblk * s.n;
+// A GOP of a plain FP32 batch: its operator, dequantised y^, lambda and
+// output s (x for TV).
+struct F32Item {
+    Operator* op;
+    const float* y;
+    const float* lam;
+    float* S;
+    int nblk;
+};
+
+// Total-variation recovery (k_tv.hip) in FP32, pixel domain, for up to
+// kF32Batch GOPs of one shape: the GOPs' images are stacked in xs (their
+// rows in item order) so the dual and primal steps run once per group,
+// and the two Phi products run batched on FP32 MFMA (R = x Phi^T - y^,
+// Gd = R Phi).  xs receives x; the caller points each item at its rows.
+static void tv_fp32(Ctx* c, const Shape& s, const std::vector<F32Item>& its, float* xs,
+                    hipStream_t st) {
+    const int ng = (int)its.size();
+    CSV_REQUIRE(ng >= 1 && ng <= kF32Batch, CSV_EINVAL, "FP32 batch size");
+    int total = 0;
+    for (const F32Item& it : its) total += it.nblk;
+    const size_t nn = (size_t)total * s.n;
     float* nuh = static_cast<float*>(scratch(c, "tv_nuh", nn * 4));
     float* nuv = static_cast<float*>(scratch(c, "tv_nuv", nn * 4));
     float* wh = static_cast<float*>(scratch(c, "tv_wh", nn * 4));
@@ -302,31 +323,61 @@ static void tv_fp32(Ctx* c, const Shape& s, Operator* op, const float* y, const 
     float* ph = static_cast<float*>(scratch(c, "tv_ph", nn * 4));
     float* pv = static_cast<float*>(scratch(c, "tv_pv", nn * 4));
     float* Gd = static_cast<float*>(scratch(c, "Gd", nn * 4));
-    float* R = static_cast<float*>(scratch(c, "Rm", (size_t)nblk * s.Mp * 4));
-    for (float* p : {S, nuh, nuv, wh, wv}) launch_fill_f32(p, 0.f, nn, st);
+    float* R = static_cast<float*>(scratch(c, "Rm", (size_t)total * s.Mp * 4));
+    float* lam = static_cast<float*>(scratch(c, "tv_lam", (size_t)total * 4));
+    float* alpha = static_cast<float*>(scratch(c, "tv_alpha", (size_t)total * 4));
+    F32Batch bt{};
+    size_t off = 0;
+    for (int g = 0; g < ng; ++g) {
+        const F32Item& it = its[g];
+        bt.j[g] = F32Job{it.op->phi32, it.y, it.lam, it.op->lip, nullptr, xs + off * s.n,
+                         Gd + off * s.n, R + off * s.Mp, it.nblk};
+        launch_copy_f32(lam + off, it.lam, (size_t)it.nblk, st);
+        launch_tv_alpha(it.op->lip, it.lam, it.nblk, alpha + off, st);
+        off += (size_t)it.nblk;
+    }
+    for (float* p : {xs, nuh, nuv, wh, wv}) launch_fill_f32(p, 0.f, nn, st);
     for (int k = 0; k < s.T; ++k) {
-        launch_tv_dual(S, nuh, nuv, wh, wv, ph, pv, lam, nblk, s.B, s.B, st);
-        launch_gemm_nt(S, op->phi32, R, nblk, s.Mp, s.n, s.n, s.n, s.Mp, y, s.Mp, s.M, st);
-        launch_gemm_nn(R, op->phi32, Gd, nblk, s.n, s.Mp, s.Mp, s.n, s.n, st);
-        launch_tv_primal(S, Gd, ph, pv, lam, op->lip, nblk, s.B, s.B, st);
+        launch_tv_dual(xs, nuh, nuv, wh, wv, ph, pv, lam, total, s.B, s.B, st);
+        launch_f32_forward(bt, ng, s.n, s.M, s.Mp, st);
+        launch_f32_adjoint(bt, ng, s.n, s.Mp, st);
+        launch_tv_primal(xs, Gd, ph, pv, alpha, total, s.B, s.B, st);
     }
 }
 
-static void fista_fp32(Ctx* c, const Shape& s, Operator* op, const float* y, const float* lam,
-                       int nblk, float* S, hipStream_t st) {
-    const size_t nn = (size_t)nblk * s.n;
-    float* V = static_cast<float*>(scratch(c, "V", nn * 4));
-    float* Gd = static_cast<float*>(scratch(c, "Gd", nn * 4));
-    float* R = static_cast<float*>(scratch(c, "Rm", (size_t)nblk * s.Mp * 4));
+// Plain FP32 FISTA for up to kF32Batch GOPs of one shape (n, M, M_p, T,
+// ISTA), all sharing each launch (k_fp32_mfma.hip).  Each GOP k of the
+// batch has its own iterate scratch ("V#k", "Gd#k", "Rm#k").
+
+static void fista_fp32(Ctx* c, const Shape& s, const std::vector<F32Item>& its, hipStream_t st) {
+    const int ng = (int)its.size();
+    CSV_REQUIRE(ng >= 1 && ng <= kF32Batch, CSV_EINVAL, "FP32 batch size");
+    F32Batch bt{};
+    for (int g = 0; g < ng; ++g) {
+        const F32Item& it = its[g];
+        const size_t nn = (size_t)it.nblk * s.n;
+        const std::string tag = "#" + std::to_string(g);
+        F32Job& j = bt.j[g];
+        j.op = it.op->a32;
+        j.y = it.y;
+        j.lam = it.lam;
+        j.lip = it.op->lip;
+        j.S = it.S;
+        j.V = static_cast<float*>(scratch(c, "V" + tag, nn * 4));
+        j.G = static_cast<float*>(scratch(c, "Gd" + tag, nn * 4));
+        j.R = static_cast<float*>(scratch(c, "Rm" + tag, (size_t)it.nblk * s.Mp * 4));
+        j.nblk = it.nblk;
+    }
     const float* beta = beta_table(c, s.T, (s.flags & CSV_FLAG_ISTA) != 0, st);
-    launch_fill_f32(S, 0.f, nn, st);
-    launch_fill_f32(V, 0.f, nn, st);
+    for (int g = 0; g < ng; ++g) {
+        launch_fill_f32(bt.j[g].S, 0.f, (size_t)its[g].nblk * s.n, st);
+        launch_fill_f32(bt.j[g].V, 0.f, (size_t)its[g].nblk * s.n, st);
+    }
     for (int k = 0; k < s.T; ++k) {
-        // residual A v - y^ (forward product, epilogue subtracts y^; padded rows 0)
-        launch_gemm_nt(V, op->a32, R, nblk, s.Mp, s.n, s.n, s.n, s.Mp, y, s.Mp, s.M, st);
-        // gradient A^T (A v - y^)
-        launch_gemm_nn(R, op->a32, Gd, nblk, s.n, s.Mp, s.Mp, s.n, s.n, st);
-        launch_prox(S, V, Gd, lam, op->lip, beta, k, nblk, s.n, st);
+        // residual A v - y^ (padded rows 0), gradient A^T (A v - y^), prox
+        launch_f32_forward(bt, ng, s.n, s.M, s.Mp, st);
+        launch_f32_adjoint(bt, ng, s.n, s.Mp, st);
+        launch_f32_prox(bt, ng, s.n, beta, k, st);
     }
 }
 
@@ -500,14 +551,14 @@ void recover(Ctx* c, const Shape& s, Operator* op, const int8_t* codes, const ui
     const float* y = prepare(c, s, op, codes, exps, nblk, lam, "", st);
     if (tv && s.precision == CSV_FP32) {
         ProfScope ps(c, "tv_fp32", st);
-        tv_fp32(c, s, op, y, lam, nblk, S, st);
+        tv_fp32(c, s, {F32Item{op, y, lam, S, nblk}}, S, st);
     } else if (tv) {
         FusedJob j{&s, op, y, lam, S, nblk};
         j.tv = true;
         fista_bf16(c, {j}, st);
     } else if (s.precision == CSV_FP32) {
         ProfScope ps(c, "fista_fp32", st);
-        fista_fp32(c, s, op, y, lam, nblk, S, st);
+        fista_fp32(c, s, {F32Item{op, y, lam, S, nblk}}, st);
     } else {
         fista_bf16(c, {FusedJob{&s, op, y, lam, S, nblk}}, st);
     }
@@ -779,7 +830,9 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
     const bool spread = count > 1;
     if (spread) ensure_aux(c);
     auto lane_of = [&](int i) { return spread ? c->aux[i % Ctx::kAux] : st; };
-    auto g0_of = [&](int i) { return spread ? "g0@" + std::to_string(i % Ctx::kAux) : std::string("g0"); };
+    auto g0_of = [&](int i) {
+        return spread ? "g0@" + std::to_string(i % Ctx::kAux) : std::string("g0");
+    };
     // scratch is sized before any launch that reads it
     for (int i = 0; i < count; ++i) {
         const Shape& s = shapes[i];
@@ -807,22 +860,61 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
     }
     if (spread) join_aux(c, st);
     std::vector<FusedJob> jobs;
+    // plain FP32 GOPs (l1 and TV): grouped by shape and solver, each group's
+    // launches shared
+    std::map<std::tuple<int, int, int, int, int, int>, std::vector<int>> f32_groups;
     for (int i = 0; i < count; ++i) {
         const Shape& s = shapes[i];
         Item& it = items[i];
         if (!it.nblk) continue;
-        if ((s.flags & CSV_FLAG_TV) && s.precision == CSV_FP32) {
-            ProfScope ps(c, "tv_fp32", st);      // shares the context's FP32 scratch: serial
-            tv_fp32(c, s, it.op, it.y, it.lam, it.nblk, it.S, st);
-        } else if (s.flags & CSV_FLAG_TV) {
+        if (s.precision == CSV_FP32) {
+            const int tv = (s.flags & CSV_FLAG_TV) ? 1 : 0;
+            f32_groups[std::make_tuple(tv, s.n, s.M, s.Mp, s.T,
+                                       (s.flags & CSV_FLAG_ISTA) ? 1 : 0)]
+                .push_back(i);
+            continue;
+        }
+        if (s.flags & CSV_FLAG_TV) {
             FusedJob j{&shapes[i], it.op, it.y, it.lam, it.S, it.nblk};
             j.tv = true;
             jobs.push_back(j);
-        } else if (s.precision == CSV_FP32) {
-            ProfScope ps(c, "fista_fp32", st);   // shares the context's FP32 scratch: serial
-            fista_fp32(c, s, it.op, it.y, it.lam, it.nblk, it.S, st);
         } else {
             jobs.push_back(FusedJob{&shapes[i], it.op, it.y, it.lam, it.S, it.nblk});
+        }
+    }
+    int tv_batches = 0;   // names each TV batch's stacked image buffer
+    for (const auto& kv : f32_groups) {
+        const std::vector<int>& idx = kv.second;
+        const bool tv = std::get<0>(kv.first) != 0;
+        for (size_t a = 0; a < idx.size(); a += kF32Batch) {
+            std::vector<F32Item> its;
+            std::vector<int> members;
+            int total = 0;
+            for (size_t b = a; b < idx.size() && b < a + kF32Batch; ++b) {
+                const Item& it = items[idx[b]];
+                its.push_back(F32Item{it.op, it.y, it.lam, it.S, it.nblk});
+                members.push_back(idx[b]);
+                total += it.nblk;
+            }
+            const Shape& s0 = shapes[idx[a]];
+            if (tv) {
+                // the batch's images stacked in one buffer; each GOP's S
+                // then points at its rows (synthesis and the FP64 check
+                // read them there)
+                ProfScope ps(c, "tv_fp32", st);
+                const std::string xname = "tv_x@" + std::to_string(tv_batches++);
+                float* xs = static_cast<float*>(scratch(c, xname, (size_t)total * s0.n * 4));
+                tv_fp32(c, s0, its, xs, st);
+                size_t off = 0;
+                for (int i : members) {
+                    items[i].S = xs + off * s0.n;
+                    off += (size_t)items[i].nblk;
+                }
+            } else {
+                // the context's FP32 scratch: one batch at a time
+                ProfScope ps(c, "fista_fp32", st);
+                fista_fp32(c, s0, its, st);
+            }
         }
     }
     if (!jobs.empty()) fista_bf16(c, jobs, st);

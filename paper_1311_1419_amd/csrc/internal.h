@@ -177,15 +177,9 @@ void launch_operator_setup(Operator* op, hipStream_t st);
 void launch_power_iteration(Operator* op, int* gram, hipStream_t st);   // gram: M x M int32 scratch
 void launch_dequant(const int8_t* codes, const uint8_t* exps, int nblk, int M, int Mp,
                     double s_phi, float* y, hipStream_t st);
-void launch_gemm_nt(const float* X, const float* WT, float* C, int R, int N, int K,
-                    int ldx, int ldw, int ldc, const float* sub, int ldsub, int nvalid,
-                    hipStream_t st);
-void launch_gemm_nn(const float* X, const float* W, float* C, int R, int N, int K,
-                    int ldx, int ldw, int ldc, hipStream_t st);
 void launch_row_absmax(const float* X, int R, int N, int ld, float scale, float* out, hipStream_t st);
 void launch_fill_f32(float* p, float v, size_t count, hipStream_t st);
-void launch_prox(float* s, float* v, const float* g, const float* lam, const double* lip,
-                 const float* beta, int k, int R, int n, hipStream_t st);
+void launch_copy_f32(float* dst, const float* src, size_t count, hipStream_t st);
 void launch_synth(const float* s, const float* dct, const uint8_t* key, int W, int H, int B,
                   int nbx, int nb, int n_frames, uint8_t* out_u8, float* out_f32, hipStream_t st);
 void launch_final64(const double* a64t, const float* s, const int8_t* codes, const uint8_t* exps,
@@ -201,6 +195,33 @@ void launch_whole_measure(const Shape& s, const uint8_t* frames, int n_frames, s
 void launch_whole_quantise(const long long* y, int M, int n_frames, int8_t* codes, uint8_t* exps,
                            int32_t* y32, hipStream_t st);
 // whole-frame recovery: products with the resident int8 Q, output, FP64 check
+// Plain FP32 recovery of a batch of up to kF32Batch GOPs of one shape
+// (k_fp32_mfma.hip): per GOP its operator (M_p x n FP32: A for l1, Phi for
+// TV), its dequantised y^ (nblk x M_p), lambda, step constant, and the
+// iterates s, v, gradient G (nblk x n) and residual R (nblk x M_p).
+constexpr int kF32Batch = 16;
+struct F32Job {
+    const float* op;
+    const float* y;
+    const float* lam;
+    const double* lip;
+    float* S;
+    float* V;
+    float* G;
+    float* R;
+    int nblk;
+};
+struct F32Batch {
+    F32Job j[kF32Batch];
+};
+// R = V A^T - y^ (rows m < M; zero for M <= m < M_p), on FP32 MFMA
+void launch_f32_forward(const F32Batch& bt, int ngop, int n, int M, int Mp, hipStream_t st);
+// G = R A, on FP32 MFMA
+void launch_f32_adjoint(const F32Batch& bt, int ngop, int n, int Mp, hipStream_t st);
+// soft threshold and momentum on (S, V) with G, per GOP
+void launch_f32_prox(const F32Batch& bt, int ngop, int n, const float* beta, int k,
+                     hipStream_t st);
+
 // A batch of up to kWholeBatch GOPs of one shape, each with its own Q
 // (passed by value as a kernel argument); x, y, r are [GOP][F][.] arrays.
 constexpr int kWholeBatch = 16;
@@ -243,7 +264,10 @@ void launch_whole_objective(const int8_t* q, const float* x, int F, int H, int W
 void launch_tv_dual(const float* x, float* nuh, float* nuv, float* wh, float* wv, float* ph,
                     float* pv, const float* lam, int nblk, int BH, int BW, hipStream_t st);
 void launch_tv_primal(float* x, const float* g, const float* ph, const float* pv,
-                      const float* lam, const double* lip, int nblk, int BH, int BW, hipStream_t st);
+                      const float* alpha, int nblk, int BH, int BW, hipStream_t st);
+// alpha[b] = 1 / (L + 8 beta(lam[b])) for count images of one operator (lip: its L)
+void launch_tv_alpha(const double* lip, const float* lam, int count, float* alpha,
+                     hipStream_t st);
 void launch_tv_final64(const int8_t* q, const float* x, const int8_t* codes, const uint8_t* exps,
                        const float* lam, int nblk, int M, int B, double s_phi, double* obj,
                        hipStream_t st);

@@ -1,8 +1,7 @@
 // Decoder-side kernels: operator setup (A = Phi Psi, FP64), step constant by
-// FP64 power iteration, dequantisation, the plain FP32 recovery passes
-// (forward product with residual epilogue, adjoint product, threshold and
-// momentum pass), synthesis onto the decoded key frame and the FP64 final
-// objective.
+// FP64 power iteration, dequantisation, the per-row maximum behind lambda,
+// synthesis onto the decoded key frame and the FP64 final objective.  The
+// plain FP32 recovery passes live in k_fp32_mfma.hip.
 #include "internal.h"
 #include "mfma.h"
 
@@ -218,121 +217,6 @@ void launch_dequant(const int8_t* codes, const uint8_t* exps, int nblk, int M, i
     CSV_HIP(hipGetLastError());
 }
 
-// ------------------------------------------------------ plain FP32 GEMMs
-// 64 x 64 output tile per workgroup, K in chunks of 16, 4 x 4 outputs per
-// thread.  Row bounds guarded (R arbitrary); N and K multiples of 16.
-constexpr int GT = 64, GK = 16;
-
-// C[r][c] = sum_k X[r][k] WT[c][k]  (- sub[r][c] when sub, for c < nvalid;
-// zero for c >= nvalid).
-__global__ __launch_bounds__(256) void gemm_nt_kernel(const float* __restrict__ X,
-                                                     const float* __restrict__ WT,
-                                                     float* __restrict__ C, int R, int N, int K,
-                                                     int ldx, int ldw, int ldc,
-                                                     const float* __restrict__ sub, int ldsub,
-                                                     int nvalid) {
-    __shared__ float As[GK][GT + 4];
-    __shared__ float Bs[GK][GT + 4];
-    const int tid = threadIdx.x;
-    const int r0 = blockIdx.y * GT, c0 = blockIdx.x * GT;
-    const int tr = (tid >> 4) * 4, tc = (tid & 15) * 4;
-    float acc[4][4] = {};
-    const int lr = tid >> 2, lk = (tid & 3) * 4;
-    for (int k0 = 0; k0 < K; k0 += GK) {
-        float4 xa = make_float4(0.f, 0.f, 0.f, 0.f), wb = xa;
-        if (r0 + lr < R) xa = *reinterpret_cast<const float4*>(X + (size_t)(r0 + lr) * ldx + k0 + lk);
-        if (c0 + lr < N) wb = *reinterpret_cast<const float4*>(WT + (size_t)(c0 + lr) * ldw + k0 + lk);
-        As[lk + 0][lr] = xa.x; As[lk + 1][lr] = xa.y; As[lk + 2][lr] = xa.z; As[lk + 3][lr] = xa.w;
-        Bs[lk + 0][lr] = wb.x; Bs[lk + 1][lr] = wb.y; Bs[lk + 2][lr] = wb.z; Bs[lk + 3][lr] = wb.w;
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < GK; ++k) {
-            const float4 a = *reinterpret_cast<const float4*>(&As[k][tr]);
-            const float4 b = *reinterpret_cast<const float4*>(&Bs[k][tc]);
-            const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(av[i], bv[j], acc[i][j]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = r0 + tr + i;
-        if (r >= R) continue;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int c = c0 + tc + j;
-            if (c >= N) continue;
-            float v = acc[i][j];
-            if (c >= nvalid) v = 0.f;
-            else if (sub) v -= sub[(size_t)r * ldsub + c];
-            C[(size_t)r * ldc + c] = v;
-        }
-    }
-}
-
-// C[r][c] = sum_k X[r][k] W[k][c].
-__global__ __launch_bounds__(256) void gemm_nn_kernel(const float* __restrict__ X,
-                                                     const float* __restrict__ W,
-                                                     float* __restrict__ C, int R, int N, int K,
-                                                     int ldx, int ldw, int ldc) {
-    __shared__ float As[GK][GT + 4];
-    __shared__ float Bs[GK][GT + 4];
-    const int tid = threadIdx.x;
-    const int r0 = blockIdx.y * GT, c0 = blockIdx.x * GT;
-    const int tr = (tid >> 4) * 4, tc = (tid & 15) * 4;
-    float acc[4][4] = {};
-    const int lr = tid >> 2, lk = (tid & 3) * 4;       // X tile: 64 rows x 16 k
-    const int wk = tid >> 4, wc = (tid & 15) * 4;      // W tile: 16 k x 64 cols
-    for (int k0 = 0; k0 < K; k0 += GK) {
-        float4 xa = make_float4(0.f, 0.f, 0.f, 0.f), wb = xa;
-        if (r0 + lr < R) xa = *reinterpret_cast<const float4*>(X + (size_t)(r0 + lr) * ldx + k0 + lk);
-        if (c0 + wc < N) wb = *reinterpret_cast<const float4*>(W + (size_t)(k0 + wk) * ldw + c0 + wc);
-        As[lk + 0][lr] = xa.x; As[lk + 1][lr] = xa.y; As[lk + 2][lr] = xa.z; As[lk + 3][lr] = xa.w;
-        *reinterpret_cast<float4*>(&Bs[wk][wc]) = wb;
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < GK; ++k) {
-            const float4 a = *reinterpret_cast<const float4*>(&As[k][tr]);
-            const float4 b = *reinterpret_cast<const float4*>(&Bs[k][tc]);
-            const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(av[i], bv[j], acc[i][j]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = r0 + tr + i;
-        if (r >= R) continue;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int c = c0 + tc + j;
-            if (c < N) C[(size_t)r * ldc + c] = acc[i][j];
-        }
-    }
-}
-
-void launch_gemm_nt(const float* X, const float* WT, float* C, int R, int N, int K, int ldx,
-                    int ldw, int ldc, const float* sub, int ldsub, int nvalid, hipStream_t st) {
-    if (R <= 0) return;
-    gemm_nt_kernel<<<dim3(ceil_div(N, GT), ceil_div(R, GT)), dim3(256), 0, st>>>(
-        X, WT, C, R, N, K, ldx, ldw, ldc, sub, ldsub, nvalid);
-    CSV_HIP(hipGetLastError());
-}
-
-void launch_gemm_nn(const float* X, const float* W, float* C, int R, int N, int K, int ldx,
-                    int ldw, int ldc, hipStream_t st) {
-    if (R <= 0) return;
-    gemm_nn_kernel<<<dim3(ceil_div(N, GT), ceil_div(R, GT)), dim3(256), 0, st>>>(X, W, C, R, N, K,
-                                                                                ldx, ldw, ldc);
-    CSV_HIP(hipGetLastError());
-}
-
 // out[r] = scale * max_c |X[r][c]|, one wave per row.
 __global__ __launch_bounds__(256) void row_absmax_kernel(const float* __restrict__ X, int R, int N,
                                                         int ld, float scale,
@@ -369,44 +253,15 @@ void launch_fill_f32(float* p, float v, size_t count, hipStream_t st) {
     CSV_HIP(hipGetLastError());
 }
 
-// Threshold and momentum pass of iteration k (0-based):
-//   u = v - g / L;  s_new = soft(u, lam_b / L);  v = s_new + beta_k (s_new - s)
-// with soft(u, t) = max(u - t, 0) + min(u + t, 0) (exactly 0 for |u| <= t).
-__global__ __launch_bounds__(256) void prox_kernel(float* __restrict__ s, float* __restrict__ v,
-                                                  const float* __restrict__ g,
-                                                  const float* __restrict__ lam,
-                                                  const double* __restrict__ lip,
-                                                  const float* __restrict__ beta, int k, int R,
-                                                  int n) {
-    const size_t i4 = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-    if (i4 >= (size_t)R * n) return;   // n % 4 == 0: a float4 never straddles rows
-    const int r = (int)(i4 / n);
-    const float inv_l = (float)(1.0 / lip[0]);
-    const float tau = lam[r] * inv_l;
-    const float bk = beta[k];
-    const float4 vv = *reinterpret_cast<const float4*>(v + i4);
-    const float4 gg = *reinterpret_cast<const float4*>(g + i4);
-    const float4 ss = *reinterpret_cast<const float4*>(s + i4);
-    const float vin[4] = {vv.x, vv.y, vv.z, vv.w}, gin[4] = {gg.x, gg.y, gg.z, gg.w};
-    const float sin_[4] = {ss.x, ss.y, ss.z, ss.w};
-    float so[4], vo[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const float u = fmaf(-gin[j], inv_l, vin[j]);
-        const float sn = fmaxf(u - tau, 0.f) + fminf(u + tau, 0.f);
-        so[j] = sn;
-        vo[j] = fmaf(bk, sn - sin_[j], sn);
-    }
-    *reinterpret_cast<float4*>(s + i4) = make_float4(so[0], so[1], so[2], so[3]);
-    *reinterpret_cast<float4*>(v + i4) = make_float4(vo[0], vo[1], vo[2], vo[3]);
+__global__ void copy_f32_kernel(float* __restrict__ dst, const float* __restrict__ src,
+                                size_t count) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = src[i];
 }
 
-void launch_prox(float* s, float* v, const float* g, const float* lam, const double* lip,
-                 const float* beta, int k, int R, int n, hipStream_t st) {
-    const size_t threads = (size_t)R * n / 4;
-    if (!threads) return;
-    prox_kernel<<<dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st>>>(s, v, g, lam, lip,
-                                                                              beta, k, R, n);
+void launch_copy_f32(float* dst, const float* src, size_t count, hipStream_t st) {
+    if (!count) return;
+    copy_f32_kernel<<<dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st>>>(dst, src, count);
     CSV_HIP(hipGetLastError());
 }
 

@@ -1,0 +1,197 @@
+// Plain FP32 recovery on the FP32 matrix cores: the two products of every
+// iteration (forward R = V A^T - y^, adjoint G = R A) as tiled GEMMs on
+// v_mfma_f32_32x32x2_f32 (FP32 products, FP32 accumulation), for a batch of
+// GOPs of one shape that share every launch (grid.z = GOP, each GOP's
+// operator and arrays passed by value), plus the batched threshold and
+// momentum pass.  The sums run in a fixed order: results depend only on the
+// shapes, and a GOP decodes identically alone or in a batch.
+#include "internal.h"
+#include "mfma.h"
+
+namespace csv {
+
+// Workgroup tile 128 x 128 of C, four waves in 2 x 2, each 64 x 64 (2 x 2
+// accumulator tiles of 32 x 32); K in chunks of 16 staged in LDS (X as
+// [k][row], B as [k][col], both padded by 4 floats per row), double
+// buffered, the next chunk's global loads in flight during the MFMAs.
+constexpr int kGM = 128, kGN = 128, kGK = 16, kGP = kGM + 4;
+
+// C = X B for GOP g = blockIdx.z, rows of X are blocks (b < nblk):
+//   FWD: X = V_g (nblk x K, K = n), B[k][c] = A_g[c][k] (c over Mp);
+//        C = R_g (nblk x Mp): acc - y^_g for c < M, 0 for M <= c < Mp.
+//   ADJ: X = R_g (nblk x K, K = Mp), B[k][c] = A_g[k][c] (c over n);
+//        C = G_g (nblk x n).
+template <bool FWD>
+__global__ __launch_bounds__(256) void f32_gemm_kernel(F32Batch bt, int N, int K, int M) {
+    const F32Job& jb = bt.j[blockIdx.z];
+    const int nblk = jb.nblk;
+    const int r0 = blockIdx.y * kGM, c0 = blockIdx.x * kGN;
+    if (r0 >= nblk) return;   // the whole workgroup: this GOP has fewer blocks
+    const float* __restrict__ X = FWD ? jb.V : jb.R;
+    const float* __restrict__ W = jb.op;   // Mp x n, row-major
+    const int ldw = FWD ? K : N;
+    __shared__ float Xs[2][kGK][kGP];
+    __shared__ float Bs[2][kGK][kGP];
+    const int tid = threadIdx.x, w = tid >> 6, ln = tid & 63;
+    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+
+    // per-thread staging: two float4 of X (rows e / 4, k (e % 4) 4) and two
+    // of B (FWD: cols e / 4, k (e % 4) 4; ADJ: k e / 32, cols (e % 32) 4)
+    float4 xr[2], br[2];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = tid + 256 * h;
+            const int row = e >> 2, kq = (e & 3) * 4;
+            xr[h] = r0 + row < nblk
+                        ? *reinterpret_cast<const float4*>(X + (size_t)(r0 + row) * K + k0 + kq)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (FWD) {
+                br[h] = c0 + row < N
+                            ? *reinterpret_cast<const float4*>(W + (size_t)(c0 + row) * ldw + k0 + kq)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+            } else {
+                const int kr = e >> 5, cq = (e & 31) * 4;
+                br[h] = c0 + cq < N
+                            ? *reinterpret_cast<const float4*>(W + (size_t)(k0 + kr) * ldw + c0 + cq)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = tid + 256 * h;
+            const int row = e >> 2, kq = (e & 3) * 4;
+            Xs[buf][kq + 0][row] = xr[h].x;
+            Xs[buf][kq + 1][row] = xr[h].y;
+            Xs[buf][kq + 2][row] = xr[h].z;
+            Xs[buf][kq + 3][row] = xr[h].w;
+            if (FWD) {
+                Bs[buf][kq + 0][row] = br[h].x;
+                Bs[buf][kq + 1][row] = br[h].y;
+                Bs[buf][kq + 2][row] = br[h].z;
+                Bs[buf][kq + 3][row] = br[h].w;
+            } else {
+                const int kr = e >> 5, cq = (e & 31) * 4;
+                *reinterpret_cast<float4*>(&Bs[buf][kr][cq]) = br[h];
+            }
+        }
+    };
+
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx16{};
+    const int kh = ln >> 5, lc = ln & 31;
+    load(0);
+    store(0);
+    __syncthreads();
+    const int nch = K / kGK;
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nch) load((ch + 1) * kGK);   // in flight during this chunk's MFMAs
+#pragma unroll
+        for (int ks = 0; ks < kGK / 2; ++ks) {
+            const int kk = 2 * ks + kh;
+            const float a0 = Xs[buf][kk][wr + lc], a1 = Xs[buf][kk][wr + 32 + lc];
+            const float b0 = Bs[buf][kk][wc + lc], b1 = Bs[buf][kk][wc + 32 + lc];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        if (ch + 1 < nch) store(buf ^ 1);   // the other buffer: last read before the
+        __syncthreads();                    // previous barrier
+    }
+    // accumulator (lane l, register r) = C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]
+    float* __restrict__ C = FWD ? jb.R : jb.G;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = r0 + wr + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
+                const int col = c0 + wc + 32 * j + lc;
+                if (row < nblk && col < N) {
+                    float v = acc[i][j][r];
+                    if (FWD) v = col < M ? v - jb.y[(size_t)row * N + col] : 0.f;
+                    C[(size_t)row * N + col] = v;
+                }
+            }
+}
+
+// u = v - g / L; s_k = soft(u, lam / L); v = s_k + beta_k (s_k - s_{k-1}),
+// four coefficients per thread; grid (ceil(max nblk n / 1024), GOPs).
+__global__ __launch_bounds__(256) void f32_prox_kernel(F32Batch bt, int n,
+                                                      const float* __restrict__ beta, int k) {
+    const F32Job& jb = bt.j[blockIdx.y];
+    const size_t i4 = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i4 >= (size_t)jb.nblk * n) return;   // n % 4 == 0: a float4 never straddles rows
+    const int r = (int)(i4 / n);
+    const float inv_l = (float)(1.0 / jb.lip[0]);
+    const float tau = jb.lam[r] * inv_l;
+    const float bk = beta[k];
+    const float4 vv = *reinterpret_cast<const float4*>(jb.V + i4);
+    const float4 gg = *reinterpret_cast<const float4*>(jb.G + i4);
+    const float4 ss = *reinterpret_cast<const float4*>(jb.S + i4);
+    const float vin[4] = {vv.x, vv.y, vv.z, vv.w}, gin[4] = {gg.x, gg.y, gg.z, gg.w};
+    const float sin_[4] = {ss.x, ss.y, ss.z, ss.w};
+    float so[4], vo[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float u = fmaf(-gin[j], inv_l, vin[j]);
+        const float sn = fmaxf(u - tau, 0.f) + fminf(u + tau, 0.f);
+        so[j] = sn;
+        vo[j] = fmaf(bk, sn - sin_[j], sn);
+    }
+    *reinterpret_cast<float4*>(jb.S + i4) = make_float4(so[0], so[1], so[2], so[3]);
+    *reinterpret_cast<float4*>(jb.V + i4) = make_float4(vo[0], vo[1], vo[2], vo[3]);
+}
+
+static void check_batch(const F32Batch& bt, int ngop, int n, int Mp) {
+    CSV_REQUIRE(ngop >= 1 && ngop <= kF32Batch, CSV_EINVAL, "FP32 batch size");
+    CSV_REQUIRE(n % kGK == 0 && Mp % kGK == 0 && n % 4 == 0, CSV_EUNSUPPORTED,
+                "FP32 product shape");
+    for (int g = 0; g < ngop; ++g)
+        CSV_REQUIRE(bt.j[g].nblk >= 0, CSV_EINVAL, "negative block count");
+}
+
+static int max_rows(const F32Batch& bt, int ngop) {
+    int m = 0;
+    for (int g = 0; g < ngop; ++g) m = std::max(m, bt.j[g].nblk);
+    return m;
+}
+
+void launch_f32_forward(const F32Batch& bt, int ngop, int n, int M, int Mp, hipStream_t st) {
+    check_batch(bt, ngop, n, Mp);
+    const int rows = max_rows(bt, ngop);
+    if (!rows) return;
+    f32_gemm_kernel<true><<<dim3(ceil_div(Mp, kGN), ceil_div(rows, kGM), ngop), dim3(256), 0,
+                            st>>>(bt, Mp, n, M);
+    CSV_HIP(hipGetLastError());
+}
+
+void launch_f32_adjoint(const F32Batch& bt, int ngop, int n, int Mp, hipStream_t st) {
+    check_batch(bt, ngop, n, Mp);
+    const int rows = max_rows(bt, ngop);
+    if (!rows) return;
+    f32_gemm_kernel<false><<<dim3(ceil_div(n, kGN), ceil_div(rows, kGM), ngop), dim3(256), 0,
+                             st>>>(bt, n, Mp, Mp);
+    CSV_HIP(hipGetLastError());
+}
+
+void launch_f32_prox(const F32Batch& bt, int ngop, int n, const float* beta, int k,
+                     hipStream_t st) {
+    check_batch(bt, ngop, n, 16);
+    const int rows = max_rows(bt, ngop);
+    if (!rows) return;
+    const size_t threads = (size_t)rows * n / 4;
+    f32_prox_kernel<<<dim3((unsigned)((threads + 255) / 256), ngop), dim3(256), 0, st>>>(bt, n,
+                                                                                       beta, k);
+    CSV_HIP(hipGetLastError());
+}
+
+}  // namespace csv

@@ -35,13 +35,12 @@ __global__ __launch_bounds__(256) void tv_dual_kernel(const float* __restrict__ 
     tv_dual_at(x + (size_t)b * n, k, i, j, BH, BW, idx, lam[b], nuh, nuv, wh, wv, ph, pv);
 }
 
-// x <- x - alpha (g + D^T p), one thread per pixel.
+// x <- x - alpha_b (g + D^T p), one thread per pixel (alpha per image).
 __global__ __launch_bounds__(256) void tv_primal_kernel(float* __restrict__ x,
                                                         const float* __restrict__ g,
                                                         const float* __restrict__ ph,
                                                         const float* __restrict__ pv,
-                                                        const float* __restrict__ lam,
-                                                        const double* __restrict__ lip, int nblk,
+                                                        const float* __restrict__ alpha, int nblk,
                                                         int BH, int BW) {
     const int n = BH * BW;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -49,8 +48,14 @@ __global__ __launch_bounds__(256) void tv_primal_kernel(float* __restrict__ x,
     const int b = (int)(idx / n), k = (int)(idx - (size_t)b * n);
     const int i = k / BW, j = k - i * BW;
     const float dt = tv_dtp_at(ph + (size_t)b * n, pv + (size_t)b * n, k, i, j, BH, BW);
-    const float alpha = tv_alpha(lip[0], tv_beta(lam[b]));
-    x[idx] -= alpha * (g[idx] + dt);
+    x[idx] -= alpha[b] * (g[idx] + dt);
+}
+
+// alpha_b = 1 / (L + 8 beta(lam_b)) for the images of one operator.
+__global__ void tv_alpha_kernel(const double* __restrict__ lip, const float* __restrict__ lam,
+                                int count, float* __restrict__ alpha) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < count) alpha[b] = tv_alpha(lip[0], tv_beta(lam[b]));
 }
 
 // FP64 check per block (one workgroup): r = s_Phi Q x - y^ with y^ =
@@ -115,11 +120,18 @@ void launch_tv_dual(const float* x, float* nuh, float* nuv, float* wh, float* wv
 }
 
 void launch_tv_primal(float* x, const float* g, const float* ph, const float* pv,
-                      const float* lam, const double* lip, int nblk, int BH, int BW, hipStream_t st) {
+                      const float* alpha, int nblk, int BH, int BW, hipStream_t st) {
     const size_t t = (size_t)nblk * BH * BW;
     if (!t) return;
-    tv_primal_kernel<<<dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st>>>(x, g, ph, pv, lam,
-                                                                             lip, nblk, BH, BW);
+    tv_primal_kernel<<<dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st>>>(x, g, ph, pv, alpha,
+                                                                             nblk, BH, BW);
+    CSV_HIP(hipGetLastError());
+}
+
+void launch_tv_alpha(const double* lip, const float* lam, int count, float* alpha,
+                     hipStream_t st) {
+    if (count <= 0) return;
+    tv_alpha_kernel<<<dim3(ceil_div(count, 256)), dim3(256), 0, st>>>(lip, lam, count, alpha);
     CSV_HIP(hipGetLastError());
 }
 
