@@ -381,6 +381,10 @@ static void fista_fp32(Ctx* c, const Shape& s, const std::vector<F32Item>& its, 
     }
 }
 
+static void ensure_aux(Ctx* c);
+static void fork_aux(Ctx* c, hipStream_t st);
+static void join_aux(Ctx* c, hipStream_t st);
+
 // One recovery job of the fused path: nblk blocks of one operator.
 struct FusedJob {
     const Shape* s;
@@ -493,19 +497,35 @@ static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st
     }
     CSV_HIP(hipMemcpyAsync(dev, host, off_i, hipMemcpyHostToDevice, st));
     if (!c->capturing) CSV_HIP(hipEventRecord(c->stage_done, st));
-    for (const Launch& L : launches) {
+    // several classes run side by side: largest first, round-robin over st
+    // and the auxiliary streams, so small classes fill the CUs that a large
+    // class leaves idle (each class has its own queues; no workgroup waits
+    // for another)
+    std::sort(launches.begin(), launches.end(), [](const Launch& a, const Launch& b) {
+        return (double)a.count * a.n * a.Mp > (double)b.count * b.n * b.Mp;
+    });
+    const bool spread = launches.size() > 1;
+    if (spread) {
+        ensure_aux(c);
+        fork_aux(c, st);
+    }
+    for (size_t k = 0; k < launches.size(); ++k) {
+        const Launch& L = launches[k];
+        const int lane = (int)(k % (Ctx::kAux + 1));
+        const hipStream_t ls = lane == 0 ? st : c->aux[lane - 1];
         const auto* tiles = reinterpret_cast<const FusedTile*>(dev + L.tiles_off);
         const auto* qoff = reinterpret_cast<const int*>(dev + L.qoff_off);
         const auto* queue = reinterpret_cast<const int*>(dev + L.queue_off);
         auto* ctr = reinterpret_cast<int*>(dev + L.ctr_off);
         if (L.tv) {
-            ProfScope ps(c, "tv_bf16", st);
-            launch_tv_bf16_class(L.n, L.Mp, tiles, qoff, queue, ctr, L.count, device_cus(), st);
+            ProfScope ps(c, "tv_bf16", ls);
+            launch_tv_bf16_class(L.n, L.Mp, tiles, qoff, queue, ctr, L.count, device_cus(), ls);
         } else {
-            ProfScope ps(c, "fista_bf16", st);
-            launch_fista_bf16_class(L.n, L.Mp, tiles, qoff, queue, ctr, L.count, st, variant);
+            ProfScope ps(c, "fista_bf16", ls);
+            launch_fista_bf16_class(L.n, L.Mp, tiles, qoff, queue, ctr, L.count, ls, variant);
         }
     }
+    if (spread) join_aux(c, st);
 }
 
 // Time one fused launch over nblk blocks with kernel variant `variant`
@@ -773,12 +793,12 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
                  uint8_t* const* frames_out, float* const* cs_float_out, double* const* obj_out,
                  hipStream_t st) {
     struct Item {
-        Operator* op;
+        Operator* op = nullptr;
         bool whole = false;
-        int nblk;
-        float* S;
-        float* lam;
-        const float* y;
+        int nblk = 0;
+        float* S = nullptr;
+        float* lam = nullptr;
+        const float* y = nullptr;
     };
     std::vector<Item> items(count);
     for (int i = 0; i < count; ++i) {
@@ -838,7 +858,9 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
         const Shape& s = shapes[i];
         if (!items[i].nblk) continue;
         const std::string tag = "#" + std::to_string(i);
-        items[i].S = static_cast<float*>(scratch(c, "S" + tag, (size_t)items[i].nblk * s.n * 4));
+        // FP32 TV GOPs get rows of their batch's stacked image buffer later
+        if (!(s.precision == CSV_FP32 && (s.flags & CSV_FLAG_TV)))
+            items[i].S = static_cast<float*>(scratch(c, "S" + tag, (size_t)items[i].nblk * s.n * 4));
         items[i].lam = static_cast<float*>(scratch(c, "lam" + tag, (size_t)items[i].nblk * 4));
         scratch(c, "yhat" + tag, (size_t)items[i].nblk * s.Mp * 4);
         scratch(c, g0_of(i), (size_t)items[i].nblk * s.n * 4);
