@@ -68,7 +68,10 @@ int csv_server_destroy(csv_server* srv);
 
 /* Register a stream: validates p (precision is taken from the server),
  * builds its operator (measurement matrix, A, step constant) synchronously
- * and returns its id. */
+ * and returns its id.  CSV_EUNSUPPORTED when the server's precision has no
+ * recovery for the stream: a BF16 server needs a fused kernel for its block
+ * size and M (for CSV_FLAG_TV: 16 x 16 blocks, M up to 128); whole-frame
+ * streams (CSV_FLAG_WHOLE_FRAME) need an FP32 server and CSV_FLAG_TV. */
 int csv_server_register_stream(csv_server* srv, const csv_params* p, uint32_t* sid);
 
 /* Submit one GOP of stream sid.  t_arrival: csv_clock() seconds (<= 0:

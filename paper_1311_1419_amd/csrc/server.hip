@@ -441,9 +441,14 @@ int csv_server_register_stream(csv_server* srv, const csv_params* p, uint32_t* s
         si.p.precision = s.o.precision;
         si.s = resolve(&si.p);
         CSV_REQUIRE(si.s.G >= 2, CSV_EINVAL, "a served stream needs CS frames (gop >= 2)");
-        if (s.o.precision == CSV_BF16)
-            CSV_REQUIRE(fused_class_supported(si.s.n, si.s.Mp), CSV_EUNSUPPORTED,
-                        "no fused kernel for this block size and M");
+        const bool tv = (si.s.flags & CSV_FLAG_TV) != 0;
+        if (si.s.flags & CSV_FLAG_WHOLE_FRAME)
+            CSV_REQUIRE(tv && s.o.precision == CSV_FP32, CSV_EUNSUPPORTED,
+                        "whole-frame streams are served in FP32 with CSV_FLAG_TV");
+        else if (s.o.precision == CSV_BF16)
+            CSV_REQUIRE(tv ? tv_class_supported(si.s.n, si.s.Mp)
+                           : fused_class_supported(si.s.n, si.s.Mp),
+                        CSV_EUNSUPPORTED, "no fused kernel for this block size and M");
         s.ex->prepare(si);   // operator setup outside the server lock
         std::lock_guard<std::mutex> lk(s.mu);
         s.streams.push_back(si);

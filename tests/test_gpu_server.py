@@ -1,7 +1,8 @@
 """The serving loop on the GPU: every request decoded inside a mixed,
 continuously batched stream of requests equals the same GOP decoded alone
 (fused BF16 path; tiles never mix GOPs, so the results are bit-identical),
-and a Poisson arrival run completes every request with latency stats."""
+the same for an FP32 server with TV and whole-frame streams, and a Poisson
+arrival run completes every request with latency stats."""
 import time
 
 import numpy as np
@@ -81,3 +82,46 @@ def test_poisson_load_completes(ctx):
         st = srv.stats()
         assert st["completed"] == 60 and st["p99_ms"] >= st["p50_ms"] > 0
         assert st["mpix_per_s"] > 0
+
+
+def test_served_fp32_tv_and_whole_frame_streams(ctx):
+    """An FP32 server mixing block l1, block TV and whole-frame TV streams:
+    every served GOP equals the same GOP decoded alone; a BF16 server
+    refuses the streams it has no kernel for at registration."""
+    import paper_1311_1419_amd as P
+    announce("server: FP32 TV and whole-frame streams")
+    base = sv.qcif_tiny().with_(gop=3, iters=60)
+    kinds = [dict(flags=0), dict(flags=P.CSV_FLAG_TV),
+             dict(flags=P.CSV_FLAG_TV | P.CSV_FLAG_WHOLE_FRAME, m=400)]
+    items = []
+    for k, kw in enumerate(kinds):
+        spec = base.with_(stream_id=40 + k)
+        p = P.Params.from_spec(spec, precision=P.CSV_FP32, **kw)
+        gs = ctx.encode_gop(dev(spec.video()), p)
+        items.append((p, gs, host(ctx.decode_gop(gs, p)[0])))
+    torch.cuda.synchronize()
+    with P.Server(0, hip_streams=2, precision=P.CSV_FP32) as srv:
+        sids = [srv.register_stream(p) for p, _, _ in items]
+        tickets = [(i, srv.submit(sids[i], gs, P.clock())) for rep in range(2)
+                   for i, (p, gs, _) in enumerate(items)]
+        outs = {}
+        deadline = time.time() + 60
+        while len(outs) < len(tickets) and time.time() < deadline:
+            for i, t in tickets:
+                if t in outs:
+                    continue
+                p = items[i][0]
+                buf = torch.empty((p.gop, p.height, p.width), dtype=torch.uint8, device="cuda")
+                if srv.poll(t, buf):
+                    outs[t] = (i, buf)
+            time.sleep(0.001)
+        assert len(outs) == len(tickets)
+        for t, (i, buf) in outs.items():
+            assert np.array_equal(host(buf), items[i][2]), f"request {t} of stream {i}"
+        assert srv.stats()["failed"] == 0
+    with P.Server(0, hip_streams=2) as srv:   # BF16
+        for kw in (dict(flags=P.CSV_FLAG_TV | P.CSV_FLAG_WHOLE_FRAME, m=400),
+                   dict(flags=P.CSV_FLAG_TV, block=32, m=102)):
+            with pytest.raises(P.CsvError) as ei:
+                srv.register_stream(P.Params.from_spec(base, **kw))
+            assert ei.value.code == P._native.CSV_EUNSUPPORTED
