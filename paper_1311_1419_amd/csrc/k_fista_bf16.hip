@@ -363,7 +363,7 @@ static std::vector<ClassEntry>& class_table() {
         {1024, 128, {CSV_V(1024, 128, 1, 8, 4, 2, 2, 1), CSV_V(1024, 128, 1, 8, 4, 2, 0, 1)}, 0},
         {1024, 224, {CSV_V(1024, 224, 1, 8, 4, 2, 2, 1), CSV_V(1024, 224, 1, 8, 4, 2, 0, 1)}, 0},
         {1024, 256,
-         {CSV_V(1024, 256, 1, 8, 4, 2, 2, 1), CSV_V(1024, 256, 1, 8, 4, 2, 0, 1),
+         {CSV_V(1024, 256, 1, 8, 4, 2, 0, 1), CSV_V(1024, 256, 1, 8, 4, 2, 2, 1),
           CSV_V(1024, 256, 1, 8, 8, 2, 2, 1), CSV_V(1024, 256, 1, 8, 4, 2, 1, 1)},
          0},
         {1024, 416,
