@@ -351,17 +351,17 @@ static std::vector<ClassEntry>& class_table() {
           CSV_V(256, 64, 2, 8, 4, 2, 0, 1), CSV_V(256, 64, 4, 8, 4, 2, 0, 1)},
          0},
         {256, 96,
-         {CSV_V(256, 96, 2, 8, 4, 2, 0, 1), CSV_V(256, 96, 4, 8, 4, 2, 0, 1),
-          CSV_V(256, 96, 2, 4, 2, 2, 0, 2), CSV_V(256, 96, 1, 4, 2, 2, 0, 3)},
+         {CSV_V(256, 96, 2, 4, 2, 2, 0, 2), CSV_V(256, 96, 4, 8, 4, 2, 0, 1),
+          CSV_V(256, 96, 2, 8, 4, 2, 0, 1), CSV_V(256, 96, 1, 4, 2, 2, 0, 3)},
          0},
         {256, 128,
          {CSV_V(256, 128, 2, 4, 2, 2, 0, 2), CSV_V(256, 128, 1, 4, 2, 2, 0, 3),
           CSV_V(256, 128, 2, 8, 4, 2, 0, 1), CSV_V(256, 128, 4, 8, 4, 2, 0, 1)},
          0},
-        {1024, 32, {CSV_V(1024, 32, 1, 8, 4, 2, 2, 1), CSV_V(1024, 32, 1, 8, 4, 2, 0, 1)}, 0},
-        {1024, 64, {CSV_V(1024, 64, 1, 8, 4, 2, 2, 1), CSV_V(1024, 64, 1, 8, 4, 2, 0, 1)}, 0},
-        {1024, 128, {CSV_V(1024, 128, 1, 8, 4, 2, 2, 1), CSV_V(1024, 128, 1, 8, 4, 2, 0, 1)}, 0},
-        {1024, 224, {CSV_V(1024, 224, 1, 8, 4, 2, 2, 1), CSV_V(1024, 224, 1, 8, 4, 2, 0, 1)}, 0},
+        {1024, 32, {CSV_V(1024, 32, 1, 8, 4, 2, 0, 1), CSV_V(1024, 32, 1, 8, 4, 2, 2, 1)}, 0},
+        {1024, 64, {CSV_V(1024, 64, 1, 8, 4, 2, 0, 1), CSV_V(1024, 64, 1, 8, 4, 2, 2, 1)}, 0},
+        {1024, 128, {CSV_V(1024, 128, 1, 8, 4, 2, 0, 1), CSV_V(1024, 128, 1, 8, 4, 2, 2, 1)}, 0},
+        {1024, 224, {CSV_V(1024, 224, 1, 8, 4, 2, 0, 1), CSV_V(1024, 224, 1, 8, 4, 2, 2, 1)}, 0},
         {1024, 256,
          {CSV_V(1024, 256, 1, 8, 4, 2, 0, 1), CSV_V(1024, 256, 1, 8, 4, 2, 2, 1),
           CSV_V(1024, 256, 1, 8, 8, 2, 2, 1), CSV_V(1024, 256, 1, 8, 4, 2, 1, 1)},
