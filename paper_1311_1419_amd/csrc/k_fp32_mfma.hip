@@ -10,34 +10,38 @@
 
 namespace csv {
 
-// Workgroup tile 128 x 128 of C, four waves in 2 x 2, each 64 x 64 (2 x 2
-// accumulator tiles of 32 x 32); K in chunks of 16 staged in LDS (X as
-// [k][row], B as [k][col], both padded by 4 floats per row), double
-// buffered, the next chunk's global loads in flight during the MFMAs.
-constexpr int kGM = 128, kGN = 128, kGK = 16, kGP = kGM + 4;
+// Workgroup tile 128 x TN of C (TN = 128, or 64 for narrow outputs), four
+// waves in 2 x 2, each 64 x TN/2 (2 x TN/64 accumulator tiles of 32 x 32);
+// K in chunks of 16 staged in LDS (X as [k][row], B as [k][col], both padded
+// by 4 floats per row), double buffered, the next chunk's global loads in
+// flight during the MFMAs.
+constexpr int kGM = 128, kGK = 16, kGP = kGM + 4;
 
 // C = X B for GOP g = blockIdx.z, rows of X are blocks (b < nblk):
 //   FWD: X = V_g (nblk x K, K = n), B[k][c] = A_g[c][k] (c over Mp);
 //        C = R_g (nblk x Mp): acc - y^_g for c < M, 0 for M <= c < Mp.
 //   ADJ: X = R_g (nblk x K, K = Mp), B[k][c] = A_g[k][c] (c over n);
 //        C = G_g (nblk x n).
-template <bool FWD>
+template <bool FWD, int TN>
 __global__ __launch_bounds__(256) void f32_gemm_kernel(F32Batch bt, int N, int K, int M) {
+    constexpr int NJ = TN / 64;     // accumulator tiles per wave along the columns
+    constexpr int NB = TN / 64;     // float4 of B staged per thread per chunk
     const F32Job& jb = bt.j[blockIdx.z];
     const int nblk = jb.nblk;
-    const int r0 = blockIdx.y * kGM, c0 = blockIdx.x * kGN;
+    const int r0 = blockIdx.y * kGM, c0 = blockIdx.x * TN;
     if (r0 >= nblk) return;   // the whole workgroup: this GOP has fewer blocks
     const float* __restrict__ X = FWD ? jb.V : jb.R;
     const float* __restrict__ W = jb.op;   // Mp x n, row-major
     const int ldw = FWD ? K : N;
     __shared__ float Xs[2][kGK][kGP];
-    __shared__ float Bs[2][kGK][kGP];
+    __shared__ float Bs[2][kGK][TN + 4];
     const int tid = threadIdx.x, w = tid >> 6, ln = tid & 63;
-    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+    const int wr = (w >> 1) * 64, wc = (w & 1) * (TN / 2);
 
-    // per-thread staging: two float4 of X (rows e / 4, k (e % 4) 4) and two
-    // of B (FWD: cols e / 4, k (e % 4) 4; ADJ: k e / 32, cols (e % 32) 4)
-    float4 xr[2], br[2];
+    // per-thread staging: two float4 of X (rows e / 4, k (e % 4) 4) and NB
+    // of B (FWD: cols e / 4, k (e % 4) 4; ADJ: k e / (TN / 4), cols
+    // (e % (TN / 4)) 4)
+    float4 xr[2], br[NB];
     auto load = [&](int k0) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -46,15 +50,20 @@ __global__ __launch_bounds__(256) void f32_gemm_kernel(F32Batch bt, int N, int K
             xr[h] = r0 + row < nblk
                         ? *reinterpret_cast<const float4*>(X + (size_t)(r0 + row) * K + k0 + kq)
                         : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int h = 0; h < NB; ++h) {
+            const int e = tid + 256 * h;
             if (FWD) {
-                br[h] = c0 + row < N
-                            ? *reinterpret_cast<const float4*>(W + (size_t)(c0 + row) * ldw + k0 + kq)
-                            : make_float4(0.f, 0.f, 0.f, 0.f);
+                const int col = e >> 2, kq = (e & 3) * 4;
+                const float* src = W + (size_t)(c0 + col) * ldw + k0 + kq;
+                br[h] = c0 + col < N ? *reinterpret_cast<const float4*>(src)
+                                     : make_float4(0.f, 0.f, 0.f, 0.f);
             } else {
-                const int kr = e >> 5, cq = (e & 31) * 4;
-                br[h] = c0 + cq < N
-                            ? *reinterpret_cast<const float4*>(W + (size_t)(k0 + kr) * ldw + c0 + cq)
-                            : make_float4(0.f, 0.f, 0.f, 0.f);
+                const int kr = e / (TN / 4), cq = (e % (TN / 4)) * 4;
+                const float* src = W + (size_t)(k0 + kr) * ldw + c0 + cq;
+                br[h] = c0 + cq < N ? *reinterpret_cast<const float4*>(src)
+                                    : make_float4(0.f, 0.f, 0.f, 0.f);
             }
         }
     };
@@ -67,23 +76,28 @@ __global__ __launch_bounds__(256) void f32_gemm_kernel(F32Batch bt, int N, int K
             Xs[buf][kq + 1][row] = xr[h].y;
             Xs[buf][kq + 2][row] = xr[h].z;
             Xs[buf][kq + 3][row] = xr[h].w;
+        }
+#pragma unroll
+        for (int h = 0; h < NB; ++h) {
+            const int e = tid + 256 * h;
             if (FWD) {
-                Bs[buf][kq + 0][row] = br[h].x;
-                Bs[buf][kq + 1][row] = br[h].y;
-                Bs[buf][kq + 2][row] = br[h].z;
-                Bs[buf][kq + 3][row] = br[h].w;
+                const int col = e >> 2, kq = (e & 3) * 4;
+                Bs[buf][kq + 0][col] = br[h].x;
+                Bs[buf][kq + 1][col] = br[h].y;
+                Bs[buf][kq + 2][col] = br[h].z;
+                Bs[buf][kq + 3][col] = br[h].w;
             } else {
-                const int kr = e >> 5, cq = (e & 31) * 4;
+                const int kr = e / (TN / 4), cq = (e % (TN / 4)) * 4;
                 *reinterpret_cast<float4*>(&Bs[buf][kr][cq]) = br[h];
             }
         }
     };
 
-    floatx16 acc[2][2];
+    floatx16 acc[2][NJ];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = floatx16{};
+        for (int j = 0; j < NJ; ++j) acc[i][j] = floatx16{};
     const int kh = ln >> 5, lc = ln & 31;
     load(0);
     store(0);
@@ -96,11 +110,12 @@ __global__ __launch_bounds__(256) void f32_gemm_kernel(F32Batch bt, int N, int K
         for (int ks = 0; ks < kGK / 2; ++ks) {
             const int kk = 2 * ks + kh;
             const float a0 = Xs[buf][kk][wr + lc], a1 = Xs[buf][kk][wr + 32 + lc];
-            const float b0 = Bs[buf][kk][wc + lc], b1 = Bs[buf][kk][wc + 32 + lc];
-            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const float b = Bs[buf][kk][wc + 32 * j + lc];
+                acc[0][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b, acc[0][j], 0, 0, 0);
+                acc[1][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b, acc[1][j], 0, 0, 0);
+            }
         }
         if (ch + 1 < nch) store(buf ^ 1);   // the other buffer: last read before the
         __syncthreads();                    // previous barrier
@@ -110,7 +125,7 @@ __global__ __launch_bounds__(256) void f32_gemm_kernel(F32Batch bt, int N, int K
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NJ; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = r0 + wr + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
@@ -169,8 +184,12 @@ void launch_f32_forward(const F32Batch& bt, int ngop, int n, int M, int Mp, hipS
     check_batch(bt, ngop, n, Mp);
     const int rows = max_rows(bt, ngop);
     if (!rows) return;
-    f32_gemm_kernel<true><<<dim3(ceil_div(Mp, kGN), ceil_div(rows, kGM), ngop), dim3(256), 0,
-                            st>>>(bt, Mp, n, M);
+    if (Mp <= 64)
+        f32_gemm_kernel<true, 64><<<dim3(ceil_div(Mp, 64), ceil_div(rows, kGM), ngop), dim3(256), 0,
+                                    st>>>(bt, Mp, n, M);
+    else
+        f32_gemm_kernel<true, 128><<<dim3(ceil_div(Mp, 128), ceil_div(rows, kGM), ngop), dim3(256),
+                                     0, st>>>(bt, Mp, n, M);
     CSV_HIP(hipGetLastError());
 }
 
@@ -178,8 +197,8 @@ void launch_f32_adjoint(const F32Batch& bt, int ngop, int n, int Mp, hipStream_t
     check_batch(bt, ngop, n, Mp);
     const int rows = max_rows(bt, ngop);
     if (!rows) return;
-    f32_gemm_kernel<false><<<dim3(ceil_div(n, kGN), ceil_div(rows, kGM), ngop), dim3(256), 0,
-                             st>>>(bt, n, Mp, Mp);
+    f32_gemm_kernel<false, 128><<<dim3(ceil_div(n, 128), ceil_div(rows, kGM), ngop), dim3(256), 0,
+                                  st>>>(bt, n, Mp, Mp);
     CSV_HIP(hipGetLastError());
 }
 
