@@ -148,3 +148,42 @@ def test_decode_of_fp8_measured_gop(ctx, spec):
         assert np.max(np.abs(fl8[t - 1].astype(np.float64) - ref8.cs_float[t - 1])) <= MAXABS_TOL
         assert abs(psnr(frames[t], out8[t]) - psnr(frames[t], ref8.frames[t])) <= PSNR_TOL
         assert abs(psnr(frames[t], out8[t]) - psnr(frames[t], out[t])) <= 0.25
+
+
+def test_mixed64_batch_sampled_blocks(ctx):
+    """The 64-stream mixed workload (176x144 / 352x288 / 640x480, GOP 4-32,
+    B 16/32, M/n 0.05-0.4: seven fused classes running side by side) decoded
+    as one batch; for one stream of every (B, M) pair the oracle recovers
+    three sampled blocks one by one and the GPU's pixels must agree."""
+    announce("bf16 mixed 64-stream batch, sampled blocks")
+    specs = sv.mixed_streams(64)
+    params = [_bf16(s) for s in specs]
+    videos = [s.video() for s in specs]
+    gss = [ctx.encode_gop(dev(v), p) for v, p in zip(videos, params)]
+    outs = ctx.decode_batch(list(zip(gss, params)), want_float=True)
+    first = {}
+    for i, s in enumerate(specs):
+        first.setdefault((s.block, s.m), i)
+    rng = np.random.default_rng(64)
+    for (bsz, m), i in sorted(first.items()):
+        s = specs[i]
+        fl = host(outs[i][1])
+        key = host(outs[i][0])[0].astype(np.float64)
+        codes, exps = host(gss[i].codes), host(gss[i].exps)
+        q = philox.measurement_matrix_q(m, s.n, s.phi_seed, s.stream_id)
+        s_phi = philox.phi_scale(m)
+        a = cs.operator(q, s_phi, bsz)
+        L, _, _ = cs.lipschitz(q, s_phi)
+        nbx = (s.width + bsz - 1) // bsz
+        nb = codes.shape[1]
+        for _ in range(3):
+            t, b = int(rng.integers(0, s.gop - 1)), int(rng.integers(0, nb))
+            y = cs.dequantise(codes[t, b][:, None], exps[t, b:b + 1], s_phi)
+            lam = cs.lambdas(a, y)
+            x = cs.synthesise(cs.fista(a, y, lam, L, s.iters), bsz)[:, 0].reshape(bsz, bsz)
+            by, bx = divmod(b, nbx)
+            hh = min(bsz, s.height - by * bsz)
+            ww = min(bsz, s.width - bx * bsz)
+            sl = (slice(by * bsz, by * bsz + hh), slice(bx * bsz, bx * bsz + ww))
+            ref = key[sl] + x[:hh, :ww]
+            assert np.max(np.abs(fl[t][sl] - ref)) <= MAXABS_TOL, (i, t, b)
