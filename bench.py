@@ -18,6 +18,7 @@ from __future__ import annotations
 import argparse
 import collections
 import json
+import re
 import os
 import sys
 import time
@@ -28,7 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "recovered Mpixel/s at M/n=0.25, BF16-MFMA vs FP32, ≤0.1dB PSNR loss; p99 ms"
-KERNEL_SRC = os.path.join(ROOT, "paper_1311_1419_amd", "csrc", "k_fista_bf16.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_1311_1419_amd", "csrc", f)
+              for f in ("k_fista_bf16.hip", "fused_common.h")]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "fista_bf16_vga640x480_m256_x16_pmc.md")
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
 WORKLOAD = "vga640x480-g16-b32-m256-t300-x16streams"
@@ -115,7 +117,7 @@ def measured_traffic(streams):
     txt = open(PMC_SUMMARY).read()
     sha = re.search(r"kernel_source_sha256: (\w+)", txt)
     tb = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
-    cur = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    cur = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SRC)).hexdigest()
     if not sha or not tb or sha.group(1) != cur:
         return None
     return int(tb.group(1))
@@ -611,11 +613,17 @@ def main():
         ceilings = None if args.no_ceilings else ctx.probe_ceilings()
     variant = P.kernel_choice(32, 256)[0]
     # L2 -> CU bytes of the fused launch: every tile of 32 blocks reads both
-    # fragment layouts of its operator (2 x Mp x n bf16) once per iteration
+    # fragment layouts of its operator (2 x Mp x n bf16) once per iteration,
+    # less the last `nl` forward K steps of each of the Mp / 32 forward tiles
+    # (1 KiB fragments) that a variant named "..._lds<nl>" or "..._ldsi<nl>"
+    # keeps in LDS
+    nl_m = re.search(r"_ldsi?(\d+)$", variant)
+    nl = int(nl_m.group(1)) if nl_m else 0
     tiles = sum(-(-((s.gop - 1) * ((s.height + 31) // 32) * ((s.width + 31) // 32)) // 32)
                 for s in specs)
     l2_bytes = sum(-(-((s.gop - 1) * ((s.height + 31) // 32) * ((s.width + 31) // 32)) // 32)
-                   * s.iters * 2 * (-(-s.m // 32) * 32) * s.n * 2 for s in specs)
+                   * s.iters * (2 * (-(-s.m // 32) * 32) * s.n * 2
+                                - (-(-s.m // 32)) * nl * 1024) for s in specs)
 
     value = px_per_step * args.steps / wall / 1e6
     avg_k_s = (k_ms / max(k_n, 1)) / 1e3

@@ -46,16 +46,32 @@ __device__ inline int next_tile(const int* __restrict__ qoff, const int* __restr
 
 // Forward product for this wave's NF output tiles (mt_i, fct), mt_i =
 // (w + W i) / CT.  af holds the first kPF K steps on entry.  Loads the first
-// kPA adjoint steps (rows rt0 + r / CT) into aa before returning.
-template <int N, int MP, int CT, int NF, int AR, int W, int kPF, int kPA>
+// kPA adjoint steps (rows rt0 + r / CT) into aa before returning.  With
+// NL > 0 the last NL K steps of every tile come from the wave's LDS copy Al
+// ([NF][NL][64] fragments) instead of global memory: after the global steps,
+// or with ILV one after each of the first NL rounds of the global ring, so
+// that the ring's loads stay in flight while they run.
+template <int N, int MP, int CT, int NF, int AR, int W, int kPF, int kPA, int NL = 0,
+          bool ILV = false>
 __device__ inline void forward_tiles(u16x8 (&af)[kPF][NF], u16x8 (&aa)[kPA][AR],
                                      floatx16 (&acc)[NF], const gu16x8* ffwd, const gu16x8* fadj,
-                                     const u16x8* Vb, int w, int ln, int fct, int rt0) {
-    constexpr int KSF = N / 16, KSA = MP / 16;
+                                     const u16x8* Vb, int w, int ln, int fct, int rt0,
+                                     const u16x8* Al = nullptr) {
+    constexpr int KSF = N / 16, KSA = MP / 16, KSG = KSF - NL;
+    static_assert(NL >= 0 && KSG >= kPF && KSG % kPF == 0, "LDS steps must leave whole rings");
+    static_assert(!ILV || (KSG - kPF) / kPF >= NL, "too few ring rounds to interleave");
+    auto lds_step = [&](int j) {
+        const int ks = KSG + j;
+        const bf16x8 b = __builtin_bit_cast(bf16x8, Vb[(ks * CT + fct) * 64 + ln]);
+#pragma unroll
+        for (int i = 0; i < NF; ++i)
+            acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, Al[(i * NL + j) * 64 + ln]), b, acc[i], 0, 0, 0);
+    };
 #pragma unroll
     for (int i = 0; i < NF; ++i) acc[i] = floatx16{};
 #pragma unroll 1
-    for (int ks0 = 0; ks0 < KSF - kPF; ks0 += kPF) {
+    for (int ks0 = 0; ks0 < KSG - kPF; ks0 += kPF) {
 #pragma unroll
         for (int j = 0; j < kPF; ++j) {
             const int ks = ks0 + j;
@@ -68,10 +84,13 @@ __device__ inline void forward_tiles(u16x8 (&af)[kPF][NF], u16x8 (&aa)[kPA][AR],
                 af[j][i] = ffwd[((size_t)mt * KSF + ks + kPF) * 64 + ln];
             }
         }
+        if constexpr (ILV && NL > 0) {
+            if (ks0 / kPF < NL) lds_step(ks0 / kPF);
+        }
     }
 #pragma unroll
-    for (int j = 0; j < kPF; ++j) {   // last kPF steps: no further forward loads
-        const int ks = KSF - kPF + j;
+    for (int j = 0; j < kPF; ++j) {   // last kPF global steps: no further forward loads
+        const int ks = KSG - kPF + j;
         const bf16x8 b = __builtin_bit_cast(bf16x8, Vb[(ks * CT + fct) * 64 + ln]);
 #pragma unroll
         for (int i = 0; i < NF; ++i)
@@ -82,6 +101,10 @@ __device__ inline void forward_tiles(u16x8 (&af)[kPF][NF], u16x8 (&aa)[kPA][AR],
             for (int r = 0; r < AR; ++r)
                 aa[j][r] = fadj[((size_t)(rt0 + r / CT) * KSA + j) * 64 + ln];
         }
+    }
+    if constexpr (!ILV) {
+#pragma unroll
+        for (int j = 0; j < NL; ++j) lds_step(j);   // LDS-resident steps
     }
 }
 

@@ -70,7 +70,12 @@ void launch_bf16_frag_layout(Operator* op, hipStream_t st) {
 // SPL: accumulator tiles per wave whose s_{k-1} lives in LDS rather than in
 // registers (the registers go to deeper operator rings instead).  OCC
 // workgroups share a CU, so a wave gets 512 / (W OCC / 4) registers.
-template <int N, int MP, int CT, int W, int kPF, int kPA, int SPL, int OCC>
+// NL: the last NL forward K steps of each wave's operator rows are kept in
+// LDS, copied when a tile's operator differs from the previous tile's, so
+// that every iteration reads NL fewer fragments through the L1 return path
+// (the kernel's bound at n = 1024).  NL < 0: -NL such steps, interleaved
+// with the global ring rounds instead of run after them.
+template <int N, int MP, int CT, int W, int kPF, int kPA, int SPL, int OCC, int NLS>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W * OCC / 4)))
 void fista_bf16_kernel(
     const FusedTile* __restrict__ tiles, const int* __restrict__ qoff,
@@ -85,6 +90,8 @@ void fista_bf16_kernel(
     constexpr int FT = (TT + W - 1) / W;         // forward tiles per wave (max)
     constexpr int KSF = N / 16, KSA = MP / 16;   // K steps of forward / adjoint
     constexpr bool YREG = false;                 // y read from L2 in the epilogue (registers are the limit)
+    constexpr int NL = NLS < 0 ? -NLS : NLS;     // LDS-resident forward K steps
+    constexpr bool ILV = NLS < 0;
     static_assert(RT * CT >= 2 && (RT * CT) % 2 == 0 && W % CT == 0, "unsupported class");
     static_assert(KSF % kPF == 0 && KSA % kPA == 0 && KSF >= kPF && KSA >= kPA,
                   "ring depth must divide the K steps");
@@ -93,11 +100,16 @@ void fista_bf16_kernel(
     u16x8* Rb = reinterpret_cast<u16x8*>(lds + (size_t)KSF * CT * 1024);  // [KSA][CT][64]
     float4* Sl = reinterpret_cast<float4*>(lds + (size_t)(KSF + KSA) * CT * 1024);
     // Sl: [W][SPL][4][64] float4, lane l's 16 values of a tile at q * 64 + l
+    u16x8* Al = reinterpret_cast<u16x8*>(lds + (size_t)(KSF + KSA) * CT * 1024 +
+                                         (size_t)W * SPL * 4096);
+    // Al: [W][FT][NL][64], forward fragments (mt_i, KSF - NL + j) of wave w
+    static_assert(NL == 0 || KSF - NL >= kPF, "LDS steps leave no global ring");
     __shared__ int s_tile;
 
     const int tid = threadIdx.x, w = tid >> 6, ln = tid & 63, h = ln >> 5, col = ln & 31;
     const int fct = w % CT;                      // column tile of this wave's forward tiles
     const int nft = (TT - w + W - 1) / W;        // forward tiles of this wave: FT, FT-1 or 0
+    const void* al_src = nullptr;                // operator whose fragments Al holds
 
     for (;;) {
         if (tid == 0) s_tile = next_tile(qoff, queue, counters);
@@ -112,6 +124,18 @@ void fista_bf16_kernel(
         const float inv_l = (float)(1.0 / tl.lip[0]);
         const int T = tl.T;
         const float* __restrict__ beta = tl.beta;
+        if constexpr (NL > 0) {
+            // each lane reads back only what it wrote itself: no barrier
+            if (nft == FT && tl.frag_fwd != al_src) {
+#pragma unroll
+                for (int i = 0; i < FT; ++i)
+#pragma unroll
+                    for (int j = 0; j < NL; ++j)
+                        Al[((w * FT + i) * NL + j) * 64 + ln] =
+                            ffwd[((size_t)((w + W * i) / CT) * KSF + KSF - NL + j) * 64 + ln];
+                al_src = tl.frag_fwd;
+            }
+        }
 
         float tau[CT];
 #pragma unroll
@@ -160,8 +184,9 @@ void fista_bf16_kernel(
             // ---- forward: P = A V, R = P - y  (nft tiles for this wave)
             if (nft == FT) {
                 floatx16 acc[FT];
-                forward_tiles<N, MP, CT, FT, AR, W, kPF, kPA>(af, aa, acc, ffwd, fadj, Vb, w, ln, fct,
-                                                              w * RT);
+                forward_tiles<N, MP, CT, FT, AR, W, kPF, kPA, NL, ILV>(af, aa, acc, ffwd, fadj, Vb, w, ln,
+                                                                  fct, w * RT,
+                                                                  Al + (size_t)w * FT * NL * 64);
 #pragma unroll
                 for (int i = 0; i < FT; ++i)
                     store_residual<MP, CT, YREG>(acc[i], yv[YREG ? i : 0], yg, tl.nblk,
@@ -309,17 +334,18 @@ void fista_bf16_kernel(
     }
 }
 
-template <int N, int MP, int CT, int W, int PF, int PA, int SPL, int OCC>
+template <int N, int MP, int CT, int W, int PF, int PA, int SPL, int OCC, int NL>
 static void launch_class(const FusedTile* tiles, const int* qoff, const int* queue, int* counters,
                          int grid, hipStream_t st) {
     static_assert(W * OCC % 4 == 0 && W * OCC <= 32, "waves per CU");
-    const size_t lds = (size_t)(N / 16) * CT * 1024 + (size_t)(MP / 16) * CT * 1024 +
-                       (size_t)W * SPL * 4096;
-    static_assert(((size_t)(N / 16) * CT * 1024 + (size_t)(MP / 16) * CT * 1024 +
-                   (size_t)W * SPL * 4096 + 64) * OCC <= 160 * 1024,
-                  "LDS of OCC workgroups exceeds a CU");
-    auto* fn = &fista_bf16_kernel<N, MP, CT, W, PF, PA, SPL, OCC>;
-    ensure_lds_limit<&fista_bf16_kernel<N, MP, CT, W, PF, PA, SPL, OCC>>(lds);
+    constexpr size_t kFT = ((MP / 32) * CT + W - 1) / W;
+    constexpr size_t kNL = NL < 0 ? -NL : NL;
+    constexpr size_t kLds = (size_t)(N / 16) * CT * 1024 + (size_t)(MP / 16) * CT * 1024 +
+                            (size_t)W * SPL * 4096 + (size_t)W * kFT * kNL * 1024;
+    static_assert((kLds + 64) * OCC <= 160 * 1024, "LDS of OCC workgroups exceeds a CU");
+    const size_t lds = kLds;
+    auto* fn = &fista_bf16_kernel<N, MP, CT, W, PF, PA, SPL, OCC, NL>;
+    ensure_lds_limit<&fista_bf16_kernel<N, MP, CT, W, PF, PA, SPL, OCC, NL>>(lds);
     fn<<<dim3(grid), dim3(64 * W), lds, st>>>(tiles, qoff, queue, counters);
     CSV_HIP(hipGetLastError());
 }
@@ -331,7 +357,17 @@ static void launch_class(const FusedTile* tiles, const int* qoff, const int* que
 #define CSV_V(NN, MM, CT, W, PF, PA, SPL, OCC)                                    \
     FusedVariant {                                                                 \
         "ct" #CT "_w" #W "_pf" #PF "_pa" #PA "_spl" #SPL "_o" #OCC, CT, OCC,      \
-            &launch_class<NN, MM, CT, W, PF, PA, SPL, OCC>                         \
+            &launch_class<NN, MM, CT, W, PF, PA, SPL, OCC, 0>                      \
+    }
+#define CSV_VL(NN, MM, CT, W, PF, PA, SPL, OCC, NL)                                    \
+    FusedVariant {                                                                      \
+        "ct" #CT "_w" #W "_pf" #PF "_pa" #PA "_spl" #SPL "_o" #OCC "_lds" #NL, CT, OCC, \
+            &launch_class<NN, MM, CT, W, PF, PA, SPL, OCC, NL>                          \
+    }
+#define CSV_VLI(NN, MM, CT, W, PF, PA, SPL, OCC, NL)                                    \
+    FusedVariant {                                                                       \
+        "ct" #CT "_w" #W "_pf" #PF "_pa" #PA "_spl" #SPL "_o" #OCC "_ldsi" #NL, CT, OCC, \
+            &launch_class<NN, MM, CT, W, PF, PA, SPL, OCC, -NL>                          \
     }
 
 struct ClassEntry {
@@ -358,13 +394,26 @@ static std::vector<ClassEntry>& class_table() {
          {CSV_V(256, 128, 2, 4, 2, 2, 0, 2), CSV_V(256, 128, 1, 4, 2, 2, 0, 3),
           CSV_V(256, 128, 2, 8, 4, 2, 0, 1), CSV_V(256, 128, 4, 8, 4, 2, 0, 1)},
          0},
-        {1024, 32, {CSV_V(1024, 32, 1, 8, 4, 2, 0, 1), CSV_V(1024, 32, 1, 8, 4, 2, 2, 1)}, 0},
-        {1024, 64, {CSV_V(1024, 64, 1, 8, 4, 2, 0, 1), CSV_V(1024, 64, 1, 8, 4, 2, 2, 1)}, 0},
-        {1024, 128, {CSV_V(1024, 128, 1, 8, 4, 2, 0, 1), CSV_V(1024, 128, 1, 8, 4, 2, 2, 1)}, 0},
-        {1024, 224, {CSV_V(1024, 224, 1, 8, 4, 2, 0, 1), CSV_V(1024, 224, 1, 8, 4, 2, 2, 1)}, 0},
+        {1024, 32,
+         {CSV_VLI(1024, 32, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 32, 1, 8, 4, 2, 0, 1),
+          CSV_V(1024, 32, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 32, 1, 8, 4, 2, 0, 1, 8)},
+         0},
+        {1024, 64,
+         {CSV_V(1024, 64, 1, 8, 4, 2, 0, 1), CSV_V(1024, 64, 1, 8, 4, 2, 2, 1),
+          CSV_VL(1024, 64, 1, 8, 4, 2, 0, 1, 8), CSV_VLI(1024, 64, 1, 8, 4, 2, 0, 1, 8)},
+         0},
+        {1024, 128,
+         {CSV_VLI(1024, 128, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 128, 1, 8, 4, 2, 0, 1),
+          CSV_V(1024, 128, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 128, 1, 8, 4, 2, 0, 1, 8)},
+         0},
+        {1024, 224,
+         {CSV_VLI(1024, 224, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 224, 1, 8, 4, 2, 0, 1),
+          CSV_V(1024, 224, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 224, 1, 8, 4, 2, 0, 1, 8)},
+         0},
         {1024, 256,
-         {CSV_V(1024, 256, 1, 8, 4, 2, 0, 1), CSV_V(1024, 256, 1, 8, 4, 2, 2, 1),
-          CSV_V(1024, 256, 1, 8, 8, 2, 2, 1), CSV_V(1024, 256, 1, 8, 4, 2, 1, 1)},
+         {CSV_VLI(1024, 256, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 256, 1, 8, 4, 2, 0, 1),
+          CSV_V(1024, 256, 1, 8, 4, 2, 2, 1), CSV_V(1024, 256, 1, 8, 8, 2, 2, 1),
+          CSV_V(1024, 256, 1, 8, 4, 2, 1, 1), CSV_VL(1024, 256, 1, 8, 4, 2, 0, 1, 8)},
          0},
         {1024, 416,
          {CSV_V(1024, 416, 1, 8, 2, 2, 2, 1), CSV_V(1024, 416, 1, 8, 4, 2, 2, 1),
@@ -374,6 +423,8 @@ static std::vector<ClassEntry>& class_table() {
     return t;
 }
 #undef CSV_V
+#undef CSV_VL
+#undef CSV_VLI
 
 static ClassEntry* find_class(int n, int Mp) {
     for (auto& c : class_table())
