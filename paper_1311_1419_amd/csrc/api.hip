@@ -5,6 +5,9 @@
 #include <cstring>
 #include <mutex>
 
+#include <map>
+#include <tuple>
+
 #include "internal.h"
 
 namespace csv {
@@ -220,7 +223,7 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
     const size_t sz_q = Mp * n, sz_a64 = Mp * n * 8, sz_a32 = Mp * n * 4;
     const size_t sz_frag = Mp * n * 2, sz_lip = 64, sz_dct = n * 4, sz_dct64 = n * 8;
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
-    const size_t total = 2 * al(sz_q) + 2 * al(sz_a64) + 2 * al(sz_a32) + 4 * al(sz_frag) +
+    const size_t total = 2 * al(sz_q) + al(sz_a64) + 2 * al(sz_a32) + 4 * al(sz_frag) +
                          al(sz_lip) + al(sz_dct) + al(sz_dct64);
     char* base = static_cast<char*>(ctx_alloc(c, total));
     op->bytes = total;
@@ -233,7 +236,6 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
     op->q = reinterpret_cast<int8_t*>(take(sz_q));
     op->q8 = reinterpret_cast<uint8_t*>(take(sz_q));
     op->a64 = reinterpret_cast<double*>(take(sz_a64));
-    op->a64t = reinterpret_cast<double*>(take(sz_a64));
     op->a32 = reinterpret_cast<float*>(take(sz_a32));
     op->phi32 = reinterpret_cast<float*>(take(sz_a32));
     op->frag_fwd = reinterpret_cast<uint16_t*>(take(sz_frag));
@@ -587,7 +589,7 @@ void recover(Ctx* c, const Shape& s, Operator* op, const int8_t* codes, const ui
         if (tv)
             launch_tv_final64(op->q, S, codes, exps, lam, nblk, s.M, s.B, op->s_phi, obj_out, st);
         else
-            launch_final64(op->a64t, S, codes, exps, lam, nblk, s.M, s.Mp, s.n, op->s_phi,
+            launch_final64(op->a64, S, codes, exps, lam, nblk, s.M, s.Mp, s.n, op->s_phi,
                            obj_out, st);
     }
 }
@@ -941,20 +943,40 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
     }
     if (!jobs.empty()) fista_bf16(c, jobs, st);
     if (spread) fork_aux(c, st);
+    if (obj_out) {
+        // FP64 checks of the DCT-l1 GOPs: one launch per (n, M, Mp) group of up
+        // to kF64Batch on the launch stream, beside the syntheses on the lanes
+        std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+        for (int i = 0; i < count; ++i)
+            if (items[i].nblk && obj_out[i] && !(shapes[i].flags & CSV_FLAG_TV))
+                groups[{shapes[i].n, shapes[i].M, shapes[i].Mp}].push_back(i);
+        for (const auto& kv : groups) {
+            const std::vector<int>& mem = kv.second;
+            for (size_t g0 = 0; g0 < mem.size(); g0 += kF64Batch) {
+                F64Batch bt{};
+                int ng = 0;
+                for (size_t k = g0; k < mem.size() && ng < kF64Batch; ++k) {
+                    const int i = mem[k];
+                    const Item& it = items[i];
+                    bt.j[ng++] = F64Job{it.op->a64, it.S,   in[i].codes,      in[i].exps,
+                                        it.lam,     obj_out[i], it.op->s_phi, it.nblk};
+                }
+                const Shape& s0 = shapes[mem[g0]];
+                ProfScope ps(c, "final64", st);
+                launch_final64_batch(bt, ng, s0.M, s0.Mp, s0.n, st);
+            }
+        }
+    }
     for (int i = 0; i < count; ++i) {
         const Shape& s = shapes[i];
         const Item& it = items[i];
         if (!it.nblk) continue;
         const hipStream_t ls = lane_of(i);
         const bool tv = (s.flags & CSV_FLAG_TV) != 0;
-        if (obj_out && obj_out[i]) {
+        if (obj_out && obj_out[i] && tv) {
             ProfScope ps(c, "final64", ls);
-            if (tv)
-                launch_tv_final64(it.op->q, it.S, in[i].codes, in[i].exps, it.lam, it.nblk, s.M,
-                                  s.B, it.op->s_phi, obj_out[i], ls);
-            else
-                launch_final64(it.op->a64t, it.S, in[i].codes, in[i].exps, it.lam, it.nblk, s.M,
-                               s.Mp, s.n, it.op->s_phi, obj_out[i], ls);
+            launch_tv_final64(it.op->q, it.S, in[i].codes, in[i].exps, it.lam, it.nblk, s.M, s.B,
+                              it.op->s_phi, obj_out[i], ls);
         }
         ProfScope ps(c, "synth", ls);
         const size_t fs = (size_t)s.W * s.H;

@@ -61,8 +61,7 @@ struct Operator {
     double s_phi = 0;
     int8_t* q = nullptr;          // Mp x n, rows >= M zero
     uint8_t* q8 = nullptr;        // Mp x n, Q as OCP E4M3 bytes (FP8 measurement form)
-    double* a64 = nullptr;        // Mp x n, A = s_phi Q Psi
-    double* a64t = nullptr;       // n x Mp, A transposed (final FP64 check)
+    double* a64 = nullptr;        // Mp x n, A = s_phi Q Psi (final FP64 check)
     float* a32 = nullptr;         // Mp x n
     float* phi32 = nullptr;       // Mp x n, s_phi Q
     uint16_t* frag_fwd = nullptr; // bf16 A in forward-product fragment order
@@ -182,7 +181,24 @@ void launch_fill_f32(float* p, float v, size_t count, hipStream_t st);
 void launch_copy_f32(float* dst, const float* src, size_t count, hipStream_t st);
 void launch_synth(const float* s, const float* dct, const uint8_t* key, int W, int H, int B,
                   int nbx, int nb, int n_frames, uint8_t* out_u8, float* out_f32, hipStream_t st);
-void launch_final64(const double* a64t, const float* s, const int8_t* codes, const uint8_t* exps,
+// FP64 final check of the DCT-l1 recovery for up to kF64Batch GOPs of one
+// (n, M, Mp) shape in one launch (grid.y = GOP).
+struct F64Job {
+    const double* a64;      // Mp x n operator (FP64)
+    const float* s;         // nblk x n coefficients
+    const int8_t* codes;    // nblk x M
+    const uint8_t* exps;    // nblk
+    const float* lam;       // nblk
+    double* obj;            // nblk x 2
+    double s_phi;
+    int nblk;
+};
+constexpr int kF64Batch = 16;
+struct F64Batch {
+    F64Job j[kF64Batch];
+};
+void launch_final64_batch(const F64Batch& bt, int ngop, int M, int Mp, int n, hipStream_t st);
+void launch_final64(const double* a64, const float* s, const int8_t* codes, const uint8_t* exps,
                     const float* lam, int nblk, int M, int Mp, int n, double s_phi, double* obj,
                     hipStream_t st);
 

@@ -25,9 +25,8 @@ __global__ void dct_table_kernel(int B, double* __restrict__ c64, float* __restr
 __global__ __launch_bounds__(256) void operator_kernel(const int8_t* __restrict__ q, int M, int B,
                                                       double s_phi, const double* __restrict__ c64,
                                                       double* __restrict__ a64,
-                                                      double* __restrict__ a64t,
                                                       float* __restrict__ a32,
-                                                      float* __restrict__ phi32, int Mp) {
+                                                      float* __restrict__ phi32) {
     extern __shared__ double sh[];
     const int n = B * B;
     double* X = sh;          // B x B
@@ -52,7 +51,6 @@ __global__ __launch_bounds__(256) void operator_kernel(const int8_t* __restrict_
         for (int c = 0; c < B; ++c) acc += U[k * B + c] * C[l * B + c];
         const double a = s_phi * acc;
         a64[(size_t)m * n + i] = a;
-        a64t[(size_t)i * Mp + m] = a;
         a32[(size_t)m * n + i] = (float)a;
         phi32[(size_t)m * n + i] = (float)(s_phi * X[i]);
     }
@@ -172,8 +170,7 @@ void launch_operator_setup(Operator* op, hipStream_t st) {
     dct_table_kernel<<<dim3(ceil_div(n, 256)), dim3(256), 0, st>>>(B, c64, op->dct);
     CSV_HIP(hipGetLastError());
     operator_kernel<<<dim3(op->Mp), dim3(256), 3 * n * sizeof(double), st>>>(
-        op->q, op->M, B, op->s_phi, c64, op->a64, op->a64t, op->a32,
-        op->phi32, op->Mp);
+        op->q, op->M, B, op->s_phi, c64, op->a64, op->a32, op->phi32);
     CSV_HIP(hipGetLastError());
 }
 
@@ -269,43 +266,68 @@ void launch_copy_f32(float* dst, const float* src, size_t count, hipStream_t st)
 // Residual block X = C^T S C (eq. (4) adds it to the decoded key frame), or
 // X = S itself when dct is NULL (pixel-domain recovery); float output =
 // key + X, uint8 output = clip(round-half-even(key + X)).
-// One workgroup per block, one thread per pixel.
+//
+// One wave per block, both products of the 2-D inverse DCT on the FP32
+// matrix cores (B = 32: 32x32x2, B = 16: 16x16x4; G = 64 / B lane groups,
+// lane = g B + col).  Stage 1 forms U^T = S^T C: in K step t lane (g, col)
+// feeds S[G t + g][col] and C[G t + g][col], 64 consecutive floats of each.
+// Its accumulator holds U[r = col][c = rho(i, g)] in register i, which is
+// already the A operand of stage 2, X = U C, when K step i pairs lane group
+// g with row rho(i, g) of C.  The result X[rho(i, g)][col] is in register i.
 template <int B>
-__global__ __launch_bounds__(B * B) void synth_kernel(const float* __restrict__ s,
-                                                     const float* __restrict__ dct,
-                                                     const uint8_t* __restrict__ key, int W, int H,
-                                                     int nbx, int nb, uint8_t* __restrict__ out_u8,
-                                                     float* __restrict__ out_f32) {
-    constexpr int n = B * B;
-    __shared__ float S[n];
-    __shared__ float U[n];
-    __shared__ float C[n];
-    const int gb = blockIdx.x, t = gb / nb, b = gb % nb;
-    const int tid = threadIdx.x;
-    const int r = tid / B, c = tid % B;
-    float x;
-    if (dct == nullptr) {   // pixel-domain residual (TV recovery)
-        x = s[(size_t)gb * n + tid];
+__device__ inline int synth_row(int i, int g) {
+    return B == 32 ? 8 * (i / 4) + 4 * g + i % 4 : 4 * g + i;
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void synth_kernel(const float* __restrict__ s,
+                                                   const float* __restrict__ dct,
+                                                   const uint8_t* __restrict__ key, int W, int H,
+                                                   int nbx, int nb, int total,
+                                                   uint8_t* __restrict__ out_u8,
+                                                   float* __restrict__ out_f32) {
+    static_assert(B == 16 || B == 32, "block size");
+    constexpr int n = B * B, G = 64 / B, NS = B / G;   // NS: K steps = accumulator registers
+    typedef float acc_t __attribute__((ext_vector_type(NS)));
+    const int gb = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (gb >= total) return;   // whole waves
+    const int ln = threadIdx.x & 63, g = ln / B, col = ln % B;
+    const int t = gb / nb, b = gb % nb;
+    const float* __restrict__ sb = s + (size_t)gb * n;
+    acc_t x = {};
+    if (dct != nullptr) {
+        acc_t u = {};
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const float a = sb[64 * k + ln], c = dct[64 * k + ln];
+            if constexpr (B == 32)
+                u = __builtin_amdgcn_mfma_f32_32x32x2f32(a, c, u, 0, 0, 0);
+            else
+                u = __builtin_amdgcn_mfma_f32_16x16x4f32(a, c, u, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            const float c = dct[synth_row<B>(i, g) * B + col];
+            if constexpr (B == 32)
+                x = __builtin_amdgcn_mfma_f32_32x32x2f32(u[i], c, x, 0, 0, 0);
+            else
+                x = __builtin_amdgcn_mfma_f32_16x16x4f32(u[i], c, x, 0, 0, 0);
+        }
     } else {
-        S[tid] = s[(size_t)gb * n + tid];
-        C[tid] = dct[tid];
-        __syncthreads();
-        float u = 0.f;   // U[r][l = c] = sum_k C[k][r] S[k][l]
-#pragma unroll 8
-        for (int k = 0; k < B; ++k) u = fmaf(C[k * B + r], S[k * B + c], u);
-        U[tid] = u;
-        __syncthreads();
-        x = 0.f;   // X[r][c] = sum_l U[r][l] C[l][c]
-#pragma unroll 8
-        for (int l = 0; l < B; ++l) x = fmaf(U[r * B + l], C[l * B + c], x);
+#pragma unroll
+        for (int i = 0; i < NS; ++i) x[i] = sb[synth_row<B>(i, g) * B + col];
     }
-    const int py = (b / nbx) * B + r, px = (b % nbx) * B + c;
-    if (py < H && px < W) {
-        const size_t pix = (size_t)py * W + px;
-        const float f = (float)key[pix] + x;
-        const size_t o = (size_t)t * W * H + pix;
-        if (out_f32) out_f32[o] = f;
-        out_u8[o] = (uint8_t)fminf(fmaxf(rintf(f), 0.f), 255.f);
+    const int px = (b % nbx) * B + col, py0 = (b / nbx) * B;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        const int py = py0 + synth_row<B>(i, g);
+        if (py < H && px < W) {
+            const size_t pix = (size_t)py * W + px;
+            const float f = (float)key[pix] + x[i];
+            const size_t o = (size_t)t * W * H + pix;
+            if (out_f32) out_f32[o] = f;
+            out_u8[o] = (uint8_t)fminf(fmaxf(rintf(f), 0.f), 255.f);
+        }
     }
 }
 
@@ -313,118 +335,155 @@ void launch_synth(const float* s, const float* dct, const uint8_t* key, int W, i
                   int nbx, int nb, int n_frames, uint8_t* out_u8, float* out_f32, hipStream_t st) {
     const int total = nb * n_frames;
     if (!total) return;
+    CSV_REQUIRE(B == 16 || B == 32, CSV_EUNSUPPORTED, "synthesis supports B = 16 and 32");
+    const dim3 grid((unsigned)((total + 3) / 4));
     if (B == 16)
-        synth_kernel<16><<<dim3(total), dim3(256), 0, st>>>(s, dct, key, W, H, nbx, nb, out_u8,
-                                                            out_f32);
+        synth_kernel<16><<<grid, dim3(256), 0, st>>>(s, dct, key, W, H, nbx, nb, total, out_u8,
+                                                     out_f32);
     else
-        synth_kernel<32><<<dim3(total), dim3(1024), 0, st>>>(s, dct, key, W, H, nbx, nb, out_u8,
-                                                             out_f32);
+        synth_kernel<32><<<grid, dim3(256), 0, st>>>(s, dct, key, W, H, nbx, nb, total, out_u8,
+                                                     out_f32);
     CSV_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------- FP64 final check
 // Per block: r = A s - y^ with y^ = s_phi c 2^e recomputed exactly in FP64;
 // obj = 1/2 ||r||^2 + lam ||s||_1 and ||r|| / ||y^||.  The product A s runs
-// on FP64 MFMA (16x16x4): a workgroup owns 16 blocks (one MFMA column tile)
+// on FP64 MFMA (16x16x4): a workgroup owns 32 blocks (two MFMA column tiles)
 // and all padded rows; wave w takes row tiles w, w+4, ...  Coefficients are
-// staged in LDS as FP64 in K chunks of 64; A comes from the transposed copy
-// A^T (n x Mp), read four 128-byte rows per fragment.
+// staged in LDS as FP64 in K chunks of 64.  A is read row-major (Mp x n):
+// K step (p, e) of a 16-wide K slice gives lane quarter q the index
+// 16 p + 4 q + e, so each lane fetches the four steps of a slice with one
+// 32-byte load, and the next slice's loads are in flight during the MFMAs.
 typedef double doublex4 __attribute__((ext_vector_type(4)));
-constexpr int F64_BLK = 16, F64_KC = 32;
+constexpr int F64_CB = 2, F64_BLK = 16 * F64_CB, F64_KC = 64;
 
 // RTW: row tiles (of 16) per wave, ceil(Mp / 64).
+// GOP blockIdx.y of the batch.
 template <int RTW>
-__global__ __launch_bounds__(256) void final64_kernel(const double* __restrict__ a64t,
-                                                     const float* __restrict__ s,
-                                                     const int8_t* __restrict__ codes,
-                                                     const uint8_t* __restrict__ exps,
-                                                     const float* __restrict__ lam, int nblk,
-                                                     int M, int Mp, int n, double s_phi,
-                                                     double* __restrict__ obj) {
-    __shared__ double Sd[F64_KC][F64_BLK];
-    __shared__ double red[3][4][F64_BLK];
+__global__ __launch_bounds__(256) void final64_kernel(F64Batch bt, int M, int Mp, int n) {
+    const F64Job& jb = bt.j[blockIdx.y];
+    const int nblk = jb.nblk;
     const int b0 = blockIdx.x * F64_BLK;
+    if (b0 >= nblk) return;   // the whole workgroup: this GOP has fewer blocks
+    const double* __restrict__ a64 = jb.a64;
+    const float* __restrict__ s = jb.s;
+    const int8_t* __restrict__ codes = jb.codes;
+    const uint8_t* __restrict__ exps = jb.exps;
+    const float* __restrict__ lam = jb.lam;
+    double* __restrict__ obj = jb.obj;
+    const double s_phi = jb.s_phi;
+    __shared__ double Sd[F64_KC][F64_BLK + 1];
+    __shared__ double red[3][4][F64_BLK];
     const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
-    const int j = ln & 15, kq = ln >> 4;   // MFMA column (block) and K quarter
+    const int j = ln & 15, kq = ln >> 4;   // MFMA column and K quarter
     const int nrt = Mp / 16;
-    doublex4 acc[RTW];
+    doublex4 acc[RTW][F64_CB];
 #pragma unroll
-    for (int i = 0; i < RTW; ++i) acc[i] = doublex4{0.0, 0.0, 0.0, 0.0};
-    double l1 = 0.0;   // sum |s| over the staged entries of this thread
-    const int sb = tid >> 4, sk = (tid & 15) * 2;   // staging: block sb, k sk, sk+1
-    // operator fragments of one K chunk; the next chunk's loads are issued
-    // before this chunk's products so their latency overlaps the MFMAs
-    double av[F64_KC / 4][RTW], an[F64_KC / 4][RTW];
-    auto load_chunk = [&](double (&dst)[F64_KC / 4][RTW], int k0) {
+    for (int i = 0; i < RTW; ++i)
 #pragma unroll
-        for (int kk = 0; kk < F64_KC / 4; ++kk) {
-            const size_t krow = (size_t)(k0 + 4 * kk + kq) * Mp;
-#pragma unroll
-            for (int i = 0; i < RTW; ++i) {
-                const int rt = wv + 4 * i;
-                dst[kk][i] = rt < nrt ? a64t[krow + rt * 16 + j] : 0.0;
-            }
+        for (int ct = 0; ct < F64_CB; ++ct) acc[i][ct] = doublex4{0.0, 0.0, 0.0, 0.0};
+    // staging: thread (sb, sk) moves s[b0 + sb][k0 + sk .. k0 + sk + 7] to LDS
+    const int sb = tid >> 3, sk = (tid & 7) * 8;
+    const bool s_ok = b0 + sb < nblk;
+    const float* __restrict__ srow = s + (size_t)(s_ok ? b0 + sb : 0) * n + sk;
+    float4 s0 = make_float4(0.f, 0.f, 0.f, 0.f), s1 = s0;
+    auto load_s = [&](int k0) {
+        if (s_ok) {
+            s0 = *reinterpret_cast<const float4*>(srow + k0);
+            s1 = *reinterpret_cast<const float4*>(srow + k0 + 4);
         }
     };
-    load_chunk(an, 0);
-    for (int k0 = 0; k0 < n; k0 += F64_KC) {
+    double l1 = 0.0;   // sum |s| over the staged entries of this thread
+    // operator rows of this lane: m = rt * 16 + j, K offset 4 kq within a slice
+    const double* arow[RTW];
 #pragma unroll
-        for (int kk = 0; kk < F64_KC / 4; ++kk)
-#pragma unroll
-            for (int i = 0; i < RTW; ++i) av[kk][i] = an[kk][i];
-        if (k0 + F64_KC < n) load_chunk(an, k0 + F64_KC);
-        float2 v = make_float2(0.f, 0.f);
-        if (b0 + sb < nblk) v = *reinterpret_cast<const float2*>(s + (size_t)(b0 + sb) * n + k0 + sk);
-        __syncthreads();
-        Sd[sk + 0][sb] = v.x;
-        Sd[sk + 1][sb] = v.y;
-        l1 += fabs((double)v.x) + fabs((double)v.y);
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < F64_KC / 4; ++kk) {
-            const double bv = Sd[4 * kk + kq][j];
-#pragma unroll
-            for (int i = 0; i < RTW; ++i)
-                acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk][i], bv, acc[i], 0, 0, 0);
-        }
+    for (int i = 0; i < RTW; ++i) {
+        const int rt = wv + 4 * i;
+        arow[i] = a64 + (size_t)(rt < nrt ? rt * 16 + j : 0) * n + 4 * kq;
     }
-    // D layout (FP64 16x16x4): lane j + 16 q, register r holds row q + 4 r, column j
-    double rr = 0.0, yy = 0.0;
-    const int b = b0 + j;
-    if (b < nblk) {
-        const int e = exps[b];
+    doublex4 av[RTW], an[RTW];
+    auto load_a = [&](doublex4 (&dst)[RTW], int kb) {
 #pragma unroll
-        for (int i = 0; i < RTW; ++i) {
-            const int rt = wv + 4 * i;
-            if (rt < nrt) {
+        for (int i = 0; i < RTW; ++i)
+            dst[i] = wv + 4 * i < nrt ? *reinterpret_cast<const doublex4*>(arow[i] + kb)
+                                      : doublex4{0.0, 0.0, 0.0, 0.0};
+    };
+    load_s(0);
+    load_a(an, 0);
+    for (int k0 = 0; k0 < n; k0 += F64_KC) {
+        __syncthreads();   // every wave is done with the previous chunk
+        const float sv[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int m = rt * 16 + kq + 4 * r;
-                    if (m < M) {
-                        const double yh = s_phi * ldexp((double)codes[(size_t)b * M + m], e);
-                        const double d = acc[i][r] - yh;
-                        rr += d * d;
-                        yy += yh * yh;
-                    }
+        for (int e = 0; e < 8; ++e) {
+            Sd[sk + e][sb] = sv[e];
+            l1 += fabs((double)sv[e]);
+        }
+        if (k0 + F64_KC < n) load_s(k0 + F64_KC);
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < F64_KC / 16; ++p) {
+#pragma unroll
+            for (int i = 0; i < RTW; ++i) av[i] = an[i];
+            if (k0 + 16 * p + 16 < n) load_a(an, k0 + 16 * p + 16);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+#pragma unroll
+                for (int ct = 0; ct < F64_CB; ++ct) {
+                    const double bv = Sd[16 * p + 4 * kq + e][16 * ct + j];
+#pragma unroll
+                    for (int i = 0; i < RTW; ++i)
+                        acc[i][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][e], bv, acc[i][ct],
+                                                                          0, 0, 0);
                 }
             }
         }
     }
-    // lanes j, j+16, j+32, j+48 share column j
-    rr += __shfl_xor(rr, 16);
-    rr += __shfl_xor(rr, 32);
-    yy += __shfl_xor(yy, 16);
-    yy += __shfl_xor(yy, 32);
-    // staging threads 16 sb .. 16 sb + 15 summed |s| of block sb
+    // D layout (FP64 16x16x4): lane j + 16 q, register r holds row q + 4 r, column j
+    double rr[F64_CB], yy[F64_CB];
+#pragma unroll
+    for (int ct = 0; ct < F64_CB; ++ct) {
+        rr[ct] = 0.0;
+        yy[ct] = 0.0;
+        const int b = b0 + 16 * ct + j;
+        if (b < nblk) {
+            const int e = exps[b];
+#pragma unroll
+            for (int i = 0; i < RTW; ++i) {
+                const int rt = wv + 4 * i;
+                if (rt < nrt) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int m = rt * 16 + kq + 4 * r;
+                        if (m < M) {
+                            const double yh = s_phi * ldexp((double)codes[(size_t)b * M + m], e);
+                            const double d = acc[i][ct][r] - yh;
+                            rr[ct] += d * d;
+                            yy[ct] += yh * yh;
+                        }
+                    }
+                }
+            }
+        }
+        // lanes j, j+16, j+32, j+48 share column j
+        rr[ct] += __shfl_xor(rr[ct], 16);
+        rr[ct] += __shfl_xor(rr[ct], 32);
+        yy[ct] += __shfl_xor(yy[ct], 16);
+        yy[ct] += __shfl_xor(yy[ct], 32);
+    }
+    // staging threads 8 sb .. 8 sb + 7 summed |s| of block sb
     double l1w = l1;
 #pragma unroll
-    for (int off = 8; off > 0; off >>= 1) l1w += __shfl_xor(l1w, off);
+    for (int off = 4; off > 0; off >>= 1) l1w += __shfl_xor(l1w, off);
     __syncthreads();
     if (ln < 16) {
-        red[0][wv][ln] = rr;
-        red[1][wv][ln] = yy;
+#pragma unroll
+        for (int ct = 0; ct < F64_CB; ++ct) {
+            red[0][wv][16 * ct + ln] = rr[ct];
+            red[1][wv][16 * ct + ln] = yy[ct];
+        }
     }
-    if ((tid & 15) == 0) red[2][0][sb] = l1w;   // 16 blocks, one writer each
+    if ((tid & 7) == 0) red[2][0][sb] = l1w;   // 32 blocks, one writer each
     __syncthreads();
     if (tid < F64_BLK && b0 + tid < nblk) {
         const int bb = b0 + tid;
@@ -435,24 +494,36 @@ __global__ __launch_bounds__(256) void final64_kernel(const double* __restrict__
     }
 }
 
-void launch_final64(const double* a64t, const float* s, const int8_t* codes, const uint8_t* exps,
-                    const float* lam, int nblk, int M, int Mp, int n, double s_phi, double* obj,
-                    hipStream_t st) {
-    if (nblk <= 0) return;
+void launch_final64_batch(const F64Batch& bt, int ngop, int M, int Mp, int n, hipStream_t st) {
+    CSV_REQUIRE(ngop >= 1 && ngop <= kF64Batch, CSV_EINVAL, "FP64 check batch size");
     const int rtw = ceil_div(Mp, 64);
-    CSV_REQUIRE(rtw <= 7 && n % F64_KC == 0, CSV_EUNSUPPORTED,
-                "final FP64 check: padded M above 448 or n not a multiple of 32");
-    const dim3 grid(ceil_div(nblk, F64_BLK)), block(256);
+    CSV_REQUIRE(rtw <= 7 && n % F64_KC == 0 && Mp % 16 == 0 && M <= Mp, CSV_EUNSUPPORTED,
+                "final FP64 check: padded M above 448 or n not a multiple of 64");
+    int rows = 0;
+    for (int g = 0; g < ngop; ++g) {
+        CSV_REQUIRE(bt.j[g].nblk >= 0, CSV_EINVAL, "negative block count");
+        rows = std::max(rows, bt.j[g].nblk);
+    }
+    if (!rows) return;
+    const dim3 grid(ceil_div(rows, F64_BLK), ngop), block(256);
     switch (rtw) {
-#define CSV_F64(R)                                                                      \
-    case R:                                                                             \
-        final64_kernel<R><<<grid, block, 0, st>>>(a64t, s, codes, exps, lam, nblk, M, Mp, n, \
-                                                   s_phi, obj);                          \
+#define CSV_F64(R)                                                                       \
+    case R:                                                                              \
+        final64_kernel<R><<<grid, block, 0, st>>>(bt, M, Mp, n);                           \
         break;
         CSV_F64(1) CSV_F64(2) CSV_F64(3) CSV_F64(4) CSV_F64(5) CSV_F64(6) CSV_F64(7)
 #undef CSV_F64
     }
     CSV_HIP(hipGetLastError());
+}
+
+void launch_final64(const double* a64, const float* s, const int8_t* codes, const uint8_t* exps,
+                    const float* lam, int nblk, int M, int Mp, int n, double s_phi, double* obj,
+                    hipStream_t st) {
+    if (nblk <= 0) return;
+    F64Batch bt{};
+    bt.j[0] = F64Job{a64, s, codes, exps, lam, obj, s_phi, nblk};
+    launch_final64_batch(bt, 1, M, Mp, n, st);
 }
 
 }  // namespace csv
