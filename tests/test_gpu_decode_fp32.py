@@ -146,3 +146,23 @@ def test_bad_params_rejected(ctx):
     for bad in (dict(gop=0), dict(width=170), dict(m=0, rho=0.0), dict(lambda_frac=-1.0)):
         with pytest.raises(P.CsvError):
             _gpu_params(spec).with_(**bad).resolve()
+
+
+def test_context_memory_budget(ctx):
+    """A context whose budget cannot hold a stream's operator and working
+    set refuses with CSV_ENOMEM instead of allocating past it, and stays
+    usable for a GOP that fits."""
+    import paper_1311_1419_amd as P
+    from paper_1311_1419_amd import _native as N
+    announce("context memory budget")
+    big = sv.vga_precision(0.25, gop=2)
+    small = sv.qcif_tiny()
+    with P.Context(0, mem_budget=4 << 20) as c:
+        with pytest.raises(P.CsvError) as ei:
+            c.decode_gop(c.encode_gop(dev(big.video()), _gpu_params(big)), _gpu_params(big))
+        assert ei.value.code == N.CSV_ENOMEM
+        frames = small.video()
+        op = codec.Params.from_spec(small)
+        ref = codec.decode_gop(codec.encode_gop(frames, op), op)
+        out, _, _ = c.decode_gop(c.encode_gop(dev(frames), _gpu_params(small)), _gpu_params(small))
+        assert np.array_equal(host(out)[0], ref.frames[0])
