@@ -59,6 +59,7 @@ __device__ inline void forward_tiles(u16x8 (&af)[kPF][NF], u16x8 (&aa)[kPA][AR],
                                      const u16x8* Al = nullptr) {
     constexpr int KSF = N / 16, KSA = MP / 16, KSG = KSF - NL;
     static_assert(NL >= 0 && KSG >= kPF && KSG % kPF == 0, "LDS steps must leave whole rings");
+    static_assert(kPA <= kPF, "the adjoint head is loaded during the last kPF forward steps");
     static_assert(!ILV || (KSG - kPF) / kPF >= NL, "too few ring rounds to interleave");
     auto lds_step = [&](int j) {
         const int ks = KSG + j;

@@ -187,3 +187,20 @@ def test_mixed64_batch_sampled_blocks(ctx):
             sl = (slice(by * bsz, by * bsz + hh), slice(bx * bsz, bx * bsz + ww))
             ref = key[sl] + x[:hh, :ww]
             assert np.max(np.abs(fl[t][sl] - ref)) <= MAXABS_TOL, (i, t, b)
+
+
+def test_full_batch_equals_alone(ctx):
+    """The 16-camera 640x480 GOP-16 M=256 batch (2256 tiles of 32 blocks:
+    persistent workgroups take several tiles and switch between the
+    streams' operators) decodes every GOP bit for bit as it decodes alone
+    (141 tiles, at most one per workgroup)."""
+    announce("bf16 16 x vga g16 m256 batch vs alone")
+    specs = [sv.vga_precision(0.25, stream=s) for s in range(16)]
+    items = []
+    for spec in specs:
+        p = _bf16(spec)
+        items.append((ctx.encode_gop(dev(spec.video()), p), p))
+    batch = ctx.decode_batch(items, want_float=True)
+    for i, (gs, p) in enumerate(items):
+        fa = ctx.decode_gop(gs, p, want_float=True)[1]
+        assert bool((fa == batch[i][1]).all()), f"stream {i}"
