@@ -366,7 +366,6 @@ static void fista_fp32(Ctx* c, const Shape& s, const std::vector<F32Item>& its, 
         j.lip = it.op->lip;
         j.S = it.S;
         j.V = static_cast<float*>(scratch(c, "V" + tag, nn * 4));
-        j.G = static_cast<float*>(scratch(c, "Gd" + tag, nn * 4));
         j.R = static_cast<float*>(scratch(c, "Rm" + tag, (size_t)it.nblk * s.Mp * 4));
         j.nblk = it.nblk;
     }
@@ -376,10 +375,10 @@ static void fista_fp32(Ctx* c, const Shape& s, const std::vector<F32Item>& its, 
         launch_fill_f32(bt.j[g].V, 0.f, (size_t)its[g].nblk * s.n, st);
     }
     for (int k = 0; k < s.T; ++k) {
-        // residual A v - y^ (padded rows 0), gradient A^T (A v - y^), prox
+        // residual A v - y^ (padded rows 0); gradient A^T (A v - y^) and the
+        // threshold and momentum step in one pass
         launch_f32_forward(bt, ng, s.n, s.M, s.Mp, st);
-        launch_f32_adjoint(bt, ng, s.n, s.Mp, st);
-        launch_f32_prox(bt, ng, s.n, beta, k, st);
+        launch_f32_adjoint_prox(bt, ng, s.n, s.Mp, beta, k, st);
     }
 }
 

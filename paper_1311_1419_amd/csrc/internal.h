@@ -234,9 +234,11 @@ struct F32Batch {
 void launch_f32_forward(const F32Batch& bt, int ngop, int n, int M, int Mp, hipStream_t st);
 // G = R A, on FP32 MFMA
 void launch_f32_adjoint(const F32Batch& bt, int ngop, int n, int Mp, hipStream_t st);
-// soft threshold and momentum on (S, V) with G, per GOP
-void launch_f32_prox(const F32Batch& bt, int ngop, int n, const float* beta, int k,
-                     hipStream_t st);
+// G = R A with the FISTA step of iteration k applied to each output in
+// place of storing it: u = V - G / L, S = soft(u, lam / L),
+// V = S + beta_k (S - S_prev); G is not written
+void launch_f32_adjoint_prox(const F32Batch& bt, int ngop, int n, int Mp, const float* beta,
+                             int k, hipStream_t st);
 
 // A batch of up to kWholeBatch GOPs of one shape, each with its own Q
 // (passed by value as a kernel argument); x, y, r are [GOP][F][.] arrays.

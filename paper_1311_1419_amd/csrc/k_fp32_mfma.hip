@@ -2,8 +2,8 @@
 // iteration (forward R = V A^T - y^, adjoint G = R A) as tiled GEMMs on
 // v_mfma_f32_32x32x2_f32 (FP32 products, FP32 accumulation), for a batch of
 // GOPs of one shape that share every launch (grid.z = GOP, each GOP's
-// operator and arrays passed by value), plus the batched threshold and
-// momentum pass.  The sums run in a fixed order: results depend only on the
+// operator and arrays passed by value); the threshold and momentum step
+// runs in the adjoint's epilogue.  The sums run in a fixed order: results depend only on the
 // shapes, and a GOP decodes identically alone or in a batch.
 #include "internal.h"
 #include "mfma.h"
@@ -21,9 +21,13 @@ constexpr int kGM = 128, kGK = 16, kGP = kGM + 4;
 //   FWD: X = V_g (nblk x K, K = n), B[k][c] = A_g[c][k] (c over Mp);
 //        C = R_g (nblk x Mp): acc - y^_g for c < M, 0 for M <= c < Mp.
 //   ADJ: X = R_g (nblk x K, K = Mp), B[k][c] = A_g[k][c] (c over n);
-//        C = G_g (nblk x n).
-template <bool FWD, int TN>
-__global__ __launch_bounds__(256) void f32_gemm_kernel(F32Batch bt, int N, int K, int M) {
+//        C = G_g (nblk x n), or with PROX the FISTA step of iteration k on
+//        (S_g, V_g) from each G entry, which is then not stored.
+template <bool FWD, int TN, bool PROX = false>
+__global__ __launch_bounds__(256) void f32_gemm_kernel(F32Batch bt, int N, int K, int M,
+                                                      const float* __restrict__ beta = nullptr,
+                                                      int kit = 0) {
+    static_assert(!(FWD && PROX), "the step follows the adjoint product");
     constexpr int NJ = TN / 64;     // accumulator tiles per wave along the columns
     constexpr int NB = TN / 64;     // float4 of B staged per thread per chunk
     const F32Job& jb = bt.j[blockIdx.z];
@@ -121,49 +125,46 @@ __global__ __launch_bounds__(256) void f32_gemm_kernel(F32Batch bt, int N, int K
         __syncthreads();                    // previous barrier
     }
     // accumulator (lane l, register r) = C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]
-    float* __restrict__ C = FWD ? jb.R : jb.G;
+    if constexpr (PROX) {
+        // u = v - g / L; s_k = soft(u, lam / L); v = s_k + beta_k (s_k - s_{k-1})
+        const float inv_l = (float)(1.0 / jb.lip[0]);
+        const float bk = beta[kit];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < NJ; ++j)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = r0 + wr + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
-                const int col = c0 + wc + 32 * j + lc;
-                if (row < nblk && col < N) {
-                    float v = acc[i][j][r];
-                    if (FWD) v = col < M ? v - jb.y[(size_t)row * N + col] : 0.f;
-                    C[(size_t)row * N + col] = v;
+                if (row >= nblk) continue;
+                const float tau = jb.lam[row] * inv_l;
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    const int col = c0 + wc + 32 * j + lc;
+                    if (col < N) {
+                        const size_t o = (size_t)row * N + col;
+                        const float u = fmaf(-acc[i][j][r], inv_l, jb.V[o]);
+                        const float sn = fmaxf(u - tau, 0.f) + fminf(u + tau, 0.f);
+                        jb.V[o] = fmaf(bk, sn - jb.S[o], sn);
+                        jb.S[o] = sn;
+                    }
                 }
             }
-}
-
-// u = v - g / L; s_k = soft(u, lam / L); v = s_k + beta_k (s_k - s_{k-1}),
-// four coefficients per thread; grid (ceil(max nblk n / 1024), GOPs).
-__global__ __launch_bounds__(256) void f32_prox_kernel(F32Batch bt, int n,
-                                                      const float* __restrict__ beta, int k) {
-    const F32Job& jb = bt.j[blockIdx.y];
-    const size_t i4 = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-    if (i4 >= (size_t)jb.nblk * n) return;   // n % 4 == 0: a float4 never straddles rows
-    const int r = (int)(i4 / n);
-    const float inv_l = (float)(1.0 / jb.lip[0]);
-    const float tau = jb.lam[r] * inv_l;
-    const float bk = beta[k];
-    const float4 vv = *reinterpret_cast<const float4*>(jb.V + i4);
-    const float4 gg = *reinterpret_cast<const float4*>(jb.G + i4);
-    const float4 ss = *reinterpret_cast<const float4*>(jb.S + i4);
-    const float vin[4] = {vv.x, vv.y, vv.z, vv.w}, gin[4] = {gg.x, gg.y, gg.z, gg.w};
-    const float sin_[4] = {ss.x, ss.y, ss.z, ss.w};
-    float so[4], vo[4];
+    } else {
+        float* __restrict__ C = FWD ? jb.R : jb.G;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const float u = fmaf(-gin[j], inv_l, vin[j]);
-        const float sn = fmaxf(u - tau, 0.f) + fminf(u + tau, 0.f);
-        so[j] = sn;
-        vo[j] = fmaf(bk, sn - sin_[j], sn);
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = r0 + wr + 32 * i + 8 * (r >> 2) + 4 * kh + (r & 3);
+                    const int col = c0 + wc + 32 * j + lc;
+                    if (row < nblk && col < N) {
+                        float v = acc[i][j][r];
+                        if (FWD) v = col < M ? v - jb.y[(size_t)row * N + col] : 0.f;
+                        C[(size_t)row * N + col] = v;
+                    }
+                }
     }
-    *reinterpret_cast<float4*>(jb.S + i4) = make_float4(so[0], so[1], so[2], so[3]);
-    *reinterpret_cast<float4*>(jb.V + i4) = make_float4(vo[0], vo[1], vo[2], vo[3]);
 }
 
 static void check_batch(const F32Batch& bt, int ngop, int n, int Mp) {
@@ -202,14 +203,14 @@ void launch_f32_adjoint(const F32Batch& bt, int ngop, int n, int Mp, hipStream_t
     CSV_HIP(hipGetLastError());
 }
 
-void launch_f32_prox(const F32Batch& bt, int ngop, int n, const float* beta, int k,
-                     hipStream_t st) {
-    check_batch(bt, ngop, n, 16);
+void launch_f32_adjoint_prox(const F32Batch& bt, int ngop, int n, int Mp, const float* beta,
+                             int k, hipStream_t st) {
+    check_batch(bt, ngop, n, Mp);
+    CSV_REQUIRE(beta != nullptr && k >= 0, CSV_EINVAL, "FISTA step table");
     const int rows = max_rows(bt, ngop);
     if (!rows) return;
-    const size_t threads = (size_t)rows * n / 4;
-    f32_prox_kernel<<<dim3((unsigned)((threads + 255) / 256), ngop), dim3(256), 0, st>>>(bt, n,
-                                                                                       beta, k);
+    f32_gemm_kernel<false, 128, true><<<dim3(ceil_div(n, 128), ceil_div(rows, kGM), ngop),
+                                        dim3(256), 0, st>>>(bt, n, Mp, Mp, beta, k);
     CSV_HIP(hipGetLastError());
 }
 
