@@ -60,8 +60,11 @@ def _decode_compare(ctx, spec, flags=0, **okw):
 
 @pytest.mark.parametrize("spec", [sv.qcif_tiny(), sv.cif_sweep(4, 0.1, iters=300),
                                   sv.cif_sweep(4, 0.5, iters=300),
-                                  sv.qcif_tiny().with_(block=32, m=256, gop=3)],
-                         ids=["qcif-tiny", "cif-m26", "cif-m128", "qcif-b32-padded"])
+                                  sv.qcif_tiny().with_(block=32, m=256, gop=3),
+                                  sv.qcif_tiny().with_(m=150, gop=2),
+                                  sv.qcif_tiny().with_(block=32, m=300, gop=2)],
+                         ids=["qcif-tiny", "cif-m26", "cif-m128", "qcif-b32-padded",
+                              "qcif-m150-mp160", "qcif-b32-m300-mp320"])
 def test_decode_fp32_matches_oracle(ctx, spec):
     announce(f"decode fp32 {spec.width}x{spec.height} G={spec.gop} B={spec.block} M={spec.m}")
     _decode_compare(ctx, spec)
