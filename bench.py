@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--psnr-floor", type=float, default=32.0,
                     help="configure mode: PSNR floor standing in for the tracking requirement")
     ap.add_argument("--serve-window", type=float, default=2.0, help="seconds per sweep point")
-    ap.add_argument("--serve-loads", type=str, default="0.01,0.02,0.04,0.08,0.16,0.32",
+    ap.add_argument("--serve-loads", type=str, default="0.01,0.02,0.04,0.08,0.16,0.24,0.32",
                     help="fractions of the cameras' nominal GOP rates")
     return ap.parse_args()
 
