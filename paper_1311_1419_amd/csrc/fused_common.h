@@ -122,25 +122,29 @@ __device__ inline void load_fwd_head(u16x8 (&af)[kPF][NF], const gu16x8* ffwd, i
 }
 
 // R = P - y for one forward tile, written to LDS as bf16 (y from registers
-// or from global memory).
-template <int MP, int CT, bool YREG>
+// or from global memory).  NEG: R' = (y - P) * scale instead, so that an
+// adjoint accumulator started at v ends at v - A^T (P - y) scale.
+template <int MP, int CT, bool YREG, bool NEG = false>
 __device__ inline void store_residual(const floatx16& acc, const floatx16& yv, const gfloat* yg,
-                                      int nblk, int mt, int fct, int ln, u16x8* Rb) {
+                                      int nblk, int mt, int fct, int ln, u16x8* Rb,
+                                      float scale = 1.f) {
     const int h = ln >> 5, b = fct * 32 + (ln & 31);
-    floatx16 rr = acc;
+    floatx16 yy = {};
     if constexpr (YREG) {
-        rr -= yv;
+        yy = yv;
     } else if (b < nblk) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const gfloat* yp = yg + (size_t)b * MP + mt * 32 + 8 * q + 4 * h;
-            const float4 y4 = make_float4(yp[0], yp[1], yp[2], yp[3]);
-            rr[4 * q] -= y4.x;
-            rr[4 * q + 1] -= y4.y;
-            rr[4 * q + 2] -= y4.z;
-            rr[4 * q + 3] -= y4.w;
+            yy[4 * q] = yp[0];
+            yy[4 * q + 1] = yp[1];
+            yy[4 * q + 2] = yp[2];
+            yy[4 * q + 3] = yp[3];
         }
     }
+    floatx16 rr;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) rr[r] = NEG ? (yy[r] - acc[r]) * scale : acc[r] - yy[r];
     Rb[((2 * mt) * CT + fct) * 64 + ln] = pack_bf16(rr, 0);
     Rb[((2 * mt + 1) * CT + fct) * 64 + ln] = pack_bf16(rr, 1);
 }

@@ -14,12 +14,14 @@
 // iteration:
 //   forward  P = A V  (M x 32CT, K = n): output tiles split over the waves by
 //            M rows; V comes from LDS as bf16 B fragments; A streams from
-//            global memory (L2) as bf16 A fragments;  R = P - y  (FP32,
-//            y held in registers) is written back to LDS as bf16;
-//   adjoint  G = A^T R  (n x 32CT, K = M): each wave computes its own rows,
-//            R from LDS, A^T streamed as bf16 fragments; the threshold and
-//            momentum update runs on the accumulators in registers and the
-//            new V is written to LDS as bf16.
+//            global memory (L2) as bf16 A fragments;  R' = (y - P) / L
+//            (FP32, y read from L2) is written back to LDS as bf16;
+//   adjoint  u = V + A^T R'  (n x 32CT, K = M): each wave computes its own
+//            rows, its accumulators started at v, R' from LDS, A^T streamed
+//            as bf16 fragments, so the product ends at the gradient step
+//            u = v - A^T (A v - y) / L; the threshold and momentum update
+//            runs on the accumulators in registers and the new V is written
+//            to LDS as bf16.
 // A 32-row accumulator tile feeds the next product's K dimension without a
 // shuffle: in K step s of a 32x32x16 MFMA, lane half h, element e carries
 // row kappa_s(h, e) = 16 s + 8 (e / 4) + 4 h + e % 4 of the group, which is
@@ -189,8 +191,8 @@ void fista_bf16_kernel(
                                                                   Al + (size_t)w * FT * NL * 64);
 #pragma unroll
                 for (int i = 0; i < FT; ++i)
-                    store_residual<MP, CT, YREG>(acc[i], yv[YREG ? i : 0], yg, tl.nblk,
-                                                 (w + W * i) / CT, fct, ln, Rb);
+                    store_residual<MP, CT, YREG, true>(acc[i], yv[YREG ? i : 0], yg, tl.nblk,
+                                                       (w + W * i) / CT, fct, ln, Rb, inv_l);
             } else {
                 bool done = false;
                 if constexpr (FT > 1) {
@@ -202,8 +204,9 @@ void fista_bf16_kernel(
                                                                           Vb, w, ln, fct, w * RT);
 #pragma unroll
                         for (int i = 0; i < FT - 1; ++i)
-                            store_residual<MP, CT, YREG>(acc[i], yv[YREG ? i : 0], yg, tl.nblk,
-                                                         (w + W * i) / CT, fct, ln, Rb);
+                            store_residual<MP, CT, YREG, true>(acc[i], yv[YREG ? i : 0], yg,
+                                                               tl.nblk, (w + W * i) / CT, fct, ln,
+                                                               Rb, inv_l);
                         done = true;
                     }
                 }
@@ -225,7 +228,8 @@ void fista_bf16_kernel(
             for (int g = 0; g < NG; ++g) {
                         const int rt0 = (2 * g) / CT, ct0 = (2 * g) % CT;
                 const int rt1 = (2 * g + 1) / CT, ct1 = (2 * g + 1) % CT;
-                floatx16 ga[2] = {floatx16{}, floatx16{}};
+                // started at v: with R' = (y - A v) / L the product ends at u
+                floatx16 ga[2] = {vv[rt0][ct0], vv[rt1][ct1]};
 #pragma unroll 1
                 for (int ks0 = 0; ks0 < KSA - kPA; ks0 += kPA) {
 #pragma unroll
@@ -284,7 +288,7 @@ void fista_bf16_kernel(
                     }
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
-                        const float u = fmaf(-ga[e][r], inv_l, vv[rt][ct][r]);
+                        const float u = ga[e][r];
                         const float sn = u - __builtin_amdgcn_fmed3f(u, -tc, tc);
                         vv[rt][ct][r] = fmaf(bk, sn - spv[r], sn);
                         spv[r] = sn;
@@ -354,21 +358,16 @@ static void launch_class(const FusedTile* tiles, const int* qoff, const int* que
 // (forward, adjoint), LDS-resident state tiles and workgroups per CU.
 // Variant 0 is the default; the autotuner (csv_autotune) times them and
 // records a choice.
-#define CSV_V(NN, MM, CT, W, PF, PA, SPL, OCC)                                    \
-    FusedVariant {                                                                 \
-        "ct" #CT "_w" #W "_pf" #PF "_pa" #PA "_spl" #SPL "_o" #OCC, CT, OCC,      \
-            &launch_class<NN, MM, CT, W, PF, PA, SPL, OCC, 0>                      \
+#define CSV_VG(NN, MM, CT, W, PF, PA, SPL, OCC, NLS, SUFFIX)                               \
+    FusedVariant {                                                                         \
+        "ct" #CT "_w" #W "_pf" #PF "_pa" #PA "_spl" #SPL "_o" #OCC SUFFIX, CT, OCC,         \
+            &launch_class<NN, MM, CT, W, PF, PA, SPL, OCC, NLS>                             \
     }
-#define CSV_VL(NN, MM, CT, W, PF, PA, SPL, OCC, NL)                                    \
-    FusedVariant {                                                                      \
-        "ct" #CT "_w" #W "_pf" #PF "_pa" #PA "_spl" #SPL "_o" #OCC "_lds" #NL, CT, OCC, \
-            &launch_class<NN, MM, CT, W, PF, PA, SPL, OCC, NL>                          \
-    }
-#define CSV_VLI(NN, MM, CT, W, PF, PA, SPL, OCC, NL)                                    \
-    FusedVariant {                                                                       \
-        "ct" #CT "_w" #W "_pf" #PF "_pa" #PA "_spl" #SPL "_o" #OCC "_ldsi" #NL, CT, OCC, \
-            &launch_class<NN, MM, CT, W, PF, PA, SPL, OCC, -NL>                          \
-    }
+#define CSV_V(NN, MM, CT, W, PF, PA, SPL, OCC) CSV_VG(NN, MM, CT, W, PF, PA, SPL, OCC, 0, "")
+#define CSV_VL(NN, MM, CT, W, PF, PA, SPL, OCC, NL) \
+    CSV_VG(NN, MM, CT, W, PF, PA, SPL, OCC, NL, "_lds" #NL)
+#define CSV_VLI(NN, MM, CT, W, PF, PA, SPL, OCC, NL) \
+    CSV_VG(NN, MM, CT, W, PF, PA, SPL, OCC, -NL, "_ldsi" #NL)
 
 struct ClassEntry {
     int n, Mp;
@@ -383,15 +382,15 @@ static std::vector<ClassEntry>& class_table() {
           CSV_V(256, 32, 2, 8, 4, 2, 0, 1), CSV_V(256, 32, 4, 8, 4, 2, 0, 1)},
          0},
         {256, 64,
-         {CSV_V(256, 64, 1, 4, 4, 2, 0, 3), CSV_V(256, 64, 2, 4, 4, 2, 0, 2),
+         {CSV_V(256, 64, 2, 4, 4, 2, 0, 2), CSV_V(256, 64, 1, 4, 4, 2, 0, 3),
           CSV_V(256, 64, 2, 8, 4, 2, 0, 1), CSV_V(256, 64, 4, 8, 4, 2, 0, 1)},
          0},
         {256, 96,
-         {CSV_V(256, 96, 2, 4, 2, 2, 0, 2), CSV_V(256, 96, 4, 8, 4, 2, 0, 1),
-          CSV_V(256, 96, 2, 8, 4, 2, 0, 1), CSV_V(256, 96, 1, 4, 2, 2, 0, 3)},
+         {CSV_V(256, 96, 1, 4, 2, 2, 0, 3), CSV_V(256, 96, 2, 4, 2, 2, 0, 2),
+          CSV_V(256, 96, 4, 8, 4, 2, 0, 1), CSV_V(256, 96, 2, 8, 4, 2, 0, 1)},
          0},
         {256, 128,
-         {CSV_V(256, 128, 2, 4, 2, 2, 0, 2), CSV_V(256, 128, 1, 4, 2, 2, 0, 3),
+         {CSV_V(256, 128, 1, 4, 2, 2, 0, 3), CSV_V(256, 128, 2, 4, 2, 2, 0, 2),
           CSV_V(256, 128, 2, 8, 4, 2, 0, 1), CSV_V(256, 128, 4, 8, 4, 2, 0, 1)},
          0},
         {1024, 32,
@@ -399,8 +398,8 @@ static std::vector<ClassEntry>& class_table() {
           CSV_V(1024, 32, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 32, 1, 8, 4, 2, 0, 1, 8)},
          0},
         {1024, 64,
-         {CSV_V(1024, 64, 1, 8, 4, 2, 0, 1), CSV_V(1024, 64, 1, 8, 4, 2, 2, 1),
-          CSV_VL(1024, 64, 1, 8, 4, 2, 0, 1, 8), CSV_VLI(1024, 64, 1, 8, 4, 2, 0, 1, 8)},
+         {CSV_VLI(1024, 64, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 64, 1, 8, 4, 2, 0, 1),
+          CSV_V(1024, 64, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 64, 1, 8, 4, 2, 0, 1, 8)},
          0},
         {1024, 128,
          {CSV_VLI(1024, 128, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 128, 1, 8, 4, 2, 0, 1),
@@ -425,6 +424,7 @@ static std::vector<ClassEntry>& class_table() {
 #undef CSV_V
 #undef CSV_VL
 #undef CSV_VLI
+#undef CSV_VG
 
 static ClassEntry* find_class(int n, int Mp) {
     for (auto& c : class_table())
