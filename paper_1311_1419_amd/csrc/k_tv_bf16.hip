@@ -9,7 +9,9 @@
 //   nu = mu + beta D x;  w = shrink(D x + nu / beta, lam / beta);
 //   mu <- nu - beta w;   P = mu + beta D x;  x <- x - alpha (G + D^T P),
 // with D the forward differences inside the block (Neumann boundary); D x of
-// the dual step is kept for the primal step.
+// the dual step is kept for the primal step.  The residual goes to LDS as
+// alpha (y^ - Phi x) and the adjoint accumulator starts at x, so the Phi^T
+// product ends at x - alpha G.
 //
 // Layout.  Eight waves; wave w owns pixel group w (pixels 32 w .. 32 w + 31 =
 // image rows 2 w and 2 w + 1 of every block) in the 32x32 MFMA accumulator
@@ -185,14 +187,16 @@ void tv_bf16_kernel(const FusedTile* __restrict__ tiles, const int* __restrict__
             if (fwd) {
                 floatx16 acc[1];
                 forward_tiles<N, MP, CT, 1, 1, W, kPF, kPA>(af, aa, acc, ffwd, fadj, Vb, w, ln, 0, w);
-                store_residual<MP, CT, false>(acc[0], acc[0], yg, tl.nblk, w, 0, ln, Rb);
+                // R' = alpha (y^ - Phi V): the adjoint started at x ends at x - alpha G
+                store_residual<MP, CT, false, true>(acc[0], acc[0], yg, tl.nblk, w, 0, ln, Rb,
+                                                    alpha);
             } else {
 #pragma unroll
                 for (int p = 0; p < kPA; ++p) aa[p][0] = fadj[((size_t)w * KSA + p) * 64 + ln];
             }
             __syncthreads();
-            // ---- adjoint G = Phi^T R for group w
-            floatx16 g = {};
+            // ---- adjoint for group w: g = x - alpha Phi^T (Phi x - y^)
+            floatx16 g = x;
 #pragma unroll 1
             for (int ks0 = 0; ks0 < KSA - kPA; ks0 += kPA) {
 #pragma unroll
@@ -230,7 +234,7 @@ void tv_bf16_kernel(const FusedTile* __restrict__ tiles, const int* __restrict__
                         dt += pv[r - 8];
                     else if (w > 0)
                         dt += prow[((w - 1) * 8 + r) * 64 + ln];
-                    x[r] = fmaf(-alpha, g[r] + dt, x[r]);
+                    x[r] = fmaf(-alpha, dt, g[r]);
                 }
             }
             Vb[(2 * w) * 64 + ln] = pack_bf16(x, 0);
