@@ -223,7 +223,7 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
     const size_t sz_q = Mp * n, sz_a64 = Mp * n * 8, sz_a32 = Mp * n * 4;
     const size_t sz_frag = Mp * n * 2, sz_lip = 64, sz_dct = n * 4, sz_dct64 = n * 8;
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
-    const size_t total = 2 * al(sz_q) + al(sz_a64) + 2 * al(sz_a32) + 4 * al(sz_frag) +
+    const size_t total = 4 * al(sz_q) + al(sz_a64) + 2 * al(sz_a32) + 4 * al(sz_frag) +
                          al(sz_lip) + al(sz_dct) + al(sz_dct64);
     char* base = static_cast<char*>(ctx_alloc(c, total));
     op->bytes = total;
@@ -235,6 +235,8 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
     };
     op->q = reinterpret_cast<int8_t*>(take(sz_q));
     op->q8 = reinterpret_cast<uint8_t*>(take(sz_q));
+    op->qb_fwd = reinterpret_cast<uint8_t*>(take(sz_q));
+    op->qb_adj = reinterpret_cast<uint8_t*>(take(sz_q));
     op->a64 = reinterpret_cast<double*>(take(sz_a64));
     op->a32 = reinterpret_cast<float*>(take(sz_a32));
     op->phi32 = reinterpret_cast<float*>(take(sz_a32));
@@ -250,6 +252,7 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
         launch_q_e4m3(op->q, op->q8, s.Mp * s.n, st);
         launch_operator_setup(op.get(), st);
         launch_bf16_frag_layout(op.get(), st);
+        launch_q8_frag_layout(op.get(), st);
         int* gram = static_cast<int*>(scratch(c, "gram", (size_t)s.M * s.M * 4));
         launch_power_iteration(op.get(), gram, st);
     } catch (...) {
@@ -425,6 +428,10 @@ static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st
             FusedTile t{};
             t.frag_fwd = j.tv ? j.op->phi_frag_fwd : j.op->frag_fwd;
             t.frag_adj = j.tv ? j.op->phi_frag_adj : j.op->frag_adj;
+            t.qb_fwd = j.op->qb_fwd;
+            t.qb_adj = j.op->qb_adj;
+            t.dct = j.op->dct;
+            t.s_phi = (float)j.op->s_phi;
             t.lip = j.op->lip;
             t.y = j.y + (size_t)b0 * s.Mp;
             t.lam = j.lam + b0;

@@ -64,6 +64,8 @@ struct Operator {
     double* a64 = nullptr;        // Mp x n, A = s_phi Q Psi (final FP64 check)
     float* a32 = nullptr;         // Mp x n
     float* phi32 = nullptr;       // Mp x n, s_phi Q
+    uint8_t* qb_fwd = nullptr;    // Q + 64, forward fragment order (int8-Q fused kernel)
+    uint8_t* qb_adj = nullptr;    // Q + 64, adjoint fragment order
     uint16_t* frag_fwd = nullptr; // bf16 A in forward-product fragment order
     uint16_t* frag_adj = nullptr; // bf16 A in adjoint-product fragment order
     uint16_t* phi_frag_fwd = nullptr;   // bf16 Phi, forward fragment order (TV)
@@ -294,6 +296,10 @@ void launch_tv_final64(const int8_t* q, const float* x, const int8_t* codes, con
 struct FusedTile {
     const uint16_t* frag_fwd;
     const uint16_t* frag_adj;
+    const uint8_t* qb_fwd;   // Q + 64 in forward fragment order (k_fista_q8.hip)
+    const uint8_t* qb_adj;   // Q + 64 in adjoint fragment order
+    const float* dct;        // B x B DCT table
+    float s_phi;
     const double* lip;
     const float* y;      // nblk x Mp
     const float* lam;    // nblk
@@ -304,6 +310,9 @@ struct FusedTile {
     int n, Mp;
 };
 void launch_bf16_frag_layout(Operator* op, hipStream_t st);
+void launch_q8_frag_layout(Operator* op, hipStream_t st);
+void launch_fista_q8_m256(const FusedTile* tiles, const int* qoff, const int* queue,
+                          int* counters, int grid, hipStream_t st);
 struct FusedVariant {
     const char* name;
     int ct;    // column tiles of 32 blocks per workgroup
