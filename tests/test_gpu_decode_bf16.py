@@ -189,18 +189,33 @@ def test_mixed64_batch_sampled_blocks(ctx):
             assert np.max(np.abs(fl[t][sl] - ref)) <= MAXABS_TOL, (i, t, b)
 
 
-def test_full_batch_equals_alone(ctx):
-    """The 16-camera 640x480 GOP-16 M=256 batch (2256 tiles of 32 blocks:
-    persistent workgroups take several tiles and switch between the
-    streams' operators) decodes every GOP bit for bit as it decodes alone
-    (141 tiles, at most one per workgroup)."""
-    announce("bf16 16 x vga g16 m256 batch vs alone")
+@pytest.fixture(scope="module")
+def vga16_items(ctx):
     specs = [sv.vga_precision(0.25, stream=s) for s in range(16)]
     items = []
     for spec in specs:
         p = _bf16(spec)
         items.append((ctx.encode_gop(dev(spec.video()), p), p))
-    batch = ctx.decode_batch(items, want_float=True)
-    for i, (gs, p) in enumerate(items):
-        fa = ctx.decode_gop(gs, p, want_float=True)[1]
-        assert bool((fa == batch[i][1]).all()), f"stream {i}"
+    return items
+
+
+@pytest.mark.parametrize("variant", range(8))
+def test_full_batch_equals_alone(ctx, vga16_items, variant):
+    """The 16-camera 640x480 GOP-16 M=256 batch (2256 tiles of 32 blocks:
+    persistent workgroups take several tiles and switch between the
+    streams' operators) decodes every GOP bit for bit as it decodes alone
+    (141 tiles, at most one per workgroup), with every kernel variant of
+    the class."""
+    import paper_1311_1419_amd as P
+    name0, idx0, count = P.kernel_choice(32, 256)
+    if variant >= count:
+        pytest.skip(f"the class has {count} variants")
+    P.set_kernel_choice(32, 256, variant)
+    try:
+        announce(f"bf16 16 x vga g16 m256 batch vs alone, variant {P.kernel_choice(32, 256)[0]}")
+        batch = ctx.decode_batch(vga16_items, want_float=True)
+        for i, (gs, p) in enumerate(vga16_items):
+            fa = ctx.decode_gop(gs, p, want_float=True)[1]
+            assert bool((fa == batch[i][1]).all()), f"stream {i}"
+    finally:
+        P.set_kernel_choice(32, 256, idx0)
