@@ -219,3 +219,21 @@ def test_full_batch_equals_alone(ctx, vga16_items, variant):
             assert bool((fa == batch[i][1]).all()), f"stream {i}"
     finally:
         P.set_kernel_choice(32, 256, idx0)
+
+
+def test_batched_objective_equals_alone(ctx):
+    """The FP64 check of a batch runs one launch per (n, M) group; GOPs of
+    one group with different block counts (sizes and GOP lengths) give the
+    objectives, frames and relative residuals they give decoded alone."""
+    announce("bf16 batched FP64 check vs alone")
+    specs = [sv.vga_precision(0.25, gop=3, stream=40), sv.qcif_tiny().with_(block=32, m=256, gop=5),
+             sv.cif_sweep(4, 0.25, stream=41).with_(block=32, m=256), sv.vga_precision(0.1, gop=2)]
+    items = []
+    for spec in specs:
+        p = _bf16(spec)
+        items.append((ctx.encode_gop(dev(spec.video()), p), p))
+    batch = ctx.decode_batch(items, want_float=True, want_obj=True)
+    for i, (gs, p) in enumerate(items):
+        out, fl, obj = ctx.decode_gop(gs, p, want_float=True, want_obj=True)
+        assert bool((out == batch[i][0]).all()), f"frames {i}"
+        assert bool((obj == batch[i][2]).all()), f"objective {i}"
