@@ -12,8 +12,8 @@ with counter words 0 and 2, and outputs
 the key is advanced by the two Weyl increments before every round but the
 first.
 
-Measurement matrix (reading of "Gaussian random matrix", Sections 1, 3.1
-and 4): entry (i, j) of the M x n integer matrix Q takes word (i*n+j) mod 4 of
+Measurement matrix (the paper asks only for a random Gaussian matrix,
+Sections 1, 3.1 and 4): entry (i, j) of the M x n integer matrix Q takes word (i*n+j) mod 4 of
 philox(counter=((i*n+j) div 4, n, 0, 0), key=(phi_seed, stream_id)) and sets
 Q_ij = popcount(word) - 32, a Binomial(64, 1/2) - 32 variable in [-32, 32]:
 mean 0, variance 16, excess kurtosis -1/32.  Phi = Q / (4 sqrt(M)) then has

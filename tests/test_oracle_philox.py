@@ -3,7 +3,7 @@
 The Philox4x64-10 round function (Salmon et al., SC'11) is checked against
 numpy's own, independently written Philox bit generator; the measurement
 matrix against the moments of Binomial(64, 1/2) - 32 (Sections 1 and 4 only
-ask for a Gaussian random matrix)."""
+ask for a random Gaussian matrix)."""
 import numpy as np
 import pytest
 
