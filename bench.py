@@ -31,6 +31,17 @@ sys.path.insert(0, ROOT)
 METRIC = "recovered Mpixel/s at M/n=0.25, BF16-MFMA vs FP32, ≤0.1dB PSNR loss; p99 ms"
 KERNEL_SRC = [os.path.join(ROOT, "paper_1311_1419_amd", "csrc", f)
               for f in ("k_fista_bf16.hip", "fused_common.h")]
+
+
+def kernel_source_digest():
+    """sha256 of the profiled kernel's source: the fista_bf16_kernel template
+    (k_fista_bf16.hip, up to its launcher) followed by fused_common.h, so the
+    variant table can change without voiding the counters."""
+    import hashlib
+    txt = open(KERNEL_SRC[0]).read()
+    a = txt.index("template <int N, int MP, int CT, int W, int kPF")
+    b = txt.index("template <int N, int MP, int CT, int W, int PF,", a)
+    return hashlib.sha256((txt[a:b] + open(KERNEL_SRC[1]).read()).encode()).hexdigest()
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "fista_bf16_vga640x480_m256_x16_pmc.md")
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
 WORKLOAD = "vga640x480-g16-b32-m256-t300-x16streams"
@@ -117,7 +128,7 @@ def measured_traffic(streams):
     txt = open(PMC_SUMMARY).read()
     sha = re.search(r"kernel_source_sha256: (\w+)", txt)
     tb = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
-    cur = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SRC)).hexdigest()
+    cur = kernel_source_digest()
     if not sha or not tb or sha.group(1) != cur:
         return None
     return int(tb.group(1))

@@ -443,15 +443,17 @@ const std::vector<FusedVariant>& fused_variants(int n, int Mp) {
     return c->v;
 }
 
+// The choice of a class is process-wide and may be set (csv_autotune,
+// csv_autotune_load) while other threads decode: read and written atomically.
 int fused_choice(int n, int Mp) {
     ClassEntry* c = find_class(n, Mp);
-    return c ? c->choice : 0;
+    return c ? __atomic_load_n(&c->choice, __ATOMIC_RELAXED) : 0;
 }
 
 void set_fused_choice(int n, int Mp, int idx) {
     ClassEntry* c = find_class(n, Mp);
     CSV_REQUIRE(c && idx >= 0 && idx < (int)c->v.size(), CSV_EINVAL, "no such kernel variant");
-    c->choice = idx;
+    __atomic_store_n(&c->choice, idx, __ATOMIC_RELAXED);
 }
 
 std::vector<std::pair<int, int>> fused_classes() {
