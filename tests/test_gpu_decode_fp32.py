@@ -169,3 +169,20 @@ def test_context_memory_budget(ctx):
         ref = codec.decode_gop(codec.encode_gop(frames, op), op)
         out, _, _ = c.decode_gop(c.encode_gop(dev(frames), _gpu_params(small)), _gpu_params(small))
         assert np.array_equal(host(out)[0], ref.frames[0])
+
+
+def test_full_sampling_fp32_and_bf16_refusal(ctx):
+    """M = n (B = 16, M = 256: A is square and invertible) decodes on the
+    plain FP32 path to the FP32 bars; the fused BF16 path has no kernel for
+    a padded M above 128 at n = 256 and refuses with CSV_EUNSUPPORTED
+    before launching anything, leaving the context usable."""
+    import paper_1311_1419_amd as P
+    announce("full sampling M = n, fp32 decode and bf16 refusal")
+    spec = sv.qcif_tiny().with_(m=256, gop=2)
+    _decode_compare(ctx, spec)
+    pb = P.Params.from_spec(spec, precision=P.CSV_BF16)
+    gs = ctx.encode_gop(dev(spec.video()), pb)
+    with pytest.raises(P.CsvError) as ei:
+        ctx.decode_gop(gs, pb)
+    assert ei.value.code == P._native.CSV_EUNSUPPORTED
+    _decode_compare(ctx, sv.qcif_tiny().with_(gop=2))
