@@ -147,6 +147,29 @@ def test_objective_matches_sklearn_lasso():
         assert abs(f_ours - f_sk) <= 1e-9 * f_sk
 
 
+def test_objective_orthonormal_closed_form():
+    """With an orthonormal operator (A = I) the LASSO minimiser is soft(y,
+    lam), and the minimal objective is the Huber function of y:
+    sum_i y_i^2 / 2 where |y_i| <= lam, else lam |y_i| - lam^2 / 2."""
+    rng = np.random.default_rng(11)
+    n, nb = 64, 5
+    a = np.eye(n)
+    y = rng.normal(0, 2.0, size=(n, nb))
+    lam = rng.uniform(0.3, 2.5, size=nb)
+    s = cs.soft(y, lam[None, :])
+    ay = np.abs(y)
+    huber = np.where(ay <= lam[None, :], 0.5 * y * y, lam[None, :] * ay - 0.5 * lam[None, :] ** 2)
+    assert np.allclose(cs.objective(a, y, s, lam), huber.sum(axis=0), rtol=1e-13, atol=0)
+    # FISTA with L = 1 reaches that minimiser in one step from zero
+    assert np.allclose(cs.fista(a, y, lam, 1.0, 5), s, rtol=0, atol=1e-12)
+
+
+def test_round_to_u8_ties_to_even_and_clips():
+    """Synthesis rounding reading: round half to even, then clip to [0, 255]."""
+    f = np.array([0.5, 1.5, 2.5, 3.49999, -0.5, -3.0, 254.5, 255.5, 300.0, 127.5])
+    assert cs.round_to_u8(f).tolist() == [0, 2, 2, 3, 0, 0, 254, 255, 255, 128]
+
+
 def test_ista_and_mfista_monotone_fista_rate_bound():
     q, s_phi, a = _problem(64, 16, seed=8)
     rng = np.random.default_rng(8)
