@@ -85,3 +85,20 @@ def test_tiny_end_to_end_quality():
         assert rec > key_only
         assert rec > 25.0
     assert np.all(dec.objective > 0) and np.all(dec.rel_residual < 1.0)
+
+
+def test_lambda_scales_with_its_fraction():
+    """lambda_b = frac * ||A^T y^_b||_inf is linear in frac: decoding the
+    same stream with three times the fraction gives exactly three times every
+    lambda, and a different recovery (a larger threshold), for the l1 and the
+    TV solver alike."""
+    spec = sv.qcif_tiny().with_(gop=2, iters=60)
+    frames = spec.video()
+    for solver in ("fista", "tv"):
+        p1 = codec.Params.from_spec(spec, lambda_frac=0.01, solver=solver)
+        p3 = codec.Params.from_spec(spec, lambda_frac=0.03, solver=solver)
+        gs = codec.encode_gop(frames, p1)
+        d1, d3 = codec.decode_gop(gs, p1), codec.decode_gop(gs, p3)
+        assert np.all(d1.lam > 0)
+        assert np.allclose(d3.lam, 3.0 * d1.lam, rtol=1e-12, atol=0)
+        assert not np.array_equal(d1.cs_float, d3.cs_float)
