@@ -103,3 +103,18 @@ def test_tv_decode_beats_dct_lasso_on_surveillance_video():
     d_l1 = codec.decode_gop(gs, p)
     d_tv = codec.decode_gop(gs, codec.Params.from_spec(spec, solver="tv"))
     assert codec.psnr(frames[1], d_tv.frames[1]) > codec.psnr(frames[1], d_l1.frames[1]) + 1.0
+
+
+def test_step_of_the_iteration_closed_form():
+    """With Phi = I (L = 1) and lambda = 0 (beta = 1) the shrinkage is the
+    identity, the multipliers stay zero, and the iteration is gradient
+    descent on 1/2 ||x - y||^2 with the step alpha = 1 / (L + 8 beta) = 1/9:
+    x_k = y (1 - (8/9)^k) exactly (up to rounding), for blocks and frames."""
+    rng = np.random.default_rng(3)
+    for b in (8, (6, 10)):
+        hh, ww = (b, b) if isinstance(b, int) else b
+        n = hh * ww
+        y = rng.normal(0, 5.0, size=(n, 3))
+        for k in (1, 2, 7):
+            x = tv.recover(np.eye(n), y, np.zeros(3), 1.0, b, k)
+            assert np.allclose(x, y * (1.0 - (8.0 / 9.0) ** k), rtol=0, atol=1e-12)
