@@ -621,10 +621,17 @@ static void ensure_aux(Ctx* c);
 static void fork_aux(Ctx* c, hipStream_t st);
 static void join_aux(Ctx* c, hipStream_t st);
 
+// Lane k of the per-GOP chains: 0 is st itself, 1..kAux the auxiliary
+// streams, so that st and the kAux streams fill the process's hardware queues
+// while the chains run side by side.
+static hipStream_t chain_lane(Ctx* c, hipStream_t st, int k) {
+    return k == 0 ? st : c->aux[k - 1];
+}
+
 // Encode `count` GOPs (Section 3.1, Fig. 3): key frame coded and decoded,
 // every CS frame's residual against the decoded key frame (eqs. (2)-(3))
-// measured per block and quantised.  GOP i runs on auxiliary stream
-// i % kAux with scratch of its own (one GOP alone runs on st).
+// measured per block and quantised.  GOP i runs on lane i % (kAux + 1) with
+// scratch of its own (one GOP alone runs on st).
 void encode_gops(Ctx* c, int count, const Shape* shapes, const uint8_t* const* frames,
                  const csv_gop_stream* out, hipStream_t st) {
     std::vector<Operator*> ops(count, nullptr);
@@ -650,7 +657,7 @@ void encode_gops(Ctx* c, int count, const Shape* shapes, const uint8_t* const* f
     if (spread) fork_aux(c, st);
     for (int i = 0; i < count; ++i) {
         const Shape& s = shapes[i];
-        const hipStream_t ls = spread ? c->aux[i % Ctx::kAux] : st;
+        const hipStream_t ls = spread ? chain_lane(c, st, i % (Ctx::kAux + 1)) : st;
         const int ncs = s.G - 1;
         unsigned long long* bits = reinterpret_cast<unsigned long long*>(out[i].bits);
         if (bits) {
@@ -853,13 +860,16 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
         }
     }
     if (!any_block) return;
-    // GOP i's per-GOP kernels run on auxiliary stream i % kAux (one GOP
-    // alone stays on st); each auxiliary stream has its own lambda scratch
+    // GOP i's preparation runs on lane i % (kAux + 1), st included, and its
+    // synthesis on auxiliary stream i % kAux, beside the FP64 checks on st
+    // (one GOP alone stays on st); each lane has its own lambda scratch
     const bool spread = count > 1;
     if (spread) ensure_aux(c);
+    constexpr int kLanes = Ctx::kAux + 1;
+    auto prep_lane = [&](int i) { return spread ? chain_lane(c, st, i % kLanes) : st; };
     auto lane_of = [&](int i) { return spread ? c->aux[i % Ctx::kAux] : st; };
     auto g0_of = [&](int i) {
-        return spread ? "g0@" + std::to_string(i % Ctx::kAux) : std::string("g0");
+        return spread ? "g0@" + std::to_string(i % kLanes) : std::string("g0");
     };
     // scratch is sized before any launch that reads it
     for (int i = 0; i < count; ++i) {
@@ -877,7 +887,7 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
     for (int i = 0; i < count; ++i) {
         const Shape& s = shapes[i];
         Item& it = items[i];
-        const hipStream_t ls = lane_of(i);
+        const hipStream_t ls = prep_lane(i);
         if (it.whole) continue;
         {
             ProfScope ps(c, "key_decode", ls);
