@@ -186,3 +186,28 @@ def test_full_sampling_fp32_and_bf16_refusal(ctx):
         ctx.decode_gop(gs, pb)
     assert ei.value.code == P._native.CSV_EUNSUPPORTED
     _decode_compare(ctx, sv.qcif_tiny().with_(gop=2))
+
+
+def test_fp32_batch_equals_alone(ctx):
+    """The plain FP32 path decodes a batch group by group (GOPs of one
+    (n, M, T) shape share each product launch, every GOP with its own
+    operator and block count) and prepares the GOPs on four streams; each
+    GOP's frames, float frames and FP64 objectives equal those of the GOP
+    decoded alone, bit for bit.  Five GOPs: two groups of two (different
+    streams and sizes) and one alone, so the fifth wraps to the first
+    stream."""
+    announce("fp32 batch vs alone (5 GOPs, 3 shape groups)")
+    specs = [sv.qcif_tiny(), sv.cif_sweep(4, 0.1, stream=1), sv.qcif_tiny(stream=3),
+             sv.qcif_tiny().with_(block=32, m=102, stream_id=9, phi_seed=99),
+             sv.cif_sweep(4, 0.1, stream=2).with_(width=176, height=144)]
+    items = []
+    for spec in specs:
+        p = _gpu_params(spec)
+        items.append((ctx.encode_gop(dev(spec.video()), p), p))
+    batch = ctx.decode_batch(items, want_float=True, want_obj=True)
+    for i, (gs, p) in enumerate(items):
+        out, fl, obj = ctx.decode_gop(gs, p, want_float=True, want_obj=True)
+        bo, bf, bj = batch[i]
+        assert np.array_equal(host(out), host(bo)), f"frames {i}"
+        assert np.array_equal(host(fl), host(bf)), f"float frames {i}"
+        assert np.array_equal(host(obj), host(bj)), f"objective {i}"
