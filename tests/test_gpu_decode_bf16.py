@@ -127,6 +127,42 @@ def test_bf16_full_size_sampled_blocks(ctx):
         assert np.max(np.abs(fl[t][sl] - ref)) <= MAXABS_TOL, (t, b)
 
 
+def test_bf16_serving_hd_camera_sampled_blocks(ctx):
+    """A full-size GOP of the serving mix: one 1280x720 camera, GOP 32, B=16,
+    M/n = 0.25 (M = 64), 31 x 3600 blocks decoded as one GOP.  The oracle
+    recovers 17 sampled blocks one by one (spread over the GOP, plus the
+    last blocks of the last frame) and the GPU's pixels must agree."""
+    announce("bf16 full-size 1280x720 g32 b16 m64 sampled")
+    spec = sv.serving_cameras(6)[5][0]
+    assert (spec.width, spec.height, spec.gop, spec.block, spec.m) == (1280, 720, 32, 16, 64)
+    frames = spec.video()
+    p = _bf16(spec)
+    gs = ctx.encode_gop(dev(frames), p)
+    out, fl, _ = ctx.decode_gop(gs, p, want_float=True)
+    fl = host(fl)
+    key = host(out)[0].astype(np.float64)
+    codes, exps = host(gs.codes), host(gs.exps)
+    q = philox.measurement_matrix_q(spec.m, spec.n, spec.phi_seed, spec.stream_id)
+    s_phi = philox.phi_scale(spec.m)
+    a = cs.operator(q, s_phi, spec.block)
+    L, _, _ = cs.lipschitz(q, s_phi)
+    nb = codes.shape[1]
+    rng = np.random.default_rng(1)
+    picks = [(t, int(b)) for t in (0, 15, 30) for b in rng.choice(nb, 5, replace=False)]
+    picks += [(30, nb - 1), (30, nb - 2)]
+    bs = spec.block
+    nbx = spec.width // bs
+    for t, b in picks:
+        y = cs.dequantise(codes[t, b][:, None], exps[t, b:b + 1], s_phi)
+        lam = cs.lambdas(a, y)
+        s_hat = cs.fista(a, y, lam, L, spec.iters)
+        x = cs.synthesise(s_hat, bs)[:, 0].reshape(bs, bs)
+        by, bx = divmod(b, nbx)
+        sl = (slice(by * bs, by * bs + bs), slice(bx * bs, bx * bs + bs))
+        ref = key[sl] + x
+        assert np.max(np.abs(fl[t][sl] - ref)) <= MAXABS_TOL, (t, b)
+
+
 @pytest.mark.parametrize("spec", [sv.qcif_tiny(), sv.vga_precision(0.25, gop=3)],
                          ids=["qcif-b16-m64", "vga-b32-m256"])
 def test_decode_of_fp8_measured_gop(ctx, spec):
