@@ -73,3 +73,16 @@ def test_compression_ratio_identity():
     raw = 8 * 176 * 144
     assert cr["key"] == pytest.approx(raw / 40000)
     assert math.isfinite(cr["total"])
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built HIP library the package refuses to run: loading it,
+    and creating a decode context, raise instead of falling back."""
+    import paper_1311_1419_amd as P
+    from paper_1311_1419_amd import _native
+    monkeypatch.setattr(_native, "LIB_PATH", os.path.join(ROOT, "no-such-dir", "libcsv.so"))
+    monkeypatch.setattr(_native, "_lib", None)
+    with pytest.raises(ImportError, match="HIP library not built"):
+        _native.lib()
+    with pytest.raises(ImportError, match="HIP library not built"):
+        P.Context()
