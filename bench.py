@@ -63,13 +63,15 @@ def parse():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
     ap.add_argument("--mode", choices=["headline", "mixed", "serve", "encode", "configure", "tv",
-                                       "whole"],
+                                       "whole", "fp32", "b16"],
                     default="headline",
                     help="headline: the metric above; mixed: 64 mixed streams decoded by one "
                          "graph-captured batch; serve: 256 cameras under a Poisson load sweep; "
                          "encode: the headline cameras encoded in each measurement form; "
                          "configure: the (G, M) configurator sweep; tv: TV recovery vs l1; "
-                         "whole: whole-frame measurement with Q regenerated on the fly")
+                         "whole: whole-frame measurement with Q regenerated on the fly; "
+                         "fp32: the plain FP32 path alone on the headline workload; "
+                         "b16: the fused path on 16 x 352x288 GOP-16 B=16 M=64 cameras")
     ap.add_argument("--psnr-floor", type=float, default=32.0,
                     help="configure mode: PSNR floor standing in for the tracking requirement")
     ap.add_argument("--serve-window", type=float, default=2.0, help="seconds per sweep point")
@@ -563,6 +565,79 @@ def whole_main(args):
         "rates": res}), flush=True)
 
 
+def fp32_main(args):
+    """The plain FP32 path alone on the headline workload (16 x 640x480
+    GOP-16, B = 32, M = 256, T = 300): encode and decode as one batch per
+    step, the two FP32-MFMA products of every iteration with the residual
+    and the threshold/momentum step in their epilogues.  Per launch the
+    forward product reads v (4 n B per block) and the operator and writes
+    the residual (4 M_p B); the adjoint reads the residual and the operator
+    and, in its epilogue, reads v and s_{k-1} and writes both (16 n B)."""
+    import torch
+    import paper_1311_1419_amd as P
+    specs = make_streams(args.streams)
+    frames_dev = [torch.from_numpy(s.video()).cuda() for s in specs]
+    px = sum((s.gop - 1) * s.height * s.width for s in specs)
+    blocks = sum((s.gop - 1) * ((s.height + 31) // 32) * ((s.width + 31) // 32) for s in specs)
+    with P.Context(0) as ctx:
+        wall, per_step, _, _ = run_path(ctx, P, torch, specs, frames_dev, P.CSV_FP32,
+                                        args.steps, args.warmup)
+        k_ms, k_n = ctx.profile_query("fista_fp32")
+    it_s = k_ms / max(k_n, 1) / 1e3 / 300            # one iteration of the whole batch
+    flops = blocks * 4.0 * 256 * 1024                 # both products, one iteration
+    byts = blocks * (4 * 1024 + 4 * 256 + 4 * 256 + 16 * 1024 + 4 * 256)
+    print(json.dumps({
+        "metric": "recovered Mpixel/s, plain FP32 path, " + WORKLOAD,
+        "value": round(px * args.steps / wall / 1e6, 3), "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 4),
+        "p50_ms": round(float(np.percentile(per_step, 50)), 4),
+        "p99_ms": round(float(np.percentile(per_step, 99)), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "data": "synthetic", "config": {"workload": WORKLOAD + "-fp32", "blocks_per_step": blocks},
+        "iteration_us": round(1e6 * it_s, 2),
+        "fp32_mfma_tflops": round(flops / it_s / 1e12, 2),
+        "algorithmic_hbm_tbs": round(byts / it_s / 1e12, 3)}), flush=True)
+
+
+def b16_main(args):
+    """The fused path on the 16 x 16-block class: 16 synthetic 352x288
+    cameras, GOP 16, B = 16 (n = 256), M/n = 0.25 (M = 64), T = 300,
+    encoded and decoded as one batch per step (23 760 x 4 recovery blocks
+    in one launch of the (256, 64) class)."""
+    import torch
+    import paper_1311_1419_amd as P
+    import synthvid as sv
+    specs = [sv.cif_sweep(16, 0.25, stream=s) for s in range(args.streams)]
+    frames_dev = [torch.from_numpy(s.video()).cuda() for s in specs]
+    px = sum((s.gop - 1) * s.height * s.width for s in specs)
+    blocks = sum((s.gop - 1) * (s.height // 16) * (s.width // 16) for s in specs)
+    flops = sum((s.gop - 1) * (s.height // 16) * (s.width // 16) * 4.0 * s.m * s.n * s.iters
+                for s in specs)
+    with P.Context(0) as ctx:
+        wall, per_step, _, _ = run_path(ctx, P, torch, specs, frames_dev, P.CSV_BF16,
+                                        args.steps, args.warmup)
+        k_ms, k_n = ctx.profile_query("fista_bf16")
+    k_s = k_ms / max(k_n, 1) / 1e3
+    ach = flops / k_s / 1e12
+    print(json.dumps({
+        "metric": "recovered Mpixel/s, fused BF16 path, 16 x 352x288 GOP-16 B=16 M=64 T=300",
+        "value": round(px * args.steps / wall / 1e6, 3), "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 4),
+        "p50_ms": round(float(np.percentile(per_step, 50)), 4),
+        "p99_ms": round(float(np.percentile(per_step, 99)), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "cif352x288-g16-b16-m64-t300-x%dstreams" % args.streams,
+                   "blocks_per_step": blocks},
+        "roofline": {"bound": "mfma", "kernel": "fista_bf16_kernel[n=256,Mp=64] variant "
+                     + P.kernel_choice(16, 64)[0], "unit": "TFLOP/s",
+                     "achieved": round(ach, 2), "peak": PEAK_BF16_TFLOPS,
+                     "frac": round(ach / PEAK_BF16_TFLOPS, 4), "kernel_ms": round(1e3 * k_s, 4)}}),
+        flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -570,6 +645,13 @@ def main():
               "(the path shards by stream or GOP with no exchange between GPUs)",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_mib:
+        import torch
+        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.mode == "mixed":
         return mixed_main(args)
     if args.mode == "serve":
@@ -582,15 +664,13 @@ def main():
         return tv_main(args)
     if args.mode == "whole":
         return whole_main(args)
+    if args.mode == "fp32":
+        return fp32_main(args)
+    if args.mode == "b16":
+        return b16_main(args)
     import torch
     import paper_1311_1419_amd as P
 
-    if args.copy_mib:
-        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     specs = make_streams(args.streams)
     videos = [s.video() for s in specs]
     frames_dev = [torch.from_numpy(v).cuda() for v in videos]

@@ -183,17 +183,20 @@ def ista(a, y_hat, lam, L, iters, history=False):
     return (s, hist) if history else s
 
 
-def mfista(a, y_hat, lam, L, iters, history=False):
+def mfista(a, y_hat, lam, L, iters, history=False, iterates=False):
     """Monotone FISTA: z_k = prox step from v_k; s_k = z_k if F(z_k) <= F(s_{k-1})
     else s_{k-1} (per block); v_{k+1} = s_k + (t_k/t_{k+1})(z_k - s_k)
-    + ((t_k - 1)/t_{k+1})(s_k - s_{k-1})."""
+    + ((t_k - 1)/t_{k+1})(s_k - s_{k-1}).  With iterates=True the list of
+    (v_k, z_k, s_k), k = 1..T, is returned as well (for the pins)."""
     n, nb = a.shape[1], y_hat.shape[1]
     s_prev = np.zeros((n, nb))
     v = s_prev.copy()
     t = 1.0
     f_prev = objective(a, y_hat, s_prev, lam)
     hist = []
+    its = []
     for _ in range(iters):
+        v_k = v
         z = soft(v - a.T @ (a @ v - y_hat) / L, lam / L)
         fz = objective(a, y_hat, z, lam)
         take = fz <= f_prev
@@ -204,7 +207,14 @@ def mfista(a, y_hat, lam, L, iters, history=False):
         s_prev, f_prev, t = s, f_s, t_next
         if history:
             hist.append(f_s.copy())
-    return (s_prev, hist) if history else s_prev
+        if iterates:
+            its.append((v_k, z, s))
+    out = (s_prev,)
+    if history:
+        out += (hist,)
+    if iterates:
+        out += (its,)
+    return out if len(out) > 1 else s_prev
 
 
 # ------------------------------------------------------------ synthesis

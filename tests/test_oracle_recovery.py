@@ -208,3 +208,129 @@ def test_lambda_pixel_domain_reading():
     assert np.allclose(lam_pix, 0.01 * np.max(np.abs(phi.T @ y), axis=0))
     # orthonormal Psi preserves the 2-norm of A^T y, not its max
     assert np.allclose(np.linalg.norm(a.T @ y, axis=0), np.linalg.norm(phi.T @ y, axis=0))
+
+
+def _t_sequence(count):
+    """t_1 = 1, t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2 (Beck and Teboulle)."""
+    t = [1.0]
+    for _ in range(count):
+        t.append((1.0 + np.sqrt(1.0 + 4.0 * t[-1] ** 2)) / 2.0)
+    return t
+
+
+def _kkt_problem(m, k, seed):
+    """A sparse-recovery LASSO whose minimiser is the KKT closed form on the
+    true support (certified), as in test_fista_matches_kkt_closed_form."""
+    q, s_phi, a = _problem(m, 16, seed=m + k + seed)
+    s_true = _sparse_dct_blocks(256, k, 5, seed=k + 7 * seed)
+    y = a @ s_true
+    lam = cs.lambdas(a, y)
+    L, _, _ = cs.lipschitz(q, s_phi)
+    s_star = np.zeros_like(s_true)
+    for j in range(y.shape[1]):
+        supp = np.flatnonzero(s_true[:, j])
+        sg = np.sign(s_true[supp, j])
+        s_s = _kkt_solution(a, y[:, j], lam[j], supp, sg)
+        assert np.all(np.sign(s_s) == sg)
+        resid = y[:, j] - a[:, supp] @ s_s
+        off = np.setdiff1d(np.arange(256), supp)
+        assert np.max(np.abs(a[:, off].T @ resid)) < lam[j]
+        s_star[supp, j] = s_s
+    return a, y, lam, L, s_star
+
+
+@pytest.mark.parametrize("m,k,seed", [(64, 2, 0), (64, 4, 2), (128, 4, 2)])
+def test_mfista_and_ista_match_kkt_closed_form(m, k, seed):
+    """At convergence MFISTA and ISTA reach the certified KKT minimiser."""
+    a, y, lam, L, s_star = _kkt_problem(m, k, seed)
+    tol = 1e-10 * np.max(np.abs(s_star))
+    assert np.max(np.abs(cs.mfista(a, y, lam, L, 3000) - s_star)) <= tol
+    assert np.max(np.abs(cs.ista(a, y, lam, L, 60000) - s_star)) <= tol
+
+
+@pytest.mark.parametrize("m,k,seed", [(64, 2, 0), (64, 4, 2), (128, 4, 2)])
+def test_mfista_estimate_sequence_is_nonincreasing(m, k, seed):
+    """MFISTA's convergence proof (Beck and Teboulle, IEEE TIP 2009, the
+    monotone variant of FISTA's Lemma 4.1): with x* a minimiser, F* = F(x*),
+    u_k = t_k z_k - (t_k - 1) s_{k-1} - x*, the quantity
+    E_k = (2 / L) t_k^2 (F(s_k) - F*) + ||u_k||^2 never increases, and
+    F(s_k) - F* <= 2 L ||x*||^2 / (k + 1)^2 (s_0 = 0).  The test also checks
+    that the monotone branch (z_k rejected) is taken, so that the momentum
+    coefficients of both branches are exercised.
+
+    The proof chains these inequalities through its auxiliary sequence
+    w_k = s_{k-1} + t_k (z_k - s_{k-1}): the next extrapolation point is
+    v_{k+1} = (1 - 1 / t_{k+1}) s_k + w_k / t_{k+1}, which the test checks
+    on every iteration (this is what fixes the coefficient of z_k - s_k,
+    which only matters on rejected steps).  While no step is rejected MFISTA
+    is FISTA, iterate for iterate."""
+    a, y, lam, L, s_star = _kkt_problem(m, k, seed)
+    f_star = cs.objective(a, y, s_star, lam)
+    T = 400
+    _, hist, its = cs.mfista(a, y, lam, L, T, history=True, iterates=True)
+    t = _t_sequence(T)
+    for kk in range(1, T):
+        _, z, s = its[kk - 1]
+        s_before = its[kk - 2][2] if kk > 1 else np.zeros_like(s)
+        w = s_before + t[kk - 1] * (z - s_before)
+        v_next = (1.0 - 1.0 / t[kk]) * s + w / t[kk]
+        assert np.allclose(its[kk][0], v_next, rtol=0, atol=1e-12 * np.max(np.abs(s_star)))
+    first_rej = next((i for i, (_, z, s) in enumerate(its) if np.any(z != s)), T)
+    assert first_rej > 2
+    s_f = cs.fista(a, y, lam, L, first_rej)
+    assert np.allclose(its[first_rej - 1][2], s_f, rtol=0, atol=1e-12 * np.max(np.abs(s_star)))
+    prev_s = np.zeros_like(s_star)
+    e_prev = None
+    rejected = 0
+    for kk, (_, z, s) in enumerate(its, start=1):
+        gap = cs.objective(a, y, s, lam) - f_star
+        assert np.all(gap <= 2 * L * np.sum(s_star ** 2, axis=0) / (kk + 1) ** 2
+                      * (1 + 1e-9) + 1e-9 * f_star)
+        u = t[kk - 1] * z - (t[kk - 1] - 1.0) * prev_s - s_star
+        e = (2.0 / L) * t[kk - 1] ** 2 * gap + np.sum(u * u, axis=0)
+        if e_prev is not None:
+            assert np.all(e <= e_prev * (1 + 1e-9) + 1e-9), kk
+        rejected += int(np.sum(np.any(z != s, axis=0)))
+        e_prev, prev_s = e, s
+    assert rejected > 0
+
+
+def test_fista_estimate_sequence_is_nonincreasing():
+    """FISTA's Lemma 4.1 (Beck and Teboulle 2009): E_k = (2 / L) t_k^2
+    (F(s_k) - F*) + ||t_k s_k - (t_k - 1) s_{k-1} - x*||^2 never increases."""
+    a, y, lam, L, s_star = _kkt_problem(64, 4, 2)
+    f_star = cs.objective(a, y, s_star, lam)
+    T = 300
+    t = _t_sequence(T)
+    e_prev = None
+    prev_s = np.zeros_like(s_star)
+    for kk in range(1, T + 1):
+        s = cs.fista(a, y, lam, L, kk)
+        u = t[kk - 1] * s - (t[kk - 1] - 1.0) * prev_s - s_star
+        e = (2.0 / L) * t[kk - 1] ** 2 * (cs.objective(a, y, s, lam) - f_star) + np.sum(u * u, 0)
+        if e_prev is not None:
+            assert np.all(e <= e_prev * (1 + 1e-9) + 1e-9), kk
+        e_prev, prev_s = e, s
+
+
+def test_ista_closed_form_on_orthogonal_columns():
+    """ISTA on an operator with orthogonal columns, A = U diag(sigma)
+    (U orthonormal): the gradient step decouples per coefficient, and where
+    sigma_i c_i > lam (c = U^T y) every iterate stays on the active branch,
+    so s_k = s*_i (1 - (1 - sigma_i^2 / L)^k) with s*_i = (sigma_i c_i -
+    lam) / sigma_i^2 (and the mirror image for sigma_i c_i < -lam; zero
+    where |sigma_i c_i| <= lam).  This fixes the step 1 / L."""
+    rng = np.random.default_rng(12)
+    n = 24
+    u, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    sigma = rng.uniform(0.5, 2.0, size=n)
+    a = u * sigma[None, :]
+    c = rng.normal(0, 5.0, size=(n, 3))
+    y = u @ c
+    lam = np.array([0.4, 1.1, 2.0])
+    L = 1.3 * np.max(sigma) ** 2
+    sc = sigma[:, None] * c
+    s_star = np.sign(sc) * np.maximum(np.abs(sc) - lam[None, :], 0) / sigma[:, None] ** 2
+    for k in (1, 2, 7, 40):
+        want = s_star * (1 - (1 - sigma[:, None] ** 2 / L) ** k)
+        assert np.allclose(cs.ista(a, y, lam, L, k), want, rtol=1e-12, atol=1e-12)

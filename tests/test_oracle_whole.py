@@ -85,3 +85,27 @@ def test_whole_frame_decode_recovers_the_scene():
         key_only = np.mean([codec.psnr(frames[t], d["frames"][0]) for t in (1, 2)])
         assert out[m] > key_only
     assert out[900] > out[300]
+
+
+def test_single_block_frame_decodes_as_block_tv():
+    """A 16 x 16 frame is one B = 16 block: whole-frame decoding (eq. (1)
+    with the TV solver on the frame as one image) must give exactly the
+    block-form TV decode of the same GOP, pixel for pixel, with the same
+    lambda, step constant, objective and relative residual."""
+    rng = np.random.default_rng(8)
+    base = rng.integers(60, 190, size=(16, 16))
+    frames = np.stack([base, base + rng.integers(-20, 21, size=(16, 16)),
+                       base + rng.integers(-30, 31, size=(16, 16))]).clip(0, 255).astype(np.uint8)
+    m, seed, sid = 64, 0x5eed, 3
+    e = whole.encode_gop(frames, m, 16, seed, sid)
+    d = whole.decode_gop(e, frames.shape, m, 16, seed, sid, iters=120)
+    p = codec.Params(16, 16, 3, 16, m, seed, sid, iters=120, solver="tv")
+    gs = codec.encode_gop(frames, p)
+    assert np.array_equal(gs.codes[:, 0, :], e["codes"]) and np.array_equal(gs.exps[:, 0], e["exps"])
+    ref = codec.decode_gop(gs, p)
+    assert np.array_equal(d["frames"], ref.frames)
+    assert np.allclose(d["cs_float"], ref.cs_float, rtol=0, atol=1e-12)
+    assert np.allclose(d["lam"], ref.lam[:, 0], rtol=1e-14, atol=0)
+    assert d["L"] == ref.L
+    assert np.allclose(d["objective"], ref.objective[:, 0], rtol=1e-12, atol=0)
+    assert np.allclose(d["rel_residual"], ref.rel_residual[:, 0], rtol=1e-12, atol=0)
