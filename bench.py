@@ -60,6 +60,13 @@ def parse():
                     help="skip the device-ceiling microbenchmarks")
     ap.add_argument("--cpu-blocks", type=int, default=3000,
                     help="blocks the oracle recovers for the CPU baseline")
+    ap.add_argument("--cpu-blocks-1t", type=int, default=400,
+                    help="blocks the oracle recovers on one thread for the CPU baseline")
+    ap.add_argument("--headline-serve-load", type=float, default=0.16,
+                    help="headline mode: one serving point at this fraction of the 256 "
+                         "cameras' nominal GOP rates (0: none)")
+    ap.add_argument("--headline-serve-window", type=float, default=1.0,
+                    help="headline mode: seconds of Poisson arrivals in that point")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
     ap.add_argument("--mode", choices=["headline", "mixed", "serve", "encode", "configure", "tv",
@@ -136,17 +143,20 @@ def measured_traffic(streams):
     return int(tb.group(1))
 
 
-def cpu_baseline(spec, gs_host, n_blocks):
-    """Oracle recovery of the first n_blocks CS blocks of one GOP (host)."""
-    from oracle import cs, philox
+def host_cpu_model():
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
-    codes, exps = gs_host
-    codes = codes.reshape(-1, spec.m)[:n_blocks]
-    exps = exps.reshape(-1)[:n_blocks]
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_recovery(spec, codes, exps):
+    """The FP64 oracle's recovery of the given blocks (host), timed."""
+    from oracle import cs, philox
     t0 = time.perf_counter()
     q = philox.measurement_matrix_q(spec.m, spec.n, spec.phi_seed, spec.stream_id)
     s_phi = philox.phi_scale(spec.m)
@@ -156,12 +166,30 @@ def cpu_baseline(spec, gs_host, n_blocks):
     lam = cs.lambdas(a, y)
     s = cs.fista(a, y, lam, L, spec.iters)
     cs.synthesise(s, spec.block)
-    dt = time.perf_counter() - t0
-    px = n_blocks * spec.n
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(spec, gs_host, n_blocks, n_blocks_1t):
+    """Oracle recovery of the first CS blocks of one GOP on the host: with
+    the BLAS pool at its default size (n_blocks) and at one thread
+    (n_blocks_1t)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    codes, exps = gs_host
+    codes = codes.reshape(-1, spec.m)
+    exps = exps.reshape(-1)
+    dt = _oracle_recovery(spec, codes[:n_blocks], exps[:n_blocks])
+    with threadpool_limits(limits=1):
+        dt1 = _oracle_recovery(spec, codes[:n_blocks_1t], exps[:n_blocks_1t])
+    px, px1 = n_blocks * spec.n, n_blocks_1t * spec.n
     return {"value": px / dt / 1e6, "unit": "Mpixel/s", "cores": int(threads), "kind": "oracle",
+            "cpu_model": host_cpu_model(), "os_cpu_count": os.cpu_count(),
+            "single_thread": {"value": px1 / dt1 / 1e6, "unit": "Mpixel/s", "cores": 1,
+                              "blocks": n_blocks_1t, "seconds": round(dt1, 2)},
             "sample": f"FP64 oracle recovery (operator, step constant, lambda, {spec.iters} FISTA "
-                      f"iterations, synthesis) of {n_blocks} blocks of 32x32 at M=256 from one "
-                      f"640x480 GOP; {dt:.1f} s"}
+                      f"iterations, synthesis) of the first {n_blocks} blocks of 32x32 at M=256 "
+                      f"of one 640x480 GOP on {threads} BLAS threads ({dt:.1f} s), and of "
+                      f"{n_blocks_1t} blocks on one thread ({dt1:.1f} s)"}
 
 
 def mixed_main(args):
@@ -209,6 +237,10 @@ def mixed_main(args):
                  * ((s.width + s.block - 1) // s.block) for s in specs)
     flops = sum((s.gop - 1) * ((s.height + s.block - 1) // s.block)
                 * ((s.width + s.block - 1) // s.block) * 4.0 * s.m * s.n * s.iters for s in specs)
+    # what the MFMA units execute: M padded to whole 32-row tiles
+    flops_exec = sum((s.gop - 1) * ((s.height + s.block - 1) // s.block)
+                     * ((s.width + s.block - 1) // s.block) * 4.0 * (-(-s.m // 32) * 32) * s.n
+                     * s.iters for s in specs)
     ms = 1e3 * wall / args.steps
     print(json.dumps({
         "metric": "recovered Mpixel/s, 64 mixed streams, one graph-captured batch decode",
@@ -222,14 +254,21 @@ def mixed_main(args):
         "config": {"workload": "mixed64-qcif/cif/vga-g4..32-m/n0.05..0.4-b16/32-t300",
                    "recovered_px_per_step": px, "blocks_per_step": blocks},
         "algorithmic_tflops": round(flops / (ms / 1e3) / 1e12, 2),
+        "executed_tflops": round(flops_exec / (ms / 1e3) / 1e12, 2),
+        "executed_over_algorithmic": round(flops_exec / flops, 4),
     }), flush=True)
 
 
-def serve_main(args):
+def serve_sweep(loads, window, on_point=None):
     """256 synthetic cameras (640x480 and 1280x720, B=16, M/n 0.1 or 0.25,
-    GOP 8/16/32), Poisson GOP arrivals at a fraction of each camera's
-    nominal 2-20 GOP/s, served by the continuous-batching server; reports
-    latency and throughput per offered load."""
+    GOP 8/16/32) served by the continuous-batching server under open-loop
+    Poisson GOP arrivals at each fraction `load` of the cameras' nominal
+    2-20 GOP/s, for `window` seconds of arrivals per point.  A fresh server
+    per point; six warm-up requests are decoded and polled, then the
+    statistics are reset, so latencies, counts and rates cover only the
+    window's requests.  The served rate is the window's recovered pixels
+    over max(window, last completion - window start), so it never exceeds
+    the offered rate."""
     import torch
     import paper_1311_1419_amd as P
     import synthvid as sv
@@ -239,31 +278,29 @@ def serve_main(args):
         key = (spec.height, spec.width, spec.gop)
         if key not in pool:
             pool[key] = torch.from_numpy(spec.video()).cuda()
+    sweep = []
     with P.Context(0) as ctx:
         enc = []
         for spec, rate in cams:
             p = P.Params.from_spec(spec, precision=P.CSV_BF16)
             enc.append((p, ctx.encode_gop(pool[(spec.height, spec.width, spec.gop)], p), rate))
         torch.cuda.synchronize()
-        loads = [float(x) for x in args.serve_loads.split(",")]
-        sweep = []
         rng = np.random.default_rng(7)
         for load in loads:
-            # a fresh server per load point: latency statistics start empty
             with P.Server(0, mem_budget=48 << 30, hip_streams=2) as srv:
                 sids = [srv.register_stream(p) for p, _, _ in enc]
                 warm = [srv.submit(sids[i], enc[i][1]) for i in range(6)]
                 srv.drain(120.0)
                 for t in warm:
                     srv.poll(t)
+                srv.reset_stats()
                 arr = []
                 for i, (p, gs, rate) in enumerate(enc):
                     t = float(rng.exponential(1.0 / (rate * load)))
-                    while t < args.serve_window:
+                    while t < window:
                         arr.append((t, i))
                         t += float(rng.exponential(1.0 / (rate * load)))
                 arr.sort()
-                base = srv.stats()
                 t0 = P.clock()
                 pending = collections.deque()
 
@@ -283,19 +320,29 @@ def serve_main(args):
                     time.sleep(0.0005)
                 srv.drain(60.0)
                 st = srv.stats()
-            # the warm-up requests are included in the latency statistics only
-            # through their (short) own latencies; 6 of several hundred
-            offered = sum((enc[i][0].gop - 1) * enc[i][0].width * enc[i][0].height
-                          for _, i in arr) / args.serve_window / 1e6
-            sweep.append({"load": load, "requests": len(arr),
-                          "offered_mpix_s": round(offered, 1),
-                          "completed": st["completed"] - base["completed"],
+            offered_px = sum((enc[i][0].gop - 1) * enc[i][0].width * enc[i][0].height
+                             for _, i in arr)
+            span = max(window, st["last_done_s"] - t0) if st["completed"] else window
+            sweep.append({"load": load, "window_s": window, "requests": len(arr),
+                          "offered_mpix_s": round(offered_px / window / 1e6, 1),
+                          "completed": st["completed"],
                           "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
                           "max_ms": round(st["max_ms"], 3),
-                          "served_mpix_s": round(st["mpix_per_s"], 1),
-                          "batches": st["batches"] - base["batches"],
-                          "max_concurrent_batches": st["max_concurrent"]})
-            print(json.dumps({"sweep_point": sweep[-1]}), flush=True)
+                          "served_mpix_s": round(st["recovered_pixels"] / span / 1e6, 1),
+                          "batches": st["batches"],
+                          "max_concurrent_batches": st["max_concurrent"],
+                          "server_device_gib": round(st["device_bytes"] / 2**30, 2)})
+            if on_point:
+                on_point(sweep[-1])
+    return sweep
+
+
+def serve_main(args):
+    """The serving load sweep (serve_sweep over --serve-loads): latency and
+    throughput per offered load, the highest stable load."""
+    loads = [float(x) for x in args.serve_loads.split(",")]
+    sweep = serve_sweep(loads, args.serve_window,
+                        lambda pt: print(json.dumps({"sweep_point": pt}), flush=True))
     best = max(sweep, key=lambda r: r["served_mpix_s"])
     # stable: the server keeps up with the offered load (served within 5% of
     # offered); the highest such point is the load the server sustains
@@ -758,7 +805,12 @@ def main():
             "frac_mfma": round(achieved / ceilings["mfma_bf16_tflops"], 4),
             "frac_l2": round(l2_bytes / avg_k_s / 1e12 / ceilings["l2_read_tbs"], 4)}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(specs[0], codes_host, args.cpu_blocks)
+        line["cpu_baseline"] = cpu_baseline(specs[0], codes_host, args.cpu_blocks,
+                                            args.cpu_blocks_1t)
+    if args.headline_serve_load > 0:
+        # p50/p99 of the serving form in the same line: one short load point
+        line["serving"] = serve_sweep([args.headline_serve_load],
+                                      args.headline_serve_window)[0]
     print(json.dumps(line), flush=True)
 
 

@@ -96,7 +96,25 @@ enum {
      * resident on the device and L from the FP64 power iteration on Q Q^T
      * (M <= 16384); obj_out holds one (objective, relative residual) pair per
      * CS frame.  csv_recover_blocks and csv_operator_matrix refuse it. */
-    CSV_FLAG_WHOLE_FRAME = 32
+    CSV_FLAG_WHOLE_FRAME = 32,
+    /* Decoder: monotone FISTA (MFISTA, Beck and Teboulle 2009, the variant
+     * whose objective never increases; the check of a decreasing objective
+     * of eq. (1) read as a LASSO): each iteration takes the prox step z_k from
+     * v_k, keeps s_k = z_k if F(z_k) <= F(s_{k-1}) and s_k = s_{k-1}
+     * otherwise (per block), and extrapolates v_{k+1} = s_k + (t_k/t_{k+1})
+     * (z_k - s_k) + ((t_k - 1)/t_{k+1}) (s_k - s_{k-1}).  Still two products
+     * per iteration: A z_k is computed, A s_k and A v_{k+1} are carried as
+     * the same combinations.  DCT-l1 recovery on the plain FP32 path only
+     * (CSV_EUNSUPPORTED with CSV_BF16); CSV_EINVAL with CSV_FLAG_ISTA or
+     * CSV_FLAG_TV. */
+    CSV_FLAG_MONOTONE = 64,
+    /* Test hook for the closed loop of eqs. (2)-(4): the encoder skips the
+     * 8-bit quantiser and stores the exact integer measurements y~ = Q r as
+     * int32 in `codes` ((G-1)*N_b*M int32, 4-byte aligned; csv_encoded_size
+     * reports their bytes and 32 M bits per block); exps are written as 0.
+     * The decoder recovers from y^ = s_Phi y~.  Block DCT-l1 recovery only
+     * (CSV_EUNSUPPORTED with CSV_FLAG_TV or CSV_FLAG_WHOLE_FRAME). */
+    CSV_FLAG_NO_QUANT = 128
 };
 
 /* ------------------------------------------------------------ params */
@@ -254,8 +272,11 @@ int csv_recover_blocks(csv_ctx* ctx, const csv_params* p, int32_t n_blocks,
  * (a non-default stream).  csv_graph_launch replays it over whatever the
  * bound input buffers hold at launch time, writing the bound outputs.  The
  * graph keeps using the context's scratch: replays and other decodes on
- * that context must not overlap on the device.  Destroy the graph before
- * its context. */
+ * that context must not overlap on the device.  A later call on the same
+ * context that needs a larger scratch buffer than the capture sized moves
+ * that buffer; csv_graph_launch then returns CSV_EINVAL without launching
+ * anything (recapture after such calls, or give them their own context).
+ * Destroy the graph before its context. */
 typedef struct csv_graph csv_graph;
 int csv_graph_capture(csv_ctx* ctx, int32_t count, const csv_params* params,
                       const csv_gop_stream* in, uint8_t* const* frames_out,

@@ -36,9 +36,13 @@ enum {
 
 typedef struct {
     size_t mem_budget;          /* device bytes charged to requests (0: 4 GiB): an admitted or
-                                   running request holds its decoded frames plus its recovery
-                                   working set; a finished one holds only its frames, until
-                                   csv_poll or csv_cancel releases them */
+                                   running request holds its decoded frames plus the recovery
+                                   working set of its path (coefficients, y^, lambda and its
+                                   adjoint; the FP32 iterates and TV state where used); a
+                                   finished one holds only its frames, until csv_poll or
+                                   csv_cancel releases them.  Admission control only: resident
+                                   operators and the batch slots' grow-only scratch are not
+                                   charged (csv_stats.device_bytes reports them) */
     int32_t max_queue;          /* waiting requests beyond which csv_submit returns CSV_EAGAIN (0: 4096) */
     int32_t max_batch_blocks;   /* recovery blocks per batch (0: 262144) */
     int32_t precision;          /* CSV_BF16 or CSV_FP32 for every request */
@@ -48,15 +52,25 @@ typedef struct {
     double fake_fail_every;     /* fake executor: fail every k-th batch (0: never) */
 } csv_server_opts;
 
+/* Statistics since server creation or the last csv_server_reset_stats.
+ * Completion counts, pixels and latencies cover only requests submitted
+ * since then (a request submitted earlier that completes later is left out
+ * of them, e.g. warm-up requests). */
 typedef struct {
     uint64_t submitted, admitted, completed, rejected, cancelled, failed;
     uint64_t recovered_pixels;  /* CS pixels of completed requests */
     double p50_ms, p99_ms, mean_ms, max_ms;   /* completed requests */
     double mpix_per_s;          /* recovered pixels / (last completion - first arrival) */
-    size_t bytes_in_flight, peak_bytes;
+    size_t bytes_in_flight, peak_bytes;   /* charged against mem_budget */
     int32_t queue_depth;        /* waiting, not yet admitted */
     int32_t batches;            /* batches launched */
     int32_t max_concurrent;     /* most batches in flight at once */
+    double first_arrival_s;     /* csv_clock() of the first counted arrival (-1: none) */
+    double last_done_s;         /* csv_clock() of the last counted completion */
+    size_t device_bytes;        /* device memory the server holds, as of the latest batch
+                                   launch: resident operators, the batch slots' grow-only
+                                   scratch and the output pool; unlike bytes_in_flight this
+                                   is not bounded by mem_budget */
 } csv_stats;
 
 /* Monotonic clock in seconds (the server's latency clock). */
@@ -97,6 +111,9 @@ int csv_cancel(csv_server* srv, uint64_t ticket);
 int csv_server_drain(csv_server* srv, double timeout_s);
 
 int csv_server_stats(csv_server* srv, csv_stats* out);
+/* Start a new statistics window: counters, latencies and rates restart
+ * from zero; requests already submitted are not counted when they finish. */
+int csv_server_reset_stats(csv_server* srv);
 
 #ifdef __cplusplus
 }

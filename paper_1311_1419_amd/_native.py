@@ -25,6 +25,8 @@ CSV_FLAG_MEASURE_INT8 = 4
 CSV_FLAG_MEASURE_FP8 = 8
 CSV_FLAG_TV = 16
 CSV_FLAG_WHOLE_FRAME = 32
+CSV_FLAG_MONOTONE = 64
+CSV_FLAG_NO_QUANT = 128
 
 
 class CsvParams(C.Structure):
@@ -58,7 +60,9 @@ class CsvStats(C.Structure):
                 ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("max_ms", C.c_double),
                 ("mpix_per_s", C.c_double), ("bytes_in_flight", C.c_size_t),
                 ("peak_bytes", C.c_size_t), ("queue_depth", C.c_int32),
-                ("batches", C.c_int32), ("max_concurrent", C.c_int32)]
+                ("batches", C.c_int32), ("max_concurrent", C.c_int32),
+                ("first_arrival_s", C.c_double), ("last_done_s", C.c_double),
+                ("device_bytes", C.c_size_t)]
 
 
 class CsvCeilings(C.Structure):
@@ -145,6 +149,7 @@ _SIGS = {
     "csv_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
     "csv_server_drain": (C.c_int, [C.c_void_p, C.c_double]),
     "csv_server_stats": (C.c_int, [C.c_void_p, _P(CsvStats)]),
+    "csv_server_reset_stats": (C.c_int, [C.c_void_p]),
 }
 
 _lib = None

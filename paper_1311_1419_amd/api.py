@@ -185,9 +185,11 @@ class Context:
         m, nb = p.resolve()
         g = p.gop
         dev = self.device
+        # CSV_FLAG_NO_QUANT (test hook): exact int32 measurements instead of codes
+        cdt = torch.int32 if p.flags & N.CSV_FLAG_NO_QUANT else torch.int8
         return GopStream(
             torch.empty((p.height, p.width), dtype=torch.int16, device=dev),
-            torch.empty((g - 1, nb, m), dtype=torch.int8, device=dev),
+            torch.empty((g - 1, nb, m), dtype=cdt, device=dev),
             torch.empty((g - 1, nb), dtype=torch.uint8, device=dev),
             torch.zeros(2, dtype=torch.int64, device=dev))
 
@@ -410,7 +412,8 @@ class Context:
         _require_cuda(key_decoded, torch.uint8, "key_decoded")
         m, nb = p.resolve()
         y = torch.empty((nb, m), dtype=torch.int32, device=self.device)
-        codes = torch.empty((nb, m), dtype=torch.int8, device=self.device)
+        cdt = torch.int32 if p.flags & N.CSV_FLAG_NO_QUANT else torch.int8
+        codes = torch.empty((nb, m), dtype=cdt, device=self.device)
         exps = torch.empty((nb,), dtype=torch.uint8, device=self.device)
         N.check(N.lib().csv_measure_frame(self._h, C.byref(p.to_c()), frame.data_ptr(),
                                           key_decoded.data_ptr(), y.data_ptr(), codes.data_ptr(),
@@ -432,3 +435,4 @@ class Context:
                                            exps.data_ptr(), s.data_ptr(), lam.data_ptr(),
                                            _ptr(obj), _stream(self.device)))
         return s, lam, obj
+

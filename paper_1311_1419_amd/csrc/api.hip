@@ -58,8 +58,13 @@ Shape resolve(const csv_params* p) {
                 "precision must be CSV_FP32 or CSV_BF16");
     CSV_REQUIRE((p->flags & ~(CSV_FLAG_ISTA | CSV_FLAG_LAMBDA_PIXEL_DOMAIN |
                               CSV_FLAG_MEASURE_INT8 | CSV_FLAG_MEASURE_FP8 | CSV_FLAG_TV |
-                              CSV_FLAG_WHOLE_FRAME)) == 0,
+                              CSV_FLAG_WHOLE_FRAME | CSV_FLAG_MONOTONE | CSV_FLAG_NO_QUANT)) == 0,
                 CSV_EINVAL, "unknown flag bits");
+    CSV_REQUIRE(!(p->flags & CSV_FLAG_MONOTONE) || !(p->flags & (CSV_FLAG_ISTA | CSV_FLAG_TV)),
+                CSV_EINVAL, "CSV_FLAG_MONOTONE selects the l1 solver: not with ISTA or TV");
+    CSV_REQUIRE(!(p->flags & CSV_FLAG_NO_QUANT) ||
+                    !(p->flags & (CSV_FLAG_TV | CSV_FLAG_WHOLE_FRAME)),
+                CSV_EUNSUPPORTED, "CSV_FLAG_NO_QUANT covers block DCT-l1 recovery only");
     CSV_REQUIRE(!(p->flags & CSV_FLAG_WHOLE_FRAME) ||
                     !(p->flags & (CSV_FLAG_MEASURE_INT8 | CSV_FLAG_MEASURE_FP8)),
                 CSV_EINVAL, "whole-frame measurement is exact integer only");
@@ -130,11 +135,11 @@ void* scratch(Ctx* c, const std::string& name, size_t bytes) {
         ctx_free(c, s.ptr, s.bytes);
         s.ptr = nullptr;
         s.bytes = 0;
+        ++c->gen;   // a buffer moved: graphs captured before now hold stale pointers
     }
     const size_t want = ((bytes + 4095) / 4096) * 4096;
     s.ptr = ctx_alloc(c, want);
     s.bytes = want;
-    ++c->gen;
     return s.ptr;
 }
 
@@ -286,6 +291,31 @@ const float* beta_table(Ctx* c, int T, bool ista, hipStream_t st) {
     return d;
 }
 
+// Monotone FISTA (Beck and Teboulle 2009, MFISTA): with the same t_k,
+// v_{k+1} = s_k + (t_k / t_{k+1}) (z_k - s_k) + ((t_k - 1) / t_{k+1})
+// (s_k - s_{k-1}); the pair (t_k / t_{k+1}, (t_k - 1) / t_{k+1}) per k,
+// computed in FP64 and stored as FP32.  Kept under key -T (FISTA and ISTA
+// tables use 2 T and 2 T + 1).
+const float* mfista_table(Ctx* c, int T, hipStream_t st) {
+    const int key = -T;
+    auto it = c->beta_tables.find(key);
+    if (it != c->beta_tables.end()) return it->second.first;
+    CSV_REQUIRE(!c->capturing, CSV_EINVAL, "momentum table missing during graph capture");
+    std::vector<float> h(2 * (size_t)T);
+    double t = 1.0;
+    for (int k = 0; k < T; ++k) {
+        const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+        h[2 * k] = (float)(t / tn);
+        h[2 * k + 1] = (float)((t - 1.0) / tn);
+        t = tn;
+    }
+    float* d = static_cast<float*>(ctx_alloc(c, h.size() * 4));
+    CSV_HIP(hipMemcpyAsync(d, h.data(), h.size() * 4, hipMemcpyHostToDevice, st));
+    CSV_HIP(hipStreamSynchronize(st));
+    c->beta_tables[key] = {d, 2 * T};
+    return d;
+}
+
 // --------------------------------------------------------- recovery core
 static void lambda_pass(Ctx* c, const Shape& s, Operator* op, const float* y, int nblk, float* lam,
                         hipStream_t st, const std::string& g0name) {
@@ -351,8 +381,10 @@ static void tv_fp32(Ctx* c, const Shape& s, const std::vector<F32Item>& its, flo
 }
 
 // Plain FP32 FISTA for up to kF32Batch GOPs of one shape (n, M, M_p, T,
-// ISTA), all sharing each launch (k_fp32_mfma.hip).  Each GOP k of the
-// batch has its own iterate scratch ("V#k", "Gd#k", "Rm#k").
+// ISTA / monotone), all sharing each launch (k_fp32_mfma.hip).  Each GOP k
+// of the batch has its own iterate scratch ("V#k", "Rm#k"; the monotone
+// variant adds "Z#k", "AZ#k", "AS#k", "FS#k").
+static void mfista_fp32(Ctx* c, const Shape& s, F32Batch& bt, int ng, hipStream_t st);
 
 static void fista_fp32(Ctx* c, const Shape& s, const std::vector<F32Item>& its, hipStream_t st) {
     const int ng = (int)its.size();
@@ -371,6 +403,16 @@ static void fista_fp32(Ctx* c, const Shape& s, const std::vector<F32Item>& its, 
         j.V = static_cast<float*>(scratch(c, "V" + tag, nn * 4));
         j.R = static_cast<float*>(scratch(c, "Rm" + tag, (size_t)it.nblk * s.Mp * 4));
         j.nblk = it.nblk;
+        if (s.flags & CSV_FLAG_MONOTONE) {
+            j.Z = static_cast<float*>(scratch(c, "Z" + tag, nn * 4));
+            j.AZ = static_cast<float*>(scratch(c, "AZ" + tag, (size_t)it.nblk * s.Mp * 4));
+            j.AS = static_cast<float*>(scratch(c, "AS" + tag, (size_t)it.nblk * s.Mp * 4));
+            j.FS = static_cast<double*>(scratch(c, "FS" + tag, (size_t)it.nblk * 8));
+        }
+    }
+    if (s.flags & CSV_FLAG_MONOTONE) {
+        mfista_fp32(c, s, bt, ng, st);
+        return;
     }
     const float* beta = beta_table(c, s.T, (s.flags & CSV_FLAG_ISTA) != 0, st);
     for (int g = 0; g < ng; ++g) {
@@ -382,6 +424,25 @@ static void fista_fp32(Ctx* c, const Shape& s, const std::vector<F32Item>& its, 
         // threshold and momentum step in one pass
         launch_f32_forward(bt, ng, s.n, s.M, s.Mp, st);
         launch_f32_adjoint_prox(bt, ng, s.n, s.Mp, beta, k, st);
+    }
+}
+
+// Monotone FISTA on the batch: per iteration the adjoint with the prox step
+// (z_k), the forward product A z_k, and the per-block choice of s_k with the
+// extrapolation of v_{k+1}, A s_k and the residual A v_{k+1} - y^.
+static void mfista_fp32(Ctx* c, const Shape& s, F32Batch& bt, int ng, hipStream_t st) {
+    const float* coef = mfista_table(c, s.T, st);
+    F32Batch fz = bt;   // forward product A z_k: X = Z, output AZ, no y^
+    for (int g = 0; g < ng; ++g) {
+        fz.j[g].V = bt.j[g].Z;
+        fz.j[g].R = bt.j[g].AZ;
+        fz.j[g].y = nullptr;
+    }
+    launch_mfista_init(bt, ng, s.n, s.M, s.Mp, st);
+    for (int k = 0; k < s.T; ++k) {
+        launch_f32_adjoint_zstep(bt, ng, s.n, s.Mp, st);
+        launch_f32_forward(fz, ng, s.n, s.M, s.Mp, st);
+        launch_mfista_select(bt, ng, s.n, s.M, s.Mp, coef, k, st);
     }
 }
 
@@ -407,10 +468,16 @@ struct FusedJob {
 // idle workgroups steal from the other queues.
 static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st,
                        int variant = -1) {
-    // class key (n, Mp, tv); TV tiles are 32 blocks and use the Phi fragments
+    // class key (n, Mp, tv); TV tiles are 32 blocks and use the Phi fragments.
+    // The kernel variant of each l1 class is read once, here: the tile width
+    // and the launch below both follow that one reading, even if the
+    // autotuner changes the process-wide choice meanwhile.
     std::map<std::tuple<int, int, int>, std::vector<FusedTile>> classes;
+    std::map<std::pair<int, int>, int> pick;   // (n, Mp) -> variant index
     for (const FusedJob& j : jobs) {
         const Shape& s = *j.s;
+        CSV_REQUIRE(!(s.flags & CSV_FLAG_MONOTONE), CSV_EUNSUPPORTED,
+                    "monotone FISTA runs on the plain FP32 path only (CSV_FP32)");
         if (j.tv) {
             CSV_REQUIRE(tv_class_supported(s.n, s.Mp), CSV_EUNSUPPORTED,
                         "fused BF16 TV recovery runs on 16 x 16 blocks with M up to 128; "
@@ -420,9 +487,18 @@ static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st
                         "fused BF16 recovery has no kernel for n=" + std::to_string(s.n) +
                             ", M padded to " + std::to_string(s.Mp));
         }
-        const int nt = j.tv ? 32
-                            : variant >= 0 ? 32 * fused_variants(s.n, s.Mp)[variant].ct
-                                           : fused_tile_blocks(s.n, s.Mp);
+        int nt = 32;
+        if (!j.tv) {
+            auto pk = pick.find({s.n, s.Mp});
+            if (pk == pick.end())
+                pk = pick.emplace(std::make_pair(s.n, s.Mp),
+                                  variant >= 0 ? variant : fused_choice(s.n, s.Mp))
+                         .first;
+            const auto& vs = fused_variants(s.n, s.Mp);
+            CSV_REQUIRE(pk->second >= 0 && pk->second < (int)vs.size(), CSV_EINVAL,
+                        "no such kernel variant");
+            nt = 32 * vs[pk->second].ct;
+        }
         const float* beta = beta_table(c, s.T, (s.flags & CSV_FLAG_ISTA) != 0, st);
         for (int b0 = 0; b0 < j.nblk; b0 += nt) {
             FusedTile t{};
@@ -479,6 +555,7 @@ static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st
     struct Launch {
         int n, Mp, tv, count;
         size_t tiles_off, qoff_off, queue_off, ctr_off;
+        int variant;
     };
     std::vector<Launch> launches;
     size_t off_t = 0, off_i = tiles_bytes;
@@ -486,7 +563,15 @@ static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st
         const auto& v = kv.second;
         const int count = (int)v.size();
         Launch L{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), count,
-                 off_t, 0, 0, 0};
+                 off_t, 0, 0, 0, -1};
+        if (!L.tv) {
+            L.variant = pick.at({L.n, L.Mp});
+            // every tile must fit the workgroup of the variant that runs it
+            const int cap = 32 * fused_variants(L.n, L.Mp)[L.variant].ct;
+            for (const FusedTile& t : v)
+                CSV_REQUIRE(t.nblk >= 1 && t.nblk <= cap, CSV_EINVAL,
+                            "tile wider than the kernel variant's workgroup");
+        }
         std::memcpy(host + off_t, v.data(), v.size() * sizeof(FusedTile));
         off_t += v.size() * sizeof(FusedTile);
         int* qoff = reinterpret_cast<int*>(host + off_i);
@@ -530,7 +615,7 @@ static void fista_bf16(Ctx* c, const std::vector<FusedJob>& jobs, hipStream_t st
             launch_tv_bf16_class(L.n, L.Mp, tiles, qoff, queue, ctr, L.count, device_cus(), ls);
         } else {
             ProfScope ps(c, "fista_bf16", ls);
-            launch_fista_bf16_class(L.n, L.Mp, tiles, qoff, queue, ctr, L.count, ls, variant);
+            launch_fista_bf16_class(L.n, L.Mp, tiles, qoff, queue, ctr, L.count, ls, L.variant);
         }
     }
     if (spread) join_aux(c, st);
@@ -566,7 +651,8 @@ const float* prepare(Ctx* c, const Shape& s, Operator* op, const int8_t* codes,
                             const uint8_t* exps, int nblk, float* lam, const std::string& tag,
                             hipStream_t st, const std::string& g0name) {
     float* y = static_cast<float*>(scratch(c, "yhat" + tag, (size_t)nblk * s.Mp * 4));
-    launch_dequant(codes, exps, nblk, s.M, s.Mp, op->s_phi, y, st);
+    launch_dequant(codes, exps, nblk, s.M, s.Mp, op->s_phi, y, st,
+                   (s.flags & CSV_FLAG_NO_QUANT) != 0);
     lambda_pass(c, s, op, y, nblk, lam, st, g0name);
     return y;
 }
@@ -596,7 +682,7 @@ void recover(Ctx* c, const Shape& s, Operator* op, const int8_t* codes, const ui
             launch_tv_final64(op->q, S, codes, exps, lam, nblk, s.M, s.B, op->s_phi, obj_out, st);
         else
             launch_final64(op->a64, S, codes, exps, lam, nblk, s.M, s.Mp, s.n, op->s_phi,
-                           obj_out, st);
+                           obj_out, st, (s.flags & CSV_FLAG_NO_QUANT) != 0);
     }
 }
 
@@ -662,7 +748,10 @@ void encode_gops(Ctx* c, int count, const Shape* shapes, const uint8_t* const* f
         unsigned long long* bits = reinterpret_cast<unsigned long long*>(out[i].bits);
         if (bits) {
             launch_fill_u64(bits, 0ull, 1, ls);
-            launch_fill_u64(bits + 1, (unsigned long long)ncs * s.nb * (8ull * s.M + 8ull), 1, ls);
+            const bool raw = (s.flags & CSV_FLAG_NO_QUANT) != 0;
+            launch_fill_u64(bits + 1,
+                            (unsigned long long)ncs * s.nb * (raw ? 32ull * s.M : 8ull * s.M + 8ull),
+                            1, ls);
         }
         launch_key_encode(frames[i], s.W, s.H, s.qshift, out[i].key_levels, bits, ls);
         if (!ncs) continue;
@@ -683,7 +772,8 @@ void encode_gops(Ctx* c, int count, const Shape* shapes, const uint8_t* const* f
             launch_measure(s, ops[i]->q, ops[i]->q8, frames[i] + fs, ncs, fs, keydec[i], ymeas[i],
                            ls);
         }
-        launch_quantise(ymeas[i], s.M, s.Mp, total, out[i].codes, out[i].exps, nullptr, ls);
+        launch_quantise(ymeas[i], s.M, s.Mp, total, out[i].codes, out[i].exps, nullptr, ls,
+                        (s.flags & CSV_FLAG_NO_QUANT) != 0);
     }
     if (spread) join_aux(c, st);
 }
@@ -829,6 +919,8 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
                     "whole-frame measurements are recovered by TV in FP32 only "
                     "(CSV_FLAG_TV, CSV_FP32)");
         CSV_REQUIRE(s.G == 1 || (in[i].codes && in[i].exps), CSV_EINVAL, "codes/exps are NULL");
+        CSV_REQUIRE(!(s.flags & CSV_FLAG_MONOTONE) || s.precision == CSV_FP32, CSV_EUNSUPPORTED,
+                    "monotone FISTA runs on the plain FP32 path only (CSV_FP32)");
         items[i].op = s.G > 1 ? get_operator(c, s, st) : nullptr;
         items[i].nblk = (s.G - 1) * s.nb;
     }
@@ -910,7 +1002,7 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
         if (s.precision == CSV_FP32) {
             const int tv = (s.flags & CSV_FLAG_TV) ? 1 : 0;
             f32_groups[std::make_tuple(tv, s.n, s.M, s.Mp, s.T,
-                                       (s.flags & CSV_FLAG_ISTA) ? 1 : 0)]
+                                       s.flags & (CSV_FLAG_ISTA | CSV_FLAG_MONOTONE))]
                 .push_back(i);
             continue;
         }
@@ -975,7 +1067,8 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
                     const int i = mem[k];
                     const Item& it = items[i];
                     bt.j[ng++] = F64Job{it.op->a64, it.S,   in[i].codes,      in[i].exps,
-                                        it.lam,     obj_out[i], it.op->s_phi, it.nblk};
+                                        it.lam,     obj_out[i], it.op->s_phi, it.nblk,
+                                        (shapes[i].flags & CSV_FLAG_NO_QUANT) ? 1 : 0};
                 }
                 const Shape& s0 = shapes[mem[g0]];
                 ProfScope ps(c, "final64", st);
@@ -1076,10 +1169,12 @@ int csv_encoded_size(const csv_params* p, size_t* key_elems, size_t* code_bytes,
                      size_t* exp_bytes, uint64_t* bits_cs) {
     return guarded([&] {
         const Shape s = resolve(p);
+        const bool raw = (s.flags & CSV_FLAG_NO_QUANT) != 0;   // int32 y~, no exponent
         if (key_elems) *key_elems = (size_t)s.W * s.H;
-        if (code_bytes) *code_bytes = (size_t)(s.G - 1) * s.nb * s.M;
+        if (code_bytes) *code_bytes = (size_t)(s.G - 1) * s.nb * s.M * (raw ? 4 : 1);
         if (exp_bytes) *exp_bytes = (size_t)(s.G - 1) * s.nb;
-        if (bits_cs) *bits_cs = (uint64_t)(s.G - 1) * s.nb * (8ull * s.M + 8ull);
+        if (bits_cs)
+            *bits_cs = (uint64_t)(s.G - 1) * s.nb * (raw ? 32ull * s.M : 8ull * s.M + 8ull);
     });
 }
 
@@ -1156,6 +1251,7 @@ struct csv_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<void*> keep;   // pinned tile tables the graph uploads from
+    int gen = 0;               // the context's scratch generation at capture
 };
 
 int csv_graph_capture(csv_ctx* ctx, int32_t count, const csv_params* params,
@@ -1219,6 +1315,7 @@ int csv_graph_capture(csv_ctx* ctx, int32_t count, const csv_params* params,
             for (void* p : g->keep) (void)hipHostFree(p);
             throw Error{CSV_EHIP, std::string("graph instantiate failed: ") + hipGetErrorString(e)};
         }
+        g->gen = c->gen;
         *out = g.release();
     });
 }
@@ -1227,6 +1324,9 @@ int csv_graph_launch(csv_graph* g, void* stream) {
     return guarded([&] {
         CSV_REQUIRE(g && g->exec, CSV_EINVAL, "NULL graph");
         std::lock_guard<std::mutex> lk(g->ctx->mu);
+        CSV_REQUIRE(g->gen == C(g->ctx)->gen, CSV_EINVAL,
+                    "context scratch moved since capture (a larger decode on the same context "
+                    "grew a buffer the graph uses); recapture");
         set_device(g->ctx);
         CSV_HIP(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
     });
@@ -1405,7 +1505,8 @@ int csv_measure_frame(csv_ctx* ctx, const csv_params* p, const uint8_t* frame,
         Operator* op = get_operator(c, s, st);
         int32_t* y = static_cast<int32_t*>(scratch(c, "ymeas", (size_t)s.nb * s.Mp * 4));
         launch_measure(s, op->q, op->q8, frame, 1, (size_t)s.W * s.H, key_decoded, y, st);
-        launch_quantise(y, s.M, s.Mp, s.nb, codes, exps, y_out, st);
+        launch_quantise(y, s.M, s.Mp, s.nb, codes, exps, y_out, st,
+                        (s.flags & CSV_FLAG_NO_QUANT) != 0);
     });
 }
 

@@ -172,6 +172,9 @@ int csv_configure(csv_ctx* ctx, const csv_params* base, const uint8_t* clip, int
         CSV_REQUIRE(ctx && base && clip && gops && ms && points && best, CSV_EINVAL, "NULL argument");
         CSV_REQUIRE(n_frames >= 1 && n_g >= 1 && n_m >= 1, CSV_EINVAL,
                     "need at least one frame and one candidate");
+        CSV_REQUIRE(!(base->flags & CSV_FLAG_NO_QUANT), CSV_EUNSUPPORTED,
+                    "the configurator counts quantised bits: CSV_FLAG_NO_QUANT is a decoder test "
+                    "hook");
         std::lock_guard<std::mutex> lk(ctx->mu);
         CSV_HIP(hipSetDevice(ctx->impl.device));
         configure(&ctx->impl, *base, clip, n_frames, gops, n_g, ms, n_m, psnr_floor, points, best,

@@ -157,6 +157,8 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
                  uint8_t* const* frames_out, float* const* cs_float_out, double* const* obj_out,
                  hipStream_t st);
 const float* beta_table(Ctx* c, int T, bool ista, hipStream_t st);
+// (t_k / t_{k+1}, (t_k - 1) / t_{k+1}) for k = 1..T, interleaved (monotone FISTA)
+const float* mfista_table(Ctx* c, int T, hipStream_t st);
 
 // ------------------------------------------------------------- kernels
 // encode side (k_encode.hip)
@@ -168,16 +170,18 @@ void launch_key_decode(const int16_t* levels, int W, int H, int qstep, uint8_t* 
 void launch_measure(const Shape& s, const int8_t* q, const uint8_t* q8, const uint8_t* frames,
                     int n_frames, size_t frame_stride, const uint8_t* key, int32_t* y_scratch,
                     hipStream_t st);
+// raw: store y~ as int32 at codes, exponents 0 (CSV_FLAG_NO_QUANT)
 void launch_quantise(const int32_t* y, int M, int Mp, int total, int8_t* codes, uint8_t* exps,
-                     int32_t* y_out, hipStream_t st);
+                     int32_t* y_out, hipStream_t st, bool raw = false);
 void launch_q_e4m3(const int8_t* q, uint8_t* q8, size_t count, hipStream_t st);
 void launch_fill_u64(unsigned long long* p, unsigned long long v, int count, hipStream_t st);
 
 // decode side (k_decode.hip)
 void launch_operator_setup(Operator* op, hipStream_t st);
 void launch_power_iteration(Operator* op, int* gram, hipStream_t st);   // gram: M x M int32 scratch
+// raw: codes hold int32 y~ and exps are ignored (CSV_FLAG_NO_QUANT)
 void launch_dequant(const int8_t* codes, const uint8_t* exps, int nblk, int M, int Mp,
-                    double s_phi, float* y, hipStream_t st);
+                    double s_phi, float* y, hipStream_t st, bool raw = false);
 void launch_row_absmax(const float* X, int R, int N, int ld, float scale, float* out, hipStream_t st);
 void launch_fill_f32(float* p, float v, size_t count, hipStream_t st);
 void launch_copy_f32(float* dst, const float* src, size_t count, hipStream_t st);
@@ -194,6 +198,7 @@ struct F64Job {
     double* obj;            // nblk x 2
     double s_phi;
     int nblk;
+    int raw = 0;            // codes hold int32 y~ (CSV_FLAG_NO_QUANT)
 };
 constexpr int kF64Batch = 16;
 struct F64Batch {
@@ -202,7 +207,7 @@ struct F64Batch {
 void launch_final64_batch(const F64Batch& bt, int ngop, int M, int Mp, int n, hipStream_t st);
 void launch_final64(const double* a64, const float* s, const int8_t* codes, const uint8_t* exps,
                     const float* lam, int nblk, int M, int Mp, int n, double s_phi, double* obj,
-                    hipStream_t st);
+                    hipStream_t st, bool raw = false);
 
 // device ceilings (k_probe.hip); synchronous
 void probe_ceilings(Ctx* c, int cus, csv_ceilings* out);
@@ -220,7 +225,7 @@ void launch_whole_quantise(const long long* y, int M, int n_frames, int8_t* code
 constexpr int kF32Batch = 16;
 struct F32Job {
     const float* op;
-    const float* y;
+    const float* y;      // forward: R = V A^T - y^, or V A^T itself when NULL
     const float* lam;
     const double* lip;
     float* S;
@@ -228,6 +233,12 @@ struct F32Job {
     float* G;
     float* R;
     int nblk;
+    // monotone FISTA only: z_k (nblk x n), A z_k and A s_k (nblk x Mp) and
+    // F(s_k) per block (FP64)
+    float* Z = nullptr;
+    float* AZ = nullptr;
+    float* AS = nullptr;
+    double* FS = nullptr;
 };
 struct F32Batch {
     F32Job j[kF32Batch];
@@ -241,6 +252,20 @@ void launch_f32_adjoint(const F32Batch& bt, int ngop, int n, int Mp, hipStream_t
 // V = S + beta_k (S - S_prev); G is not written
 void launch_f32_adjoint_prox(const F32Batch& bt, int ngop, int n, int Mp, const float* beta,
                              int k, hipStream_t st);
+// Monotone FISTA (CSV_FLAG_MONOTONE), with S, V, Z, AZ, AS, FS of each job:
+//   init:   S = V = 0, A s_0 = 0, R = -y^, F(s_0) = 1/2 ||y^||^2;
+//   zstep:  G = R A and z_k = soft(V - G / L, lam / L) into Z (G not stored);
+//   select: per block F(z_k) = 1/2 ||A z_k - y^||^2 + lam ||z_k||_1 (FP64
+//           sums in a fixed order), s_k = z_k if F(z_k) <= F(s_{k-1}) else
+//           s_{k-1}, v_{k+1} = s_k + c1 (z_k - s_k) + c2 (s_k - s_{k-1}), the
+//           same combination for A s_k and A v_{k+1}, and R = A v_{k+1} - y^;
+//           coef[k] = (c1, c2) = (t_k / t_{k+1}, (t_k - 1) / t_{k+1}).
+// The forward product A z_k is launch_f32_forward on a batch whose V is Z,
+// R is AZ and y is NULL.
+void launch_mfista_init(const F32Batch& bt, int ngop, int n, int M, int Mp, hipStream_t st);
+void launch_f32_adjoint_zstep(const F32Batch& bt, int ngop, int n, int Mp, hipStream_t st);
+void launch_mfista_select(const F32Batch& bt, int ngop, int n, int M, int Mp, const float* coef,
+                          int k, hipStream_t st);
 
 // A batch of up to kWholeBatch GOPs of one shape, each with its own Q
 // (passed by value as a kernel argument); x, y, r are [GOP][F][.] arrays.

@@ -195,22 +195,28 @@ void launch_power_iteration(Operator* op, int* gram, hipStream_t st) {
 // -------------------------------------------------------- dequantisation
 // y^[b][m] = s_phi * c * 2^e for m < M (exact in FP64, rounded once to
 // FP32); zero in the padded rows M <= m < Mp.
+// raw: y^ = s_phi * y~ from int32 measurements (no quantiser).
 __global__ void dequant_kernel(const int8_t* __restrict__ codes, const uint8_t* __restrict__ exps,
-                               int nblk, int M, int Mp, double s_phi, float* __restrict__ y) {
+                               int nblk, int M, int Mp, double s_phi, float* __restrict__ y,
+                               int raw) {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (size_t)nblk * Mp) return;
     const int b = (int)(idx / Mp), m = (int)(idx % Mp);
     float v = 0.f;
-    if (m < M) v = (float)(s_phi * ldexp((double)codes[(size_t)b * M + m], (int)exps[b]));
+    if (m < M)
+        v = raw ? (float)(s_phi * (double)reinterpret_cast<const int32_t*>(codes)[(size_t)b * M + m])
+                : (float)(s_phi * ldexp((double)codes[(size_t)b * M + m], (int)exps[b]));
     y[idx] = v;
 }
 
 void launch_dequant(const int8_t* codes, const uint8_t* exps, int nblk, int M, int Mp,
-                    double s_phi, float* y, hipStream_t st) {
+                    double s_phi, float* y, hipStream_t st, bool raw) {
     const size_t total = (size_t)nblk * Mp;
     if (!total) return;
-    dequant_kernel<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st>>>(codes, exps, nblk,
-                                                                               M, Mp, s_phi, y);
+    CSV_REQUIRE(!raw || reinterpret_cast<uintptr_t>(codes) % 4 == 0, CSV_EINVAL,
+                "unquantised measurements need a 4-byte aligned codes buffer");
+    dequant_kernel<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st>>>(
+        codes, exps, nblk, M, Mp, s_phi, y, raw ? 1 : 0);
     CSV_HIP(hipGetLastError());
 }
 
@@ -447,7 +453,7 @@ __global__ __launch_bounds__(256) void final64_kernel(F64Batch bt, int M, int Mp
         yy[ct] = 0.0;
         const int b = b0 + 16 * ct + j;
         if (b < nblk) {
-            const int e = exps[b];
+            const int e = jb.raw ? 0 : exps[b];
 #pragma unroll
             for (int i = 0; i < RTW; ++i) {
                 const int rt = wv + 4 * i;
@@ -456,7 +462,10 @@ __global__ __launch_bounds__(256) void final64_kernel(F64Batch bt, int M, int Mp
                     for (int r = 0; r < 4; ++r) {
                         const int m = rt * 16 + kq + 4 * r;
                         if (m < M) {
-                            const double yh = s_phi * ldexp((double)codes[(size_t)b * M + m], e);
+                            const double yh =
+                                jb.raw ? s_phi * (double)reinterpret_cast<const int32_t*>(
+                                                     codes)[(size_t)b * M + m]
+                                       : s_phi * ldexp((double)codes[(size_t)b * M + m], e);
                             const double d = acc[i][ct][r] - yh;
                             rr[ct] += d * d;
                             yy[ct] += yh * yh;
@@ -519,10 +528,10 @@ void launch_final64_batch(const F64Batch& bt, int ngop, int M, int Mp, int n, hi
 
 void launch_final64(const double* a64, const float* s, const int8_t* codes, const uint8_t* exps,
                     const float* lam, int nblk, int M, int Mp, int n, double s_phi, double* obj,
-                    hipStream_t st) {
+                    hipStream_t st, bool raw) {
     if (nblk <= 0) return;
     F64Batch bt{};
-    bt.j[0] = F64Job{a64, s, codes, exps, lam, obj, s_phi, nblk};
+    bt.j[0] = F64Job{a64, s, codes, exps, lam, obj, s_phi, nblk, raw ? 1 : 0};
     launch_final64_batch(bt, 1, M, Mp, n, st);
 }
 

@@ -398,15 +398,25 @@ void launch_measure(const Shape& s, const int8_t* q, const uint8_t* q8, const ui
 
 // Block-floating-point 8-bit quantiser, one wave per block: m = max|y~|,
 // e = min{e >= 0 : (m + h(e)) >> e <= 127} with h(0) = 0, h(e) = 2^(e-1);
-// code = sgn(y~) ((|y~| + h(e)) >> e).
+// code = sgn(y~) ((|y~| + h(e)) >> e).  raw (the no-quantiser test form):
+// y~ itself is stored as int32 at `codes` and the exponent is 0.
 __global__ __launch_bounds__(256) void quantise_kernel(const int32_t* __restrict__ y, int M, int Mp,
                                                       int total, int8_t* __restrict__ codes,
                                                       uint8_t* __restrict__ exps,
-                                                      int32_t* __restrict__ y_out) {
+                                                      int32_t* __restrict__ y_out, int raw) {
     const int gb = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int ln = threadIdx.x & 63;
     if (gb >= total) return;   // whole wave leaves together
     const int32_t* row = y + (size_t)gb * Mp;
+    if (raw) {
+        int32_t* c32 = reinterpret_cast<int32_t*>(codes);
+        for (int m = ln; m < M; m += 64) {
+            c32[(size_t)gb * M + m] = row[m];
+            if (y_out) y_out[(size_t)gb * M + m] = row[m];
+        }
+        if (ln == 0) exps[gb] = 0;
+        return;
+    }
     int mx = 0;
     for (int m = ln; m < M; m += 64) mx = max(mx, abs(row[m]));
 #pragma unroll
@@ -424,10 +434,12 @@ __global__ __launch_bounds__(256) void quantise_kernel(const int32_t* __restrict
 }
 
 void launch_quantise(const int32_t* y, int M, int Mp, int total, int8_t* codes, uint8_t* exps,
-                     int32_t* y_out, hipStream_t st) {
+                     int32_t* y_out, hipStream_t st, bool raw) {
     if (total == 0) return;
+    CSV_REQUIRE(!raw || reinterpret_cast<uintptr_t>(codes) % 4 == 0, CSV_EINVAL,
+                "unquantised measurements need a 4-byte aligned codes buffer");
     quantise_kernel<<<dim3(ceil_div(total, 4)), dim3(256), 0, st>>>(y, M, Mp, total, codes, exps,
-                                                                    y_out);
+                                                                    y_out, raw ? 1 : 0);
     CSV_HIP(hipGetLastError());
 }
 

@@ -76,8 +76,10 @@ void launch_bf16_frag_layout(Operator* op, hipStream_t st) {
 // LDS, copied when a tile's operator differs from the previous tile's, so
 // that every iteration reads NL fewer fragments through the L1 return path
 // (the kernel's bound at n = 1024).  NL < 0: -NL such steps, interleaved
-// with the global ring rounds instead of run after them.
-template <int N, int MP, int CT, int W, int kPF, int kPA, int SPL, int OCC, int NLS>
+// with the global ring rounds instead of run after them.  OPT bit 0: each
+// wave keeps its y^ rows of the tile in registers for all T iterations
+// instead of reading them from L2 in every residual epilogue.
+template <int N, int MP, int CT, int W, int kPF, int kPA, int SPL, int OCC, int NLS, int OPT = 0>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W * OCC / 4)))
 void fista_bf16_kernel(
     const FusedTile* __restrict__ tiles, const int* __restrict__ qoff,
@@ -91,7 +93,7 @@ void fista_bf16_kernel(
     constexpr int TT = (MP / 32) * CT;           // forward output tiles
     constexpr int FT = (TT + W - 1) / W;         // forward tiles per wave (max)
     constexpr int KSF = N / 16, KSA = MP / 16;   // K steps of forward / adjoint
-    constexpr bool YREG = false;                 // y read from L2 in the epilogue (registers are the limit)
+    constexpr bool YREG = (OPT & 1) != 0;        // else y^ is read from L2 in every epilogue
     constexpr int NL = NLS < 0 ? -NLS : NLS;     // LDS-resident forward K steps
     constexpr bool ILV = NLS < 0;
     static_assert(RT * CT >= 2 && (RT * CT) % 2 == 0 && W % CT == 0, "unsupported class");
@@ -338,7 +340,7 @@ void fista_bf16_kernel(
     }
 }
 
-template <int N, int MP, int CT, int W, int PF, int PA, int SPL, int OCC, int NL>
+template <int N, int MP, int CT, int W, int PF, int PA, int SPL, int OCC, int NL, int OPT = 0>
 static void launch_class(const FusedTile* tiles, const int* qoff, const int* queue, int* counters,
                          int grid, hipStream_t st) {
     static_assert(W * OCC % 4 == 0 && W * OCC <= 32, "waves per CU");
@@ -348,8 +350,8 @@ static void launch_class(const FusedTile* tiles, const int* qoff, const int* que
                             (size_t)W * SPL * 4096 + (size_t)W * kFT * kNL * 1024;
     static_assert((kLds + 64) * OCC <= 160 * 1024, "LDS of OCC workgroups exceeds a CU");
     const size_t lds = kLds;
-    auto* fn = &fista_bf16_kernel<N, MP, CT, W, PF, PA, SPL, OCC, NL>;
-    ensure_lds_limit<&fista_bf16_kernel<N, MP, CT, W, PF, PA, SPL, OCC, NL>>(lds);
+    auto* fn = &fista_bf16_kernel<N, MP, CT, W, PF, PA, SPL, OCC, NL, OPT>;
+    ensure_lds_limit<&fista_bf16_kernel<N, MP, CT, W, PF, PA, SPL, OCC, NL, OPT>>(lds);
     fn<<<dim3(grid), dim3(64 * W), lds, st>>>(tiles, qoff, queue, counters);
     CSV_HIP(hipGetLastError());
 }
@@ -364,6 +366,11 @@ static void launch_class(const FusedTile* tiles, const int* qoff, const int* que
             &launch_class<NN, MM, CT, W, PF, PA, SPL, OCC, NLS>                             \
     }
 #define CSV_V(NN, MM, CT, W, PF, PA, SPL, OCC) CSV_VG(NN, MM, CT, W, PF, PA, SPL, OCC, 0, "")
+#define CSV_VY(NN, MM, CT, W, PF, PA, SPL, OCC)                                             \
+    FusedVariant {                                                                         \
+        "ct" #CT "_w" #W "_pf" #PF "_pa" #PA "_spl" #SPL "_o" #OCC "_yreg", CT, OCC,        \
+            &launch_class<NN, MM, CT, W, PF, PA, SPL, OCC, 0, 1>                            \
+    }
 #define CSV_VL(NN, MM, CT, W, PF, PA, SPL, OCC, NL) \
     CSV_VG(NN, MM, CT, W, PF, PA, SPL, OCC, NL, "_lds" #NL)
 #define CSV_VLI(NN, MM, CT, W, PF, PA, SPL, OCC, NL) \
@@ -383,7 +390,9 @@ static std::vector<ClassEntry>& class_table() {
          0},
         {256, 64,
          {CSV_V(256, 64, 2, 4, 4, 2, 0, 2), CSV_V(256, 64, 1, 4, 4, 2, 0, 3),
-          CSV_V(256, 64, 2, 8, 4, 2, 0, 1), CSV_V(256, 64, 4, 8, 4, 2, 0, 1)},
+          CSV_V(256, 64, 2, 8, 4, 2, 0, 1), CSV_V(256, 64, 4, 8, 4, 2, 0, 1),
+          CSV_VY(256, 64, 2, 4, 4, 2, 0, 2), CSV_VY(256, 64, 2, 4, 16, 4, 0, 1),
+          CSV_VY(256, 64, 2, 8, 8, 4, 0, 1), CSV_VY(256, 64, 1, 4, 8, 4, 0, 2)},
          0},
         {256, 96,
          {CSV_V(256, 96, 1, 4, 2, 2, 0, 3), CSV_V(256, 96, 2, 4, 2, 2, 0, 2),
@@ -423,6 +432,7 @@ static std::vector<ClassEntry>& class_table() {
     return t;
 }
 #undef CSV_V
+#undef CSV_VY
 #undef CSV_VL
 #undef CSV_VLI
 #undef CSV_VG

@@ -17,17 +17,23 @@ namespace csv {
 // flight during the MFMAs.
 constexpr int kGM = 128, kGK = 16, kGP = kGM + 4;
 
+// Epilogues of the adjoint product: store G, the FISTA step on (S, V), or
+// the monotone variant's prox step z = soft(V - G / L, lam / L) into Z.
+enum { kEpiStore = 0, kEpiFista = 1, kEpiZStep = 2 };
+
 // C = X B for GOP g = blockIdx.z, rows of X are blocks (b < nblk):
 //   FWD: X = V_g (nblk x K, K = n), B[k][c] = A_g[c][k] (c over Mp);
-//        C = R_g (nblk x Mp): acc - y^_g for c < M, 0 for M <= c < Mp.
+//        C = R_g (nblk x Mp): acc - y^_g for c < M (acc itself when y^_g
+//        is NULL), 0 for M <= c < Mp.
 //   ADJ: X = R_g (nblk x K, K = Mp), B[k][c] = A_g[k][c] (c over n);
-//        C = G_g (nblk x n), or with PROX the FISTA step of iteration k on
-//        (S_g, V_g) from each G entry, which is then not stored.
-template <bool FWD, int TN, bool PROX = false>
+//        C = G_g (nblk x n), or with EPI the FISTA step of iteration k on
+//        (S_g, V_g), or the prox step into Z_g, from each G entry, which is
+//        then not stored.
+template <bool FWD, int TN, int EPI = kEpiStore>
 __global__ __launch_bounds__(256) void f32_gemm_kernel(F32Batch bt, int N, int K, int M,
                                                       const float* __restrict__ beta = nullptr,
                                                       int kit = 0) {
-    static_assert(!(FWD && PROX), "the step follows the adjoint product");
+    static_assert(!(FWD && EPI != kEpiStore), "the step follows the adjoint product");
     constexpr int NJ = TN / 64;     // accumulator tiles per wave along the columns
     constexpr int NB = TN / 64;     // float4 of B staged per thread per chunk
     const F32Job& jb = bt.j[blockIdx.z];
@@ -125,10 +131,11 @@ __global__ __launch_bounds__(256) void f32_gemm_kernel(F32Batch bt, int N, int K
         __syncthreads();                    // previous barrier
     }
     // accumulator (lane l, register r) = C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]
-    if constexpr (PROX) {
+    if constexpr (EPI != kEpiStore) {
         // u = v - g / L; s_k = soft(u, lam / L); v = s_k + beta_k (s_k - s_{k-1})
+        // (monotone variant: z_k = soft(u, lam / L) only)
         const float inv_l = (float)(1.0 / jb.lip[0]);
-        const float bk = beta[kit];
+        const float bk = EPI == kEpiFista ? beta[kit] : 0.f;
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -143,8 +150,12 @@ __global__ __launch_bounds__(256) void f32_gemm_kernel(F32Batch bt, int N, int K
                         const size_t o = (size_t)row * N + col;
                         const float u = fmaf(-acc[i][j][r], inv_l, jb.V[o]);
                         const float sn = fmaxf(u - tau, 0.f) + fminf(u + tau, 0.f);
-                        jb.V[o] = fmaf(bk, sn - jb.S[o], sn);
-                        jb.S[o] = sn;
+                        if constexpr (EPI == kEpiZStep) {
+                            jb.Z[o] = sn;
+                        } else {
+                            jb.V[o] = fmaf(bk, sn - jb.S[o], sn);
+                            jb.S[o] = sn;
+                        }
                     }
                 }
             }
@@ -160,7 +171,8 @@ __global__ __launch_bounds__(256) void f32_gemm_kernel(F32Batch bt, int N, int K
                     const int col = c0 + wc + 32 * j + lc;
                     if (row < nblk && col < N) {
                         float v = acc[i][j][r];
-                        if (FWD) v = col < M ? v - jb.y[(size_t)row * N + col] : 0.f;
+                        if (FWD)
+                            v = col < M ? (jb.y ? v - jb.y[(size_t)row * N + col] : v) : 0.f;
                         C[(size_t)row * N + col] = v;
                     }
                 }
@@ -209,8 +221,113 @@ void launch_f32_adjoint_prox(const F32Batch& bt, int ngop, int n, int Mp, const 
     CSV_REQUIRE(beta != nullptr && k >= 0, CSV_EINVAL, "FISTA step table");
     const int rows = max_rows(bt, ngop);
     if (!rows) return;
-    f32_gemm_kernel<false, 128, true><<<dim3(ceil_div(n, 128), ceil_div(rows, kGM), ngop),
-                                        dim3(256), 0, st>>>(bt, n, Mp, Mp, beta, k);
+    f32_gemm_kernel<false, 128, kEpiFista><<<dim3(ceil_div(n, 128), ceil_div(rows, kGM), ngop),
+                                             dim3(256), 0, st>>>(bt, n, Mp, Mp, beta, k);
+    CSV_HIP(hipGetLastError());
+}
+
+void launch_f32_adjoint_zstep(const F32Batch& bt, int ngop, int n, int Mp, hipStream_t st) {
+    check_batch(bt, ngop, n, Mp);
+    for (int g = 0; g < ngop; ++g)
+        CSV_REQUIRE(bt.j[g].Z != nullptr, CSV_EINVAL, "monotone FISTA: no z buffer");
+    const int rows = max_rows(bt, ngop);
+    if (!rows) return;
+    f32_gemm_kernel<false, 128, kEpiZStep><<<dim3(ceil_div(n, 128), ceil_div(rows, kGM), ngop),
+                                             dim3(256), 0, st>>>(bt, n, Mp, Mp);
+    CSV_HIP(hipGetLastError());
+}
+
+// ----------------------------------------------------- monotone FISTA steps
+// One wave per block (four blocks per workgroup), GOP blockIdx.y.
+// Sums in FP64 over lane-strided elements, then a butterfly; lane 0's sum is
+// broadcast so that every lane takes the same decision.
+__device__ inline double wave_sum_bcast(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return __shfl(v, 0);
+}
+
+__global__ __launch_bounds__(256) void mfista_init_kernel(F32Batch bt, int n, int M, int Mp) {
+    const F32Job& jb = bt.j[blockIdx.y];
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6), ln = threadIdx.x & 63;
+    if (b >= jb.nblk) return;   // whole waves
+    double yy = 0.0;
+    for (int m = ln; m < Mp; m += 64) {
+        const size_t o = (size_t)b * Mp + m;
+        const float y = m < M ? jb.y[o] : 0.f;
+        yy += (double)y * y;
+        jb.R[o] = -y;   // A v_1 - y^ with v_1 = 0
+        jb.AS[o] = 0.f;
+    }
+    for (int i = ln; i < n; i += 64) {
+        const size_t o = (size_t)b * n + i;
+        jb.S[o] = 0.f;
+        jb.V[o] = 0.f;
+    }
+    yy = wave_sum_bcast(yy);
+    if (ln == 0) jb.FS[b] = 0.5 * yy;   // F(s_0 = 0)
+}
+
+__global__ __launch_bounds__(256) void mfista_select_kernel(F32Batch bt, int n, int M, int Mp,
+                                                           const float* __restrict__ coef,
+                                                           int k) {
+    const F32Job& jb = bt.j[blockIdx.y];
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6), ln = threadIdx.x & 63;
+    if (b >= jb.nblk) return;   // whole waves
+    const size_t on = (size_t)b * n, om = (size_t)b * Mp;
+    double l1 = 0.0, r2 = 0.0;
+    for (int i = ln; i < n; i += 64) l1 += fabs((double)jb.Z[on + i]);
+    for (int m = ln; m < M; m += 64) {
+        const double d = (double)jb.AZ[om + m] - (double)jb.y[om + m];
+        r2 += d * d;
+    }
+    l1 = wave_sum_bcast(l1);
+    r2 = wave_sum_bcast(r2);
+    const double fz = 0.5 * r2 + (double)jb.lam[b] * l1;
+    const bool take = fz <= jb.FS[b];   // ties keep z_k
+    const float c1 = coef[2 * k], c2 = coef[2 * k + 1];
+    for (int i = ln; i < n; i += 64) {
+        const float so = jb.S[on + i], z = jb.Z[on + i];
+        const float sn = take ? z : so;
+        jb.V[on + i] = sn + c1 * (z - sn) + c2 * (sn - so);
+        jb.S[on + i] = sn;
+    }
+    for (int m = ln; m < Mp; m += 64) {
+        const float ao = jb.AS[om + m], az = jb.AZ[om + m];
+        const float an = take ? az : ao;
+        const float av = an + c1 * (az - an) + c2 * (an - ao);
+        jb.AS[om + m] = an;
+        jb.R[om + m] = m < M ? av - jb.y[om + m] : 0.f;
+    }
+    if (ln == 0 && take) jb.FS[b] = fz;
+}
+
+static void check_mfista(const F32Batch& bt, int ngop) {
+    CSV_REQUIRE(ngop >= 1 && ngop <= kF32Batch, CSV_EINVAL, "FP32 batch size");
+    for (int g = 0; g < ngop; ++g) {
+        const F32Job& j = bt.j[g];
+        CSV_REQUIRE(j.nblk >= 0 && j.S && j.V && j.R && j.y && j.lam && j.Z && j.AZ && j.AS &&
+                        j.FS,
+                    CSV_EINVAL, "monotone FISTA: missing buffers");
+    }
+}
+
+void launch_mfista_init(const F32Batch& bt, int ngop, int n, int M, int Mp, hipStream_t st) {
+    check_mfista(bt, ngop);
+    const int rows = max_rows(bt, ngop);
+    if (!rows) return;
+    mfista_init_kernel<<<dim3(ceil_div(rows, 4), ngop), dim3(256), 0, st>>>(bt, n, M, Mp);
+    CSV_HIP(hipGetLastError());
+}
+
+void launch_mfista_select(const F32Batch& bt, int ngop, int n, int M, int Mp, const float* coef,
+                          int k, hipStream_t st) {
+    check_mfista(bt, ngop);
+    CSV_REQUIRE(coef != nullptr && k >= 0, CSV_EINVAL, "monotone FISTA coefficient table");
+    const int rows = max_rows(bt, ngop);
+    if (!rows) return;
+    mfista_select_kernel<<<dim3(ceil_div(rows, 4), ngop), dim3(256), 0, st>>>(bt, n, M, Mp, coef,
+                                                                            k);
     CSV_HIP(hipGetLastError());
 }
 

@@ -44,6 +44,7 @@ struct Request {
     uint8_t* out = nullptr;
     ReqState state = WAITING;
     bool cancel_requested = false;
+    bool counted = true;   // submitted since the last statistics reset
     int err = CSV_OK;
     std::string msg;
 };
@@ -59,6 +60,9 @@ class Executor {
                         const std::vector<StreamInfo>& streams) = 0;
     virtual bool done(int slot) = 0;
     virtual void copy_out(uint8_t* dst, const uint8_t* src, size_t bytes) = 0;
+    // device bytes the executor holds: operators, slot scratch, output pool
+    // (called on the worker thread, with the server lock held)
+    virtual size_t device_bytes() = 0;
 };
 
 // ------------------------------------------------------------ HIP executor
@@ -94,10 +98,12 @@ class HipExecutor : public Executor {
         (void)hipStreamDestroy(copy_);
     }
     int slots() const override { return (int)slots_.size(); }
+    // Builds the stream's operator in the shared cache (under the cache's
+    // lock).  Nothing of the slot contexts is touched here: they belong to
+    // the worker thread, which builds their momentum tables on first use.
     void prepare(StreamInfo& si) override {
         CSV_HIP(hipSetDevice(device_));
         get_operator(&setup_, si.s, copy_);
-        for (auto& sl : slots_) beta_table(sl.ctx.get(), si.s.T, (si.s.flags & CSV_FLAG_ISTA) != 0, copy_);
         CSV_HIP(hipStreamSynchronize(copy_));
     }
     uint8_t* alloc(size_t bytes) override {
@@ -113,6 +119,7 @@ class HipExecutor : public Executor {
             (void)hipGetLastError();
             throw Error{CSV_ENOMEM, "server output allocation failed"};
         }
+        pool_bytes_ += bytes;
         return static_cast<uint8_t*>(p);
     }
     void release(uint8_t* p, size_t bytes) override {
@@ -146,6 +153,12 @@ class HipExecutor : public Executor {
         CSV_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, copy_));
         CSV_HIP(hipStreamSynchronize(copy_));
     }
+    size_t device_bytes() override {
+        size_t b = pool_bytes_;
+        for (auto& sl : slots_) b += sl.ctx->used;
+        std::lock_guard<std::mutex> lk(setup_.cache->mu);   // register_stream may build
+        return b + setup_.used;
+    }
 
   private:
     struct Slot {
@@ -158,6 +171,7 @@ class HipExecutor : public Executor {
     std::vector<Slot> slots_;
     hipStream_t copy_ = nullptr;
     std::map<size_t, std::vector<void*>> pool_;
+    size_t pool_bytes_ = 0;   // every output buffer the pool holds, free or in use
 };
 
 // ----------------------------------------------------------- fake executor
@@ -190,6 +204,7 @@ class FakeExecutor : public Executor {
     void copy_out(uint8_t* dst, const uint8_t* src, size_t bytes) override {
         if (dst) std::memcpy(dst, src, bytes);
     }
+    size_t device_bytes() override { return 0; }
 
   private:
     double us_, fail_every_;
@@ -197,6 +212,28 @@ class FakeExecutor : public Executor {
     double device_free_ = 0.0;
     long launched_ = 0;
 };
+
+// Device bytes of one request's recovery working set on the path its
+// shape selects (the decode scratch of decode_gops): per block the
+// coefficients S (4 n), lambda (4), y^ (4 Mp) and lambda's adjoint g0
+// (4 n); the plain FP32 iteration adds v (4 n) and the residual (4 Mp);
+// FP32 TV adds its multipliers, shrinkage variables, P, gradient and image
+// (7 more arrays of 4 n) and its step (4); whole frames hold per CS frame
+// the TV state (7 arrays of 4 n), y^ and the residual (4 M each), the
+// forward product's partial sums (4 M per 512-pixel chunk), lambda and the
+// step (8).
+static size_t working_set_bytes(const Shape& s) {
+    const size_t F = (size_t)(s.G - 1), n = (size_t)s.n, Mp = (size_t)s.Mp;
+    if (s.flags & CSV_FLAG_WHOLE_FRAME)
+        return F * (28 * n + 8 * (size_t)s.M + 4 * (size_t)s.M * whole_fwd_parts(s.n) + 8);
+    const size_t nblk = F * s.nb;
+    size_t per = 8 * n + 4 * Mp + 4;
+    if (s.precision == CSV_FP32) {
+        per += 4 * n + 4 * Mp;
+        if (s.flags & CSV_FLAG_TV) per += 28 * n + 4;
+    }
+    return nblk * per;
+}
 
 // ------------------------------------------------------------------ server
 struct Server {
@@ -212,7 +249,8 @@ struct Server {
     size_t bytes = 0, peak = 0;
     csv_stats st{};
     std::vector<double> lat_ms;
-    double first_arrival = -1, last_done = 0;
+    double first_arrival = -1, last_done = 0;   // of requests counted since the last reset
+    size_t dev_bytes = 0;                        // executor's device bytes, worker-updated
     bool stop = false;
     std::thread worker;
 
@@ -273,6 +311,7 @@ struct Server {
                 bytes -= r->bytes - r->out_bytes;
                 r->bytes = r->out_bytes;
                 r->state = DONE;
+                if (!r->counted) continue;   // submitted before the statistics reset
                 ++st.completed;
                 const StreamInfo& si = streams[r->sid];
                 st.recovered_pixels += (uint64_t)(si.s.G - 1) * si.s.W * si.s.H;
@@ -346,6 +385,7 @@ struct Server {
                     msg = e.msg;
                 }
                 lk.lock();
+                dev_bytes = ex->device_bytes();
                 if (err != CSV_OK) finish_slot_locked(slot, err, msg);
                 continue;
             }
@@ -449,6 +489,8 @@ int csv_server_register_stream(csv_server* srv, const csv_params* p, uint32_t* s
             CSV_REQUIRE(tv ? tv_class_supported(si.s.n, si.s.Mp)
                            : fused_class_supported(si.s.n, si.s.Mp),
                         CSV_EUNSUPPORTED, "no fused kernel for this block size and M");
+        CSV_REQUIRE(!(si.s.flags & CSV_FLAG_MONOTONE) || s.o.precision == CSV_FP32,
+                    CSV_EUNSUPPORTED, "monotone FISTA runs on the plain FP32 path only");
         s.ex->prepare(si);   // operator setup outside the server lock
         std::lock_guard<std::mutex> lk(s.mu);
         s.streams.push_back(si);
@@ -478,7 +520,8 @@ int csv_submit(csv_server* srv, uint32_t sid, const csv_gop_stream* in, double t
         r->nblk = (sh.G - 1) * sh.nb;
         r->out_bytes = (size_t)sh.G * sh.W * sh.H;
         // output frames + the recovery working set of its blocks
-        r->bytes = r->out_bytes + (size_t)r->nblk * ((size_t)sh.n * 4 + (size_t)sh.Mp * 4 + 4);
+        r->bytes = r->out_bytes + working_set_bytes(sh);
+        r->counted = true;
         if (r->bytes > s.o.mem_budget) {
             ++s.st.rejected;
             throw Error{CSV_ENOMEM, "request larger than the server memory budget"};
@@ -600,7 +643,24 @@ int csv_server_stats(csv_server* srv, csv_stats* out) {
             const double span = s.last_done - s.first_arrival;
             r.mpix_per_s = span > 0 ? r.recovered_pixels / span / 1e6 : 0.0;
         }
+        r.first_arrival_s = s.first_arrival;
+        r.last_done_s = s.last_done;
+        r.device_bytes = s.dev_bytes;
         *out = r;
+    });
+}
+
+int csv_server_reset_stats(csv_server* srv) {
+    return guarded_s([&] {
+        CSV_REQUIRE(srv, CSV_EINVAL, "NULL argument");
+        Server& s = srv->impl;
+        std::lock_guard<std::mutex> lk(s.mu);
+        for (auto& kv : s.reqs) kv.second->counted = false;
+        s.st = csv_stats{};
+        s.lat_ms.clear();
+        s.first_arrival = -1;
+        s.last_done = 0;
+        s.peak = s.bytes;
     });
 }
 

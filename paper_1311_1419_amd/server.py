@@ -85,3 +85,8 @@ class Server:
         s = N.CsvStats()
         N.check(N.lib().csv_server_stats(self._h, C.byref(s)))
         return {f: getattr(s, f) for f, _ in N.CsvStats._fields_}
+
+    def reset_stats(self) -> None:
+        """Start a new statistics window (requests already submitted are
+        not counted when they finish)."""
+        N.check(N.lib().csv_server_reset_stats(self._h))

@@ -46,7 +46,7 @@ def test_host_side_validation_and_sizes():
     assert (key, code, exp, bits) == (640 * 480, 15 * 300 * 256, 15 * 300, 15 * 300 * (8 * 256 + 8))
     assert P.Params(width=176, height=144, gop=4, block=32, m=0, rho=0.25).resolve() == (256, 30)
     for bad in (dict(block=8), dict(width=170), dict(gop=0), dict(m=1025), dict(iters=0),
-                dict(key_qstep=24), dict(precision=7), dict(flags=64), dict(flags=128), dict(m=0, rho=0.0),
+                dict(key_qstep=24), dict(precision=7), dict(flags=256), dict(flags=512), dict(m=0, rho=0.0),
                 dict(flags=P.CSV_FLAG_MEASURE_INT8 | P.CSV_FLAG_MEASURE_FP8),
                 dict(flags=P.CSV_FLAG_WHOLE_FRAME | P.CSV_FLAG_MEASURE_FP8),
                 dict(lambda_frac=float("nan"))):
@@ -63,6 +63,26 @@ def test_host_side_validation_and_sizes():
     with pytest.raises(P.CsvError) as ei:
         pw.with_(gop=33).resolve()
     assert ei.value.code == -2
+
+
+def test_monotone_and_no_quant_flags():
+    """MONOTONE selects the l1 solver (not with ISTA or TV); NO_QUANT keeps
+    the exact int32 measurements (4 bytes and 32 bits per measurement, no
+    exponent) and covers block DCT-l1 recovery only."""
+    import paper_1311_1419_amd as P
+    p = P.Params(width=640, height=480, gop=16, block=32, m=256)
+    assert p.with_(flags=P.CSV_FLAG_MONOTONE).resolve() == (256, 300)
+    for bad in (P.CSV_FLAG_MONOTONE | P.CSV_FLAG_ISTA, P.CSV_FLAG_MONOTONE | P.CSV_FLAG_TV):
+        with pytest.raises(P.CsvError) as ei:
+            p.with_(flags=bad).resolve()
+        assert ei.value.code == -1
+    for bad in (P.CSV_FLAG_NO_QUANT | P.CSV_FLAG_TV, P.CSV_FLAG_NO_QUANT | P.CSV_FLAG_WHOLE_FRAME):
+        with pytest.raises(P.CsvError) as ei:
+            p.with_(flags=bad).resolve()
+        assert ei.value.code == -2
+    nq = p.with_(flags=P.CSV_FLAG_NO_QUANT | P.CSV_FLAG_MONOTONE)
+    assert P.Context.encoded_size(nq) == (640 * 480, 4 * 15 * 300 * 256, 15 * 300,
+                                          15 * 300 * 32 * 256)
 
 
 def test_compression_ratio_identity():

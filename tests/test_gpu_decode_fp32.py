@@ -35,7 +35,7 @@ def test_step_constant_and_operator(ctx, m, b):
     assert np.max(np.abs(a - cs.operator(q, s_phi, b))) < 1e-12
 
 
-def _decode_compare(ctx, spec, flags=0, **okw):
+def _decode_compare(ctx, spec, flags=0, max_abs=0.05, max_relres=2e-5, **okw):
     frames = spec.video()
     p = _gpu_params(spec, flags=flags)
     op = codec.Params.from_spec(spec, **okw)
@@ -47,14 +47,14 @@ def _decode_compare(ctx, spec, flags=0, **okw):
     assert np.array_equal(out[0], ref.frames[0])
     for t in range(1, spec.gop):
         err = np.max(np.abs(fl[t - 1].astype(np.float64) - ref.cs_float[t - 1]))
-        assert err <= 0.05, f"frame {t}: max abs {err}"
+        assert err <= max_abs, f"frame {t}: max abs {err}"
         assert np.max(np.abs(out[t].astype(int) - ref.frames[t].astype(int))) <= 1
         assert abs(psnr(frames[t], out[t]) - psnr(frames[t], ref.frames[t])) <= 0.01
     rel = np.abs(obj[..., 0] - ref.objective) / np.maximum(ref.objective, 1e-300)
     assert np.max(rel) <= 1e-5
     # ||A s - y|| / ||y|| is a few percent: FP32 error in s shows up as an
     # absolute error of the order 1e-5 (in units of ||y||)
-    assert np.max(np.abs(obj[..., 1] - ref.rel_residual)) <= 2e-5
+    assert np.max(np.abs(obj[..., 1] - ref.rel_residual)) <= max_relres
     return out, ref
 
 
@@ -211,3 +211,111 @@ def test_fp32_batch_equals_alone(ctx):
         assert np.array_equal(host(out), host(bo)), f"frames {i}"
         assert np.array_equal(host(fl), host(bf)), f"float frames {i}"
         assert np.array_equal(host(obj), host(bj)), f"objective {i}"
+
+
+@pytest.mark.parametrize("rho", [0.25, 0.1], ids=["m256", "m102"])
+def test_fp32_full_vga_frames_vs_oracle(ctx, rho):
+    """The benchmark's frame shape on the plain FP32 path: 640x480, B = 32
+    (n = 1024), M = 256 or 102, two CS frames (600 blocks: four full
+    128-row GEMM tiles and a ragged fifth) against the oracle at the FP32
+    bars."""
+    spec = sv.vga_precision(rho=rho, gop=3)
+    announce(f"decode fp32 full VGA G=3 B=32 M={spec.m}")
+    _decode_compare(ctx, spec)
+
+
+@pytest.mark.parametrize("gop", [8, 16])
+def test_fp32_cif_rho02_long_gops_vs_oracle(ctx, gop):
+    """CIF at M/n = 0.2 (M = 51, padded to 64) with GOPs of 8 and 16 frames
+    (2772 and 5940 blocks in one launch) against the oracle."""
+    spec = sv.cif_sweep(gop, 0.2, iters=300)
+    announce(f"decode fp32 CIF rho=0.2 G={gop}")
+    _decode_compare(ctx, spec)
+
+
+def test_fp32_monotone_matches_oracle_mfista(ctx):
+    """CSV_FLAG_MONOTONE (MFISTA) against the oracle's monotone FISTA, on a
+    QCIF GOP at M = 64 and a padded B = 32 GOP: objective (1e-5 relative),
+    relative residual, PSNR (0.01 dB) and uint8 frames at the FP32 bars; the
+    float frames within 0.5 grey levels.  MFISTA's per-block choice between
+    z_k and s_{k-1} compares two objectives that differ by about 1e-6 near
+    convergence, so FP32 and FP64 rounding take different branches and the
+    iterates drift apart along the objective's flat directions: an FP32
+    emulation of the same steps differs from the FP64 oracle by up to 0.10
+    grey levels and 6.5e-5 in relative residual at T = 200 with the
+    objective within 2.4e-6; the relative residual bar is 5e-4."""
+    import paper_1311_1419_amd as P
+    for spec in (sv.qcif_tiny(), sv.qcif_tiny().with_(block=32, m=256, gop=3)):
+        announce(f"decode fp32 MONOTONE B={spec.block} M={spec.m}")
+        _decode_compare(ctx, spec, flags=P.CSV_FLAG_MONOTONE, max_abs=0.5, max_relres=5e-4,
+                        solver="mfista")
+
+
+def test_fp32_monotone_objective_never_increases(ctx):
+    """MFISTA's objective is non-increasing in the iteration count on the
+    GPU too.  The oracle's plain FISTA history names an iteration k where
+    plain FISTA's objective rises (by about 2e-4 relative on this clip); on
+    the GPU plain FISTA rises there as well, while under CSV_FLAG_MONOTONE
+    the FP64 objective of every block after T = 5, 10, 20, 40, k, k + 1, 160
+    iterations never rises by more than the FP32 rounding of the decision
+    (1e-6 relative)."""
+    import paper_1311_1419_amd as P
+    announce("fp32 MONOTONE objective sequence")
+    spec = sv.qcif_tiny().with_(gop=2)
+    frames = spec.video()
+    op = codec.Params.from_spec(spec)
+    st = codec.encode_gop(frames, op)
+    q = philox.measurement_matrix_q(spec.m, spec.n, spec.phi_seed, spec.stream_id)
+    s_phi = philox.phi_scale(spec.m)
+    a = cs.operator(q, s_phi, spec.block)
+    y = cs.dequantise(st.codes[0].T, st.exps[0], s_phi)
+    lam = cs.lambdas(a, y)
+    L, _, _ = cs.lipschitz(q, s_phi)
+    _, hist = cs.fista(a, y, lam, L, 150, history=True)
+    hist = np.stack(hist)
+    rises = np.where(((hist[1:] - hist[:-1]) / hist[:-1] > 1e-4).any(axis=1))[0]
+    assert rises.size, "the clip should show plain FISTA's objective rising"
+    k = int(rises[0]) + 1   # F(s_k) < F(s_{k+1}) on some block
+
+    def objective_after(T, flags):
+        p = _gpu_params(spec.with_(iters=T), flags=flags)
+        gs = ctx.encode_gop(dev(frames), p)
+        _, _, obj = ctx.decode_gop(gs, p, want_obj=True)
+        return host(obj)[0, :, 0]
+
+    plain = np.stack([objective_after(T, 0) for T in (k, k + 1)])
+    assert np.max((plain[1] - plain[0]) / plain[0]) > 1e-5
+    mono = np.stack([objective_after(T, P.CSV_FLAG_MONOTONE)
+                     for T in sorted({5, 10, 20, 40, k, k + 1, 160})])
+    rise = np.max((mono[1:] - mono[:-1]) / np.maximum(mono[:-1], 1e-30))
+    assert rise <= 1e-6, rise
+
+
+def test_no_quant_closed_loop_cancels_key_error(ctx):
+    """Eqs. (2)-(4) on the GPU: with CSV_FLAG_NO_QUANT (exact int32
+    measurements), full sampling M = n and lambda = 0, the decoded CS frames
+    equal the originals to within the solver's convergence (0.5 grey levels
+    after 3000 iterations) although the decoded key frame they are built on
+    is off by 10 or more levels: the key frame's coding error cancels.  The
+    decoded floats also match the oracle's decode of the same measurements."""
+    import paper_1311_1419_amd as P
+    base = sv.qcif_tiny()
+    frames = base.video(3)[:, :48, :48].copy()
+    for qstep in (16, 64):
+        spec = base.with_(height=48, width=48, gop=3, m=256, iters=3000, key_qstep=qstep,
+                          lambda_frac=0.0)
+        announce(f"fp32 NO_QUANT M=n lambda=0 key step {qstep}")
+        p = _gpu_params(spec, flags=P.CSV_FLAG_NO_QUANT)
+        gs = ctx.encode_gop(dev(frames), p)
+        assert gs.codes.dtype == __import__("torch").int32
+        out, fl, _ = ctx.decode_gop(gs, p, want_float=True)
+        out, fl = host(out), host(fl)
+        key_err = np.max(np.abs(out[0].astype(int) - frames[0].astype(int)))
+        assert key_err >= 10
+        cs_err = np.max(np.abs(fl - frames[1:].astype(np.float64)))
+        assert cs_err <= 0.5, cs_err
+        op = codec.Params.from_spec(spec, no_quant=True)
+        ref_stream = codec.encode_gop(frames, op)
+        assert np.array_equal(host(gs.codes), ref_stream.y_int.astype(np.int32))
+        ref = codec.decode_gop(ref_stream, op)
+        assert np.max(np.abs(fl - ref.cs_float)) <= 0.05

@@ -94,3 +94,36 @@ def test_graph_replays_fp32_tv_and_whole_frame_batch(ctx):
                                        flags=P.CSV_FLAG_TV, iters=60)),
              (spec, P.Params.from_spec(spec.with_(stream_id=23), precision=P.CSV_FP32, iters=60))]
     _replays_match(ctx, items, _shifted)
+
+
+def test_graph_launch_refuses_after_scratch_moved():
+    """A larger eager decode on the graph's context moves scratch buffers
+    the captured graph points into; the next launch must refuse with
+    CSV_EINVAL before any GPU work instead of replaying into freed memory.
+    A recaptured graph then replays correctly."""
+    import paper_1311_1419_amd as P
+    announce("graph launch after scratch growth")
+    small = sv.qcif_tiny().with_(gop=2)
+    big = sv.vga_precision(0.25, gop=3, stream=4)
+    with P.Context(0) as c:
+        ps = P.Params.from_spec(small, precision=P.CSV_BF16)
+        pb = P.Params.from_spec(big, precision=P.CSV_BF16)
+        bs, bb = c.alloc_stream(ps), c.alloc_stream(pb)
+        c.encode_gop(dev(small.video()), ps, out=bs)
+        c.encode_gop(dev(big.video()), pb, out=bb)
+        st = torch.cuda.Stream()
+        g = c.capture_batch([(bs, ps)], st)
+        g.launch(st)
+        st.synchronize()
+        c.decode_batch([(bb, pb)])          # grows the context's scratch
+        torch.cuda.synchronize()
+        with pytest.raises(P.CsvError) as ei:
+            g.launch(st)
+        assert ei.value.code == -1 and "recapture" in str(ei.value)
+        g.close()
+        g2 = c.capture_batch([(bs, ps)], st)
+        g2.launch(st)
+        st.synchronize()
+        eager = c.decode_batch([(bs, ps)])
+        assert np.array_equal(host(g2.outputs[0][0]), host(eager[0][0]))
+        g2.close()

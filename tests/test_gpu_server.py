@@ -125,3 +125,40 @@ def test_served_fp32_tv_and_whole_frame_streams(ctx):
             with pytest.raises(P.CsvError) as ei:
                 srv.register_stream(P.Params.from_spec(base, **kw))
             assert ei.value.code == P._native.CSV_EUNSUPPORTED
+
+
+def test_register_stream_while_batches_run(ctx):
+    """Cameras joining a live service: streams registered while batches of
+    other streams are on the device (one with an iteration count no earlier
+    stream used, so its momentum table is built on the worker thread) are
+    served correctly, and every result equals the GOP decoded alone."""
+    import paper_1311_1419_amd as P
+    announce("server: register while batches run")
+    first = sv.vga_precision(0.25, gop=3, stream=6)
+    late = [sv.qcif_tiny().with_(stream_id=70, phi_seed=7070, iters=77),
+            sv.cif_sweep(4, 0.2, stream=7).with_(iters=123)]
+    items = []
+    for spec in [first] + late:
+        p = _bf16(spec)
+        gs = ctx.encode_gop(dev(spec.video()), p)
+        items.append((p, gs, host(ctx.decode_gop(gs, p)[0])))
+    torch.cuda.synchronize()
+    with P.Server(0, hip_streams=2, max_batch_blocks=600) as srv:
+        sid0 = srv.register_stream(items[0][0])
+        tickets = [(0, srv.submit(sid0, items[0][1], P.clock())) for _ in range(4)]
+        sids = [sid0] + [srv.register_stream(p) for p, _, _ in items[1:]]
+        for rep in range(2):
+            for i in range(len(items)):
+                tickets.append((i, srv.submit(sids[i], items[i][1], P.clock())))
+        srv.drain(120.0)
+        for t, (i, t_id) in enumerate(tickets):
+            p = items[i][0]
+            buf = torch.empty((p.gop, p.height, p.width), dtype=torch.uint8, device="cuda")
+            assert srv.poll(t_id, buf)
+            assert np.array_equal(host(buf), items[i][2]), f"request {t} of stream {i}"
+        st = srv.stats()
+        assert st["completed"] == len(tickets) and st["failed"] == 0
+        # the charge is a bound on the working set (lambda's adjoint is
+        # charged per request but held per preparation lane), so the device
+        # bytes need not exceed it
+        assert st["device_bytes"] > 0 and st["peak_bytes"] > 0

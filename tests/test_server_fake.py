@@ -20,7 +20,9 @@ class FakeGop:
 
 PARAMS = P.Params(width=176, height=144, gop=4, block=16, m=64)   # 297 blocks, 101 376 output bytes
 OUT_BYTES = 4 * 176 * 144
-REQ_BYTES = OUT_BYTES + 3 * 99 * (256 * 4 + 64 * 4 + 4)
+# a BF16 request's charge: its frames plus, per recovery block, the
+# coefficients and lambda's adjoint (4 n each), y^ (4 Mp) and lambda (4)
+REQ_BYTES = OUT_BYTES + 3 * 99 * (2 * 256 * 4 + 64 * 4 + 4)
 
 
 def _server(**kw):
@@ -192,3 +194,51 @@ def test_bad_server_options():
     with _server() as srv:
         with pytest.raises(N.CsvError):
             srv.register_stream(PARAMS.with_(gop=1))
+
+
+def test_working_set_charge_follows_the_path():
+    """A request is charged the recovery working set of its path: the plain
+    FP32 iteration adds v and the residual per block (4 n + 4 Mp), FP32 TV
+    its seven state arrays and step on top of that."""
+    per_bf16 = 2 * 256 * 4 + 64 * 4 + 4
+    per_fp32 = per_bf16 + 256 * 4 + 64 * 4
+    per_tv32 = per_fp32 + 7 * 256 * 4 + 4
+    for prec, flags, per in ((N.CSV_BF16, 0, per_bf16), (N.CSV_FP32, 0, per_fp32),
+                             (N.CSV_FP32, P.CSV_FLAG_TV, per_tv32)):
+        need = OUT_BYTES + 297 * per
+        with _server(mem_budget=need - 1, precision=prec) as srv:
+            sid = srv.register_stream(PARAMS.with_(flags=flags))
+            with pytest.raises(N.CsvError) as ei:
+                srv.submit(sid, FakeGop())
+            assert ei.value.code == N.CSV_ENOMEM
+        with _server(mem_budget=need, precision=prec) as srv:
+            sid = srv.register_stream(PARAMS.with_(flags=flags))
+            t = srv.submit(sid, FakeGop())
+            srv.drain(10.0)
+            assert srv.stats()["peak_bytes"] == need
+            _poll_until(srv, t)
+
+
+def test_reset_stats_starts_a_new_window():
+    """Requests submitted before csv_server_reset_stats (a warm-up) are left
+    out of the counts, pixels and latencies; the window's first arrival and
+    last completion bound the served rate."""
+    with _server(fake_us_per_block=1.0) as srv:
+        sid = srv.register_stream(PARAMS)
+        warm = [srv.submit(sid, FakeGop()) for _ in range(3)]
+        srv.drain(10.0)
+        srv.reset_stats()
+        st = srv.stats()
+        assert st["completed"] == 0 and st["p99_ms"] == 0 and st["first_arrival_s"] == -1
+        t0 = P.clock()
+        tickets = [srv.submit(sid, FakeGop(), t0 + 0.001 * i) for i in range(4)]
+        srv.drain(10.0)
+        for t in warm + tickets:
+            _poll_until(srv, t)
+        st = srv.stats()
+        assert st["submitted"] == 4 and st["completed"] == 4
+        assert st["recovered_pixels"] == 4 * 3 * 176 * 144
+        assert st["first_arrival_s"] == pytest.approx(t0)
+        assert st["last_done_s"] >= t0
+        span = st["last_done_s"] - st["first_arrival_s"]
+        assert st["mpix_per_s"] == pytest.approx(st["recovered_pixels"] / span / 1e6, rel=1e-9)
