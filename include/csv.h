@@ -255,6 +255,26 @@ int csv_measure_frame(csv_ctx* ctx, const csv_params* p, const uint8_t* frame,
                       const uint8_t* key_decoded, int32_t* y_out, int8_t* codes,
                       uint8_t* exps, void* stream);
 
+/* csv_measure_frame without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments and results as csv_measure_frame,
+ * minus the context, plus the measurement matrix the caller holds:
+ *   q: device int8 M x n row-major, as written by csv_phi_matrix for p.
+ * Runs on the calling thread's current HIP device.  Its working memory is
+ * a file-scope device array of 16 MiB per device (padded Q, Q as E4M3 for
+ * CSV_FLAG_MEASURE_FP8, and the N_b x M_p int32 measurements; M_p = M
+ * rounded up to 32), held by each device the library runs on until the
+ * process ends; every byte a call reads there is first written by that
+ * call.  Frames needing more (about 3.5 M block-measurements, e.g. beyond
+ * 1920x1088 at M/n = 0.25) return CSV_EINVAL before any GPU work, as do the
+ * other validation errors; whole-frame measurement returns
+ * CSV_EUNSUPPORTED.  Every call on one device shares that array: calls that
+ * overlap on one device (different streams, or different host threads)
+ * race and must be serialised by the caller. */
+int csv_measure_frame_noalloc(const csv_params* p, const int8_t* q, const uint8_t* frame,
+                              const uint8_t* key_decoded, int32_t* y_out, int8_t* codes,
+                              uint8_t* exps, void* stream);
+
 /* Recover n_blocks residual blocks of one stream from their codes
  * (eq. (1) as a LASSO, FISTA): s_out device float n_blocks x n DCT
  * coefficients, lambda_out device float n_blocks (may be NULL), obj_out as

@@ -11,10 +11,11 @@ from ._native import (CSV_BF16, CSV_FP32, CSV_FLAG_ISTA, CSV_FLAG_LAMBDA_PIXEL_D
                       CSV_FLAG_WHOLE_FRAME, CSV_FLAG_MONOTONE, CSV_FLAG_NO_QUANT, CsvError,
                       lib)
 from .api import (Context, GopStream, Params, kernel_choice, load_kernel_choices,
-                  set_kernel_choice)
+                  measure_frame_noalloc, set_kernel_choice)
 from .server import Server, clock
 
 __all__ = ["Context", "GopStream", "Params", "Server", "clock", "kernel_choice",
+           "measure_frame_noalloc",
            "load_kernel_choices", "set_kernel_choice", "CsvError", "CSV_BF16", "CSV_FP32",
            "CSV_FLAG_ISTA", "CSV_FLAG_LAMBDA_PIXEL_DOMAIN", "CSV_FLAG_MEASURE_INT8",
            "CSV_FLAG_MEASURE_FP8", "CSV_FLAG_TV",

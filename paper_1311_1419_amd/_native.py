@@ -116,6 +116,9 @@ _SIGS = {
                                  C.c_void_p, C.c_void_p]),
     "csv_measure_frame": (C.c_int, [C.c_void_p, _P(CsvParams), C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csv_measure_frame_noalloc": (C.c_int, [_P(CsvParams), C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p]),
     "csv_recover_blocks": (C.c_int, [C.c_void_p, _P(CsvParams), C.c_int32, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p]),

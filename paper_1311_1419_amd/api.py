@@ -436,3 +436,22 @@ class Context:
                                            _ptr(obj), _stream(self.device)))
         return s, lam, obj
 
+
+def measure_frame_noalloc(p: Params, q: torch.Tensor, frame: torch.Tensor,
+                          key_decoded: torch.Tensor, y: torch.Tensor, codes: torch.Tensor,
+                          exps: torch.Tensor) -> None:
+    """csv_measure_frame_noalloc: the measurement of one CS frame into the
+    caller's y (N_b x M int32, or None), codes (N_b x M int8; int32 with
+    CSV_FLAG_NO_QUANT) and exps (N_b uint8), with the measurement matrix q
+    (M x n int8, as Context.phi_matrix returns it); the library allocates no
+    device memory (its working memory is a fixed device array), so every
+    output is the caller's.  Runs on the current device and stream."""
+    for t, dt, name in ((q, torch.int8, "q"), (frame, torch.uint8, "frame"),
+                        (key_decoded, torch.uint8, "key_decoded"), (exps, torch.uint8, "exps")):
+        _require_cuda(t, dt, name)
+    _require_cuda(codes, torch.int32 if p.flags & N.CSV_FLAG_NO_QUANT else torch.int8, "codes")
+    if y is not None:
+        _require_cuda(y, torch.int32, "y")
+    N.check(N.lib().csv_measure_frame_noalloc(
+        C.byref(p.to_c()), q.data_ptr(), frame.data_ptr(), key_decoded.data_ptr(), _ptr(y),
+        codes.data_ptr(), exps.data_ptr(), _stream(frame.device)))

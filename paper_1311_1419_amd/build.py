@@ -18,7 +18,7 @@ OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["api.hip", "server.hip", "autotune.hip", "k_encode.hip", "k_decode.hip",
            "k_fista_bf16.hip", "k_probe.hip", "configure.hip", "k_tv.hip", "k_whole.hip",
-           "k_fp32_mfma.hip", "k_tv_bf16.hip", "k_fista_q8.hip"]
+           "k_fp32_mfma.hip", "k_tv_bf16.hip", "k_fista_q8.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1118,6 +1118,7 @@ int csv_create(csv_ctx** out, int device, size_t mem_budget) {
         CSV_HIP(hipGetDeviceCount(&count));
         CSV_REQUIRE(device >= 0 && device < count, CSV_EINVAL, "no such device");
         CSV_HIP(hipSetDevice(device));
+        noalloc_setup(device);   // the allocation-free entry point's array, once per device
         auto* c = new csv_ctx();
         c->impl.device = device;
         c->impl.budget = mem_budget;

@@ -209,6 +209,10 @@ void launch_final64(const double* a64, const float* s, const int8_t* codes, cons
                     const float* lam, int nblk, int M, int Mp, int n, double s_phi, double* obj,
                     hipStream_t st, bool raw = false);
 
+// set-up of csv_measure_frame_noalloc's device array on the current device
+// (noalloc.hip), once per device
+void noalloc_setup(int dev);
+
 // device ceilings (k_probe.hip); synchronous
 void probe_ceilings(Ctx* c, int cus, csv_ceilings* out);
 
