@@ -50,11 +50,13 @@ __device__ inline int next_tile(const int* __restrict__ qoff, const int* __restr
 // NL > 0 the last NL K steps of every tile come from the wave's LDS copy Al
 // ([NF][NL][64] fragments) instead of global memory: after the global steps,
 // or with ILV one after each of the first NL rounds of the global ring, so
-// that the ring's loads stay in flight while they run.
+// that the ring's loads stay in flight while they run.  The operator
+// pointers (type PT) address global memory, or a copy of the whole operator
+// in LDS.
 template <int N, int MP, int CT, int NF, int AR, int W, int kPF, int kPA, int NL = 0,
-          bool ILV = false>
+          bool ILV = false, class PT = gu16x8>
 __device__ inline void forward_tiles(u16x8 (&af)[kPF][NF], u16x8 (&aa)[kPA][AR],
-                                     floatx16 (&acc)[NF], const gu16x8* ffwd, const gu16x8* fadj,
+                                     floatx16 (&acc)[NF], const PT* ffwd, const PT* fadj,
                                      const u16x8* Vb, int w, int ln, int fct, int rt0,
                                      const u16x8* Al = nullptr) {
     constexpr int KSF = N / 16, KSA = MP / 16, KSG = KSF - NL;
@@ -109,8 +111,8 @@ __device__ inline void forward_tiles(u16x8 (&af)[kPF][NF], u16x8 (&aa)[kPA][AR],
     }
 }
 
-template <int N, int MP, int CT, int NF, int W, int kPF>
-__device__ inline void load_fwd_head(u16x8 (&af)[kPF][NF], const gu16x8* ffwd, int w, int ln) {
+template <int N, int MP, int CT, int NF, int W, int kPF, class PT = gu16x8>
+__device__ inline void load_fwd_head(u16x8 (&af)[kPF][NF], const PT* ffwd, int w, int ln) {
     constexpr int KSF = N / 16;
 #pragma unroll
     for (int p = 0; p < kPF; ++p)
@@ -123,7 +125,8 @@ __device__ inline void load_fwd_head(u16x8 (&af)[kPF][NF], const gu16x8* ffwd, i
 
 // R = P - y for one forward tile, written to LDS as bf16 (y from registers
 // or from global memory).  NEG: R' = (y - P) * scale instead, so that an
-// adjoint accumulator started at v ends at v - A^T (P - y) scale.
+// adjoint accumulator started at v ends at v - A^T (P - y) scale; with y in
+// registers it is held as y * scale and R' = y * scale - P * scale.
 template <int MP, int CT, bool YREG, bool NEG = false>
 __device__ inline void store_residual(const floatx16& acc, const floatx16& yv, const gfloat* yg,
                                       int nblk, int mt, int fct, int ln, u16x8* Rb,
@@ -144,7 +147,8 @@ __device__ inline void store_residual(const floatx16& acc, const floatx16& yv, c
     }
     floatx16 rr;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) rr[r] = NEG ? (yy[r] - acc[r]) * scale : acc[r] - yy[r];
+    for (int r = 0; r < 16; ++r)
+        rr[r] = !NEG ? acc[r] - yy[r] : YREG ? fmaf(-acc[r], scale, yy[r]) : (yy[r] - acc[r]) * scale;
     Rb[((2 * mt) * CT + fct) * 64 + ln] = pack_bf16(rr, 0);
     Rb[((2 * mt + 1) * CT + fct) * 64 + ln] = pack_bf16(rr, 1);
 }

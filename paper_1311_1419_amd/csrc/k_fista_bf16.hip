@@ -30,6 +30,7 @@
 // plain sums.
 #include <algorithm>
 #include <atomic>
+#include <type_traits>
 
 #include "fused_common.h"
 
@@ -78,7 +79,11 @@ void launch_bf16_frag_layout(Operator* op, hipStream_t st) {
 // (the kernel's bound at n = 1024).  NL < 0: -NL such steps, interleaved
 // with the global ring rounds instead of run after them.  OPT bit 0: each
 // wave keeps its y^ rows of the tile in registers for all T iterations
-// instead of reading them from L2 in every residual epilogue.
+// instead of reading them from L2 in every residual epilogue.  OPT bit 1:
+// both fragment layouts of the whole operator are copied to LDS when a
+// tile's operator differs from the previous tile's, and every iteration
+// reads them there instead of from L2 (small classes, where the operator
+// fits beside V and R).
 template <int N, int MP, int CT, int W, int kPF, int kPA, int SPL, int OCC, int NLS, int OPT = 0>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W * OCC / 4)))
 void fista_bf16_kernel(
@@ -94,6 +99,11 @@ void fista_bf16_kernel(
     constexpr int FT = (TT + W - 1) / W;         // forward tiles per wave (max)
     constexpr int KSF = N / 16, KSA = MP / 16;   // K steps of forward / adjoint
     constexpr bool YREG = (OPT & 1) != 0;        // else y^ is read from L2 in every epilogue
+    constexpr bool OPL = (OPT & 2) != 0;         // operator resident in LDS
+    static_assert(!(OPL && NLS != 0), "the LDS slice is part of an LDS-resident operator");
+    constexpr int OFW = (MP / 32) * KSF * 64;   // u16x8 of the forward layout (OPL)
+    constexpr int OFA = (N / 32) * KSA * 64;    // u16x8 of the adjoint layout (OPL)
+    using PT = std::conditional_t<OPL, u16x8, gu16x8>;   // operator pointee type
     constexpr int NL = NLS < 0 ? -NLS : NLS;     // LDS-resident forward K steps
     constexpr bool ILV = NLS < 0;
     static_assert(RT * CT >= 2 && (RT * CT) % 2 == 0 && W % CT == 0, "unsupported class");
@@ -107,6 +117,8 @@ void fista_bf16_kernel(
     u16x8* Al = reinterpret_cast<u16x8*>(lds + (size_t)(KSF + KSA) * CT * 1024 +
                                          (size_t)W * SPL * 4096);
     // Al: [W][FT][NL][64], forward fragments (mt_i, KSF - NL + j) of wave w
+    u16x8* Ol = Al + (size_t)W * FT * NL * 64;
+    // Ol (OPL): [forward layout OFW][adjoint layout OFA], the global order
     static_assert(NL == 0 || KSF - NL >= kPF, "LDS steps leave no global ring");
     __shared__ int s_tile;
 
@@ -114,6 +126,7 @@ void fista_bf16_kernel(
     const int fct = w % CT;                      // column tile of this wave's forward tiles
     const int nft = (TT - w + W - 1) / W;        // forward tiles of this wave: FT, FT-1 or 0
     const void* al_src = nullptr;                // operator whose fragments Al holds
+    const void* ol_src = nullptr;                // operator that Ol holds (OPL)
 
     for (;;) {
         if (tid == 0) s_tile = next_tile(qoff, queue, counters);
@@ -122,8 +135,25 @@ void fista_bf16_kernel(
         __syncthreads();
         if (t_id < 0) break;
         const FusedTile tl = tiles[t_id];
-        const gu16x8* ffwd = as_global<const gu16x8>(tl.frag_fwd);
-        const gu16x8* fadj = as_global<const gu16x8>(tl.frag_adj);
+        const PT* ffwd;
+        const PT* fadj;
+        if constexpr (OPL) {
+            // every wave is past the previous tile (barriers above): copy the
+            // new tile's operator once, then wait for the whole copy
+            if (tl.frag_fwd != ol_src) {
+                const gu16x8* gf = as_global<const gu16x8>(tl.frag_fwd);
+                const gu16x8* ga = as_global<const gu16x8>(tl.frag_adj);
+                for (int i = tid; i < OFW; i += 64 * W) Ol[i] = gf[i];
+                for (int i = tid; i < OFA; i += 64 * W) Ol[OFW + i] = ga[i];
+                ol_src = tl.frag_fwd;
+                __syncthreads();
+            }
+            ffwd = Ol;
+            fadj = Ol + OFW;
+        } else {
+            ffwd = as_global<const gu16x8>(tl.frag_fwd);
+            fadj = as_global<const gu16x8>(tl.frag_adj);
+        }
         const gfloat* yg = as_global<const gfloat>(tl.y);
         const float inv_l = (float)(1.0 / tl.lip[0]);
         const int T = tl.T;
@@ -157,7 +187,8 @@ void fista_bf16_kernel(
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int m = mt * 32 + 8 * (r / 4) + 4 * h + (r % 4);
-                    yv[i][r] = (t < TT && b < tl.nblk) ? tl.y[(size_t)b * MP + m] : 0.f;
+                    // held as y^ / L: the residual epilogue is then one FMA
+                    yv[i][r] = (t < TT && b < tl.nblk) ? tl.y[(size_t)b * MP + m] * inv_l : 0.f;
                 }
             }
         }
@@ -226,12 +257,15 @@ void fista_bf16_kernel(
             //      list); threshold and momentum on the accumulators; new V
             //      to LDS
             const float bk = beta[k];
+            const float bk1 = 1.f + bk, nbk = -bk;
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
                         const int rt0 = (2 * g) / CT, ct0 = (2 * g) % CT;
                 const int rt1 = (2 * g + 1) / CT, ct1 = (2 * g + 1) % CT;
-                // started at v: with R' = (y - A v) / L the product ends at u
-                floatx16 ga[2] = {vv[rt0][ct0], vv[rt1][ct1]};
+                // accumulated in place on v: with R' = (y - A v) / L the
+                // product ends at u = v - A^T (A v - y) / L
+                floatx16& ga0 = vv[rt0][ct0];
+                floatx16& ga1 = vv[rt1][ct1];
 #pragma unroll 1
                 for (int ks0 = 0; ks0 < KSA - kPA; ks0 += kPA) {
 #pragma unroll
@@ -243,8 +277,8 @@ void fista_bf16_kernel(
                                        : __builtin_bit_cast(bf16x8, Rb[(ks * CT + ct1) * 64 + ln]);
                         const bf16x8 a0 = __builtin_bit_cast(bf16x8, aa[j][0]);
                         const bf16x8 a1 = AR == 2 ? __builtin_bit_cast(bf16x8, aa[j][AR - 1]) : a0;
-                        ga[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, ga[0], 0, 0, 0);
-                        ga[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, ga[1], 0, 0, 0);
+                        ga0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, ga0, 0, 0, 0);
+                        ga1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, ga1, 0, 0, 0);
 #pragma unroll
                         for (int r = 0; r < AR; ++r)
                             aa[j][r] = fadj[((size_t)(w * RT + (2 * g + r) / CT) * KSA + ks + kPA) *
@@ -259,8 +293,8 @@ void fista_bf16_kernel(
                         ct1 == ct0 ? b0 : __builtin_bit_cast(bf16x8, Rb[(ks * CT + ct1) * 64 + ln]);
                     const bf16x8 a0 = __builtin_bit_cast(bf16x8, aa[j][0]);
                     const bf16x8 a1 = AR == 2 ? __builtin_bit_cast(bf16x8, aa[j][AR - 1]) : a0;
-                    ga[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, ga[0], 0, 0, 0);
-                    ga[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, ga[1], 0, 0, 0);
+                    ga0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, ga0, 0, 0, 0);
+                    ga1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, ga1, 0, 0, 0);
                     if (g + 1 < NG) {
 #pragma unroll
                         for (int r = 0; r < AR; ++r)
@@ -288,12 +322,23 @@ void fista_bf16_kernel(
                             spv[4 * q + 3] = t4.w;
                         }
                     }
+                    // s_k = u - med3(u, -tau, tau); v = s_k + beta_k (s_k - s_{k-1}).
+                    // The register-light classes (y^ in registers) take v as
+                    // (1 + beta_k) s_k - beta_k s_{k-1}, four VALU operations in
+                    // place on u and s with no register moves; the n = 1024
+                    // classes keep the form whose temporaries do not spill
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
-                        const float u = ga[e][r];
-                        const float sn = u - __builtin_amdgcn_fmed3f(u, -tc, tc);
-                        vv[rt][ct][r] = fmaf(bk, sn - spv[r], sn);
-                        spv[r] = sn;
+                        const float u = vv[rt][ct][r];
+                        if constexpr (YREG) {
+                            const float m = nbk * spv[r];
+                            spv[r] = u - __builtin_amdgcn_fmed3f(u, -tc, tc);
+                            vv[rt][ct][r] = fmaf(bk1, spv[r], m);
+                        } else {
+                            const float sn = u - __builtin_amdgcn_fmed3f(u, -tc, tc);
+                            vv[rt][ct][r] = fmaf(bk, sn - spv[r], sn);
+                            spv[r] = sn;
+                        }
                     }
                     if (ut < SPR) {
                         sp[ut < SPR ? ut : 0] = spv;
@@ -346,8 +391,10 @@ static void launch_class(const FusedTile* tiles, const int* qoff, const int* que
     static_assert(W * OCC % 4 == 0 && W * OCC <= 32, "waves per CU");
     constexpr size_t kFT = ((MP / 32) * CT + W - 1) / W;
     constexpr size_t kNL = NL < 0 ? -NL : NL;
+    constexpr size_t kOp = (OPT & 2) ? ((size_t)(MP / 32) * (N / 16) + (size_t)(N / 32) * (MP / 16)) * 1024
+                                     : 0;   // LDS-resident operator
     constexpr size_t kLds = (size_t)(N / 16) * CT * 1024 + (size_t)(MP / 16) * CT * 1024 +
-                            (size_t)W * SPL * 4096 + (size_t)W * kFT * kNL * 1024;
+                            (size_t)W * SPL * 4096 + (size_t)W * kFT * kNL * 1024 + kOp;
     static_assert((kLds + 64) * OCC <= 160 * 1024, "LDS of OCC workgroups exceeds a CU");
     const size_t lds = kLds;
     auto* fn = &fista_bf16_kernel<N, MP, CT, W, PF, PA, SPL, OCC, NL, OPT>;
@@ -371,6 +418,11 @@ static void launch_class(const FusedTile* tiles, const int* qoff, const int* que
         "ct" #CT "_w" #W "_pf" #PF "_pa" #PA "_spl" #SPL "_o" #OCC "_yreg", CT, OCC,        \
             &launch_class<NN, MM, CT, W, PF, PA, SPL, OCC, 0, 1>                            \
     }
+#define CSV_VOL(NN, MM, CT, W, PF, PA, OCC)                                                 \
+    FusedVariant {                                                                         \
+        "ct" #CT "_w" #W "_pf" #PF "_pa" #PA "_spl0_o" #OCC "_yreg_oplds", CT, OCC,         \
+            &launch_class<NN, MM, CT, W, PF, PA, 0, OCC, 0, 3>                              \
+    }
 #define CSV_VL(NN, MM, CT, W, PF, PA, SPL, OCC, NL) \
     CSV_VG(NN, MM, CT, W, PF, PA, SPL, OCC, NL, "_lds" #NL)
 #define CSV_VLI(NN, MM, CT, W, PF, PA, SPL, OCC, NL) \
@@ -385,22 +437,28 @@ struct ClassEntry {
 static std::vector<ClassEntry>& class_table() {
     static std::vector<ClassEntry> t = {
         {256, 32,
-         {CSV_V(256, 32, 2, 4, 4, 2, 0, 2), CSV_V(256, 32, 1, 4, 4, 2, 0, 3),
-          CSV_V(256, 32, 2, 8, 4, 2, 0, 1), CSV_V(256, 32, 4, 8, 4, 2, 0, 1)},
+         {CSV_VOL(256, 32, 1, 4, 4, 2, 3), CSV_VY(256, 32, 2, 4, 4, 2, 0, 2),
+          CSV_V(256, 32, 1, 4, 4, 2, 0, 3), CSV_VY(256, 32, 1, 4, 4, 2, 0, 3),
+          CSV_VOL(256, 32, 2, 4, 4, 2, 2), CSV_VOL(256, 32, 4, 8, 4, 2, 1),
+          CSV_V(256, 32, 2, 4, 4, 2, 0, 2), CSV_V(256, 32, 4, 8, 4, 2, 0, 1)},
          0},
         {256, 64,
-         {CSV_V(256, 64, 2, 4, 4, 2, 0, 2), CSV_V(256, 64, 1, 4, 4, 2, 0, 3),
-          CSV_V(256, 64, 2, 8, 4, 2, 0, 1), CSV_V(256, 64, 4, 8, 4, 2, 0, 1),
-          CSV_VY(256, 64, 2, 4, 4, 2, 0, 2), CSV_VY(256, 64, 2, 4, 16, 4, 0, 1),
-          CSV_VY(256, 64, 2, 8, 8, 4, 0, 1), CSV_VY(256, 64, 1, 4, 8, 4, 0, 2)},
+         {CSV_VOL(256, 64, 4, 8, 4, 2, 1), CSV_VY(256, 64, 2, 4, 4, 2, 0, 2),
+          CSV_V(256, 64, 2, 4, 4, 2, 0, 2), CSV_VY(256, 64, 1, 4, 8, 4, 0, 2),
+          CSV_VY(256, 64, 2, 8, 8, 4, 0, 1), CSV_VOL(256, 64, 2, 4, 4, 2, 1),
+          CSV_VOL(256, 64, 2, 8, 4, 2, 1), CSV_VY(256, 64, 1, 4, 4, 2, 0, 3)},
          0},
         {256, 96,
-         {CSV_V(256, 96, 1, 4, 2, 2, 0, 3), CSV_V(256, 96, 2, 4, 2, 2, 0, 2),
+         {CSV_VOL(256, 96, 2, 8, 2, 2, 1), CSV_VY(256, 96, 2, 4, 2, 2, 0, 2),
+          CSV_V(256, 96, 1, 4, 2, 2, 0, 3), CSV_V(256, 96, 2, 4, 2, 2, 0, 2),
+          CSV_VOL(256, 96, 1, 4, 2, 2, 1), CSV_VY(256, 96, 1, 4, 2, 2, 0, 3),
           CSV_V(256, 96, 4, 8, 4, 2, 0, 1), CSV_V(256, 96, 2, 8, 4, 2, 0, 1)},
          0},
         {256, 128,
-         {CSV_V(256, 128, 1, 4, 2, 2, 0, 3), CSV_V(256, 128, 2, 4, 2, 2, 0, 2),
-          CSV_V(256, 128, 2, 8, 4, 2, 0, 1), CSV_V(256, 128, 4, 8, 4, 2, 0, 1)},
+         {CSV_VY(256, 128, 2, 4, 2, 2, 0, 2), CSV_V(256, 128, 1, 4, 2, 2, 0, 3),
+          CSV_V(256, 128, 2, 4, 2, 2, 0, 2), CSV_VOL(256, 128, 1, 4, 2, 2, 1),
+          CSV_VY(256, 128, 1, 4, 2, 2, 0, 3), CSV_V(256, 128, 2, 8, 4, 2, 0, 1),
+          CSV_V(256, 128, 4, 8, 4, 2, 0, 1)},
          0},
         {1024, 32,
          {CSV_VLI(1024, 32, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 32, 1, 8, 4, 2, 0, 1),
@@ -433,6 +491,7 @@ static std::vector<ClassEntry>& class_table() {
 }
 #undef CSV_V
 #undef CSV_VY
+#undef CSV_VOL
 #undef CSV_VL
 #undef CSV_VLI
 #undef CSV_VG

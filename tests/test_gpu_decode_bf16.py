@@ -36,6 +36,8 @@ CASES = [
     (sv.qcif_tiny().with_(block=32, m=410, gop=2, iters=300), "qcif-b32-m410-padded"),
     (sv.qcif_tiny().with_(block=32, m=51, gop=3, iters=300), "qcif-b32-m51-padded"),
     (sv.cif_sweep(4, 0.25).with_(block=32, m=12, iters=300), "cif-b32-m12"),
+    (sv.cif_sweep(8, 0.2), "cif-g8-b16-m51"),
+    (sv.cif_sweep(16, 0.2), "cif-g16-b16-m51"),
 ]
 
 
