@@ -62,6 +62,9 @@ def parse():
                     help="blocks the oracle recovers for the CPU baseline")
     ap.add_argument("--cpu-blocks-1t", type=int, default=400,
                     help="blocks the oracle recovers on one thread for the CPU baseline")
+    ap.add_argument("--variant", type=str, default="",
+                    help="headline mode: run the (n=1024, M_p=256) class with this named kernel "
+                         "variant instead of its default (e.g. q8_w8_pf2x2_pa2x2)")
     ap.add_argument("--headline-serve-load", type=float, default=0.16,
                     help="headline mode: one serving point at this fraction of the 256 "
                          "cameras' nominal GOP rates (0: none)")
@@ -280,15 +283,16 @@ def serve_sweep(loads, window, on_point=None):
             pool[key] = torch.from_numpy(spec.video()).cuda()
     sweep = []
     with P.Context(0) as ctx:
-        enc = []
-        for spec, rate in cams:
-            p = P.Params.from_spec(spec, precision=P.CSV_BF16)
-            enc.append((p, ctx.encode_gop(pool[(spec.height, spec.width, spec.gop)], p), rate))
+        # one batch encode: the 256 cameras' operators are set up together
+        params = [P.Params.from_spec(spec, precision=P.CSV_BF16) for spec, _ in cams]
+        streams = ctx.encode_batch([(pool[(spec.height, spec.width, spec.gop)], p)
+                                    for (spec, _), p in zip(cams, params)])
+        enc = [(p, gs, rate) for p, gs, (_, rate) in zip(params, streams, cams)]
         torch.cuda.synchronize()
         rng = np.random.default_rng(7)
         for load in loads:
             with P.Server(0, mem_budget=48 << 30, hip_streams=2) as srv:
-                sids = [srv.register_stream(p) for p, _, _ in enc]
+                sids = srv.register_streams([p for p, _, _ in enc])
                 warm = [srv.submit(sids[i], enc[i][1]) for i in range(6)]
                 srv.drain(120.0)
                 for t in warm:
@@ -726,6 +730,15 @@ def main():
     flops_launch = sum((s.gop - 1) * ((s.height + 31) // 32) * ((s.width + 31) // 32)
                        * 4.0 * s.m * s.n * s.iters for s in specs)
 
+    if args.variant:
+        count = P.kernel_choice(32, 256)[2]
+        names = []
+        for i in range(count):
+            P.set_kernel_choice(32, 256, i)
+            names.append(P.kernel_choice(32, 256)[0])
+        if args.variant not in names:
+            sys.exit(f"no variant {args.variant!r} in the (1024, 256) class: {names}")
+        P.set_kernel_choice(32, 256, names.index(args.variant))
     with P.Context(0) as ctx:
         wall, per_step, outs, streams = run_path(ctx, P, torch, specs, frames_dev, P.CSV_BF16,
                                                  args.steps, args.warmup)
@@ -787,7 +800,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2) if achieved else None,
                      "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_BF16_TFLOPS, 4) if achieved else None,
-                     "traffic": measured_traffic(args.streams), "traffic_unit": "bytes/launch",
+                     "traffic": None if args.variant else measured_traffic(args.streams),
+                     "traffic_unit": "bytes/launch",
                      "kernel": f"fista_bf16_kernel[n=1024,Mp=256] variant {variant}",
                      "kernel_ms": round(1e3 * avg_k_s, 4), "flops_per_launch": flops_launch,
                      "tiles_per_launch": tiles, "l2_bytes_per_launch": l2_bytes,

@@ -87,6 +87,13 @@ int csv_server_destroy(csv_server* srv);
  * size and M (for CSV_FLAG_TV: 16 x 16 blocks, M up to 128); whole-frame
  * streams (CSV_FLAG_WHOLE_FRAME) need an FP32 server and CSV_FLAG_TV. */
 int csv_server_register_stream(csv_server* srv, const csv_params* p, uint32_t* sid);
+/* Register `count` streams at once (params and sids: host arrays of count
+ * entries): the same validation and ids as count single registrations (in
+ * order; none is registered if any is refused), with the new operators'
+ * FP64 power iterations run side by side in one launch, one workgroup per
+ * stream, so that the setup of many cameras costs about as much as one. */
+int csv_server_register_streams(csv_server* srv, int32_t count, const csv_params* params,
+                                uint32_t* sids);
 
 /* Submit one GOP of stream sid.  t_arrival: csv_clock() seconds (<= 0:
  * now).  Returns CSV_EAGAIN if the waiting queue is full, CSV_ENOMEM if the

@@ -146,6 +146,8 @@ _SIGS = {
     "csv_server_create": (C.c_int, [C.c_int, _P(CsvServerOpts), _P(C.c_void_p)]),
     "csv_server_destroy": (C.c_int, [C.c_void_p]),
     "csv_server_register_stream": (C.c_int, [C.c_void_p, _P(CsvParams), _P(C.c_uint32)]),
+    "csv_server_register_streams": (C.c_int, [C.c_void_p, C.c_int32, _P(CsvParams),
+                                              _P(C.c_uint32)]),
     "csv_submit": (C.c_int, [C.c_void_p, C.c_uint32, _P(CsvGopStream), C.c_double,
                              _P(C.c_uint64)]),
     "csv_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p, _P(C.c_int32)]),

@@ -183,12 +183,18 @@ void release_ctx(Ctx* c) {
     c->fork_ev = nullptr;
 }
 
-Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
+using OpKey = std::tuple<uint64_t, uint32_t, int, int, bool>;
+static OpKey op_key(const Shape& s) {
+    return std::make_tuple(s.seed, s.sid, s.n, s.M, (s.flags & CSV_FLAG_WHOLE_FRAME) != 0);
+}
+
+// Build the operator of s into the cache (the cache's lock held).  With
+// gram_dst set, a block operator's exact Gram matrix goes there and its
+// step constant is left to the caller's batched power iteration.
+static Operator* build_operator_locked(Ctx* c, const Shape& s, hipStream_t st,
+                                       int* gram_dst = nullptr) {
     const bool whole = (s.flags & CSV_FLAG_WHOLE_FRAME) != 0;
-    const auto key = std::make_tuple(s.seed, s.sid, s.n, s.M, whole);
-    std::lock_guard<std::mutex> lk(c->cache->mu);
-    auto it = c->cache->ops.find(key);
-    if (it != c->cache->ops.end()) return it->second.get();
+    const OpKey key = op_key(s);
     CSV_REQUIRE(!c->capturing, CSV_EINVAL, "operator setup during graph capture");
     auto op = std::make_unique<Operator>();
     op->B = s.B;
@@ -258,8 +264,12 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
         launch_operator_setup(op.get(), st);
         launch_bf16_frag_layout(op.get(), st);
         launch_q8_frag_layout(op.get(), st);
-        int* gram = static_cast<int*>(scratch(c, "gram", (size_t)s.M * s.M * 4));
-        launch_power_iteration(op.get(), gram, st);
+        if (gram_dst) {
+            launch_gram(op.get(), gram_dst, st);
+        } else {
+            int* gram = static_cast<int*>(scratch(c, "gram", (size_t)s.M * s.M * 4));
+            launch_power_iteration(op.get(), gram, st);
+        }
     } catch (...) {
         free_operator(c, op.get());
         throw;
@@ -267,6 +277,45 @@ Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
     Operator* raw = op.get();
     c->cache->ops.emplace(key, std::move(op));
     return raw;
+}
+
+Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(c->cache->mu);
+    auto it = c->cache->ops.find(op_key(s));
+    if (it != c->cache->ops.end()) return it->second.get();
+    return build_operator_locked(c, s, st);
+}
+
+void prepare_operators(Ctx* c, const Shape* shapes, int count, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(c->cache->mu);
+    // the block operators of this call that are not cached yet, once each
+    // (whole-frame operators, with their large Gram matrices, are built
+    // one at a time by get_operator)
+    std::vector<const Shape*> todo;
+    std::vector<OpKey> keys;
+    for (int i = 0; i < count; ++i) {
+        const Shape& s = shapes[i];
+        if (s.G < 2 || (s.flags & CSV_FLAG_WHOLE_FRAME)) continue;
+        const OpKey k = op_key(s);
+        if (c->cache->ops.count(k) || std::find(keys.begin(), keys.end(), k) != keys.end())
+            continue;
+        keys.push_back(k);
+        todo.push_back(&s);
+    }
+    if (todo.size() < 2) {   // nothing to batch: get_operator builds it when asked
+        return;
+    }
+    std::vector<size_t> off(todo.size() + 1, 0);
+    for (size_t i = 0; i < todo.size(); ++i)
+        off[i + 1] = off[i] + ((size_t)todo[i]->M * todo[i]->M + 63) / 64 * 64;
+    int* grams = static_cast<int*>(scratch(c, "gram_batch", off.back() * 4));
+    std::vector<Operator*> ops;
+    std::vector<int*> gp;
+    for (size_t i = 0; i < todo.size(); ++i) {
+        gp.push_back(grams + off[i]);
+        ops.push_back(build_operator_locked(c, *todo[i], st, gp.back()));
+    }
+    launch_power_batch(ops.data(), gp.data(), (int)ops.size(), st);
 }
 
 // beta_k = (t_k - 1) / t_{k+1}, t_1 = 1, t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
@@ -721,6 +770,7 @@ static hipStream_t chain_lane(Ctx* c, hipStream_t st, int k) {
 void encode_gops(Ctx* c, int count, const Shape* shapes, const uint8_t* const* frames,
                  const csv_gop_stream* out, hipStream_t st) {
     std::vector<Operator*> ops(count, nullptr);
+    prepare_operators(c, shapes, count, st);   // new streams' setup in one batch
     for (int i = 0; i < count; ++i) {
         const Shape& s = shapes[i];
         CSV_REQUIRE(frames[i] && out[i].key_levels, CSV_EINVAL, "NULL frames or key_levels");
@@ -906,6 +956,7 @@ void decode_gops(Ctx* c, int count, const Shape* shapes, const csv_gop_stream* i
         const float* y = nullptr;
     };
     std::vector<Item> items(count);
+    prepare_operators(c, shapes, count, st);   // new streams' setup in one batch
     for (int i = 0; i < count; ++i) {
         const Shape& s = shapes[i];
         CSV_REQUIRE(in[i].key_levels && frames_out[i], CSV_EINVAL, "NULL key_levels or frames_out");

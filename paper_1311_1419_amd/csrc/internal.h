@@ -140,6 +140,9 @@ void* ctx_alloc(Ctx* c, size_t bytes);
 void ctx_free(Ctx* c, void* p, size_t bytes);
 void* scratch(Ctx* c, const std::string& name, size_t bytes);
 Operator* get_operator(Ctx* c, const Shape& s, hipStream_t st);
+// Build the operators of every shape not yet cached, with one batched power
+// iteration for all of them (the setup of many new streams at once).
+void prepare_operators(Ctx* c, const Shape* shapes, int count, hipStream_t st);
 void free_operators(Ctx* c);   // when c holds the last reference to its cache
 void release_ctx(Ctx* c);      // free everything c allocated
 // Decode `count` GOPs (key frames, recovery of every CS block in one pass,
@@ -179,6 +182,21 @@ void launch_fill_u64(unsigned long long* p, unsigned long long v, int count, hip
 // decode side (k_decode.hip)
 void launch_operator_setup(Operator* op, hipStream_t st);
 void launch_power_iteration(Operator* op, int* gram, hipStream_t st);   // gram: M x M int32 scratch
+// The same for many operators: each one's exact Gram matrix (launch_gram),
+// then their power iterations side by side, one workgroup per operator,
+// kPowBatch operators per launch.
+constexpr int kPowBatch = 64;
+struct PowJob {
+    const int* gram;
+    int M, S;
+    double s_phi;
+    double* lip;
+};
+struct PowBatch {
+    PowJob j[kPowBatch];
+};
+void launch_gram(Operator* op, int* gram, hipStream_t st);
+void launch_power_batch(Operator* const* ops, int* const* grams, int count, hipStream_t st);
 // raw: codes hold int32 y~ and exps are ignored (CSV_FLAG_NO_QUANT)
 void launch_dequant(const int8_t* codes, const uint8_t* exps, int nblk, int M, int Mp,
                     double s_phi, float* y, hipStream_t st, bool raw = false);

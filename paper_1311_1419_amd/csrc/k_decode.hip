@@ -114,11 +114,9 @@ __device__ inline void block_sum2_1024(double& a, double& b, double (*red)[16]) 
 // partial sums meet by a fixed shuffle tree, and the group's first thread
 // keeps w_i.  With S = 1 a thread takes rows t, t + 1024, ... (up to 16).
 constexpr int kPowRows = 16;
-__global__ __launch_bounds__(1024) void power_kernel(const int* __restrict__ g, int M, int S,
-                                                    double s_phi, double tol, int max_iter,
-                                                    double* __restrict__ lip) {
-    extern __shared__ double v[];   // M
-    __shared__ double red[2][16];
+__device__ inline void power_iterate(const int* __restrict__ g, int M, int S, double s_phi,
+                                     double tol, int max_iter, double* __restrict__ lip,
+                                     double* v, double (*red)[16]) {
     const int tid = threadIdx.x, grp = tid / S, sl = tid - grp * S, per_pass = 1024 / S;
     for (int i = tid; i < M; i += 1024) v[i] = 1.0 / sqrt((double)M);
     __syncthreads();
@@ -164,6 +162,23 @@ __global__ __launch_bounds__(1024) void power_kernel(const int* __restrict__ g, 
     }
 }
 
+__global__ __launch_bounds__(1024) void power_kernel(const int* __restrict__ g, int M, int S,
+                                                    double s_phi, double tol, int max_iter,
+                                                    double* __restrict__ lip) {
+    extern __shared__ double v[];   // M
+    __shared__ double red[2][16];
+    power_iterate(g, M, S, s_phi, tol, max_iter, lip, v, red);
+}
+
+// The power iterations of several streams side by side, one workgroup each
+// (the same iteration as power_kernel, job blockIdx.x).
+__global__ __launch_bounds__(1024) void power_batch_kernel(PowBatch bt, double tol, int max_iter) {
+    extern __shared__ double v[];   // the largest M of the batch
+    __shared__ double red[2][16];
+    const PowJob& j = bt.j[blockIdx.x];
+    power_iterate(j.gram, j.M, j.S, j.s_phi, tol, max_iter, j.lip, v, red);
+}
+
 void launch_operator_setup(Operator* op, hipStream_t st) {
     const int B = op->B, n = op->n;
     double* c64 = op->dct64;
@@ -172,6 +187,39 @@ void launch_operator_setup(Operator* op, hipStream_t st) {
     operator_kernel<<<dim3(op->Mp), dim3(256), 3 * n * sizeof(double), st>>>(
         op->q, op->M, B, op->s_phi, c64, op->a64, op->a32, op->phi32);
     CSV_HIP(hipGetLastError());
+}
+
+static int power_threads_per_row(int M) {
+    int S = 1;   // 1024 / M rounded down to a power of two, <= 64
+    while (S < 64 && 2 * S * M <= 1024) S *= 2;
+    return S;
+}
+
+void launch_gram(Operator* op, int* gram, hipStream_t st) {
+    const int M = op->M;
+    CSV_REQUIRE(M <= 1024 * kPowRows, CSV_EUNSUPPORTED, "step constant: M above 16384");
+    CSV_REQUIRE(1024ll * op->n < (1ll << 31), CSV_EUNSUPPORTED,
+                "step constant: n too large for the exact int32 Gram matrix");
+    gram_kernel<<<dim3(ceil_div(M, 16), ceil_div(M, 16)), dim3(256), 0, st>>>(op->q, M, op->n,
+                                                                             gram);
+    CSV_HIP(hipGetLastError());
+}
+
+void launch_power_batch(Operator* const* ops, int* const* grams, int count, hipStream_t st) {
+    ensure_lds_limit<&power_batch_kernel>((size_t)1024 * kPowRows * sizeof(double));
+    for (int a = 0; a < count; a += kPowBatch) {
+        PowBatch bt{};
+        int mmax = 0;
+        const int k = std::min(kPowBatch, count - a);
+        for (int i = 0; i < k; ++i) {
+            Operator* op = ops[a + i];
+            bt.j[i] = PowJob{grams[a + i], op->M, power_threads_per_row(op->M), op->s_phi, op->lip};
+            mmax = std::max(mmax, op->M);
+        }
+        power_batch_kernel<<<dim3(k), dim3(1024), (size_t)mmax * sizeof(double), st>>>(bt, 1e-12,
+                                                                                     10000);
+        CSV_HIP(hipGetLastError());
+    }
 }
 
 void launch_power_iteration(Operator* op, int* gram, hipStream_t st) {

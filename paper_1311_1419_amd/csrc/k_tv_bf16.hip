@@ -35,6 +35,7 @@
 // and the group's first row of x to LDS, barrier.  LDS rows read before a
 // barrier are rewritten only after the next one.
 #include <algorithm>
+#include <type_traits>
 
 #include "fused_common.h"
 #include "tv_step.h"
@@ -109,11 +110,18 @@ __device__ inline void grad_group(const floatx16& x, const float* xrow, int w, i
     }
 }
 
-template <int MP, int kPF, int kPA, int OCC>
+// The forward waves keep their y^ rows of the tile in registers, scaled by
+// alpha, for all T iterations (the residual epilogue is one FMA per value).
+// OPL: both layouts of Phi (M_p x 256 bf16 fragments) are copied into LDS
+// when a tile's operator differs from the previous tile's, and every
+// iteration reads them there instead of from L2.
+template <int MP, int kPF, int kPA, int OCC, bool OPL>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2 * OCC)))
 void tv_bf16_kernel(const FusedTile* __restrict__ tiles, const int* __restrict__ qoff,
                     const int* __restrict__ queue, int* __restrict__ counters) {
     constexpr int N = 256, W = 8, CT = 1;
+    constexpr int OFW = (MP / 32) * (N / 16) * 64, OFA = (N / 32) * (MP / 16) * 64;   // u16x8
+    using PT = std::conditional_t<OPL, u16x8, gu16x8>;
     constexpr int KSF = N / 16, KSA = MP / 16;
     constexpr int TT = MP / 32;                  // forward output tiles (one per wave w < TT)
     static_assert(TT <= W, "one forward tile per wave");
@@ -123,7 +131,9 @@ void tv_bf16_kernel(const FusedTile* __restrict__ tiles, const int* __restrict__
     u16x8* Rb = reinterpret_cast<u16x8*>(lds + (size_t)KSF * 1024);         // [KSA][64]
     float* xrow = reinterpret_cast<float*>(lds + (size_t)(KSF + KSA) * 1024);   // [W][8][64]
     float* prow = xrow + W * 8 * 64;                                        // [W][8][64]
+    u16x8* Ol = reinterpret_cast<u16x8*>(prow + W * 8 * 64);                // OPL: [OFW][OFA]
     __shared__ int s_tile;
+    const void* ol_src = nullptr;
 
     const int tid = threadIdx.x, ln = tid & 63, h = ln >> 5, col = ln & 31;
     // the wave index is uniform across the wave: keep it in a scalar register
@@ -138,14 +148,36 @@ void tv_bf16_kernel(const FusedTile* __restrict__ tiles, const int* __restrict__
         __syncthreads();
         if (t_id < 0) break;
         const FusedTile tl = tiles[t_id];
-        const gu16x8* ffwd = as_global<const gu16x8>(tl.frag_fwd);
-        const gu16x8* fadj = as_global<const gu16x8>(tl.frag_adj);
+        const PT* ffwd;
+        const PT* fadj;
+        if constexpr (OPL) {
+            // every wave is past the previous tile (barriers above)
+            if (tl.frag_fwd != ol_src) {
+                const gu16x8* gf = as_global<const gu16x8>(tl.frag_fwd);
+                const gu16x8* gad = as_global<const gu16x8>(tl.frag_adj);
+                for (int i = tid; i < OFW; i += 512) Ol[i] = gf[i];
+                for (int i = tid; i < OFA; i += 512) Ol[OFW + i] = gad[i];
+                ol_src = tl.frag_fwd;
+                __syncthreads();
+            }
+            ffwd = Ol;
+            fadj = Ol + OFW;
+        } else {
+            ffwd = as_global<const gu16x8>(tl.frag_fwd);
+            fadj = as_global<const gu16x8>(tl.frag_adj);
+        }
         const gfloat* yg = as_global<const gfloat>(tl.y);
         const float lam = col < tl.nblk ? tl.lam[col] : 0.f;
         const float beta = tv_beta(lam);
         const float inv_beta = 1.f / beta, thr = lam / beta;
         const float alpha = tv_alpha(tl.lip[0], beta);
         const int T = tl.T;
+        floatx16 yv = {};   // alpha y^ of this wave's forward tile (rows 32 w ..)
+        if (fwd && col < tl.nblk) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                yv[r] = yg[(size_t)col * MP + w * 32 + 8 * (r / 4) + 4 * h + (r % 4)] * alpha;
+        }
 
         floatx16 x = {}, mh = {}, mv = {};
         {
@@ -188,8 +220,7 @@ void tv_bf16_kernel(const FusedTile* __restrict__ tiles, const int* __restrict__
                 floatx16 acc[1];
                 forward_tiles<N, MP, CT, 1, 1, W, kPF, kPA>(af, aa, acc, ffwd, fadj, Vb, w, ln, 0, w);
                 // R' = alpha (y^ - Phi V): the adjoint started at x ends at x - alpha G
-                store_residual<MP, CT, false, true>(acc[0], acc[0], yg, tl.nblk, w, 0, ln, Rb,
-                                                    alpha);
+                store_residual<MP, CT, true, true>(acc[0], yv, yg, tl.nblk, w, 0, ln, Rb, alpha);
             } else {
 #pragma unroll
                 for (int p = 0; p < kPA; ++p) aa[p][0] = fadj[((size_t)w * KSA + p) * 64 + ln];
@@ -258,10 +289,14 @@ void tv_bf16_kernel(const FusedTile* __restrict__ tiles, const int* __restrict__
 template <int MP, int PF, int PA, int OCC>
 static void launch_tv_class(const FusedTile* tiles, const int* qoff, const int* queue,
                             int* counters, int grid, hipStream_t st) {
-    constexpr size_t lds = (size_t)16 * 1024 + (size_t)(MP / 16) * 1024 + 2 * 8 * 8 * 64 * 4;
+    // the operator joins V, R and the stencil rows in LDS when it fits (M_p <= 96)
+    constexpr size_t base = (size_t)16 * 1024 + (size_t)(MP / 16) * 1024 + 2 * 8 * 8 * 64 * 4;
+    constexpr size_t op = ((size_t)(MP / 32) * 16 + (size_t)8 * (MP / 16)) * 1024;
+    constexpr bool OPL = (base + op + 64) * OCC <= 160 * 1024;
+    constexpr size_t lds = base + (OPL ? op : 0);
     static_assert((lds + 64) * OCC <= 160 * 1024, "LDS of OCC workgroups exceeds a CU");
-    auto* fn = &tv_bf16_kernel<MP, PF, PA, OCC>;
-    ensure_lds_limit<&tv_bf16_kernel<MP, PF, PA, OCC>>(lds);
+    auto* fn = &tv_bf16_kernel<MP, PF, PA, OCC, OPL>;
+    ensure_lds_limit<&tv_bf16_kernel<MP, PF, PA, OCC, OPL>>(lds);
     fn<<<dim3(grid), dim3(512), lds, st>>>(tiles, qoff, queue, counters);
     CSV_HIP(hipGetLastError());
 }

@@ -54,6 +54,10 @@ class Executor {
     virtual ~Executor() = default;
     virtual int slots() const = 0;
     virtual void prepare(StreamInfo& si) = 0;
+    // several streams' operators at once (their power iterations side by side)
+    virtual void prepare_many(std::vector<StreamInfo>& sis) {
+        for (auto& si : sis) prepare(si);
+    }
     virtual uint8_t* alloc(size_t bytes) = 0;
     virtual void release(uint8_t* p, size_t bytes) = 0;
     virtual void launch(int slot, const std::vector<Request*>& batch,
@@ -104,6 +108,14 @@ class HipExecutor : public Executor {
     void prepare(StreamInfo& si) override {
         CSV_HIP(hipSetDevice(device_));
         get_operator(&setup_, si.s, copy_);
+        CSV_HIP(hipStreamSynchronize(copy_));
+    }
+    void prepare_many(std::vector<StreamInfo>& sis) override {
+        CSV_HIP(hipSetDevice(device_));
+        std::vector<Shape> shapes;
+        for (auto& si : sis) shapes.push_back(si.s);
+        prepare_operators(&setup_, shapes.data(), (int)shapes.size(), copy_);
+        for (auto& si : sis) get_operator(&setup_, si.s, copy_);   // any not batched
         CSV_HIP(hipStreamSynchronize(copy_));
     }
     uint8_t* alloc(size_t bytes) override {
@@ -416,6 +428,26 @@ static int guarded_s(const std::function<void()>& f) {
     }
 }
 
+// Validate a stream for this server (its precision is the server's).
+static StreamInfo stream_info(Server& s, const csv_params* p) {
+    StreamInfo si;
+    si.p = *p;
+    si.p.precision = s.o.precision;
+    si.s = resolve(&si.p);
+    CSV_REQUIRE(si.s.G >= 2, CSV_EINVAL, "a served stream needs CS frames (gop >= 2)");
+    const bool tv = (si.s.flags & CSV_FLAG_TV) != 0;
+    if (si.s.flags & CSV_FLAG_WHOLE_FRAME)
+        CSV_REQUIRE(tv && s.o.precision == CSV_FP32, CSV_EUNSUPPORTED,
+                    "whole-frame streams are served in FP32 with CSV_FLAG_TV");
+    else if (s.o.precision == CSV_BF16)
+        CSV_REQUIRE(tv ? tv_class_supported(si.s.n, si.s.Mp)
+                       : fused_class_supported(si.s.n, si.s.Mp),
+                    CSV_EUNSUPPORTED, "no fused kernel for this block size and M");
+    CSV_REQUIRE(!(si.s.flags & CSV_FLAG_MONOTONE) || s.o.precision == CSV_FP32,
+                CSV_EUNSUPPORTED, "monotone FISTA runs on the plain FP32 path only");
+    return si;
+}
+
 extern "C" {
 
 double csv_clock(void) { return now_s(); }
@@ -476,25 +508,29 @@ int csv_server_register_stream(csv_server* srv, const csv_params* p, uint32_t* s
     return guarded_s([&] {
         CSV_REQUIRE(srv && p && sid, CSV_EINVAL, "NULL argument");
         Server& s = srv->impl;
-        StreamInfo si;
-        si.p = *p;
-        si.p.precision = s.o.precision;
-        si.s = resolve(&si.p);
-        CSV_REQUIRE(si.s.G >= 2, CSV_EINVAL, "a served stream needs CS frames (gop >= 2)");
-        const bool tv = (si.s.flags & CSV_FLAG_TV) != 0;
-        if (si.s.flags & CSV_FLAG_WHOLE_FRAME)
-            CSV_REQUIRE(tv && s.o.precision == CSV_FP32, CSV_EUNSUPPORTED,
-                        "whole-frame streams are served in FP32 with CSV_FLAG_TV");
-        else if (s.o.precision == CSV_BF16)
-            CSV_REQUIRE(tv ? tv_class_supported(si.s.n, si.s.Mp)
-                           : fused_class_supported(si.s.n, si.s.Mp),
-                        CSV_EUNSUPPORTED, "no fused kernel for this block size and M");
-        CSV_REQUIRE(!(si.s.flags & CSV_FLAG_MONOTONE) || s.o.precision == CSV_FP32,
-                    CSV_EUNSUPPORTED, "monotone FISTA runs on the plain FP32 path only");
+        StreamInfo si = stream_info(s, p);
         s.ex->prepare(si);   // operator setup outside the server lock
         std::lock_guard<std::mutex> lk(s.mu);
         s.streams.push_back(si);
         *sid = (uint32_t)(s.streams.size() - 1);
+    });
+}
+
+int csv_server_register_streams(csv_server* srv, int32_t count, const csv_params* params,
+                                uint32_t* sids) {
+    return guarded_s([&] {
+        CSV_REQUIRE(count >= 0, CSV_EINVAL, "negative count");
+        if (count == 0) return;
+        CSV_REQUIRE(srv && params && sids, CSV_EINVAL, "NULL argument");
+        Server& s = srv->impl;
+        std::vector<StreamInfo> sis;
+        for (int i = 0; i < count; ++i) sis.push_back(stream_info(s, &params[i]));
+        s.ex->prepare_many(sis);   // operator setup outside the server lock
+        std::lock_guard<std::mutex> lk(s.mu);
+        for (int i = 0; i < count; ++i) {
+            s.streams.push_back(sis[i]);
+            sids[i] = (uint32_t)(s.streams.size() - 1);
+        }
     });
 }
 

@@ -51,6 +51,17 @@ class Server:
         N.check(N.lib().csv_server_register_stream(self._h, C.byref(p.to_c()), C.byref(sid)))
         return sid.value
 
+    def register_streams(self, params) -> list[int]:
+        """Register several streams at once (their operators' power
+        iterations run side by side); returns their ids in order."""
+        count = len(params)
+        arr = (N.CsvParams * max(count, 1))()
+        for i, p in enumerate(params):
+            arr[i] = p.to_c()
+        sids = (C.c_uint32 * max(count, 1))()
+        N.check(N.lib().csv_server_register_streams(self._h, count, arr, sids))
+        return list(sids[:count])
+
     def submit(self, sid: int, gs, t_arrival: float = 0.0) -> int:
         """gs: a GopStream of device tensors (or, with the fake executor, any
         object whose to_c() gives non-null pointers).  Inputs must be ready:

@@ -319,3 +319,28 @@ def test_no_quant_closed_loop_cancels_key_error(ctx):
         assert np.array_equal(host(gs.codes), ref_stream.y_int.astype(np.int32))
         ref = codec.decode_gop(ref_stream, op)
         assert np.max(np.abs(fl - ref.cs_float)) <= 0.05
+
+
+def test_batched_operator_setup_equals_single():
+    """A batch decode that meets several new streams builds their operators
+    together (their power iterations side by side in one launch); every
+    step constant equals the one a fresh context computes for that stream
+    alone, bit for bit (the same iteration in the same order), and equals
+    the oracle's within 1e-9."""
+    import paper_1311_1419_amd as P
+    announce("batched operator setup vs single")
+    specs = [sv.qcif_tiny().with_(stream_id=60 + k, phi_seed=600 + k, m=[26, 64, 13, 100, 64][k],
+                                  gop=2, iters=20) for k in range(5)]
+    specs.append(sv.vga_precision(0.25, gop=2, stream=7).with_(iters=20))
+    params = [_gpu_params(s) for s in specs]
+    with P.Context(0) as c1:
+        items = [(c1.encode_gop(dev(s.video()), p), p) for s, p in zip(specs, params)]
+        c1.decode_batch(items)
+        batched = [c1.step_constant(p) for p in params]
+    with P.Context(0) as c2:
+        single = [c2.step_constant(p) for p in params]
+    assert batched == single
+    for s, (L, _) in zip(specs, batched):
+        q = philox.measurement_matrix_q(s.m, s.n, s.phi_seed, s.stream_id)
+        L_ref, _, _ = cs.lipschitz(q, philox.phi_scale(s.m))
+        assert L == pytest.approx(L_ref, rel=1e-9)

@@ -162,3 +162,32 @@ def test_register_stream_while_batches_run(ctx):
         # charged per request but held per preparation lane), so the device
         # bytes need not exceed it
         assert st["device_bytes"] > 0 and st["peak_bytes"] > 0
+
+
+def test_register_streams_batch(ctx):
+    """Several cameras registered in one call (their setup batched) get ids
+    in order and are served like single registrations; a batch with one
+    invalid stream registers none of them."""
+    import paper_1311_1419_amd as P
+    announce("server: batched registration")
+    specs = [sv.qcif_tiny().with_(stream_id=80 + k, phi_seed=8080 + k, m=[64, 26, 64, 40][k])
+             for k in range(4)]
+    items = []
+    for spec in specs:
+        p = _bf16(spec)
+        gs = ctx.encode_gop(dev(spec.video()), p)
+        items.append((p, gs, host(ctx.decode_gop(gs, p)[0])))
+    torch.cuda.synchronize()
+    with P.Server(0, hip_streams=2) as srv:
+        bad = [p for p, _, _ in items[:2]] + [items[0][0].with_(block=32, m=500)]
+        with pytest.raises(P.CsvError):
+            srv.register_streams(bad)
+        sids = srv.register_streams([p for p, _, _ in items])
+        assert sids == [0, 1, 2, 3]
+        tickets = [(i, srv.submit(sids[i], items[i][1], P.clock())) for i in range(4)]
+        srv.drain(60.0)
+        for i, t in tickets:
+            p = items[i][0]
+            buf = torch.empty((p.gop, p.height, p.width), dtype=torch.uint8, device="cuda")
+            assert srv.poll(t, buf)
+            assert np.array_equal(host(buf), items[i][2])
