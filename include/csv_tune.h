@@ -18,7 +18,10 @@ extern "C" {
 #endif
 
 /* Time every variant of the class of (block, m) on n_blocks synthetic
- * blocks with `iters` FISTA iterations (median of 3 launches each).
+ * blocks with `iters` FISTA iterations: after about 150 ms of launches of
+ * the current choice (so that no variant is timed on idle clocks), every
+ * variant is timed in two interleaved rounds, each the median of 3
+ * launches, and keeps its faster round.
  * ms_out (may be NULL) receives one time per variant (at most 8 entries);
  * *count the number of variants, *best the chosen index.  If json_path is
  * non-empty the choices of all classes are written there as JSON.

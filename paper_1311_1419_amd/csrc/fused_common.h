@@ -3,6 +3,7 @@
 // per-XCD tile queues and the forward product with its residual epilogue.
 #pragma once
 
+#include <type_traits>
 #include "internal.h"
 #include "mfma.h"
 
@@ -73,22 +74,43 @@ __device__ inline void forward_tiles(u16x8 (&af)[kPF][NF], u16x8 (&aa)[kPA][AR],
     };
 #pragma unroll
     for (int i = 0; i < NF; ++i) acc[i] = floatx16{};
-#pragma unroll 1
-    for (int ks0 = 0; ks0 < KSG - kPF; ks0 += kPF) {
+    if constexpr (KSG <= 16 && NL == 0 && std::is_same_v<PT, u16x8>) {
+        // short product on an LDS-resident operator (n = 256): fully
+        // unrolled, so the first step takes a zero accumulator operand and
+        // every fragment address is an immediate offset
 #pragma unroll
-        for (int j = 0; j < kPF; ++j) {
-            const int ks = ks0 + j;
-            const bf16x8 b = __builtin_bit_cast(bf16x8, Vb[(ks * CT + fct) * 64 + ln]);
+        for (int ks0 = 0; ks0 < KSG - kPF; ks0 += kPF) {
 #pragma unroll
-            for (int i = 0; i < NF; ++i) {
-                acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[j][i]),
-                                                                 b, acc[i], 0, 0, 0);
-                const int mt = (w + W * i) / CT;
-                af[j][i] = ffwd[((size_t)mt * KSF + ks + kPF) * 64 + ln];
+            for (int j = 0; j < kPF; ++j) {
+                const int ks = ks0 + j;
+                const bf16x8 b = __builtin_bit_cast(bf16x8, Vb[(ks * CT + fct) * 64 + ln]);
+#pragma unroll
+                for (int i = 0; i < NF; ++i) {
+                    acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, af[j][i]), b, acc[i], 0, 0, 0);
+                    const int mt = (w + W * i) / CT;
+                    af[j][i] = ffwd[((size_t)mt * KSF + ks + kPF) * 64 + ln];
+                }
             }
         }
-        if constexpr (ILV && NL > 0) {
-            if (ks0 / kPF < NL) lds_step(ks0 / kPF);
+    } else {
+#pragma unroll 1
+        for (int ks0 = 0; ks0 < KSG - kPF; ks0 += kPF) {
+#pragma unroll
+            for (int j = 0; j < kPF; ++j) {
+                const int ks = ks0 + j;
+                const bf16x8 b = __builtin_bit_cast(bf16x8, Vb[(ks * CT + fct) * 64 + ln]);
+#pragma unroll
+                for (int i = 0; i < NF; ++i) {
+                    acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        __builtin_bit_cast(bf16x8, af[j][i]), b, acc[i], 0, 0, 0);
+                    const int mt = (w + W * i) / CT;
+                    af[j][i] = ffwd[((size_t)mt * KSF + ks + kPF) * 64 + ln];
+                }
+            }
+            if constexpr (ILV && NL > 0) {
+                if (ks0 / kPF < NL) lds_step(ks0 / kPF);
+            }
         }
     }
 #pragma unroll

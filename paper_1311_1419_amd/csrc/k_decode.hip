@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const int8_t* __restrict__ q,
 // Deterministic sums of two values over the 1024 threads: wave shuffles,
 // then the 16 wave partials in order; every thread gets both totals.  Its
 // first barrier also orders every earlier LDS read before later writes.
-__device__ inline void block_sum2_1024(double& a, double& b, double (*red)[16]) {
+__device__ __forceinline__ void block_sum2_1024(double& a, double& b, double (*red)[16]) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_xor(a, off);
@@ -114,7 +114,7 @@ __device__ inline void block_sum2_1024(double& a, double& b, double (*red)[16]) 
 // partial sums meet by a fixed shuffle tree, and the group's first thread
 // keeps w_i.  With S = 1 a thread takes rows t, t + 1024, ... (up to 16).
 constexpr int kPowRows = 16;
-__device__ inline void power_iterate(const int* __restrict__ g, int M, int S, double s_phi,
+__device__ __forceinline__ void power_iterate(const int* __restrict__ g, int M, int S, double s_phi,
                                      double tol, int max_iter, double* __restrict__ lip,
                                      double* v, double (*red)[16]) {
     const int tid = threadIdx.x, grp = tid / S, sl = tid - grp * S, per_pass = 1024 / S;
@@ -162,6 +162,142 @@ __device__ inline void power_iterate(const int* __restrict__ g, int M, int S, do
     }
 }
 
+// x from lane l ^ m of the wave (m a power of two, at most 32, known at
+// compile time once the callers' loops are unrolled): ds_swizzle's bit mode
+// within each half-wave for m <= 16, ds_bpermute across the halves.
+__device__ __forceinline__ double xor_lane(double x, int m) {
+    const int lo = __double2loint(x), hi = __double2hiint(x);
+    int rl, rh;
+    switch (m) {
+#define CSV_SWZ(MM)                                                 \
+    case MM:                                                        \
+        rl = __builtin_amdgcn_ds_swizzle(lo, ((MM) << 10) | 0x1f);  \
+        rh = __builtin_amdgcn_ds_swizzle(hi, ((MM) << 10) | 0x1f);  \
+        break;
+        CSV_SWZ(1) CSV_SWZ(2) CSV_SWZ(4) CSV_SWZ(8) CSV_SWZ(16)
+#undef CSV_SWZ
+        default: {
+            const int a = (int)(((threadIdx.x & 63) ^ 32) << 2);
+            rl = __builtin_amdgcn_ds_bpermute(a, lo);
+            rh = __builtin_amdgcn_ds_bpermute(a, hi);
+        }
+    }
+    return __hiloint2double(rh, rl);
+}
+
+// The same power iteration for M <= 256 with G held in registers: the
+// 1024 threads form a 32 x 32 grid of TS x TS pieces of G (TS = 8, 4, 2, 1 as
+// M <= 256, 128, 64, 32; entries outside M x M are zero), so an iteration
+// reads no G from memory.  Thread (a, b) holds rows a TS .. a TS + TS - 1 and
+// columns b, b + 32, ... (conflict-free reads of v from LDS) and forms the
+// TS partial row sums over its columns; the 32 threads of a tile row (one half of a
+// wave) meet in a shuffle reduce-scatter that leaves each row's w_i on
+// 32 / TS lanes.  w (unnormalised) and the per-wave partial sums of v.w and
+// w.w go to LDS buffers that alternate between iterations, so one barrier
+// per iteration suffices; the next iteration reads v = w / ||w|| as w times
+// the reciprocal norm.
+template <int TS>
+__device__ __forceinline__ void power_iterate_reg(const int* __restrict__ g, int M, double s_phi,
+                                         double tol, int max_iter, double* __restrict__ lip,
+                                         double (*wb)[256], double (*red)[2][16]) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int b = lane & 31, a = 2 * wv + (lane >> 5);
+    // The row of w this lane ends with (a TS + rowoff) and whether it writes
+    // it (one lane per row).  Slot r of the lane's rows holds row
+    // a TS + (r ^ rowoff): in every halving step the rows a lane keeps are
+    // then its first slots and the rows it hands over its last, the same
+    // for every lane, so the exchange needs no per-lane selects.
+    int rowoff = 0;
+#pragma unroll
+    for (int m = 16, cnt = TS; cnt > 1; m >>= 1, cnt >>= 1) rowoff += (b & m) ? cnt / 2 : 0;
+    constexpr int kScatter = TS == 8 ? 3 : TS == 4 ? 2 : TS == 2 ? 1 : 0;
+    const int row = a * TS + rowoff;
+    const bool writer = (b & ((16 >> kScatter) * 2 - 1)) == 0;
+    int gr[TS][TS];
+#pragma unroll
+    for (int r = 0; r < TS; ++r)
+#pragma unroll
+        for (int c = 0; c < TS; ++c) {
+            const int i = a * TS + (r ^ rowoff), j = b + 32 * c;
+            gr[r][c] = (i < M && j < M) ? g[(size_t)i * M + j] : 0;
+        }
+    // both buffers: entries i >= M are never written by the iteration and
+    // must read as zero (a stale NaN times a zero G entry would not vanish)
+    if (tid < 256) {
+        wb[0][tid] = tid < M ? 1.0 / sqrt((double)M) : 0.0;
+        wb[1][tid] = 0.0;
+    }
+    __syncthreads();
+    double inv = 1.0, rq = 0.0, rq_prev = 0.0;
+    int cur = 0, it = 0;
+    for (it = 1; it <= max_iter; ++it) {
+        const int nxt = cur ^ 1;
+        // G stays as int32 in registers: without this the compiler hoists
+        // the 64 int -> FP64 conversions out of the loop and spills the
+        // 128 registers they take
+#pragma unroll
+        for (int r = 0; r < TS; ++r)
+#pragma unroll
+            for (int c = 0; c < TS; ++c) asm volatile("" : "+v"(gr[r][c]));
+        double p[TS];
+#pragma unroll
+        for (int r = 0; r < TS; ++r) p[r] = 0.0;
+#pragma unroll
+        for (int c = 0; c < TS; ++c) {
+            const double vc = wb[cur][b + 32 * c] * inv;
+#pragma unroll
+            for (int r = 0; r < TS; ++r) p[r] = fma((double)gr[r][c], vc, p[r]);
+        }
+        // reduce-scatter over the 32 lanes b: halve the rows kept per step
+#pragma unroll
+        for (int st = 0; st < 5; ++st) {
+            const int m = 16 >> st, cnt = TS >> st;   // rows held before this step
+            if (cnt > 1) {
+                const int half = cnt / 2;
+#pragma unroll
+                for (int k = 0; k < half; ++k) p[k] += xor_lane(p[k + half], m);
+            } else {
+                p[0] += xor_lane(p[0], m);
+            }
+        }
+        double pv = 0.0, pw = 0.0;
+        if (writer && row < M) {
+            const double w = p[0];
+            pv = (wb[cur][row] * inv) * w;
+            pw = w * w;
+            wb[nxt][row] = w;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            pv += xor_lane(pv, off);
+            pw += xor_lane(pw, off);
+        }
+        if (lane == 0) {
+            red[nxt][0][wv] = pv;
+            red[nxt][1][wv] = pw;
+        }
+        __syncthreads();
+        double tv = 0.0, tw = 0.0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {
+            tv += red[nxt][0][w];
+            tw += red[nxt][1][w];
+        }
+        rq = tv;
+        if (it > 1 && fabs(rq - rq_prev) <= tol * rq) break;
+        rq_prev = rq;
+        const double nw = sqrt(tw);
+        if (nw == 0.0) break;
+        inv = 1.0 / nw;
+        cur = nxt;
+    }
+    if (tid == 0) {
+        lip[0] = 1.001 * s_phi * s_phi * rq;
+        lip[1] = rq;
+        lip[2] = (double)(it > max_iter ? max_iter : it);
+    }
+}
+
 __global__ __launch_bounds__(1024) void power_kernel(const int* __restrict__ g, int M, int S,
                                                     double s_phi, double tol, int max_iter,
                                                     double* __restrict__ lip) {
@@ -170,14 +306,35 @@ __global__ __launch_bounds__(1024) void power_kernel(const int* __restrict__ g, 
     power_iterate(g, M, S, s_phi, tol, max_iter, lip, v, red);
 }
 
-// The power iterations of several streams side by side, one workgroup each
-// (the same iteration as power_kernel, job blockIdx.x).
-__global__ __launch_bounds__(1024) void power_batch_kernel(PowBatch bt, double tol, int max_iter) {
-    extern __shared__ double v[];   // the largest M of the batch
-    __shared__ double red[2][16];
-    const PowJob& j = bt.j[blockIdx.x];
-    power_iterate(j.gram, j.M, j.S, j.s_phi, tol, max_iter, j.lip, v, red);
+template <int TS>
+__global__ __launch_bounds__(1024) void power_reg_kernel(const int* __restrict__ g, int M,
+                                                        double s_phi, double tol, int max_iter,
+                                                        double* __restrict__ lip) {
+    __shared__ double wb[2][256];
+    __shared__ double red[2][2][16];
+    power_iterate_reg<TS>(g, M, s_phi, tol, max_iter, lip, wb, red);
 }
+
+// The power iterations of several streams side by side, one workgroup each
+// (job blockIdx.x; the same iteration as the single-stream kernels, so a
+// stream's step constant does not depend on its batch).  TS > 0: every job
+// of the launch has M <= 32 TS (the register form); TS = 0: G from memory.
+template <int TS>
+__global__ __launch_bounds__(1024) void power_batch_kernel(PowBatch bt, double tol, int max_iter) {
+    const PowJob& j = bt.j[blockIdx.x];
+    if constexpr (TS > 0) {
+        __shared__ double wb[2][256];
+        __shared__ double red[2][2][16];
+        power_iterate_reg<TS>(j.gram, j.M, j.s_phi, tol, max_iter, j.lip, wb, red);
+    } else {
+        extern __shared__ double v[];   // the largest M of the batch
+        __shared__ double red[2][16];
+        power_iterate(j.gram, j.M, j.S, j.s_phi, tol, max_iter, j.lip, v, red);
+    }
+}
+
+// Register-form tile size for M (0: M above 256, G from memory)
+static int power_tile(int M) { return M <= 32 ? 1 : M <= 64 ? 2 : M <= 128 ? 4 : M <= 256 ? 8 : 0; }
 
 void launch_operator_setup(Operator* op, hipStream_t st) {
     const int B = op->B, n = op->n;
@@ -205,20 +362,43 @@ void launch_gram(Operator* op, int* gram, hipStream_t st) {
     CSV_HIP(hipGetLastError());
 }
 
+// Batched launches reserve more LDS than the register form uses (96 KiB),
+// so that no two of their workgroups share a CU: a small-M workgroup leaves
+// room in the register file for a second one, which would halve the VALU
+// rate of both.
+template <int TS>
+static void power_batch_launch(const PowBatch& bt, int k, int mmax, hipStream_t st) {
+    const size_t lds = TS > 0 ? (size_t)96 << 10 : (size_t)mmax * sizeof(double);
+    ensure_lds_limit<&power_batch_kernel<TS>>((size_t)1024 * kPowRows * sizeof(double));
+    power_batch_kernel<TS><<<dim3(k), dim3(1024), lds, st>>>(bt, 1e-12, 10000);
+    CSV_HIP(hipGetLastError());
+}
+
 void launch_power_batch(Operator* const* ops, int* const* grams, int count, hipStream_t st) {
-    ensure_lds_limit<&power_batch_kernel>((size_t)1024 * kPowRows * sizeof(double));
-    for (int a = 0; a < count; a += kPowBatch) {
-        PowBatch bt{};
-        int mmax = 0;
-        const int k = std::min(kPowBatch, count - a);
-        for (int i = 0; i < k; ++i) {
-            Operator* op = ops[a + i];
-            bt.j[i] = PowJob{grams[a + i], op->M, power_threads_per_row(op->M), op->s_phi, op->lip};
-            mmax = std::max(mmax, op->M);
+    // one launch per register-form tile size present (and one for M > 256),
+    // up to kPowBatch jobs each
+    for (const int ts : {8, 4, 2, 1, 0}) {
+        std::vector<int> idx;
+        for (int i = 0; i < count; ++i)
+            if (power_tile(ops[i]->M) == ts) idx.push_back(i);
+        for (size_t a = 0; a < idx.size(); a += kPowBatch) {
+            PowBatch bt{};
+            int mmax = 0;
+            const int k = (int)std::min<size_t>(kPowBatch, idx.size() - a);
+            for (int i = 0; i < k; ++i) {
+                Operator* op = ops[idx[a + i]];
+                bt.j[i] = PowJob{grams[idx[a + i]], op->M, power_threads_per_row(op->M), op->s_phi,
+                                 op->lip};
+                mmax = std::max(mmax, op->M);
+            }
+            switch (ts) {
+                case 8: power_batch_launch<8>(bt, k, mmax, st); break;
+                case 4: power_batch_launch<4>(bt, k, mmax, st); break;
+                case 2: power_batch_launch<2>(bt, k, mmax, st); break;
+                case 1: power_batch_launch<1>(bt, k, mmax, st); break;
+                default: power_batch_launch<0>(bt, k, mmax, st); break;
+            }
         }
-        power_batch_kernel<<<dim3(k), dim3(1024), (size_t)mmax * sizeof(double), st>>>(bt, 1e-12,
-                                                                                     10000);
-        CSV_HIP(hipGetLastError());
     }
 }
 
@@ -230,13 +410,19 @@ void launch_power_iteration(Operator* op, int* gram, hipStream_t st) {
     gram_kernel<<<dim3(ceil_div(M, 16), ceil_div(M, 16)), dim3(256), 0, st>>>(op->q, M, op->n,
                                                                              gram);
     CSV_HIP(hipGetLastError());
-    // v in LDS, beyond the 64 KB default
-    ensure_lds_limit<&power_kernel>((size_t)1024 * kPowRows * sizeof(double));
-    int S = 1;   // threads per row: 1024 / M rounded down to a power of two, <= 64
-    while (S < 64 && 2 * S * M <= 1024) S *= 2;
-    const size_t lds = (size_t)M * sizeof(double);
-    power_kernel<<<dim3(1), dim3(1024), lds, st>>>(gram, M, S, op->s_phi, 1e-12, 10000,
-                                                   op->lip);
+    switch (power_tile(M)) {
+        case 8: power_reg_kernel<8><<<1, 1024, 0, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip); break;
+        case 4: power_reg_kernel<4><<<1, 1024, 0, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip); break;
+        case 2: power_reg_kernel<2><<<1, 1024, 0, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip); break;
+        case 1: power_reg_kernel<1><<<1, 1024, 0, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip); break;
+        default: {
+            // v in LDS, beyond the 64 KB default
+            ensure_lds_limit<&power_kernel>((size_t)1024 * kPowRows * sizeof(double));
+            const size_t lds = (size_t)M * sizeof(double);
+            power_kernel<<<dim3(1), dim3(1024), lds, st>>>(gram, M, power_threads_per_row(M),
+                                                           op->s_phi, 1e-12, 10000, op->lip);
+        }
+    }
     CSV_HIP(hipGetLastError());
 }
 

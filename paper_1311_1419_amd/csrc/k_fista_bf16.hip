@@ -100,6 +100,8 @@ void fista_bf16_kernel(
     constexpr int KSF = N / 16, KSA = MP / 16;   // K steps of forward / adjoint
     constexpr bool YREG = (OPT & 1) != 0;        // else y^ is read from L2 in every epilogue
     constexpr bool OPL = (OPT & 2) != 0;         // operator resident in LDS
+    constexpr bool PP = YREG && OPL;             // ping-pong state (register-light classes)
+    static_assert(!PP || SPL == 0, "ping-pong state keeps every tile in registers");
     static_assert(!(OPL && NLS != 0), "the LDS slice is part of an LDS-resident operator");
     constexpr int OFW = (MP / 32) * KSF * 64;   // u16x8 of the forward layout (OPL)
     constexpr int OFA = (N / 32) * KSA * 64;    // u16x8 of the adjoint layout (OPL)
@@ -192,13 +194,15 @@ void fista_bf16_kernel(
                 }
             }
         }
-        floatx16 sp[SPR > 0 ? SPR : 1], vv[RT][CT];
+        // PP: vv and pp swap roles every iteration (see the threshold below)
+        floatx16 sp[(SPR > 0 && !PP) ? SPR : 1], vv[RT][CT], pp[RT][CT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) {
                 const int u = rt * CT + ct;
-                if (u < SPR) sp[u] = floatx16{};
+                if (!PP && u < SPR) sp[u] = floatx16{};
+                if constexpr (PP) pp[rt][ct] = floatx16{};
                 vv[rt][ct] = floatx16{};
                 const int g = w * RT + rt;
                 const u16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -215,7 +219,17 @@ void fista_bf16_kernel(
         if (nft == FT) load_fwd_head<N, MP, CT, FT, W, kPF>(af, ffwd, w, ln);
         __syncthreads();
 
-        for (int k = 0; k < T; ++k) {
+        // Iterations in pairs (PP) or one at a time.  X: the accumulators, v
+        // on entry; Y (PP only): p = -beta_k s_{k-1} on entry.  PP leaves v in
+        // Y and the next p in X, so the arrays trade roles every iteration.
+        constexpr int NP = PP ? 2 : 1;
+        for (int k0 = 0; k0 < T; k0 += NP) {
+#pragma unroll
+          for (int par = 0; par < NP; ++par) {
+            const int k = k0 + par;
+            if (NP == 2 && k >= T) break;
+            floatx16 (&X)[RT][CT] = par ? pp : vv;
+            floatx16 (&Y)[RT][CT] = par ? vv : pp;
             // ---- forward: P = A V, R = P - y  (nft tiles for this wave)
             if (nft == FT) {
                 floatx16 acc[FT];
@@ -258,14 +272,17 @@ void fista_bf16_kernel(
             //      to LDS
             const float bk = beta[k];
             const float bk1 = 1.f + bk, nbk = -bk;
+            // PP: p for the next iteration, -beta_{k+1} s_k; after the last
+            // iteration X holds s_T itself
+            const float nbn = PP ? (k + 1 < T ? -beta[k + 1] : 1.f) : 0.f;
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
                         const int rt0 = (2 * g) / CT, ct0 = (2 * g) % CT;
                 const int rt1 = (2 * g + 1) / CT, ct1 = (2 * g + 1) % CT;
                 // accumulated in place on v: with R' = (y - A v) / L the
                 // product ends at u = v - A^T (A v - y) / L
-                floatx16& ga0 = vv[rt0][ct0];
-                floatx16& ga1 = vv[rt1][ct1];
+                floatx16& ga0 = X[rt0][ct0];
+                floatx16& ga1 = X[rt1][ct1];
 #pragma unroll 1
                 for (int ks0 = 0; ks0 < KSA - kPA; ks0 += kPA) {
 #pragma unroll
@@ -309,52 +326,68 @@ void fista_bf16_kernel(
                     const int ut = 2 * g + e;
                     const int gg = w * RT + rt;
                     const float tc = tau[ct];
-                    floatx16 spv;
-                    if (ut < SPR) {
-                        spv = sp[ut < SPR ? ut : 0];
-                    } else {
+                    if constexpr (PP) {
+                        // s_k = u - med3(u, -tau, tau); v = (1 + beta_k) s_k + p, where
+                        // p = -beta_k s_{k-1} was formed by the previous iteration
+                        // (the same two roundings as forming it here).  The two
+                        // state arrays trade roles each iteration, so the four
+                        // VALU operations write in place with no register moves
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const float4 t4 = Sl[((w * SPL + ut - SPR) * 4 + q) * 64 + ln];
-                            spv[4 * q] = t4.x;
-                            spv[4 * q + 1] = t4.y;
-                            spv[4 * q + 2] = t4.z;
-                            spv[4 * q + 3] = t4.w;
-                        }
-                    }
-                    // s_k = u - med3(u, -tau, tau); v = s_k + beta_k (s_k - s_{k-1}).
-                    // The register-light classes (y^ in registers) take v as
-                    // (1 + beta_k) s_k - beta_k s_{k-1}, four VALU operations in
-                    // place on u and s with no register moves; the n = 1024
-                    // classes keep the form whose temporaries do not spill
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const float u = vv[rt][ct][r];
-                        if constexpr (YREG) {
-                            const float m = nbk * spv[r];
-                            spv[r] = u - __builtin_amdgcn_fmed3f(u, -tc, tc);
-                            vv[rt][ct][r] = fmaf(bk1, spv[r], m);
-                        } else {
+                        for (int r = 0; r < 16; ++r) {
+                            const float u = X[rt][ct][r];
                             const float sn = u - __builtin_amdgcn_fmed3f(u, -tc, tc);
-                            vv[rt][ct][r] = fmaf(bk, sn - spv[r], sn);
-                            spv[r] = sn;
+                            Y[rt][ct][r] = fmaf(bk1, sn, Y[rt][ct][r]);
+                            X[rt][ct][r] = nbn * sn;
+                        }
+                    } else {
+                        floatx16 spv;
+                        if (ut < SPR) {
+                            spv = sp[ut < SPR ? ut : 0];
+                        } else {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const float4 t4 = Sl[((w * SPL + ut - SPR) * 4 + q) * 64 + ln];
+                                spv[4 * q] = t4.x;
+                                spv[4 * q + 1] = t4.y;
+                                spv[4 * q + 2] = t4.z;
+                                spv[4 * q + 3] = t4.w;
+                            }
+                        }
+                        // s_k = u - med3(u, -tau, tau); v = s_k + beta_k (s_k - s_{k-1}).
+                        // With y^ in registers v is taken as (1 + beta_k) s_k -
+                        // beta_k s_{k-1} (four VALU operations); the n = 1024
+                        // classes keep the form whose temporaries do not spill
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const float u = X[rt][ct][r];
+                            if constexpr (YREG) {
+                                const float m = nbk * spv[r];
+                                spv[r] = u - __builtin_amdgcn_fmed3f(u, -tc, tc);
+                                X[rt][ct][r] = fmaf(bk1, spv[r], m);
+                            } else {
+                                const float sn = u - __builtin_amdgcn_fmed3f(u, -tc, tc);
+                                X[rt][ct][r] = fmaf(bk, sn - spv[r], sn);
+                                spv[r] = sn;
+                            }
+                        }
+                        if (ut < SPR) {
+                            sp[ut < SPR ? ut : 0] = spv;
+                        } else {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                Sl[((w * SPL + ut - SPR) * 4 + q) * 64 + ln] =
+                                    make_float4(spv[4 * q], spv[4 * q + 1], spv[4 * q + 2], spv[4 * q + 3]);
                         }
                     }
-                    if (ut < SPR) {
-                        sp[ut < SPR ? ut : 0] = spv;
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            Sl[((w * SPL + ut - SPR) * 4 + q) * 64 + ln] =
-                                make_float4(spv[4 * q], spv[4 * q + 1], spv[4 * q + 2], spv[4 * q + 3]);
-                    }
-                    Vb[((2 * gg) * CT + ct) * 64 + ln] = pack_bf16(vv[rt][ct], 0);
-                    Vb[((2 * gg + 1) * CT + ct) * 64 + ln] = pack_bf16(vv[rt][ct], 1);
+                    const floatx16& vn = PP ? Y[rt][ct] : X[rt][ct];
+                    Vb[((2 * gg) * CT + ct) * 64 + ln] = pack_bf16(vn, 0);
+                    Vb[((2 * gg + 1) * CT + ct) * 64 + ln] = pack_bf16(vn, 1);
                 }
             }
             __syncthreads();
+          }
         }
-        // ---- write s_T
+        // ---- write s_T (PP: in vv after an odd number of iterations, else in pp)
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -362,7 +395,9 @@ void fista_bf16_kernel(
                 const int b = ct * 32 + col;
                 const int ut = rt * CT + ct;
                 floatx16 a;
-                if (ut < SPR) {
+                if constexpr (PP) {
+                    a = (T & 1) ? vv[rt][ct] : pp[rt][ct];
+                } else if (ut < SPR) {
                     a = sp[ut < SPR ? ut : 0];
                 } else {
 #pragma unroll
@@ -437,22 +472,22 @@ struct ClassEntry {
 static std::vector<ClassEntry>& class_table() {
     static std::vector<ClassEntry> t = {
         {256, 32,
-         {CSV_VOL(256, 32, 1, 4, 4, 2, 3), CSV_VY(256, 32, 2, 4, 4, 2, 0, 2),
-          CSV_V(256, 32, 1, 4, 4, 2, 0, 3), CSV_VY(256, 32, 1, 4, 4, 2, 0, 3),
-          CSV_VOL(256, 32, 2, 4, 4, 2, 2), CSV_VOL(256, 32, 4, 8, 4, 2, 1),
-          CSV_V(256, 32, 2, 4, 4, 2, 0, 2), CSV_V(256, 32, 4, 8, 4, 2, 0, 1)},
+         {CSV_VOL(256, 32, 2, 4, 4, 2, 2), CSV_VOL(256, 32, 2, 4, 8, 2, 2),
+          CSV_VOL(256, 32, 1, 4, 4, 2, 3), CSV_VOL(256, 32, 4, 8, 4, 2, 1),
+          CSV_VOL(256, 32, 4, 8, 8, 2, 1), CSV_VY(256, 32, 2, 4, 4, 2, 0, 2),
+          CSV_VY(256, 32, 1, 4, 4, 2, 0, 3), CSV_V(256, 32, 1, 4, 4, 2, 0, 3)},
          0},
         {256, 64,
-         {CSV_VOL(256, 64, 4, 8, 4, 2, 1), CSV_VY(256, 64, 2, 4, 4, 2, 0, 2),
-          CSV_V(256, 64, 2, 4, 4, 2, 0, 2), CSV_VY(256, 64, 1, 4, 8, 4, 0, 2),
-          CSV_VY(256, 64, 2, 8, 8, 4, 0, 1), CSV_VOL(256, 64, 2, 4, 4, 2, 1),
-          CSV_VOL(256, 64, 2, 8, 4, 2, 1), CSV_VY(256, 64, 1, 4, 4, 2, 0, 3)},
+         {CSV_VOL(256, 64, 4, 8, 4, 2, 1), CSV_VOL(256, 64, 4, 8, 8, 2, 1),
+          CSV_VOL(256, 64, 4, 8, 8, 4, 1), CSV_VOL(256, 64, 2, 8, 8, 2, 1),
+          CSV_VOL(256, 64, 2, 8, 16, 2, 1), CSV_VY(256, 64, 2, 4, 4, 2, 0, 2),
+          CSV_V(256, 64, 2, 4, 4, 2, 0, 2)},
          0},
         {256, 96,
-         {CSV_VOL(256, 96, 2, 8, 2, 2, 1), CSV_VY(256, 96, 2, 4, 2, 2, 0, 2),
-          CSV_V(256, 96, 1, 4, 2, 2, 0, 3), CSV_V(256, 96, 2, 4, 2, 2, 0, 2),
-          CSV_VOL(256, 96, 1, 4, 2, 2, 1), CSV_VY(256, 96, 1, 4, 2, 2, 0, 3),
-          CSV_V(256, 96, 4, 8, 4, 2, 0, 1), CSV_V(256, 96, 2, 8, 4, 2, 0, 1)},
+         {CSV_VOL(256, 96, 2, 8, 4, 3, 1), CSV_VOL(256, 96, 2, 8, 8, 3, 1),
+          CSV_VOL(256, 96, 2, 8, 8, 2, 1), CSV_VOL(256, 96, 2, 8, 4, 2, 1),
+          CSV_VOL(256, 96, 2, 8, 16, 3, 1), CSV_VY(256, 96, 2, 4, 2, 2, 0, 2),
+          CSV_VY(256, 96, 1, 4, 2, 2, 0, 3), CSV_V(256, 96, 1, 4, 2, 2, 0, 3)},
          0},
         {256, 128,
          {CSV_VY(256, 128, 2, 4, 2, 2, 0, 2), CSV_V(256, 128, 1, 4, 2, 2, 0, 3),

@@ -21,7 +21,8 @@ def _gpu_params(spec, **kw):
     return P.Params.from_spec(spec, precision=P.CSV_FP32, **kw)
 
 
-@pytest.mark.parametrize("m,b", [(64, 16), (13, 16), (128, 16), (256, 32), (410, 32), (1024, 32)])
+@pytest.mark.parametrize("m,b", [(64, 16), (13, 16), (51, 16), (128, 16), (200, 16), (256, 32),
+                                 (410, 32), (1024, 32)])
 def test_step_constant_and_operator(ctx, m, b):
     import paper_1311_1419_amd as P
     announce(f"operator/L m={m} B={b}")
@@ -332,10 +333,14 @@ def test_batched_operator_setup_equals_single():
     specs = [sv.qcif_tiny().with_(stream_id=60 + k, phi_seed=600 + k, m=[26, 64, 13, 100, 64][k],
                                   gop=2, iters=20) for k in range(5)]
     specs.append(sv.vga_precision(0.25, gop=2, stream=7).with_(iters=20))
+    specs.append(sv.vga_precision(0.3, gop=2, stream=8).with_(iters=20))   # M > 256: G from memory
     params = [_gpu_params(s) for s in specs]
+    assert specs[-1].m > 256
     with P.Context(0) as c1:
-        items = [(c1.encode_gop(dev(s.video()), p), p) for s, p in zip(specs, params)]
-        c1.decode_batch(items)
+        # one batch encode meets all the new streams at once: their operators
+        # are built together (one power-iteration launch per register-form size)
+        streams = c1.encode_batch([(dev(s.video()), p) for s, p in zip(specs, params)])
+        c1.decode_batch(list(zip(streams, params)))
         batched = [c1.step_constant(p) for p in params]
     with P.Context(0) as c2:
         single = [c2.step_constant(p) for p in params]
