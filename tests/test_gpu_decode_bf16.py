@@ -38,6 +38,12 @@ CASES = [
     (sv.cif_sweep(4, 0.25).with_(block=32, m=12, iters=300), "cif-b32-m12"),
     (sv.cif_sweep(8, 0.2), "cif-g8-b16-m51"),
     (sv.cif_sweep(16, 0.2), "cif-g16-b16-m51"),
+    # odd and minimal iteration counts: the n = 256 kernels keep s and v in two
+    # arrays that trade roles every iteration, so s_T sits in either
+    (sv.qcif_tiny().with_(iters=77), "qcif-b16-m64-t77"),
+    (sv.cif_sweep(4, 0.1).with_(iters=1), "cif-b16-m26-t1"),
+    (sv.cif_sweep(4, 0.3).with_(iters=3), "cif-b16-m77-t3"),
+    (sv.cif_sweep(4, 0.5).with_(iters=2), "cif-b16-m128-t2"),
 ]
 
 
