@@ -362,14 +362,10 @@ void launch_gram(Operator* op, int* gram, hipStream_t st) {
     CSV_HIP(hipGetLastError());
 }
 
-// Batched launches reserve more LDS than the register form uses (96 KiB),
-// so that no two of their workgroups share a CU: a small-M workgroup leaves
-// room in the register file for a second one, which would halve the VALU
-// rate of both.
 template <int TS>
 static void power_batch_launch(const PowBatch& bt, int k, int mmax, hipStream_t st) {
-    const size_t lds = TS > 0 ? (size_t)96 << 10 : (size_t)mmax * sizeof(double);
-    ensure_lds_limit<&power_batch_kernel<TS>>((size_t)1024 * kPowRows * sizeof(double));
+    const size_t lds = TS > 0 ? 0 : (size_t)mmax * sizeof(double);
+    if (TS == 0) ensure_lds_limit<&power_batch_kernel<0>>((size_t)1024 * kPowRows * sizeof(double));
     power_batch_kernel<TS><<<dim3(k), dim3(1024), lds, st>>>(bt, 1e-12, 10000);
     CSV_HIP(hipGetLastError());
 }
