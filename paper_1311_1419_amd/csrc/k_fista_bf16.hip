@@ -518,7 +518,7 @@ static std::vector<ClassEntry>& class_table() {
           FusedVariant{"q8_w8_pf2x2_pa2x2", 1, 1, &launch_fista_q8_m256}},
          0},
         {1024, 416,
-         {CSV_V(1024, 416, 1, 8, 2, 2, 0, 1), CSV_V(1024, 416, 1, 8, 2, 2, 2, 1),
+         {CSV_V(1024, 416, 1, 8, 2, 2, 2, 1), CSV_V(1024, 416, 1, 8, 2, 2, 0, 1),
           CSV_V(1024, 416, 1, 8, 4, 2, 2, 1)},
          0},
     };
