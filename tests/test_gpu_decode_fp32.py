@@ -34,6 +34,9 @@ def test_step_constant_and_operator(ctx, m, b):
     s_phi = philox.phi_scale(m)
     L_ref, _, it_ref = cs.lipschitz(q, s_phi)
     assert L == pytest.approx(L_ref, rel=1e-9)
+    # the same iteration, summed in another order: the stopping test may flip
+    # by a step where the relative change sits at the tolerance
+    assert abs(it - it_ref) <= 2
     a = host(ctx.operator_matrix(p))
     assert np.max(np.abs(a - cs.operator(q, s_phi, b))) < 1e-12
 
