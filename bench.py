@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--psnr-floor", type=float, default=32.0,
                     help="configure mode: PSNR floor standing in for the tracking requirement")
     ap.add_argument("--serve-window", type=float, default=2.0, help="seconds per sweep point")
+    ap.add_argument("--serve-streams", type=int, default=2,
+                    help="HIP streams the server spreads consecutive batches over (1-4)")
     ap.add_argument("--serve-loads", type=str, default="0.01,0.02,0.04,0.08,0.16,0.24,0.32",
                     help="fractions of the cameras' nominal GOP rates")
     return ap.parse_args()
@@ -262,7 +264,7 @@ def mixed_main(args):
     }), flush=True)
 
 
-def serve_sweep(loads, window, on_point=None):
+def serve_sweep(loads, window, on_point=None, hip_streams=2):
     """256 synthetic cameras (640x480 and 1280x720, B=16, M/n 0.1 or 0.25,
     GOP 8/16/32) served by the continuous-batching server under open-loop
     Poisson GOP arrivals at each fraction `load` of the cameras' nominal
@@ -291,7 +293,7 @@ def serve_sweep(loads, window, on_point=None):
         torch.cuda.synchronize()
         rng = np.random.default_rng(7)
         for load in loads:
-            with P.Server(0, mem_budget=48 << 30, hip_streams=2) as srv:
+            with P.Server(0, mem_budget=48 << 30, hip_streams=hip_streams) as srv:
                 sids = srv.register_streams([p for p, _, _ in enc])
                 warm = [srv.submit(sids[i], enc[i][1]) for i in range(6)]
                 srv.drain(120.0)
@@ -346,7 +348,8 @@ def serve_main(args):
     throughput per offered load, the highest stable load."""
     loads = [float(x) for x in args.serve_loads.split(",")]
     sweep = serve_sweep(loads, args.serve_window,
-                        lambda pt: print(json.dumps({"sweep_point": pt}), flush=True))
+                        lambda pt: print(json.dumps({"sweep_point": pt}), flush=True),
+                        hip_streams=args.serve_streams)
     best = max(sweep, key=lambda r: r["served_mpix_s"])
     # stable: the server keeps up with the offered load (served within 5% of
     # offered); the highest such point is the load the server sustains
