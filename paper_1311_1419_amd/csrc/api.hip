@@ -220,7 +220,7 @@ static Operator* build_operator_locked(Ctx* c, const Shape& s, hipStream_t st,
         try {
             launch_phi_q(op->q, s.M, s.Mp, s.n, s.seed, (uint64_t)s.sid, st);
             launch_transpose_q(op->q, s.Mp, s.n, op->qt, st);
-            int* gram = static_cast<int*>(scratch(c, "gram", (size_t)s.M * s.M * 4));
+            int* gram = static_cast<int*>(scratch(c, "gram", (size_t)s.M * gram_ld(s.M) * 4));
             launch_power_iteration(op.get(), gram, st);
         } catch (...) {
             free_operator(c, op.get());
@@ -267,7 +267,7 @@ static Operator* build_operator_locked(Ctx* c, const Shape& s, hipStream_t st,
         if (gram_dst) {
             launch_gram(op.get(), gram_dst, st);
         } else {
-            int* gram = static_cast<int*>(scratch(c, "gram", (size_t)s.M * s.M * 4));
+            int* gram = static_cast<int*>(scratch(c, "gram", (size_t)s.M * gram_ld(s.M) * 4));
             launch_power_iteration(op.get(), gram, st);
         }
     } catch (...) {
@@ -307,7 +307,7 @@ void prepare_operators(Ctx* c, const Shape* shapes, int count, hipStream_t st) {
     }
     std::vector<size_t> off(todo.size() + 1, 0);
     for (size_t i = 0; i < todo.size(); ++i)
-        off[i + 1] = off[i] + ((size_t)todo[i]->M * todo[i]->M + 63) / 64 * 64;
+        off[i + 1] = off[i] + ((size_t)todo[i]->M * gram_ld(todo[i]->M) + 63) / 64 * 64;
     int* grams = static_cast<int*>(scratch(c, "gram_batch", off.back() * 4));
     std::vector<Operator*> ops;
     std::vector<int*> gp;

@@ -57,9 +57,11 @@ __global__ __launch_bounds__(256) void operator_kernel(const int8_t* __restrict_
 }
 
 // Integer Gram matrix G = Q Q^T (M x M), exact in 32-bit integers
-// (|G_ij| <= 32*32*n < 2^31, checked by the launcher).
+// (|G_ij| <= 32*32*n < 2^31, checked by the launcher), rows of ld >= M
+// entries; the columns M <= j < ld come out zero (Q's rows beyond M read
+// as zero).
 __global__ __launch_bounds__(256) void gram_kernel(const int8_t* __restrict__ q, int M, int n,
-                                                  int* __restrict__ g) {
+                                                  int ld, int* __restrict__ g) {
     __shared__ int Qa[16][65];
     __shared__ int Qb[16][65];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const int8_t* __restrict__ q,
         for (int c = 0; c < 64; ++c) acc += Qa[ty][c] * Qb[tx][c];
         __syncthreads();
     }
-    if (i < M && j < M) g[(size_t)i * M + j] = acc;
+    if (i < M && j < ld) g[(size_t)i * ld + j] = acc;
 }
 
 // Deterministic sums of two values over the 1024 threads: wave shuffles,
@@ -107,38 +109,79 @@ __device__ __forceinline__ void block_sum2_1024(double& a, double& b, double (*r
 
 // Power iteration on G (FP64): v0 = 1/sqrt(M); w = G v; Rayleigh quotient
 // rq = v.w; stop once |rq - rq_prev| <= tol rq (from the second step), else
-// v = w / ||w||.  One workgroup of 1024 threads, v in LDS (M <= 16384).  S
-// adjacent threads share a row (S = 1024 / M rounded down to a power of
-// two, at most 64): thread s of the group sums j = s, s + S, ... of
-// G[j][i] v[j] (G symmetric: consecutive groups read consecutive i), the S
-// partial sums meet by a fixed shuffle tree, and the group's first thread
-// keeps w_i.  With S = 1 a thread takes rows t, t + 1024, ... (up to 16).
-constexpr int kPowRows = 16;
+// v = w / ||w||.  One workgroup of 1024 threads, v in LDS (M <= 16384), G
+// read from memory in every step.  G is symmetric, so column i of G gives
+// w_i, and the columns are read as 16-byte quads (rows padded to
+// ld = gram_ld(M), zero beyond M): S adjacent threads share a quad (S =
+// 1024 / (ld / 4) rounded down to a power of two, at most 64), thread s of
+// the group sums rows j = s, s + S, ... with kPowUnroll quad loads in
+// flight, the S partial sums meet by a fixed shuffle tree, and the group's
+// first thread keeps the quad's four entries of w.  With S = 1 a thread
+// takes quads t, t + 1024, ... (KQ of them at most).
+constexpr int kPowMaxM = 16384;
+template <int KQ>
 __device__ __forceinline__ void power_iterate(const int* __restrict__ g, int M, int S, double s_phi,
-                                     double tol, int max_iter, double* __restrict__ lip,
-                                     double* v, double (*red)[16]) {
+                                              double tol, int max_iter, double* __restrict__ lip,
+                                              double* v, double (*red)[16]) {
+    constexpr int kPowUnroll = 8;   // quad loads in flight per thread
+    const int ld = (M + 3) & ~3, nq = ld >> 2;
     const int tid = threadIdx.x, grp = tid / S, sl = tid - grp * S, per_pass = 1024 / S;
-    for (int i = tid; i < M; i += 1024) v[i] = 1.0 / sqrt((double)M);
+    const int4* __restrict__ g4 = reinterpret_cast<const int4*>(g);
+    for (int i = tid; i < ld; i += 1024) v[i] = i < M ? 1.0 / sqrt((double)M) : 0.0;
     __syncthreads();
     double rq = 0.0, rq_prev = 0.0;
     int it = 0;
     for (it = 1; it <= max_iter; ++it) {
-        double w[kPowRows];
+        double w[KQ][4];
         double pv = 0.0, pw = 0.0;
 #pragma unroll
-        for (int k = 0; k < kPowRows; ++k) {
-            if (per_pass * k >= M) break;   // uniform
-            const int i = grp + per_pass * k;
-            double acc = 0.0;
-            if (i < M) {
-#pragma unroll 16
-                for (int j = sl; j < M; j += S) acc = fma((double)g[(size_t)j * M + i], v[j], acc);
+        for (int k = 0; k < KQ; ++k) {
+            if (per_pass * k >= nq) break;   // uniform
+            const int q = grp + per_pass * k;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            if (q < nq) {
+                for (int j0 = sl; j0 < M; j0 += S * kPowUnroll) {
+                    int4 e[kPowUnroll];
+                    double vj[kPowUnroll];
+                    // every load in bounds and unconditional (rows past M
+                    // re-read row M - 1 and their terms get a zero factor),
+                    // so all kPowUnroll are in flight before the first FMA
+#pragma unroll
+                    for (int u = 0; u < kPowUnroll; ++u) {
+                        const int j = j0 + S * u;
+                        const int jc = j < M ? j : M - 1;
+                        e[u] = g4[(unsigned)(jc * nq + q)];   // < 2^26
+                        const double vc = v[jc];
+                        vj[u] = j < M ? vc : 0.0;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the FMAs
+#pragma unroll
+                    for (int u = 0; u < kPowUnroll; ++u) {
+                        a0 = fma((double)e[u].x, vj[u], a0);
+                        a1 = fma((double)e[u].y, vj[u], a1);
+                        a2 = fma((double)e[u].z, vj[u], a2);
+                        a3 = fma((double)e[u].w, vj[u], a3);
+                    }
+                }
             }
-            for (int off = S >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-            w[k] = acc;
-            if (i < M && sl == 0) {
-                pv = fma(v[i], acc, pv);
-                pw = fma(acc, acc, pw);
+            for (int off = S >> 1; off > 0; off >>= 1) {
+                a0 += __shfl_xor(a0, off);
+                a1 += __shfl_xor(a1, off);
+                a2 += __shfl_xor(a2, off);
+                a3 += __shfl_xor(a3, off);
+            }
+            w[k][0] = a0;
+            w[k][1] = a1;
+            w[k][2] = a2;
+            w[k][3] = a3;
+            if (q < nq && sl == 0) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    if (4 * q + c < M) {
+                        pv = fma(v[4 * q + c], w[k][c], pv);
+                        pw = fma(w[k][c], w[k][c], pw);
+                    }
+                }
             }
         }
         block_sum2_1024(pv, pw, red);   // also: every thread has finished reading v
@@ -148,10 +191,14 @@ __device__ __forceinline__ void power_iterate(const int* __restrict__ g, int M, 
         const double nw = sqrt(pw);
         if (nw == 0.0) break;
 #pragma unroll
-        for (int k = 0; k < kPowRows; ++k) {
-            if (per_pass * k >= M) break;
-            const int i = grp + per_pass * k;
-            if (i < M && sl == 0) v[i] = w[k] / nw;
+        for (int k = 0; k < KQ; ++k) {
+            if (per_pass * k >= nq) break;
+            const int q = grp + per_pass * k;
+            if (q < nq && sl == 0) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (4 * q + c < M) v[4 * q + c] = w[k][c] / nw;
+            }
         }
         __syncthreads();
     }
@@ -213,13 +260,14 @@ __device__ __forceinline__ void power_iterate_reg(const int* __restrict__ g, int
     constexpr int kScatter = TS == 8 ? 3 : TS == 4 ? 2 : TS == 2 ? 1 : 0;
     const int row = a * TS + rowoff;
     const bool writer = (b & ((16 >> kScatter) * 2 - 1)) == 0;
+    const int ld = (M + 3) & ~3;   // G's padded row length
     int gr[TS][TS];
 #pragma unroll
     for (int r = 0; r < TS; ++r)
 #pragma unroll
         for (int c = 0; c < TS; ++c) {
             const int i = a * TS + (r ^ rowoff), j = b + 32 * c;
-            gr[r][c] = (i < M && j < M) ? g[(size_t)i * M + j] : 0;
+            gr[r][c] = (i < M && j < M) ? g[(size_t)i * ld + j] : 0;
         }
     // both buffers: entries i >= M are never written by the iteration and
     // must read as zero (a stale NaN times a zero G entry would not vanish)
@@ -298,12 +346,13 @@ __device__ __forceinline__ void power_iterate_reg(const int* __restrict__ g, int
     }
 }
 
+template <int KQ>
 __global__ __launch_bounds__(1024) void power_kernel(const int* __restrict__ g, int M, int S,
                                                     double s_phi, double tol, int max_iter,
                                                     double* __restrict__ lip) {
-    extern __shared__ double v[];   // M
+    extern __shared__ double v[];   // gram_ld(M)
     __shared__ double red[2][16];
-    power_iterate(g, M, S, s_phi, tol, max_iter, lip, v, red);
+    power_iterate<KQ>(g, M, S, s_phi, tol, max_iter, lip, v, red);
 }
 
 template <int TS>
@@ -318,8 +367,9 @@ __global__ __launch_bounds__(1024) void power_reg_kernel(const int* __restrict__
 // The power iterations of several streams side by side, one workgroup each
 // (job blockIdx.x; the same iteration as the single-stream kernels, so a
 // stream's step constant does not depend on its batch).  TS > 0: every job
-// of the launch has M <= 32 TS (the register form); TS = 0: G from memory.
-template <int TS>
+// of the launch has M <= 32 TS (the register form); TS = 0: G from memory,
+// at most KQ column quads per thread.
+template <int TS, int KQ = 1>
 __global__ __launch_bounds__(1024) void power_batch_kernel(PowBatch bt, double tol, int max_iter) {
     const PowJob& j = bt.j[blockIdx.x];
     if constexpr (TS > 0) {
@@ -327,9 +377,9 @@ __global__ __launch_bounds__(1024) void power_batch_kernel(PowBatch bt, double t
         __shared__ double red[2][2][16];
         power_iterate_reg<TS>(j.gram, j.M, j.s_phi, tol, max_iter, j.lip, wb, red);
     } else {
-        extern __shared__ double v[];   // the largest M of the batch
+        extern __shared__ double v[];   // gram_ld of the largest M of the batch
         __shared__ double red[2][16];
-        power_iterate(j.gram, j.M, j.S, j.s_phi, tol, max_iter, j.lip, v, red);
+        power_iterate<KQ>(j.gram, j.M, j.S, j.s_phi, tol, max_iter, j.lip, v, red);
     }
 }
 
@@ -346,27 +396,33 @@ void launch_operator_setup(Operator* op, hipStream_t st) {
     CSV_HIP(hipGetLastError());
 }
 
-static int power_threads_per_row(int M) {
-    int S = 1;   // 1024 / M rounded down to a power of two, <= 64
-    while (S < 64 && 2 * S * M <= 1024) S *= 2;
+// Threads per column quad of the memory form: 1024 / (gram_ld(M) / 4)
+// rounded down to a power of two, at most 64
+static int power_threads_per_quad(int M) {
+    const int nq = gram_ld(M) / 4;
+    int S = 1;
+    while (S < 64 && 2 * S * nq <= 1024) S *= 2;
     return S;
 }
+// Column quads per thread the memory form needs (its KQ)
+static int power_quads_per_thread(int M) { return gram_ld(M) / 4 <= 1024 ? 1 : 4; }
 
 void launch_gram(Operator* op, int* gram, hipStream_t st) {
     const int M = op->M;
-    CSV_REQUIRE(M <= 1024 * kPowRows, CSV_EUNSUPPORTED, "step constant: M above 16384");
+    CSV_REQUIRE(M <= kPowMaxM, CSV_EUNSUPPORTED, "step constant: M above 16384");
     CSV_REQUIRE(1024ll * op->n < (1ll << 31), CSV_EUNSUPPORTED,
                 "step constant: n too large for the exact int32 Gram matrix");
-    gram_kernel<<<dim3(ceil_div(M, 16), ceil_div(M, 16)), dim3(256), 0, st>>>(op->q, M, op->n,
-                                                                             gram);
+    const int ld = gram_ld(M);
+    gram_kernel<<<dim3(ceil_div(ld, 16), ceil_div(M, 16)), dim3(256), 0, st>>>(op->q, M, op->n,
+                                                                              ld, gram);
     CSV_HIP(hipGetLastError());
 }
 
-template <int TS>
+template <int TS, int KQ = 1>
 static void power_batch_launch(const PowBatch& bt, int k, int mmax, hipStream_t st) {
-    const size_t lds = TS > 0 ? 0 : (size_t)mmax * sizeof(double);
-    if (TS == 0) ensure_lds_limit<&power_batch_kernel<0>>((size_t)1024 * kPowRows * sizeof(double));
-    power_batch_kernel<TS><<<dim3(k), dim3(1024), lds, st>>>(bt, 1e-12, 10000);
+    const size_t lds = TS > 0 ? 0 : (size_t)gram_ld(mmax) * sizeof(double);
+    if (TS == 0) ensure_lds_limit<&power_batch_kernel<0, KQ>>((size_t)kPowMaxM * sizeof(double));
+    power_batch_kernel<TS, KQ><<<dim3(k), dim3(1024), lds, st>>>(bt, 1e-12, 10000);
     CSV_HIP(hipGetLastError());
 }
 
@@ -383,7 +439,7 @@ void launch_power_batch(Operator* const* ops, int* const* grams, int count, hipS
             const int k = (int)std::min<size_t>(kPowBatch, idx.size() - a);
             for (int i = 0; i < k; ++i) {
                 Operator* op = ops[idx[a + i]];
-                bt.j[i] = PowJob{grams[idx[a + i]], op->M, power_threads_per_row(op->M), op->s_phi,
+                bt.j[i] = PowJob{grams[idx[a + i]], op->M, power_threads_per_quad(op->M), op->s_phi,
                                  op->lip};
                 mmax = std::max(mmax, op->M);
             }
@@ -392,20 +448,20 @@ void launch_power_batch(Operator* const* ops, int* const* grams, int count, hipS
                 case 4: power_batch_launch<4>(bt, k, mmax, st); break;
                 case 2: power_batch_launch<2>(bt, k, mmax, st); break;
                 case 1: power_batch_launch<1>(bt, k, mmax, st); break;
-                default: power_batch_launch<0>(bt, k, mmax, st); break;
+                default:
+                    if (power_quads_per_thread(mmax) == 1)
+                        power_batch_launch<0, 1>(bt, k, mmax, st);
+                    else
+                        power_batch_launch<0, 4>(bt, k, mmax, st);
+                    break;
             }
         }
     }
 }
 
 void launch_power_iteration(Operator* op, int* gram, hipStream_t st) {
+    launch_gram(op, gram, st);
     const int M = op->M;
-    CSV_REQUIRE(M <= 1024 * kPowRows, CSV_EUNSUPPORTED, "step constant: M above 16384");
-    CSV_REQUIRE(1024ll * op->n < (1ll << 31), CSV_EUNSUPPORTED,
-                "step constant: n too large for the exact int32 Gram matrix");
-    gram_kernel<<<dim3(ceil_div(M, 16), ceil_div(M, 16)), dim3(256), 0, st>>>(op->q, M, op->n,
-                                                                             gram);
-    CSV_HIP(hipGetLastError());
     switch (power_tile(M)) {
         case 8: power_reg_kernel<8><<<1, 1024, 0, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip); break;
         case 4: power_reg_kernel<4><<<1, 1024, 0, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip); break;
@@ -413,10 +469,17 @@ void launch_power_iteration(Operator* op, int* gram, hipStream_t st) {
         case 1: power_reg_kernel<1><<<1, 1024, 0, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip); break;
         default: {
             // v in LDS, beyond the 64 KB default
-            ensure_lds_limit<&power_kernel>((size_t)1024 * kPowRows * sizeof(double));
-            const size_t lds = (size_t)M * sizeof(double);
-            power_kernel<<<dim3(1), dim3(1024), lds, st>>>(gram, M, power_threads_per_row(M),
-                                                           op->s_phi, 1e-12, 10000, op->lip);
+            const size_t lds = (size_t)gram_ld(M) * sizeof(double);
+            const int S = power_threads_per_quad(M);
+            if (power_quads_per_thread(M) == 1) {
+                ensure_lds_limit<&power_kernel<1>>((size_t)kPowMaxM * sizeof(double));
+                power_kernel<1><<<dim3(1), dim3(1024), lds, st>>>(gram, M, S, op->s_phi, 1e-12,
+                                                                   10000, op->lip);
+            } else {
+                ensure_lds_limit<&power_kernel<4>>((size_t)kPowMaxM * sizeof(double));
+                power_kernel<4><<<dim3(1), dim3(1024), lds, st>>>(gram, M, S, op->s_phi, 1e-12,
+                                                                   10000, op->lip);
+            }
         }
     }
     CSV_HIP(hipGetLastError());
