@@ -14,6 +14,13 @@ namespace csv {
 // the LDS counter too and force a full wait before every LDS read.
 typedef __attribute__((address_space(1))) const u16x8 gu16x8;
 typedef __attribute__((address_space(1))) const float gfloat;
+// Tables the kernel only reads, at addresses uniform over the workgroup
+// (the momentum factors, the step constant): through the constant address
+// space with a uniform address these become scalar loads, which the wave
+// does not wait for before its next LDS access the way it waits for a
+// flat load.
+typedef __attribute__((address_space(4))) const float cfloat;
+typedef __attribute__((address_space(4))) const double cdouble;
 template <class T>
 __device__ inline T* as_global(const void* p) {
     return (T*)(p);

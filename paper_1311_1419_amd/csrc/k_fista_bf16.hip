@@ -133,7 +133,9 @@ void fista_bf16_kernel(
     for (;;) {
         if (tid == 0) s_tile = next_tile(qoff, queue, counters);
         __syncthreads();
-        const int t_id = s_tile;
+        // uniform: the descriptor and the tables it points to are then
+        // read with scalar loads
+        const int t_id = __builtin_amdgcn_readfirstlane(s_tile);
         __syncthreads();
         if (t_id < 0) break;
         const FusedTile tl = tiles[t_id];
@@ -157,9 +159,10 @@ void fista_bf16_kernel(
             fadj = as_global<const gu16x8>(tl.frag_adj);
         }
         const gfloat* yg = as_global<const gfloat>(tl.y);
-        const float inv_l = (float)(1.0 / tl.lip[0]);
+        const float inv_l = (float)(1.0 / as_global<cdouble>(tl.lip)[0]);
         const int T = tl.T;
-        const float* __restrict__ beta = tl.beta;
+        const cfloat* __restrict__ beta = as_global<cfloat>(tl.beta);
+        const gfloat* __restrict__ lamg = as_global<gfloat>(tl.lam);
         if constexpr (NL > 0) {
             // each lane reads back only what it wrote itself: no barrier
             if (nft == FT && tl.frag_fwd != al_src) {
@@ -177,7 +180,7 @@ void fista_bf16_kernel(
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
             const int b = ct * 32 + col;
-            tau[ct] = b < tl.nblk ? tl.lam[b] * inv_l : 0.f;
+            tau[ct] = b < tl.nblk ? lamg[b] * inv_l : 0.f;
         }
         floatx16 yv[YREG ? FT : 1];
         if constexpr (YREG) {
@@ -190,7 +193,7 @@ void fista_bf16_kernel(
                 for (int r = 0; r < 16; ++r) {
                     const int m = mt * 32 + 8 * (r / 4) + 4 * h + (r % 4);
                     // held as y^ / L: the residual epilogue is then one FMA
-                    yv[i][r] = (t < TT && b < tl.nblk) ? tl.y[(size_t)b * MP + m] * inv_l : 0.f;
+                    yv[i][r] = (t < TT && b < tl.nblk) ? yg[(size_t)b * MP + m] * inv_l : 0.f;
                 }
             }
         }

@@ -137,7 +137,9 @@ void fista_q8_kernel(const FusedTile* __restrict__ tiles, const int* __restrict_
     for (;;) {
         if (tid == 0) s_tile = next_tile(qoff, queue, counters);
         __syncthreads();
-        const int t_id = s_tile;
+        // uniform: the descriptor and the tables it points to are then
+        // read with scalar loads
+        const int t_id = __builtin_amdgcn_readfirstlane(s_tile);
         __syncthreads();
         if (t_id < 0) break;
         const FusedTile tl = tiles[t_id];
@@ -145,11 +147,11 @@ void fista_q8_kernel(const FusedTile* __restrict__ tiles, const int* __restrict_
         const gu32x4* qa = as_global<const gu32x4>(tl.qb_adj);   // [32][KSA / 2][64] pairs
         const gfloat* yg = as_global<const gfloat>(tl.y);
         const gfloat* dct = as_global<const gfloat>(tl.dct);
-        const float inv_l = (float)(1.0 / tl.lip[0]);
+        const float inv_l = (float)(1.0 / as_global<cdouble>(tl.lip)[0]);
         const float sphi = tl.s_phi, rscale = tl.s_phi * inv_l;
         const int T = tl.T, nblk = tl.nblk;
-        const float* __restrict__ beta = tl.beta;
-        const float tau = col < nblk ? tl.lam[col] * inv_l : 0.f;
+        const cfloat* __restrict__ beta = as_global<cfloat>(tl.beta);
+        const float tau = col < nblk ? as_global<const gfloat>(tl.lam)[col] * inv_l : 0.f;
         // DCT fragments in LDS: ct[s] = A[i][k] = C[k][i], cn[s] = A[l][j] = C[l][j]
         if (w < 4) {
             const int s = w & 1;
