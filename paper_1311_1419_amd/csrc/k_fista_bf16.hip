@@ -83,7 +83,8 @@ void launch_bf16_frag_layout(Operator* op, hipStream_t st) {
 // both fragment layouts of the whole operator are copied to LDS when a
 // tile's operator differs from the previous tile's, and every iteration
 // reads them there instead of from L2 (small classes, where the operator
-// fits beside V and R).
+// fits beside V and R).  OPT bit 2: s and v in two register arrays that
+// trade roles every iteration (implied by bits 0 and 1 together).
 template <int N, int MP, int CT, int W, int kPF, int kPA, int SPL, int OCC, int NLS, int OPT = 0>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W * OCC / 4)))
 void fista_bf16_kernel(
@@ -100,7 +101,7 @@ void fista_bf16_kernel(
     constexpr int KSF = N / 16, KSA = MP / 16;   // K steps of forward / adjoint
     constexpr bool YREG = (OPT & 1) != 0;        // else y^ is read from L2 in every epilogue
     constexpr bool OPL = (OPT & 2) != 0;         // operator resident in LDS
-    constexpr bool PP = YREG && OPL;             // ping-pong state (register-light classes)
+    constexpr bool PP = (YREG && OPL) || (OPT & 4) != 0;   // ping-pong state
     static_assert(!PP || SPL == 0, "ping-pong state keeps every tile in registers");
     static_assert(!(OPL && NLS != 0), "the LDS slice is part of an LDS-resident operator");
     constexpr int OFW = (MP / 32) * KSF * 64;   // u16x8 of the forward layout (OPL)
@@ -465,6 +466,11 @@ static void launch_class(const FusedTile* tiles, const int* qoff, const int* que
     CSV_VG(NN, MM, CT, W, PF, PA, SPL, OCC, NL, "_lds" #NL)
 #define CSV_VLI(NN, MM, CT, W, PF, PA, SPL, OCC, NL) \
     CSV_VG(NN, MM, CT, W, PF, PA, SPL, OCC, -NL, "_ldsi" #NL)
+#define CSV_VLIP(NN, MM, CT, W, PF, PA, OCC, NL)                                            \
+    FusedVariant {                                                                         \
+        "ct" #CT "_w" #W "_pf" #PF "_pa" #PA "_spl0_o" #OCC "_ldsi" #NL "_pp", CT, OCC,     \
+            &launch_class<NN, MM, CT, W, PF, PA, 0, OCC, -NL, 4>                            \
+    }
 
 struct ClassEntry {
     int n, Mp;
@@ -500,24 +506,29 @@ static std::vector<ClassEntry>& class_table() {
          0},
         {1024, 32,
          {CSV_VLI(1024, 32, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 32, 1, 8, 4, 2, 0, 1),
-          CSV_V(1024, 32, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 32, 1, 8, 4, 2, 0, 1, 8)},
+          CSV_V(1024, 32, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 32, 1, 8, 4, 2, 0, 1, 8),
+          CSV_VLIP(1024, 32, 1, 8, 4, 2, 1, 8)},
          0},
         {1024, 64,
          {CSV_VLI(1024, 64, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 64, 1, 8, 4, 2, 0, 1),
-          CSV_V(1024, 64, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 64, 1, 8, 4, 2, 0, 1, 8)},
+          CSV_V(1024, 64, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 64, 1, 8, 4, 2, 0, 1, 8),
+          CSV_VLIP(1024, 64, 1, 8, 4, 2, 1, 8)},
          0},
         {1024, 128,
          {CSV_VLI(1024, 128, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 128, 1, 8, 4, 2, 0, 1),
-          CSV_V(1024, 128, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 128, 1, 8, 4, 2, 0, 1, 8)},
+          CSV_V(1024, 128, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 128, 1, 8, 4, 2, 0, 1, 8),
+          CSV_VLIP(1024, 128, 1, 8, 4, 2, 1, 8)},
          0},
         {1024, 224,
          {CSV_VLI(1024, 224, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 224, 1, 8, 4, 2, 0, 1),
-          CSV_V(1024, 224, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 224, 1, 8, 4, 2, 0, 1, 8)},
+          CSV_V(1024, 224, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 224, 1, 8, 4, 2, 0, 1, 8),
+          CSV_VLIP(1024, 224, 1, 8, 4, 2, 1, 8)},
          0},
         {1024, 256,
          {CSV_VLI(1024, 256, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 256, 1, 8, 4, 2, 0, 1),
           CSV_V(1024, 256, 1, 8, 4, 2, 2, 1), CSV_V(1024, 256, 1, 8, 8, 2, 2, 1),
           CSV_V(1024, 256, 1, 8, 4, 2, 1, 1), CSV_VL(1024, 256, 1, 8, 4, 2, 0, 1, 8),
+          CSV_VLIP(1024, 256, 1, 8, 4, 2, 1, 8),
           FusedVariant{"q8_w8_pf2x2_pa2x2", 1, 1, &launch_fista_q8_m256}},
          0},
         {1024, 416,
@@ -532,6 +543,7 @@ static std::vector<ClassEntry>& class_table() {
 #undef CSV_VOL
 #undef CSV_VL
 #undef CSV_VLI
+#undef CSV_VLIP
 #undef CSV_VG
 
 static ClassEntry* find_class(int n, int Mp) {

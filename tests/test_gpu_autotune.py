@@ -20,7 +20,8 @@ SPECS = [(sv.qcif_tiny(), "b16-m64"), (sv.cif_sweep(4, 0.1), "b16-m26"),
          (sv.qcif_tiny().with_(block=32, m=51, gop=2, iters=300), "b32-m51"),
          (sv.qcif_tiny().with_(block=32, m=205, gop=2, iters=300), "b32-m205"),
          (sv.vga_precision(0.4, gop=2), "b32-m410"),
-         (sv.qcif_tiny().with_(block=32, m=25, gop=3, iters=300), "b32-m25")]
+         (sv.qcif_tiny().with_(block=32, m=25, gop=3, iters=300), "b32-m25"),
+         (sv.qcif_tiny().with_(block=32, m=25, gop=2, iters=77), "b32-m25-t77")]
 
 
 @pytest.mark.parametrize("spec", [s for s, _ in SPECS], ids=[i for _, i in SPECS])
