@@ -770,8 +770,8 @@ def main():
     # fragment layouts of its operator (2 x Mp x n bf16) once per iteration,
     # less the last `nl` forward K steps of each of the Mp / 32 forward tiles
     # (1 KiB fragments) that a variant named "..._lds<nl>" or "..._ldsi<nl>"
-    # keeps in LDS
-    nl_m = re.search(r"_ldsi?(\d+)$", variant)
+    # (optionally followed by "_pp") keeps in LDS
+    nl_m = re.search(r"_ldsi?(\d+)(_pp)?$", variant)
     nl = int(nl_m.group(1)) if nl_m else 0
     tiles = sum(-(-((s.gop - 1) * ((s.height + 31) // 32) * ((s.width + 31) // 32)) // 32)
                 for s in specs)

@@ -505,24 +505,24 @@ static std::vector<ClassEntry>& class_table() {
           CSV_V(256, 128, 4, 8, 4, 2, 0, 1)},
          0},
         {1024, 32,
-         {CSV_VLI(1024, 32, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 32, 1, 8, 4, 2, 0, 1),
-          CSV_V(1024, 32, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 32, 1, 8, 4, 2, 0, 1, 8),
-          CSV_VLIP(1024, 32, 1, 8, 4, 2, 1, 8)},
+         {CSV_VLIP(1024, 32, 1, 8, 4, 2, 1, 8), CSV_VLI(1024, 32, 1, 8, 4, 2, 0, 1, 8),
+          CSV_V(1024, 32, 1, 8, 4, 2, 0, 1), CSV_V(1024, 32, 1, 8, 4, 2, 2, 1),
+          CSV_VL(1024, 32, 1, 8, 4, 2, 0, 1, 8)},
          0},
         {1024, 64,
-         {CSV_VLI(1024, 64, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 64, 1, 8, 4, 2, 0, 1),
-          CSV_V(1024, 64, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 64, 1, 8, 4, 2, 0, 1, 8),
-          CSV_VLIP(1024, 64, 1, 8, 4, 2, 1, 8)},
+         {CSV_VLIP(1024, 64, 1, 8, 4, 2, 1, 8), CSV_VLI(1024, 64, 1, 8, 4, 2, 0, 1, 8),
+          CSV_V(1024, 64, 1, 8, 4, 2, 0, 1), CSV_V(1024, 64, 1, 8, 4, 2, 2, 1),
+          CSV_VL(1024, 64, 1, 8, 4, 2, 0, 1, 8)},
          0},
         {1024, 128,
-         {CSV_VLI(1024, 128, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 128, 1, 8, 4, 2, 0, 1),
-          CSV_V(1024, 128, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 128, 1, 8, 4, 2, 0, 1, 8),
-          CSV_VLIP(1024, 128, 1, 8, 4, 2, 1, 8)},
+         {CSV_VLIP(1024, 128, 1, 8, 4, 2, 1, 8), CSV_VLI(1024, 128, 1, 8, 4, 2, 0, 1, 8),
+          CSV_V(1024, 128, 1, 8, 4, 2, 0, 1), CSV_V(1024, 128, 1, 8, 4, 2, 2, 1),
+          CSV_VL(1024, 128, 1, 8, 4, 2, 0, 1, 8)},
          0},
         {1024, 224,
-         {CSV_VLI(1024, 224, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 224, 1, 8, 4, 2, 0, 1),
-          CSV_V(1024, 224, 1, 8, 4, 2, 2, 1), CSV_VL(1024, 224, 1, 8, 4, 2, 0, 1, 8),
-          CSV_VLIP(1024, 224, 1, 8, 4, 2, 1, 8)},
+         {CSV_VLIP(1024, 224, 1, 8, 4, 2, 1, 8), CSV_VLI(1024, 224, 1, 8, 4, 2, 0, 1, 8),
+          CSV_V(1024, 224, 1, 8, 4, 2, 0, 1), CSV_V(1024, 224, 1, 8, 4, 2, 2, 1),
+          CSV_VL(1024, 224, 1, 8, 4, 2, 0, 1, 8)},
          0},
         {1024, 256,
          {CSV_VLI(1024, 256, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 256, 1, 8, 4, 2, 0, 1),
