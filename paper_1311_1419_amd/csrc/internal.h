@@ -183,7 +183,7 @@ void launch_fill_u64(unsigned long long* p, unsigned long long v, int count, hip
 void launch_operator_setup(Operator* op, hipStream_t st);
 // The exact Gram matrix QQ^T is stored row-major with rows padded to
 // gram_ld(M) int32 (zero beyond column M), so rows start 16-byte aligned.
-inline int gram_ld(int M) { return round_up(M, 4); }
+__host__ __device__ inline int gram_ld(int M) { return (M + 3) & ~3; }
 void launch_power_iteration(Operator* op, int* gram, hipStream_t st);   // gram: M x gram_ld(M) scratch
 // The same for many operators: each one's exact Gram matrix (launch_gram),
 // then their power iterations side by side, one workgroup per operator,

@@ -124,7 +124,7 @@ __device__ __forceinline__ void power_iterate(const int* __restrict__ g, int M, 
                                               double tol, int max_iter, double* __restrict__ lip,
                                               double* v, double (*red)[16]) {
     constexpr int kPowUnroll = 8;   // quad loads in flight per thread
-    const int ld = (M + 3) & ~3, nq = ld >> 2;
+    const int ld = gram_ld(M), nq = ld >> 2;
     const int tid = threadIdx.x, grp = tid / S, sl = tid - grp * S, per_pass = 1024 / S;
     const int4* __restrict__ g4 = reinterpret_cast<const int4*>(g);
     for (int i = tid; i < ld; i += 1024) v[i] = i < M ? 1.0 / sqrt((double)M) : 0.0;
@@ -260,7 +260,7 @@ __device__ __forceinline__ void power_iterate_reg(const int* __restrict__ g, int
     constexpr int kScatter = TS == 8 ? 3 : TS == 4 ? 2 : TS == 2 ? 1 : 0;
     const int row = a * TS + rowoff;
     const bool writer = (b & ((16 >> kScatter) * 2 - 1)) == 0;
-    const int ld = (M + 3) & ~3;   // G's padded row length
+    const int ld = gram_ld(M);   // G's padded row length
     int gr[TS][TS];
 #pragma unroll
     for (int r = 0; r < TS; ++r)
