@@ -221,7 +221,8 @@ static Operator* build_operator_locked(Ctx* c, const Shape& s, hipStream_t st,
             launch_phi_q(op->q, s.M, s.Mp, s.n, s.seed, (uint64_t)s.sid, st);
             launch_transpose_q(op->q, s.Mp, s.n, op->qt, st);
             int* gram = static_cast<int*>(scratch(c, "gram", (size_t)s.M * gram_ld(s.M) * 4));
-            launch_power_iteration(op.get(), gram, st);
+            void* work = power_work_bytes(s.M) ? scratch(c, "pow_work", power_work_bytes(s.M)) : nullptr;
+            launch_power_iteration(op.get(), gram, work, st);
         } catch (...) {
             free_operator(c, op.get());
             throw;
@@ -268,7 +269,8 @@ static Operator* build_operator_locked(Ctx* c, const Shape& s, hipStream_t st,
             launch_gram(op.get(), gram_dst, st);
         } else {
             int* gram = static_cast<int*>(scratch(c, "gram", (size_t)s.M * gram_ld(s.M) * 4));
-            launch_power_iteration(op.get(), gram, st);
+            void* work = power_work_bytes(s.M) ? scratch(c, "pow_work", power_work_bytes(s.M)) : nullptr;
+            launch_power_iteration(op.get(), gram, work, st);
         }
     } catch (...) {
         free_operator(c, op.get());
@@ -315,7 +317,10 @@ void prepare_operators(Ctx* c, const Shape* shapes, int count, hipStream_t st) {
         gp.push_back(grams + off[i]);
         ops.push_back(build_operator_locked(c, *todo[i], st, gp.back()));
     }
-    launch_power_batch(ops.data(), gp.data(), (int)ops.size(), st);
+    size_t wb = 0;
+    for (const Shape* sh : todo) wb = std::max(wb, power_work_bytes(sh->M));
+    void* work = wb ? scratch(c, "pow_work", wb) : nullptr;
+    launch_power_batch(ops.data(), gp.data(), (int)ops.size(), work, st);
 }
 
 // beta_k = (t_k - 1) / t_{k+1}, t_1 = 1, t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2

@@ -184,7 +184,11 @@ void launch_operator_setup(Operator* op, hipStream_t st);
 // The exact Gram matrix QQ^T is stored row-major with rows padded to
 // gram_ld(M) int32 (zero beyond column M), so rows start 16-byte aligned.
 __host__ __device__ inline int gram_ld(int M) { return (M + 3) & ~3; }
-void launch_power_iteration(Operator* op, int* gram, hipStream_t st);   // gram: M x gram_ld(M) scratch
+// Scratch a power iteration needs beside G (its many-workgroup form's row
+// slices, iterates and state; 0 where the one-workgroup forms run)
+size_t power_work_bytes(int M);
+void launch_power_iteration(Operator* op, int* gram, void* work,
+                            hipStream_t st);   // gram: M x gram_ld(M) scratch
 // The same for many operators: each one's exact Gram matrix (launch_gram),
 // then their power iterations side by side, one workgroup per operator,
 // kPowBatch operators per launch.
@@ -199,7 +203,8 @@ struct PowBatch {
     PowJob j[kPowBatch];
 };
 void launch_gram(Operator* op, int* gram, hipStream_t st);
-void launch_power_batch(Operator* const* ops, int* const* grams, int count, hipStream_t st);
+void launch_power_batch(Operator* const* ops, int* const* grams, int count, void* work,
+                        hipStream_t st);
 // raw: codes hold int32 y~ and exps are ignored (CSV_FLAG_NO_QUANT)
 void launch_dequant(const int8_t* codes, const uint8_t* exps, int nblk, int M, int Mp,
                     double s_phi, float* y, hipStream_t st, bool raw = false);

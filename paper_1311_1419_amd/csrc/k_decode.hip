@@ -109,78 +109,68 @@ __device__ __forceinline__ void block_sum2_1024(double& a, double& b, double (*r
 
 // Power iteration on G (FP64): v0 = 1/sqrt(M); w = G v; Rayleigh quotient
 // rq = v.w; stop once |rq - rq_prev| <= tol rq (from the second step), else
-// v = w / ||w||.  One workgroup of 1024 threads, v in LDS (M <= 16384), G
-// read from memory in every step.  G is symmetric, so column i of G gives
-// w_i, and the columns are read as 16-byte quads (rows padded to
+// v = w / ||w||.  One workgroup of 1024 threads for 256 < M <= kPowMultiMinM,
+// v in LDS, G read from memory in every step.  G is symmetric, so column i
+// of G gives w_i, and the columns are read as 16-byte quads (rows padded to
 // ld = gram_ld(M), zero beyond M): S adjacent threads share a quad (S =
 // 1024 / (ld / 4) rounded down to a power of two, at most 64), thread s of
 // the group sums rows j = s, s + S, ... with kPowUnroll quad loads in
 // flight, the S partial sums meet by a fixed shuffle tree, and the group's
-// first thread keeps the quad's four entries of w.  With S = 1 a thread
-// takes quads t, t + 1024, ... (KQ of them at most).
+// first thread keeps the quad's four entries of w.
 constexpr int kPowMaxM = 16384;
-template <int KQ>
+constexpr int kPowUnroll = 8;       // quad loads in flight per thread
+constexpr int kPowMultiMinM = 384;  // above this M the many-workgroup form runs
 __device__ __forceinline__ void power_iterate(const int* __restrict__ g, int M, int S, double s_phi,
                                               double tol, int max_iter, double* __restrict__ lip,
                                               double* v, double (*red)[16]) {
-    constexpr int kPowUnroll = 8;   // quad loads in flight per thread
     const int ld = gram_ld(M), nq = ld >> 2;
-    const int tid = threadIdx.x, grp = tid / S, sl = tid - grp * S, per_pass = 1024 / S;
+    const int tid = threadIdx.x, q = tid / S, sl = tid - q * S;   // S nq <= 1024
     const int4* __restrict__ g4 = reinterpret_cast<const int4*>(g);
     for (int i = tid; i < ld; i += 1024) v[i] = i < M ? 1.0 / sqrt((double)M) : 0.0;
     __syncthreads();
     double rq = 0.0, rq_prev = 0.0;
     int it = 0;
     for (it = 1; it <= max_iter; ++it) {
-        double w[KQ][4];
         double pv = 0.0, pw = 0.0;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        if (q < nq) {
+            for (int j0 = sl; j0 < M; j0 += S * kPowUnroll) {
+                int4 e[kPowUnroll];
+                double vj[kPowUnroll];
+                // every load in bounds and unconditional (rows past M
+                // re-read row M - 1 and their terms get a zero factor),
+                // so all kPowUnroll are in flight before the first FMA
 #pragma unroll
-        for (int k = 0; k < KQ; ++k) {
-            if (per_pass * k >= nq) break;   // uniform
-            const int q = grp + per_pass * k;
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            if (q < nq) {
-                for (int j0 = sl; j0 < M; j0 += S * kPowUnroll) {
-                    int4 e[kPowUnroll];
-                    double vj[kPowUnroll];
-                    // every load in bounds and unconditional (rows past M
-                    // re-read row M - 1 and their terms get a zero factor),
-                    // so all kPowUnroll are in flight before the first FMA
+                for (int u = 0; u < kPowUnroll; ++u) {
+                    const int j = j0 + S * u;
+                    const int jc = j < M ? j : M - 1;
+                    e[u] = g4[(unsigned)(jc * nq + q)];   // < 2^26
+                    const double vc = v[jc];
+                    vj[u] = j < M ? vc : 0.0;
+                }
+                __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the FMAs
 #pragma unroll
-                    for (int u = 0; u < kPowUnroll; ++u) {
-                        const int j = j0 + S * u;
-                        const int jc = j < M ? j : M - 1;
-                        e[u] = g4[(unsigned)(jc * nq + q)];   // < 2^26
-                        const double vc = v[jc];
-                        vj[u] = j < M ? vc : 0.0;
-                    }
-                    __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the FMAs
-#pragma unroll
-                    for (int u = 0; u < kPowUnroll; ++u) {
-                        a0 = fma((double)e[u].x, vj[u], a0);
-                        a1 = fma((double)e[u].y, vj[u], a1);
-                        a2 = fma((double)e[u].z, vj[u], a2);
-                        a3 = fma((double)e[u].w, vj[u], a3);
-                    }
+                for (int u = 0; u < kPowUnroll; ++u) {
+                    a0 = fma((double)e[u].x, vj[u], a0);
+                    a1 = fma((double)e[u].y, vj[u], a1);
+                    a2 = fma((double)e[u].z, vj[u], a2);
+                    a3 = fma((double)e[u].w, vj[u], a3);
                 }
             }
-            for (int off = S >> 1; off > 0; off >>= 1) {
-                a0 += __shfl_xor(a0, off);
-                a1 += __shfl_xor(a1, off);
-                a2 += __shfl_xor(a2, off);
-                a3 += __shfl_xor(a3, off);
-            }
-            w[k][0] = a0;
-            w[k][1] = a1;
-            w[k][2] = a2;
-            w[k][3] = a3;
-            if (q < nq && sl == 0) {
+        }
+        for (int off = S >> 1; off > 0; off >>= 1) {
+            a0 += __shfl_xor(a0, off);
+            a1 += __shfl_xor(a1, off);
+            a2 += __shfl_xor(a2, off);
+            a3 += __shfl_xor(a3, off);
+        }
+        const double w[4] = {a0, a1, a2, a3};
+        if (q < nq && sl == 0) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    if (4 * q + c < M) {
-                        pv = fma(v[4 * q + c], w[k][c], pv);
-                        pw = fma(w[k][c], w[k][c], pw);
-                    }
+            for (int c = 0; c < 4; ++c) {
+                if (4 * q + c < M) {
+                    pv = fma(v[4 * q + c], w[c], pv);
+                    pw = fma(w[c], w[c], pw);
                 }
             }
         }
@@ -190,15 +180,10 @@ __device__ __forceinline__ void power_iterate(const int* __restrict__ g, int M, 
         rq_prev = rq;
         const double nw = sqrt(pw);
         if (nw == 0.0) break;
+        if (q < nq && sl == 0) {
 #pragma unroll
-        for (int k = 0; k < KQ; ++k) {
-            if (per_pass * k >= nq) break;
-            const int q = grp + per_pass * k;
-            if (q < nq && sl == 0) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if (4 * q + c < M) v[4 * q + c] = w[k][c] / nw;
-            }
+            for (int c = 0; c < 4; ++c)
+                if (4 * q + c < M) v[4 * q + c] = w[c] / nw;
         }
         __syncthreads();
     }
@@ -346,13 +331,12 @@ __device__ __forceinline__ void power_iterate_reg(const int* __restrict__ g, int
     }
 }
 
-template <int KQ>
 __global__ __launch_bounds__(1024) void power_kernel(const int* __restrict__ g, int M, int S,
                                                     double s_phi, double tol, int max_iter,
                                                     double* __restrict__ lip) {
     extern __shared__ double v[];   // gram_ld(M)
     __shared__ double red[2][16];
-    power_iterate<KQ>(g, M, S, s_phi, tol, max_iter, lip, v, red);
+    power_iterate(g, M, S, s_phi, tol, max_iter, lip, v, red);
 }
 
 template <int TS>
@@ -367,9 +351,9 @@ __global__ __launch_bounds__(1024) void power_reg_kernel(const int* __restrict__
 // The power iterations of several streams side by side, one workgroup each
 // (job blockIdx.x; the same iteration as the single-stream kernels, so a
 // stream's step constant does not depend on its batch).  TS > 0: every job
-// of the launch has M <= 32 TS (the register form); TS = 0: G from memory,
-// at most KQ column quads per thread.
-template <int TS, int KQ = 1>
+// of the launch has M <= 32 TS (the register form); TS = 0: G from memory
+// (256 < M <= kPowMultiMinM).
+template <int TS>
 __global__ __launch_bounds__(1024) void power_batch_kernel(PowBatch bt, double tol, int max_iter) {
     const PowJob& j = bt.j[blockIdx.x];
     if constexpr (TS > 0) {
@@ -379,7 +363,164 @@ __global__ __launch_bounds__(1024) void power_batch_kernel(PowBatch bt, double t
     } else {
         extern __shared__ double v[];   // gram_ld of the largest M of the batch
         __shared__ double red[2][16];
-        power_iterate<KQ>(j.gram, j.M, j.S, j.s_phi, tol, max_iter, j.lip, v, red);
+        power_iterate(j.gram, j.M, j.S, j.s_phi, tol, max_iter, j.lip, v, red);
+    }
+}
+
+// The power iteration for large M over many workgroups, one step per pair
+// of launches.  power_part_kernel: workgroup (x, y) sums rows
+// [y rs, y rs + rs) of G for the column quads x 256 .. x 256 + 255 (one per
+// thread, as in the one-workgroup form, G symmetric) into its row slice of
+// `part`.  power_step_kernel: one workgroup adds the slices in order, forms
+// v.w, w.w and the stopping test of the one-workgroup form, and writes
+// v = w / ||w|| to the other iterate buffer.  Both return at once after the
+// test has fired, so the host can queue steps in chunks and read `done`
+// between chunks.
+struct PowState {
+    double rq_prev;
+    int it, done;
+};
+
+__global__ __launch_bounds__(256) void power_part_kernel(const int* __restrict__ g, int M, int rs,
+                                                        const double* __restrict__ v,
+                                                        double* __restrict__ part,
+                                                        const PowState* __restrict__ st) {
+    if (st->done) return;
+    const int ld = gram_ld(M), nq = ld >> 2;
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= nq) return;
+    const int j0 = blockIdx.y * rs, j1 = min(M, j0 + rs);   // j0 < M by the grid
+    const int4* __restrict__ g4 = reinterpret_cast<const int4*>(g);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int jb = j0; jb < j1; jb += kPowUnroll) {
+        int4 e[kPowUnroll];
+        double vj[kPowUnroll];
+        // rows past the slice re-read its last row with a zero factor
+#pragma unroll
+        for (int u = 0; u < kPowUnroll; ++u) {
+            const int j = jb + u;
+            const int jc = j < j1 ? j : j1 - 1;
+            e[u] = g4[(unsigned)(jc * nq + q)];   // < 2^26
+            const double vc = v[jc];
+            vj[u] = j < j1 ? vc : 0.0;
+        }
+        __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the FMAs
+#pragma unroll
+        for (int u = 0; u < kPowUnroll; ++u) {
+            a0 = fma((double)e[u].x, vj[u], a0);
+            a1 = fma((double)e[u].y, vj[u], a1);
+            a2 = fma((double)e[u].z, vj[u], a2);
+            a3 = fma((double)e[u].w, vj[u], a3);
+        }
+    }
+    double* out = part + (size_t)blockIdx.y * ld + 4 * q;
+    out[0] = a0;
+    out[1] = a1;
+    out[2] = a2;
+    out[3] = a3;
+}
+
+__global__ __launch_bounds__(1024) void power_step_kernel(int M, int ns,
+                                                         const double* __restrict__ part,
+                                                         const double* __restrict__ v,
+                                                         double* __restrict__ vn,
+                                                         PowState* __restrict__ st, double s_phi,
+                                                         double tol, int max_iter,
+                                                         double* __restrict__ lip) {
+    __shared__ double red[2][16];
+    if (st->done) return;
+    const int ld = gram_ld(M);
+    double pv = 0.0, pw = 0.0;
+    for (int i = threadIdx.x; i < M; i += 1024) {
+        // four running sums over slices y = 0, 1, 2, 3 mod 4 (four loads in
+        // flight), added in a fixed order
+        double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+        int y = 0;
+        for (; y + 4 <= ns; y += 4) {
+            w0 += part[(size_t)y * ld + i];
+            w1 += part[(size_t)(y + 1) * ld + i];
+            w2 += part[(size_t)(y + 2) * ld + i];
+            w3 += part[(size_t)(y + 3) * ld + i];
+        }
+        for (; y < ns; ++y) w0 += part[(size_t)y * ld + i];
+        const double w = (w0 + w1) + (w2 + w3);
+        pv = fma(v[i], w, pv);
+        pw = fma(w, w, pw);
+        vn[i] = w;   // normalised below, by this same thread
+    }
+    block_sum2_1024(pv, pw, red);
+    const int it = st->it + 1;
+    const double rq = pv, nw = sqrt(pw);
+    // as the one-workgroup loop: stop on the relative change (from the
+    // second step), on a zero w, or after max_iter steps
+    if ((it > 1 && fabs(rq - st->rq_prev) <= tol * rq) || nw == 0.0 || it >= max_iter) {
+        __syncthreads();   // every thread has read st before it changes
+        if (threadIdx.x == 0) {
+            lip[0] = 1.001 * s_phi * s_phi * rq;
+            lip[1] = rq;
+            lip[2] = (double)it;
+            st->done = 1;
+        }
+        return;
+    }
+    for (int i = threadIdx.x; i < M; i += 1024) vn[i] = vn[i] / nw;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->rq_prev = rq;
+        st->it = it;
+    }
+}
+
+__global__ void power_init_kernel(int M, double* __restrict__ v, PowState* __restrict__ st) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < gram_ld(M)) v[i] = i < M ? 1.0 / sqrt((double)M) : 0.0;
+    if (i == 0) *st = PowState{0.0, 0, 0};
+}
+
+// Row slices of the many-workgroup form: the partial sums (ns x ld FP64)
+// stay near 256 KiB, which the single step workgroup reads in every step.
+static void power_multi_shape(int M, int* ns, int* rs) {
+    const int ld = gram_ld(M);
+    int n = std::max(1, std::min(32768 / ld, ceil_div(M, kPowUnroll)));
+    *rs = round_up(ceil_div(M, n), kPowUnroll);
+    *ns = ceil_div(M, *rs);
+}
+
+size_t power_work_bytes(int M) {
+    if (M <= kPowMultiMinM) return 0;
+    int ns, rs;
+    power_multi_shape(M, &ns, &rs);
+    const size_t ld = gram_ld(M);
+    return ((size_t)ns * ld + 2 * ld) * sizeof(double) + 256;
+}
+
+// The many-workgroup power iteration of one operator: steps queued in
+// chunks of kPowChunk, the host reading the state's `done` between chunks.
+static void power_multi(Operator* op, const int* gram, void* work, hipStream_t st) {
+    const int M = op->M, ld = gram_ld(M), nq = ld / 4;
+    int ns, rs;
+    power_multi_shape(M, &ns, &rs);
+    double* part = static_cast<double*>(work);
+    double* v0 = part + (size_t)ns * ld;
+    double* v1 = v0 + ld;
+    PowState* state = reinterpret_cast<PowState*>(v1 + ld);
+    constexpr int kMaxIter = 10000, kPowChunk = 64;
+    power_init_kernel<<<dim3(ceil_div(ld, 256)), dim3(256), 0, st>>>(M, v0, state);
+    CSV_HIP(hipGetLastError());
+    const dim3 grid(ceil_div(nq, 256), ns);
+    for (int k0 = 0; k0 < kMaxIter; k0 += kPowChunk) {
+        for (int k = k0; k < std::min(kMaxIter, k0 + kPowChunk); ++k) {
+            const double* vc = (k & 1) ? v1 : v0;
+            double* vx = (k & 1) ? v0 : v1;
+            power_part_kernel<<<grid, dim3(256), 0, st>>>(gram, M, rs, vc, part, state);
+            power_step_kernel<<<dim3(1), dim3(1024), 0, st>>>(M, ns, part, vc, vx, state, op->s_phi,
+                                                              1e-12, kMaxIter, op->lip);
+        }
+        CSV_HIP(hipGetLastError());
+        int done = 0;
+        CSV_HIP(hipMemcpyAsync(&done, &state->done, sizeof(int), hipMemcpyDeviceToHost, st));
+        CSV_HIP(hipStreamSynchronize(st));
+        if (done) return;
     }
 }
 
@@ -404,8 +545,6 @@ static int power_threads_per_quad(int M) {
     while (S < 64 && 2 * S * nq <= 1024) S *= 2;
     return S;
 }
-// Column quads per thread the memory form needs (its KQ)
-static int power_quads_per_thread(int M) { return gram_ld(M) / 4 <= 1024 ? 1 : 4; }
 
 void launch_gram(Operator* op, int* gram, hipStream_t st) {
     const int M = op->M;
@@ -418,21 +557,24 @@ void launch_gram(Operator* op, int* gram, hipStream_t st) {
     CSV_HIP(hipGetLastError());
 }
 
-template <int TS, int KQ = 1>
+template <int TS>
 static void power_batch_launch(const PowBatch& bt, int k, int mmax, hipStream_t st) {
-    const size_t lds = TS > 0 ? 0 : (size_t)gram_ld(mmax) * sizeof(double);
-    if (TS == 0) ensure_lds_limit<&power_batch_kernel<0, KQ>>((size_t)kPowMaxM * sizeof(double));
-    power_batch_kernel<TS, KQ><<<dim3(k), dim3(1024), lds, st>>>(bt, 1e-12, 10000);
+    const size_t lds = TS > 0 ? 0 : (size_t)gram_ld(mmax) * sizeof(double);   // <= 3 KiB
+    power_batch_kernel<TS><<<dim3(k), dim3(1024), lds, st>>>(bt, 1e-12, 10000);
     CSV_HIP(hipGetLastError());
 }
 
-void launch_power_batch(Operator* const* ops, int* const* grams, int count, hipStream_t st) {
-    // one launch per register-form tile size present (and one for M > 256),
-    // up to kPowBatch jobs each
+void launch_power_batch(Operator* const* ops, int* const* grams, int count, void* work,
+                        hipStream_t st) {
+    // one launch per register-form tile size present (and one for the
+    // one-workgroup memory form), up to kPowBatch jobs each; above
+    // kPowMultiMinM one many-workgroup iteration per operator, in turn
+    for (int i = 0; i < count; ++i)
+        if (ops[i]->M > kPowMultiMinM) power_multi(ops[i], grams[i], work, st);
     for (const int ts : {8, 4, 2, 1, 0}) {
         std::vector<int> idx;
         for (int i = 0; i < count; ++i)
-            if (power_tile(ops[i]->M) == ts) idx.push_back(i);
+            if (power_tile(ops[i]->M) == ts && ops[i]->M <= kPowMultiMinM) idx.push_back(i);
         for (size_t a = 0; a < idx.size(); a += kPowBatch) {
             PowBatch bt{};
             int mmax = 0;
@@ -448,38 +590,28 @@ void launch_power_batch(Operator* const* ops, int* const* grams, int count, hipS
                 case 4: power_batch_launch<4>(bt, k, mmax, st); break;
                 case 2: power_batch_launch<2>(bt, k, mmax, st); break;
                 case 1: power_batch_launch<1>(bt, k, mmax, st); break;
-                default:
-                    if (power_quads_per_thread(mmax) == 1)
-                        power_batch_launch<0, 1>(bt, k, mmax, st);
-                    else
-                        power_batch_launch<0, 4>(bt, k, mmax, st);
-                    break;
+                default: power_batch_launch<0>(bt, k, mmax, st); break;
             }
         }
     }
 }
 
-void launch_power_iteration(Operator* op, int* gram, hipStream_t st) {
+void launch_power_iteration(Operator* op, int* gram, void* work, hipStream_t st) {
     launch_gram(op, gram, st);
     const int M = op->M;
+    if (M > kPowMultiMinM) {
+        power_multi(op, gram, work, st);
+        return;
+    }
     switch (power_tile(M)) {
         case 8: power_reg_kernel<8><<<1, 1024, 0, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip); break;
         case 4: power_reg_kernel<4><<<1, 1024, 0, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip); break;
         case 2: power_reg_kernel<2><<<1, 1024, 0, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip); break;
         case 1: power_reg_kernel<1><<<1, 1024, 0, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip); break;
-        default: {
-            // v in LDS, beyond the 64 KB default
+        default: {   // 256 < M <= kPowMultiMinM: v in LDS (at most 3 KiB)
             const size_t lds = (size_t)gram_ld(M) * sizeof(double);
-            const int S = power_threads_per_quad(M);
-            if (power_quads_per_thread(M) == 1) {
-                ensure_lds_limit<&power_kernel<1>>((size_t)kPowMaxM * sizeof(double));
-                power_kernel<1><<<dim3(1), dim3(1024), lds, st>>>(gram, M, S, op->s_phi, 1e-12,
-                                                                   10000, op->lip);
-            } else {
-                ensure_lds_limit<&power_kernel<4>>((size_t)kPowMaxM * sizeof(double));
-                power_kernel<4><<<dim3(1), dim3(1024), lds, st>>>(gram, M, S, op->s_phi, 1e-12,
-                                                                   10000, op->lip);
-            }
+            power_kernel<<<dim3(1), dim3(1024), lds, st>>>(gram, M, power_threads_per_quad(M),
+                                                           op->s_phi, 1e-12, 10000, op->lip);
         }
     }
     CSV_HIP(hipGetLastError());
