@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (counter calibration)")
     ap.add_argument("--mode", choices=["headline", "mixed", "serve", "encode", "configure", "tv",
-                                       "whole", "fp32", "b16"],
+                                       "whole", "fp32", "b16", "setup"],
                     default="headline",
                     help="headline: the metric above; mixed: 64 mixed streams decoded by one "
                          "graph-captured batch; serve: 256 cameras under a Poisson load sweep; "
@@ -81,7 +81,8 @@ def parse():
                          "configure: the (G, M) configurator sweep; tv: TV recovery vs l1; "
                          "whole: whole-frame measurement with Q regenerated on the fly; "
                          "fp32: the plain FP32 path alone on the headline workload; "
-                         "b16: the fused path on 16 x 352x288 GOP-16 B=16 M=64 cameras")
+                         "b16: the fused path on 16 x 352x288 GOP-16 B=16 M=64 cameras; "
+                         "setup: a new stream's operator and step constant per (M, n)")
     ap.add_argument("--psnr-floor", type=float, default=32.0,
                     help="configure mode: PSNR floor standing in for the tracking requirement")
     ap.add_argument("--serve-window", type=float, default=2.0, help="seconds per sweep point")
@@ -692,6 +693,41 @@ def b16_main(args):
         flush=True)
 
 
+def setup_main(args):
+    """Wall time of a new stream's setup (measurement matrix, operator, its
+    fragment layouts, the exact Gram matrix and the FP64 power iteration for
+    the step constant) per (M, n), each shape once in one context after a
+    small warm-up stream; block operators at B = 32 and whole-frame ones."""
+    import paper_1311_1419_amd as P
+    cases = [("block", 32, m) for m in (256, 320, 352, 410, 512, 768, 1024)] + \
+            [("whole", (48, 64), m) for m in (1500, 3000)]
+    res = {}
+    with P.Context(0) as ctx:
+        ctx.step_constant(P.Params(width=64, height=64, gop=2, block=16, m=13, phi_seed=1,
+                                   stream_id=1))
+        for k, (kind, b, m) in enumerate(cases):
+            if kind == "block":
+                p = P.Params(width=64, height=64, gop=2, block=b, m=m, phi_seed=7000 + k,
+                             stream_id=2)
+                key, n = f"block_m{m}_n{b * b}", b * b
+            else:
+                h, w = b
+                p = P.Params(width=w, height=h, gop=2, block=16, m=m, phi_seed=7000 + k,
+                             stream_id=2, precision=P.CSV_FP32,
+                             flags=P.CSV_FLAG_WHOLE_FRAME | P.CSV_FLAG_TV)
+                key, n = f"whole_m{m}_n{h * w}", h * w
+            t0 = time.perf_counter()
+            _, it = ctx.step_constant(p)
+            ms = 1e3 * (time.perf_counter() - t0)
+            res[key] = {"ms": round(ms, 2), "power_iterations": int(it),
+                        "us_per_iteration_upper": round(1e3 * ms / max(1, int(it)), 2)}
+            print(json.dumps({"setup_point": {key: res[key]}}), flush=True)
+    print(json.dumps({"metric": "new-stream setup ms (operator and step constant)",
+                      "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+                      "data": "synthetic", "config": {"workload": "stream setup"},
+                      "points": res}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -722,6 +758,8 @@ def main():
         return fp32_main(args)
     if args.mode == "b16":
         return b16_main(args)
+    if args.mode == "setup":
+        return setup_main(args)
     import torch
     import paper_1311_1419_amd as P
 

@@ -119,7 +119,7 @@ __device__ __forceinline__ void block_sum2_1024(double& a, double& b, double (*r
 // first thread keeps the quad's four entries of w.
 constexpr int kPowMaxM = 16384;
 constexpr int kPowUnroll = 8;       // quad loads in flight per thread
-constexpr int kPowMultiMinM = 384;  // above this M the many-workgroup form runs
+constexpr int kPowMultiMinM = 320;  // above this M the many-workgroup form runs
 __device__ __forceinline__ void power_iterate(const int* __restrict__ g, int M, int S, double s_phi,
                                               double tol, int max_iter, double* __restrict__ lip,
                                               double* v, double (*red)[16]) {
@@ -559,7 +559,7 @@ void launch_gram(Operator* op, int* gram, hipStream_t st) {
 
 template <int TS>
 static void power_batch_launch(const PowBatch& bt, int k, int mmax, hipStream_t st) {
-    const size_t lds = TS > 0 ? 0 : (size_t)gram_ld(mmax) * sizeof(double);   // <= 3 KiB
+    const size_t lds = TS > 0 ? 0 : (size_t)gram_ld(mmax) * sizeof(double);   // <= 2.5 KiB
     power_batch_kernel<TS><<<dim3(k), dim3(1024), lds, st>>>(bt, 1e-12, 10000);
     CSV_HIP(hipGetLastError());
 }
@@ -608,7 +608,7 @@ void launch_power_iteration(Operator* op, int* gram, void* work, hipStream_t st)
         case 4: power_reg_kernel<4><<<1, 1024, 0, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip); break;
         case 2: power_reg_kernel<2><<<1, 1024, 0, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip); break;
         case 1: power_reg_kernel<1><<<1, 1024, 0, st>>>(gram, M, op->s_phi, 1e-12, 10000, op->lip); break;
-        default: {   // 256 < M <= kPowMultiMinM: v in LDS (at most 3 KiB)
+        default: {   // 256 < M <= kPowMultiMinM: v in LDS (at most 2.5 KiB)
             const size_t lds = (size_t)gram_ld(M) * sizeof(double);
             power_kernel<<<dim3(1), dim3(1024), lds, st>>>(gram, M, power_threads_per_quad(M),
                                                            op->s_phi, 1e-12, 10000, op->lip);
