@@ -24,7 +24,9 @@ def _gpu_params(spec, **kw):
 @pytest.mark.parametrize("m,b", [(64, 16), (13, 16), (51, 16), (128, 16), (200, 16), (256, 32),
                                  (410, 32), (1024, 32),
                                  # edges of the register-form tile sizes (32, 64, 128, 256 rows)
-                                 (1, 16), (32, 16), (33, 16), (129, 16), (257, 32)])
+                                 (1, 16), (32, 16), (33, 16), (129, 16), (257, 32),
+                                 # last one-workgroup memory form, first many-workgroup form
+                                 (320, 32), (321, 32)])
 def test_step_constant_and_operator(ctx, m, b):
     import paper_1311_1419_amd as P
     announce(f"operator/L m={m} B={b}")
