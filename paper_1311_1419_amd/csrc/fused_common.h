@@ -62,9 +62,9 @@ __device__ inline int next_tile(const int* __restrict__ qoff, const int* __restr
 // pointers (type PT) address global memory, or a copy of the whole operator
 // in LDS.
 template <int N, int MP, int CT, int NF, int AR, int W, int kPF, int kPA, int NL = 0,
-          bool ILV = false, class PT = gu16x8>
+          bool ILV = false, class PT = gu16x8, class PTA = PT>
 __device__ inline void forward_tiles(u16x8 (&af)[kPF][NF], u16x8 (&aa)[kPA][AR],
-                                     floatx16 (&acc)[NF], const PT* ffwd, const PT* fadj,
+                                     floatx16 (&acc)[NF], const PT* ffwd, const PTA* fadj,
                                      const u16x8* Vb, int w, int ln, int fct, int rt0,
                                      const u16x8* Al = nullptr) {
     constexpr int KSF = N / 16, KSA = MP / 16, KSG = KSF - NL;

@@ -84,7 +84,9 @@ void launch_bf16_frag_layout(Operator* op, hipStream_t st) {
 // tile's operator differs from the previous tile's, and every iteration
 // reads them there instead of from L2 (small classes, where the operator
 // fits beside V and R).  OPT bit 2: s and v in two register arrays that
-// trade roles every iteration (implied by bits 0 and 1 together).
+// trade roles every iteration (implied by bits 0 and 1 together).  OPT bit
+// 3: only the adjoint layout of the operator is copied to LDS, the forward
+// one streams from L2 (classes where one layout fits beside V and R).
 template <int N, int MP, int CT, int W, int kPF, int kPA, int SPL, int OCC, int NLS, int OPT = 0>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(W * OCC / 4)))
 void fista_bf16_kernel(
@@ -101,12 +103,15 @@ void fista_bf16_kernel(
     constexpr int KSF = N / 16, KSA = MP / 16;   // K steps of forward / adjoint
     constexpr bool YREG = (OPT & 1) != 0;        // else y^ is read from L2 in every epilogue
     constexpr bool OPL = (OPT & 2) != 0;         // operator resident in LDS
+    constexpr bool OPA = (OPT & 8) != 0;         // adjoint layout alone resident in LDS
+    static_assert(!(OPL && OPA), "the adjoint layout is part of an LDS-resident operator");
     constexpr bool PP = (YREG && OPL) || (OPT & 4) != 0;   // ping-pong state
     static_assert(!PP || SPL == 0, "ping-pong state keeps every tile in registers");
     static_assert(!(OPL && NLS != 0), "the LDS slice is part of an LDS-resident operator");
     constexpr int OFW = (MP / 32) * KSF * 64;   // u16x8 of the forward layout (OPL)
     constexpr int OFA = (N / 32) * KSA * 64;    // u16x8 of the adjoint layout (OPL)
-    using PT = std::conditional_t<OPL, u16x8, gu16x8>;   // operator pointee type
+    using PT = std::conditional_t<OPL, u16x8, gu16x8>;   // forward operator pointee type
+    using PTA = std::conditional_t<OPL || OPA, u16x8, gu16x8>;   // adjoint's
     constexpr int NL = NLS < 0 ? -NLS : NLS;     // LDS-resident forward K steps
     constexpr bool ILV = NLS < 0;
     static_assert(RT * CT >= 2 && (RT * CT) % 2 == 0 && W % CT == 0, "unsupported class");
@@ -121,7 +126,8 @@ void fista_bf16_kernel(
                                          (size_t)W * SPL * 4096);
     // Al: [W][FT][NL][64], forward fragments (mt_i, KSF - NL + j) of wave w
     u16x8* Ol = Al + (size_t)W * FT * NL * 64;
-    // Ol (OPL): [forward layout OFW][adjoint layout OFA], the global order
+    // Ol (OPL): [forward layout OFW][adjoint layout OFA], the global order;
+    // (OPA): [adjoint layout OFA]
     static_assert(NL == 0 || KSF - NL >= kPF, "LDS steps leave no global ring");
     __shared__ int s_tile;
 
@@ -141,8 +147,18 @@ void fista_bf16_kernel(
         if (t_id < 0) break;
         const FusedTile tl = tiles[t_id];
         const PT* ffwd;
-        const PT* fadj;
-        if constexpr (OPL) {
+        const PTA* fadj;
+        if constexpr (OPA) {
+            // as OPL below, the adjoint layout only
+            if (tl.frag_adj != ol_src) {
+                const gu16x8* ga = as_global<const gu16x8>(tl.frag_adj);
+                for (int i = tid; i < OFA; i += 64 * W) Ol[i] = ga[i];
+                ol_src = tl.frag_adj;
+                __syncthreads();
+            }
+            ffwd = as_global<const gu16x8>(tl.frag_fwd);
+            fadj = Ol;
+        } else if constexpr (OPL) {
             // every wave is past the previous tile (barriers above): copy the
             // new tile's operator once, then wait for the whole copy
             if (tl.frag_fwd != ol_src) {
@@ -431,7 +447,8 @@ static void launch_class(const FusedTile* tiles, const int* qoff, const int* que
     constexpr size_t kFT = ((MP / 32) * CT + W - 1) / W;
     constexpr size_t kNL = NL < 0 ? -NL : NL;
     constexpr size_t kOp = (OPT & 2) ? ((size_t)(MP / 32) * (N / 16) + (size_t)(N / 32) * (MP / 16)) * 1024
-                                     : 0;   // LDS-resident operator
+                           : (OPT & 8) ? (size_t)(N / 32) * (MP / 16) * 1024
+                                       : 0;   // LDS-resident operator (or its adjoint layout)
     constexpr size_t kLds = (size_t)(N / 16) * CT * 1024 + (size_t)(MP / 16) * CT * 1024 +
                             (size_t)W * SPL * 4096 + (size_t)W * kFT * kNL * 1024 + kOp;
     static_assert((kLds + 64) * OCC <= 160 * 1024, "LDS of OCC workgroups exceeds a CU");
@@ -466,6 +483,11 @@ static void launch_class(const FusedTile* tiles, const int* qoff, const int* que
     CSV_VG(NN, MM, CT, W, PF, PA, SPL, OCC, NL, "_lds" #NL)
 #define CSV_VLI(NN, MM, CT, W, PF, PA, SPL, OCC, NL) \
     CSV_VG(NN, MM, CT, W, PF, PA, SPL, OCC, -NL, "_ldsi" #NL)
+#define CSV_VOA(NN, MM, CT, W, PF, PA, OCC, OPTV, SUFFIX)                                  \
+    FusedVariant {                                                                         \
+        "ct" #CT "_w" #W "_pf" #PF "_pa" #PA "_spl0_o" #OCC SUFFIX, CT, OCC,                \
+            &launch_class<NN, MM, CT, W, PF, PA, 0, OCC, 0, OPTV>                           \
+    }
 #define CSV_VLIP(NN, MM, CT, W, PF, PA, OCC, NL)                                            \
     FusedVariant {                                                                         \
         "ct" #CT "_w" #W "_pf" #PF "_pa" #PA "_spl0_o" #OCC "_ldsi" #NL "_pp", CT, OCC,     \
@@ -499,7 +521,14 @@ static std::vector<ClassEntry>& class_table() {
           CSV_VY(256, 96, 1, 4, 2, 2, 0, 3), CSV_V(256, 96, 1, 4, 2, 2, 0, 3)},
          0},
         {256, 128,
-         {CSV_VY(256, 128, 2, 4, 2, 2, 0, 2), CSV_V(256, 128, 1, 4, 2, 2, 0, 3),
+         {CSV_VOA(256, 128, 2, 8, 8, 4, 1, 13, "_yreg_opadj_pp"),
+          CSV_VY(256, 128, 2, 4, 2, 2, 0, 2),
+          CSV_VOA(256, 128, 2, 8, 8, 8, 1, 13, "_yreg_opadj_pp"),
+          CSV_VOA(256, 128, 2, 8, 8, 2, 1, 13, "_yreg_opadj_pp"),
+          CSV_VOA(256, 128, 2, 8, 16, 4, 1, 13, "_yreg_opadj_pp"),
+          CSV_VOA(256, 128, 2, 8, 8, 4, 1, 9, "_yreg_opadj"),
+          CSV_VOA(256, 128, 2, 8, 4, 2, 1, 9, "_yreg_opadj"),
+          CSV_V(256, 128, 1, 4, 2, 2, 0, 3),
           CSV_V(256, 128, 2, 4, 2, 2, 0, 2), CSV_VOL(256, 128, 1, 4, 2, 2, 1),
           CSV_VY(256, 128, 1, 4, 2, 2, 0, 3), CSV_V(256, 128, 2, 8, 4, 2, 0, 1),
           CSV_V(256, 128, 4, 8, 4, 2, 0, 1)},
@@ -544,6 +573,7 @@ static std::vector<ClassEntry>& class_table() {
 #undef CSV_VL
 #undef CSV_VLI
 #undef CSV_VLIP
+#undef CSV_VOA
 #undef CSV_VG
 
 static ClassEntry* find_class(int n, int Mp) {
