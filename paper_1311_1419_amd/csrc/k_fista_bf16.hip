@@ -554,10 +554,10 @@ static std::vector<ClassEntry>& class_table() {
           CSV_VL(1024, 224, 1, 8, 4, 2, 0, 1, 8)},
          0},
         {1024, 256,
-         {CSV_VLI(1024, 256, 1, 8, 4, 2, 0, 1, 8), CSV_V(1024, 256, 1, 8, 4, 2, 0, 1),
-          CSV_V(1024, 256, 1, 8, 4, 2, 2, 1), CSV_V(1024, 256, 1, 8, 8, 2, 2, 1),
-          CSV_V(1024, 256, 1, 8, 4, 2, 1, 1), CSV_VL(1024, 256, 1, 8, 4, 2, 0, 1, 8),
-          CSV_VLIP(1024, 256, 1, 8, 4, 2, 1, 8),
+         {CSV_VLIP(1024, 256, 1, 8, 4, 2, 1, 8), CSV_VLI(1024, 256, 1, 8, 4, 2, 0, 1, 8),
+          CSV_V(1024, 256, 1, 8, 4, 2, 0, 1), CSV_V(1024, 256, 1, 8, 4, 2, 2, 1),
+          CSV_V(1024, 256, 1, 8, 8, 2, 2, 1), CSV_V(1024, 256, 1, 8, 4, 2, 1, 1),
+          CSV_VL(1024, 256, 1, 8, 4, 2, 0, 1, 8),
           FusedVariant{"q8_w8_pf2x2_pa2x2", 1, 1, &launch_fista_q8_m256}},
          0},
         {1024, 416,
