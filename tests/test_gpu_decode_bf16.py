@@ -38,12 +38,15 @@ CASES = [
     (sv.cif_sweep(4, 0.25).with_(block=32, m=12, iters=300), "cif-b32-m12"),
     (sv.cif_sweep(8, 0.2), "cif-g8-b16-m51"),
     (sv.cif_sweep(16, 0.2), "cif-g16-b16-m51"),
-    # odd and minimal iteration counts: the n = 256 kernels keep s and v in two
+    # odd and minimal iteration counts: the class defaults keep s and v in two
     # arrays that trade roles every iteration, so s_T sits in either
     (sv.qcif_tiny().with_(iters=77), "qcif-b16-m64-t77"),
     (sv.cif_sweep(4, 0.1).with_(iters=1), "cif-b16-m26-t1"),
     (sv.cif_sweep(4, 0.3).with_(iters=3), "cif-b16-m77-t3"),
     (sv.cif_sweep(4, 0.5).with_(iters=2), "cif-b16-m128-t2"),
+    (sv.cif_sweep(4, 0.5).with_(iters=5), "cif-b16-m128-t5"),
+    (sv.vga_precision(0.25, gop=2).with_(iters=7), "vga-b32-m256-t7"),
+    (sv.qcif_tiny().with_(block=32, m=102, gop=2, iters=9), "qcif-b32-m102-t9"),
 ]
 
 
