@@ -90,9 +90,11 @@ int csv_server_register_stream(csv_server* srv, const csv_params* p, uint32_t* s
 /* Register `count` streams at once (params and sids: host arrays of count
  * entries): the same validation and ids as count single registrations (in
  * order; none is registered if any is refused), with the new operators'
- * FP64 power iterations run side by side, one workgroup per stream and one
- * launch per size class (M up to 32, 64, 128, 256, above), so that the setup
- * of many cameras costs about as much as the slowest of them. */
+ * FP64 power iterations for M <= 320 run side by side, one workgroup per
+ * stream and one launch per size class (M up to 32, 64, 128, 256, 320), so
+ * that the setup of many cameras costs about as much as the slowest of
+ * them; operators with larger M run their many-workgroup power iterations
+ * one after another. */
 int csv_server_register_streams(csv_server* srv, int32_t count, const csv_params* params,
                                 uint32_t* sids);
 
