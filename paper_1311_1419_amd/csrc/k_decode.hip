@@ -261,6 +261,12 @@ __device__ __forceinline__ void power_iterate_reg(const int* __restrict__ g, int
         wb[1][tid] = 0.0;
     }
     __syncthreads();
+    // this lane's entries of the unnormalised w (v = w * inv), read right
+    // after each barrier so that their latency hides behind the sums and
+    // the norm
+    double wn[TS];
+#pragma unroll
+    for (int c = 0; c < TS; ++c) wn[c] = wb[0][b + 32 * c];
     double inv = 1.0, rq = 0.0, rq_prev = 0.0;
     int cur = 0, it = 0;
     for (it = 1; it <= max_iter; ++it) {
@@ -277,7 +283,7 @@ __device__ __forceinline__ void power_iterate_reg(const int* __restrict__ g, int
         for (int r = 0; r < TS; ++r) p[r] = 0.0;
 #pragma unroll
         for (int c = 0; c < TS; ++c) {
-            const double vc = wb[cur][b + 32 * c] * inv;
+            const double vc = wn[c] * inv;
 #pragma unroll
             for (int r = 0; r < TS; ++r) p[r] = fma((double)gr[r][c], vc, p[r]);
         }
@@ -300,8 +306,10 @@ __device__ __forceinline__ void power_iterate_reg(const int* __restrict__ g, int
             pw = w * w;
             wb[nxt][row] = w;
         }
+        // only every (32 >> kScatter)-th lane holds a row (the others add
+        // zeros), so the sum starts at that stride
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
+        for (int off = 32; off >= (32 >> kScatter); off >>= 1) {
             pv += xor_lane(pv, off);
             pw += xor_lane(pw, off);
         }
@@ -310,6 +318,8 @@ __device__ __forceinline__ void power_iterate_reg(const int* __restrict__ g, int
             red[nxt][1][wv] = pw;
         }
         __syncthreads();
+#pragma unroll
+        for (int c = 0; c < TS; ++c) wn[c] = wb[nxt][b + 32 * c];
         double tv = 0.0, tw = 0.0;
 #pragma unroll
         for (int w = 0; w < 16; ++w) {
